@@ -1,0 +1,144 @@
+"""Seeded synthetic snapshot matrices (inputs only; no rPOD arithmetic here).
+
+The paper's quasi-geostrophic snapshots are not public, so tests and the
+benchmark use synthetic matrices with the same layout: an m x n snapshot
+matrix S (m grid cells, n snapshots), stored column-major, i.e. as a row-major
+array St of shape (n, m) whose row t is snapshot t (Sec. 4.1, the snapshot
+matrix collects one field per column).
+
+Both the GPU path and the CPU oracle draw their inputs from this module.
+Every generator is keyed by (seed, stream, column) through numpy's
+SeedSequence, so the matrix does not depend on how it is chunked.
+
+Generators
+----------
+lowrank_exp     S = U diag(sigma) V^T + noise, U and V orthonormal from the
+                Householder QR of seeded Gaussian matrices (diag(R) > 0),
+                sigma_k = exp(-decay k), k = 1..K.
+fourier_field   a QG-like field on a cell-centred nx x ny grid of
+                [0,1] x [0,2]: each snapshot is a sum of the n_modes
+                lowest Dirichlet modes sin(kx x) sin(ky y),
+                kx = pi a, ky = pi b / 2, with amplitude |k|^-beta times a
+                stationary unit-variance AR(1) series, plus white noise.
+"""
+
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+# stream ids: 1 = U, 2 = V, 3 = noise, 4 = AR(1) series, 5 = shape draws
+_S_U, _S_V, _S_NOISE, _S_AR, _S_SHAPE = 1, 2, 3, 4, 5
+
+
+def rng(seed, stream, *extra):
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(stream), *map(int, extra)]))
+
+
+def _orthonormal(rows, cols, seed, stream):
+    """Q of the Householder QR of a seeded rows x cols Gaussian matrix, diag(R) > 0."""
+    G = rng(seed, stream).standard_normal((rows, cols))
+    Q, R = np.linalg.qr(G, mode="reduced")
+    return Q * np.sign(np.diag(R))[None, :]
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _add_noise(St, noise_std, seed, col0=0):
+    """Add i.i.d. N(0, noise_std^2) noise; column t uses its own stream (seed, 3, t)."""
+    if noise_std == 0.0:
+        return St
+    m = St.shape[1]
+
+    def one(t):
+        St[t] += noise_std * rng(seed, _S_NOISE, col0 + t).standard_normal(m).astype(St.dtype)
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(one, range(St.shape[0])))
+    return St
+
+
+def lowrank_exp(m, n, decay=0.1, noise_std=1e-4, seed=1, K=None, dtype=np.float64):
+    """S = U diag(exp(-decay k)) V^T + noise, returned as St (n, m) plus factors.
+
+    K defaults to min(m, n). noise_std is the standard deviation of the
+    Gaussian noise (variance noise_std**2).
+    """
+    K = min(m, n) if K is None else K
+    U = _orthonormal(m, K, seed, _S_U)
+    V = _orthonormal(n, K, seed, _S_V)
+    sigma = np.exp(-decay * np.arange(1, K + 1))
+    St = (V * sigma[None, :]) @ U.T          # (n, m) = (U diag(s) V^T)^T
+    St = np.ascontiguousarray(St)
+    _add_noise(St, noise_std, seed)
+    return dict(St=St.astype(dtype, copy=False), U=U, V=V, sigma=sigma)
+
+
+def fourier_modes(nx, ny, n_modes):
+    """The n_modes lowest modes (a, b), a, b >= 1, ordered by |k| then a then b.
+
+    |k|^2 = pi^2 (a^2 + b^2 / 4); the integer key 4 a^2 + b^2 orders it exactly.
+    Only a < nx and b < ny are used, where the sampled sines are orthogonal.
+    """
+    amax = min(nx - 1, 4 * int(np.sqrt(n_modes)) + 8)
+    bmax = min(ny - 1, 8 * int(np.sqrt(n_modes)) + 16)
+    cand = [(4 * a * a + b * b, a, b) for a in range(1, amax + 1) for b in range(1, bmax + 1)]
+    cand.sort()
+    if len(cand) < n_modes:
+        raise ValueError("grid too small for the requested number of modes")
+    modes = np.array([(a, b) for _, a, b in cand[:n_modes]], dtype=np.int64)
+    kmag = np.pi * np.sqrt(modes[:, 0] ** 2 + modes[:, 1] ** 2 / 4.0)
+    return modes, kmag
+
+
+def fourier_basis(nx, ny, modes):
+    """F (m x n_modes): column = sin(kx x_i) sin(ky y_j) at cell centres, row = i + nx j.
+
+    x_i = (i + 1/2)/nx on [0,1], y_j = 2 (j + 1/2)/ny on [0,2], so
+    kx x_i = pi a (i + 1/2)/nx and ky y_j = pi b (j + 1/2)/ny.
+    Columns are exactly orthogonal with squared norm nx ny / 4.
+    """
+    ix = np.arange(nx) + 0.5
+    iy = np.arange(ny) + 0.5
+    sx = np.sin(np.pi * np.outer(modes[:, 0], ix) / nx)   # (K, nx)
+    sy = np.sin(np.pi * np.outer(modes[:, 1], iy) / ny)   # (K, ny)
+    F = (sy[:, :, None] * sx[:, None, :]).reshape(len(modes), nx * ny)
+    return F.T
+
+
+def ar1_series(n, k, phi, seed, stream=_S_AR):
+    """k independent stationary unit-variance AR(1) series of length n: (n, k)."""
+    eps = rng(seed, stream).standard_normal((n, k))
+    T = np.empty((n, k))
+    T[0] = eps[0]
+    c = np.sqrt(1.0 - phi * phi)
+    for t in range(1, n):
+        T[t] = phi * T[t - 1] + c * eps[t]
+    return T
+
+
+def fourier_field(nx, ny, n, n_modes=200, beta=1.5, phi=0.95, noise_std=1e-4, seed=2,
+                  dtype=np.float64, col_block=512, amp_scale=None):
+    """QG-like snapshot field; returns dict(St=(n, m) array, modes, kmag, amp, T, ...).
+
+    Snapshot t = sum_k amp_k T[t, k] F[:, k] + noise, amp_k = |k|^-beta
+    (times amp_scale[k] when given).
+    """
+    m = nx * ny
+    modes, kmag = fourier_modes(nx, ny, n_modes)
+    amp = kmag ** (-beta)
+    if amp_scale is not None:
+        amp = amp * np.asarray(amp_scale)
+    T = ar1_series(n, n_modes, phi, seed)
+    F = fourier_basis(nx, ny, modes)                       # (m, K)
+    St = np.empty((n, m), dtype=dtype)
+    C = T * amp[None, :]                                   # (n, K)
+    for t0 in range(0, n, col_block):
+        t1 = min(n, t0 + col_block)
+        blk = C[t0:t1] @ F.T
+        _add_noise(blk, noise_std, seed, col0=t0)
+        St[t0:t1] = blk
+    return dict(St=St, modes=modes, kmag=kmag, amp=amp, T=T, nx=nx, ny=ny)
+
