@@ -1,0 +1,155 @@
+/*
+ * rpod.h - C ABI of the MI355X randomized POD library (librpod.so).
+ *
+ * Randomized proper orthogonal decomposition (rPOD) of a snapshot matrix,
+ * after Sec. 4.2 and Alg. 1 ("randomized POD with subspace iterations") of
+ * Besabe, Girfoglio, Quaini, Rozza, arXiv 2504.15350: from an m x n snapshot
+ * matrix S (m grid cells, n snapshots, one snapshot per column as in the
+ * snapshot matrix of Sec. 4.1) and a target rank r, oversampling p and q
+ * subspace iterations, compute
+ *   Phi   (m x r)  the first r approximate left singular vectors (POD modes),
+ *   sigma (r)      the matching approximate singular values, descending,
+ *   A     (r x n)  the modal coefficients A = Phi^T S (Sec. 4.3, the matrix
+ *                  whose column (k-1) N^t + p holds the coefficients of
+ *                  snapshot (t_p, mu_k)).
+ *
+ * Every step runs on the GPU bound to the plan's stream: Gaussian sketch,
+ * the products with S and S^T, CholeskyQR2 re-orthonormalisation after every
+ * product (same span as step 3 of Alg. 1), T = Q^T S, the SVD of the small T,
+ * the lift Phi = Q U_hat and the coefficients.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Device pointers are HIP device addresses on the current device; host
+ *    pointers are marked "host". The caller owns every buffer (S, outputs,
+ *    workspace); the library never allocates or frees device memory.
+ *  - Matrices are column-major. S has leading dimension ld >= m (element
+ *    (i, j) at S[j*ld + i]). Phi is m x r with leading dimension m; A is r x n
+ *    with leading dimension r; sigma is r contiguous doubles.
+ *  - Output element type: double when the S dtype is RPOD_F64, float for
+ *    RPOD_F32, RPOD_BF16 and RPOD_F16. sigma is always double.
+ *  - Calls that take a plan only enqueue work on the plan's stream and return
+ *    at once. Errors found on the device (non-finite data, a rank-deficient
+ *    sketch) are recorded in a device status word that rpod_status_query()
+ *    reads after synchronising the stream.
+ *  - Arguments are validated before anything is enqueued; on an error
+ *    nothing is launched and rpod_last_error() describes the problem.
+ *  - No C++ exception crosses this interface.
+ *  - Results are deterministic: the same plan, seed and input give bitwise
+ *    identical outputs (fixed-order reductions, no floating-point atomics).
+ *  - Signs: every mode is flipped so that its entry of largest magnitude is
+ *    positive (the lowest row index wins ties); the coefficient row follows.
+ */
+#ifndef RPOD_H
+#define RPOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RPOD_OK = 0,
+    RPOD_EINVAL = 1,        /* invalid argument; nothing was enqueued            */
+    RPOD_EINVAL_DATA = 2,   /* NaN or Inf found in S (reported by status_query)  */
+    RPOD_ENOMEM = 3,        /* workspace smaller than rpod_workspace_size()      */
+    RPOD_EHIP = 4,          /* a HIP runtime call or kernel launch failed        */
+    RPOD_EUNSUPPORTED = 5,  /* l = r + p > 128, or an unsupported dtype          */
+    RPOD_EBREAKDOWN = 6     /* a sketch stayed rank-deficient after the shifted
+                               CholeskyQR retry (e.g. S = 0, or l > rank(S) in
+                               exact arithmetic); outputs are not meaningful     */
+} rpod_status;
+
+typedef enum {
+    RPOD_F64 = 0,   /* S in double; all arithmetic FP64                           */
+    RPOD_F32 = 1,   /* S in float; products on FP32 matrix cores, FP64 small ops  */
+    RPOD_BF16 = 2,  /* S in bfloat16 (mixed precision; see rpod_desc.flags)       */
+    RPOD_F16 = 3    /* S in IEEE half (mixed precision)                           */
+} rpod_dtype;
+
+/* Device status word bits (rpod_status_query). */
+#define RPOD_FLAG_SHIFTED     0x1  /* a Cholesky needed the shifted retry (informational) */
+#define RPOD_FLAG_BREAKDOWN   0x2  /* -> RPOD_EBREAKDOWN */
+#define RPOD_FLAG_NONFINITE   0x4  /* -> RPOD_EINVAL_DATA */
+#define RPOD_FLAG_JACOBI_SLOW 0x8  /* small SVD hit its sweep limit (informational) */
+
+/* Problem description.
+ *   m, n   rows (grid cells) and columns (snapshots) of S, both >= 1.
+ *   ld     leading dimension of S, >= m.
+ *   dtype  an rpod_dtype value: storage type of S.
+ *   r      target rank, >= 1;  p oversampling, >= 0;  q subspace iterations, >= 0.
+ *          The sketch width l = r + p must satisfy l <= min(m, n) and l <= 128.
+ *   flags  reserved, must be 0. */
+typedef struct {
+    int64_t m, n, ld;
+    int32_t dtype;
+    int32_t r, p, q;
+    uint32_t flags;
+} rpod_desc;
+
+typedef struct rpod_plan_s* rpod_plan;
+
+/* Bytes of device workspace a plan for *desc needs (written to *bytes).
+ * Returns RPOD_EINVAL / RPOD_EUNSUPPORTED for a description rpod_plan_create
+ * would reject. */
+rpod_status rpod_workspace_size(const rpod_desc* desc, size_t* bytes);
+
+/* Create a plan bound to `hip_stream` (a hipStream_t; NULL = default stream).
+ * `workspace` is a device buffer of at least rpod_workspace_size() bytes,
+ * 256-byte aligned, owned by the caller and used exclusively by this plan
+ * until rpod_plan_destroy(). The workspace is cleared on `hip_stream` here.
+ * The plan object itself is host memory owned by the library. */
+rpod_status rpod_plan_create(rpod_plan* plan, const rpod_desc* desc,
+                             void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Release the host-side plan (the caller frees the workspace). Synchronises
+ * the plan's stream first. */
+rpod_status rpod_plan_destroy(rpod_plan plan);
+
+/* Randomized POD of S (Alg. 1 of Sec. 4.2 with re-orthonormalisation after
+ * every product with S or S^T), enqueued on the plan's stream.
+ *   S      device, m x n column-major, leading dimension desc.ld, desc.dtype.
+ *   seed   selects the Gaussian sketch (rpod_generate_omega with this seed).
+ *   Phi    device, m x r column-major (ld = m), output.
+ *   sigma  device, r doubles, output, descending.
+ *   A      device, r x n column-major (ld = r), output, A = Phi^T S.
+ * Buffers must not overlap each other or the workspace. */
+rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed,
+                         void* Phi, double* sigma, void* A);
+
+/* Synchronise the plan's stream and read the device status word of the last
+ * compute call (OR of RPOD_FLAG_* bits) into *device_flags (host, may be NULL).
+ * Returns RPOD_EINVAL_DATA if RPOD_FLAG_NONFINITE is set, RPOD_EBREAKDOWN if
+ * RPOD_FLAG_BREAKDOWN is set, RPOD_EHIP on a runtime error, else RPOD_OK. */
+rpod_status rpod_status_query(rpod_plan plan, int32_t* device_flags);
+
+/* The Gaussian sketch of Alg. 1 step 1 (entries N(0,1), Sec. 4.2), drawn on
+ * the GPU: out (device) receives the n x l matrix column-major with leading
+ * dimension ldo >= n, as double (dtype RPOD_F64) or float (RPOD_F32, the
+ * double value rounded to nearest).
+ * Definition: entry (j, c) uses Philox4x32-10 (Salmon et al., SC'11) with
+ * key (seed mod 2^32, seed div 2^32) and counter (j mod 2^32, j div 2^32,
+ * c div 2, 0), giving words x0..x3; a = (x0>>5)*2^26 + (x1>>6),
+ * b = (x2>>5)*2^26 + (x3>>6), u1 = (a + 1/2) 2^-53, u2 = b 2^-53,
+ * rho = sqrt(-2 ln u1), theta = 6.283185307179586 u2; even c takes
+ * rho cos(theta), odd c takes rho sin(theta). Enqueued on hip_stream. */
+rpod_status rpod_generate_omega(uint64_t seed, int64_t n, int32_t l, int32_t dtype,
+                                void* out, int64_t ldo, void* hip_stream);
+
+/* Raw Philox words behind the sketch: out (device, uint32) receives
+ * n * ceil(l/2) * 4 words, element ((j * ceil(l/2) + t) * 4 + w) = word w of
+ * the call for row j, column pair t. Enqueued on hip_stream. */
+rpod_status rpod_sketch_bits(uint64_t seed, int64_t n, int32_t l, uint32_t* out,
+                             void* hip_stream);
+
+/* Human-readable description of the last error on the calling thread
+ * (static storage, valid until the next call on that thread). */
+const char* rpod_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPOD_H */

@@ -1,0 +1,190 @@
+"""Python binding of librpod.so (randomized POD on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/rpod.h. PyTorch supplies device
+memory and streams. There is no fallback path: if the library is not built,
+every entry point raises.
+
+Layout convention: a column-major m x n matrix is a row-major torch tensor
+of shape (n, m). So the snapshot matrix S is passed as St with St[j] =
+snapshot j, the modes come back as Phi_t (r, m) with Phi_t[k] = mode k, and
+the coefficients as A_t (n, r) with A_t[j, k] = coefficient k of snapshot j.
+"""
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["RpodError", "Plan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
+           "STATUS", "FLAG_SHIFTED", "FLAG_BREAKDOWN", "FLAG_NONFINITE", "FLAG_JACOBI_SLOW"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpod.so")
+
+STATUS = {0: "RPOD_OK", 1: "RPOD_EINVAL", 2: "RPOD_EINVAL_DATA", 3: "RPOD_ENOMEM", 4: "RPOD_EHIP",
+          5: "RPOD_EUNSUPPORTED", 6: "RPOD_EBREAKDOWN"}
+FLAG_SHIFTED, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_JACOBI_SLOW = 0x1, 0x2, 0x4, 0x8
+
+_DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}
+
+
+class RpodError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("r", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librpod.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2504_15350_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        sig = {
+            "rpod_workspace_size": [ctypes.POINTER(_Desc), ctypes.POINTER(ctypes.c_size_t)],
+            "rpod_plan_create": [ctypes.POINTER(vp), ctypes.POINTER(_Desc), vp, ctypes.c_size_t, vp],
+            "rpod_plan_destroy": [vp],
+            "rpod_compute": [vp, vp, u64, vp, vp, vp],
+            "rpod_status_query": [vp, ctypes.POINTER(i32)],
+            "rpod_generate_omega": [u64, i64, i32, i32, vp, i64, vp],
+            "rpod_sketch_bits": [u64, i64, i32, vp, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.rpod_last_error.argtypes = []
+        L.rpod_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise RpodError(status, lib().rpod_last_error().decode())
+
+
+def _stream_ptr(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream), s
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(m, n, r, p, q, dtype, ld=None, flags=0):
+    if dtype not in _DTYPES:
+        raise TypeError(f"unsupported dtype {dtype}")
+    return _Desc(int(m), int(n), int(m if ld is None else ld), _DTYPES[dtype], int(r), int(p), int(q), int(flags))
+
+
+def workspace_size(m, n, r, p, q, dtype, ld=None):
+    d = make_desc(m, n, r, p, q, dtype, ld)
+    out = ctypes.c_size_t(0)
+    _check(lib().rpod_workspace_size(ctypes.byref(d), ctypes.byref(out)))
+    return out.value
+
+
+class Plan:
+    """A plan for one matrix shape: rpod_plan_create / rpod_compute / rpod_status_query."""
+
+    def __init__(self, m, n, r, p, q, dtype=torch.float32, ld=None, device="cuda", stream=None):
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.m, self.n, self.r, self.p, self.q = int(m), int(n), int(r), int(p), int(q)
+        self.ld = self.m if ld is None else int(ld)
+        self.dtype = dtype
+        self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
+        self._desc = make_desc(m, n, r, p, q, dtype, ld)
+        nbytes = workspace_size(m, n, r, p, q, dtype, ld)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        sptr, self.stream = _stream_ptr(stream, self.device)
+        h = ctypes.c_void_p()
+        _check(lib().rpod_plan_create(ctypes.byref(h), ctypes.byref(self._desc), _dev_ptr(self.workspace),
+                                      nbytes, sptr))
+        self._h = h
+
+    def compute(self, St, seed, out=None, check=True):
+        """rPOD of the column-major S given as St (n, ld) -> (Phi_t (r, m), sigma (r,), A_t (n, r)).
+
+        With check=True the stream is synchronised and the device status
+        word is turned into an exception; check=False only enqueues.
+        """
+        if St.dtype != self.dtype or St.device != self.device:
+            raise TypeError("St must be a tensor of the plan's dtype on the plan's device")
+        if St.dim() != 2 or St.shape[0] != self.n or St.shape[1] < self.m:
+            raise ValueError(f"St must have shape ({self.n}, >= {self.m})")
+        if St.stride(1) != 1 or St.stride(0) != self.ld:
+            raise ValueError("St must be row-major with row stride equal to the plan's ld")
+        if out is None:
+            Phi = torch.empty((self.r, self.m), dtype=self.out_dtype, device=self.device)
+            sigma = torch.empty((self.r,), dtype=torch.float64, device=self.device)
+            A = torch.empty((self.n, self.r), dtype=self.out_dtype, device=self.device)
+        else:
+            Phi, sigma, A = out
+        _check(lib().rpod_compute(self._h, _dev_ptr(St), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                  _dev_ptr(Phi), _dev_ptr(sigma), _dev_ptr(A)))
+        if check:
+            self.status()
+        return Phi, sigma, A
+
+    def status(self):
+        """Synchronise and return the device flags; raise on an error status."""
+        fl = ctypes.c_int32(0)
+        st = lib().rpod_status_query(self._h, ctypes.byref(fl))
+        self.last_flags = fl.value
+        _check(st)
+        return fl.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rpod_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rpod(St, r, p, q, seed, stream=None):
+    """One-shot rPOD of St (n, m), a column-major m x n snapshot matrix."""
+    n, m = St.shape
+    plan = Plan(m, n, r, p, q, dtype=St.dtype, ld=St.stride(0), device=St.device, stream=stream)
+    out = plan.compute(St, seed)
+    plan.close()
+    return out
+
+
+def generate_omega(seed, n, l, dtype=torch.float64, device="cuda", stream=None):
+    """The n x l Gaussian sketch as an (l, n) tensor (column-major n x l)."""
+    out = torch.empty((l, n), dtype=dtype, device=device)
+    sptr, s = _stream_ptr(stream, torch.device(device))
+    _check(lib().rpod_generate_omega(ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), n, l, _DTYPES[dtype],
+                                     _dev_ptr(out), n, sptr))
+    s.synchronize()
+    return out
+
+
+def sketch_bits(seed, n, l, device="cuda", stream=None):
+    """Raw Philox words as an int32 tensor of shape (n, ceil(l/2), 4) (bit pattern of uint32)."""
+    out = torch.empty((n, (l + 1) // 2, 4), dtype=torch.int32, device=device)
+    sptr, s = _stream_ptr(stream, torch.device(device))
+    _check(lib().rpod_sketch_bits(ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), n, l, _dev_ptr(out), sptr))
+    s.synchronize()
+    return out

@@ -1,0 +1,252 @@
+// Passes over the snapshot matrix S on the matrix cores (gfx950).
+//
+//   k_sx   Y = S X   (sketch of Alg. 1 step 2, the S-products of step 3, and
+//                     the small applications Y R^-1 / Q U_hat)
+//   k_stq  Z = S^T Q (the S^T-products of step 3 and T^T = S^T Q of step 5)
+//
+// Both stream S column-major straight from HBM into registers in the
+// operand layout of the 16x16x4 MFMA, so no LDS staging is needed: the row
+// index of S is permuted inside an MFMA tile (free for the M and K
+// dimensions as long as both operands agree), which turns every load into a
+// 16-byte (FP32) or 32-byte (FP64) contiguous vector load.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace rpod {
+
+template <typename T>
+using V4 = typename vec4_of<T>::type;
+
+// Four consecutive rows i..i+3 of column j, rows >= lim or columns >= n read 0.
+template <bool VEC, typename T>
+__device__ __forceinline__ V4<T> load_rows4(const T* S, int64_t ld, int64_t lim, int64_t n,
+                                            int64_t i, int64_t j) {
+    V4<T> v = {0, 0, 0, 0};
+    if (j < n) {
+        const T* p = S + j * ld + i;
+        if (VEC && i + 3 < lim) {
+            v = *reinterpret_cast<const V4<T>*>(p);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (i + t < lim) v[t] = p[t];
+        }
+    }
+    return v;
+}
+
+template <typename Tout, typename T>
+__device__ __forceinline__ void store4(Tout* p, T a, T b, T c, T d) {
+    typedef typename vec4_of<Tout>::type VO;
+    VO v = {(Tout)a, (Tout)b, (Tout)c, (Tout)d};
+    *reinterpret_cast<VO*>(p) = v;
+}
+
+// ---------------------------------------------------------------------------
+// Y = S X. Workgroup = 4 waves = 256 rows of S; every wave owns 64 rows and
+// all 16*NT output columns. Per 16-column step a lane loads rows
+// 4*(l%16)..+3 of four columns (one vector each) and a 4-vector of X per
+// output tile; MFMA (t, c, s) uses row slot t, output tile c, column slot s:
+//   A[mm][k] = S[iw + 4 mm + t][j0 + 4 k + s],  B[k][nn] = X[j0 + 4 k + s][16 c + nn]
+// so output row mm of MFMA t is global row iw + 4 mm + t.
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tout, int NT, bool VEC>
+__global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m, int64_t n,
+                                            const Tin* __restrict__ X, int64_t ldX, Tout* Y,
+                                            int64_t ldY, int64_t mstore, const int* cond,
+                                            int cond_mask) {
+    if (cond != nullptr && !(*cond & cond_mask)) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int64_t iw = (int64_t)blockIdx.x * 256 + wave * 64;
+    const int64_t irow = iw + 4 * r16;
+
+    V4<Tin> acc[4][NT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[t][c] = V4<Tin>{0, 0, 0, 0};
+
+    if (iw < m) {
+        for (int64_t j0 = 0; j0 < n; j0 += 16) {
+            V4<Tin> a[4], b[NT];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[s] = load_rows4<VEC>(S, ldS, m, n, irow, j0 + 4 * kg + s);
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+                b[c] = *reinterpret_cast<const V4<Tin>*>(X + (int64_t)(16 * c + r16) * ldX + j0 + 4 * kg);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) acc[t][c] = mfma_16x16x4(a[s][t], b[c][s], acc[t][c]);
+        }
+    }
+    // component v of acc[t][c] is MFMA row mm = mfma_row(kg, v), i.e. global
+    // row iw + 4 mm + t: rows t = 0..3 are contiguous
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        Tout* py = Y + (int64_t)(16 * c + r16) * ldY;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = iw + 4 * mfma_row<Tin>(kg, v);
+            if (row + 3 < mstore) {
+                store4<Tout>(py + row, acc[0][c][v], acc[1][c][v], acc[2][c][v], acc[3][c][v]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (row + t < mstore) py[row + t] = (Tout)acc[t][c][v];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Z_s = S_s^T Q_s for row split s. Workgroup = 4 waves = 256 columns of S
+// (each wave 4 tiles of 16 columns), streaming its split of rows 16 at a
+// time. MFMA (u, c, s) with column tile u, output tile c, row slot s:
+//   A[mm][k] = S[i0 + 4 k + s][jw + 16 u + mm],  B[k][nn] = Q[i0 + 4 k + s][16 c + nn].
+// ---------------------------------------------------------------------------
+template <typename Tin, int NT, bool VEC>
+__global__ __launch_bounds__(256) void k_stq(const Tin* __restrict__ S, int64_t ldS, int64_t m,
+                                             int64_t n, const Tin* __restrict__ Q, int64_t ldQ,
+                                             double* __restrict__ Zp, int64_t nP, int64_t split_rows) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int64_t jw = (int64_t)blockIdx.x * 256 + wave * 64;
+    const int64_t ib = (int64_t)blockIdx.y * split_rows;
+    const int64_t ie = (ib + split_rows < m) ? ib + split_rows : m;
+
+    V4<Tin> acc[4][NT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[u][c] = V4<Tin>{0, 0, 0, 0};
+
+    if (jw < n) {
+        for (int64_t i0 = ib; i0 < ie; i0 += 16) {
+            V4<Tin> a[4], b[NT];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = load_rows4<VEC>(S, ldS, ie, n, i0 + 4 * kg, jw + 16 * u + r16);
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+                b[c] = *reinterpret_cast<const V4<Tin>*>(Q + (int64_t)(16 * c + r16) * ldQ + i0 + 4 * kg);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) acc[u][c] = mfma_16x16x4(a[u][s], b[c][s], acc[u][c]);
+        }
+    }
+    double* zp = Zp + (int64_t)blockIdx.y * nP * (16 * NT);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            double* pz = zp + (int64_t)(16 * c + r16) * nP + jw + 16 * u;
+            if constexpr (sizeof(Tin) == 4) {
+                store4<double>(pz + 4 * kg, acc[u][c][0], acc[u][c][1], acc[u][c][2], acc[u][c][3]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pz[mfma_row<Tin>(kg, v)] = acc[u][c][v];
+            }
+        }
+}
+
+__global__ void k_reduce_slabs(const double* __restrict__ Zp, int nsplit, int64_t count,
+                               double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += Zp[(int64_t)k * count + e];
+    out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tout, int NT>
+static hipError_t sx_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const void* X, int64_t ldX,
+                        void* Y, int64_t ldY, int64_t mstore, const int* cond, int cond_mask,
+                        hipStream_t st) {
+    const int64_t rows = mstore > m ? mstore : m;
+    dim3 grid((unsigned)((rows + 255) / 256));
+    const bool vec = (ldS % 4 == 0) && ((uintptr_t)S % (4 * sizeof(Tin)) == 0);
+    if (vec)
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
+                           (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
+    else
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
+                           (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Tout>
+static hipError_t sx_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* X,
+                              int64_t ldX, void* Y, int64_t ldY, int64_t mstore, const int* cond,
+                              int cond_mask, hipStream_t st) {
+    switch (nt) {
+#define RPOD_SX_CASE(K) \
+    case K: return sx_nt<Tin, Tout, K>(S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+        RPOD_SX_CASE(1) RPOD_SX_CASE(2) RPOD_SX_CASE(3) RPOD_SX_CASE(4)
+        RPOD_SX_CASE(5) RPOD_SX_CASE(6) RPOD_SX_CASE(7) RPOD_SX_CASE(8)
+#undef RPOD_SX_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sx(int tin, int tout, int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
+                     const void* X, int64_t ldX, void* Y, int64_t ldY, int64_t mstore, const int* cond,
+                     int cond_mask, hipStream_t st) {
+    if (tin == DT_F64 && tout == DT_F64)
+        return sx_dispatch<double, double>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+    if (tin == DT_F64 && tout == DT_F32)
+        return sx_dispatch<double, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+    if (tin == DT_F32 && tout == DT_F32)
+        return sx_dispatch<float, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+    return hipErrorInvalidValue;
+}
+
+template <typename Tin, int NT>
+static hipError_t stq_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q, int64_t ldQ,
+                         double* Zp, int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
+    dim3 grid((unsigned)(nP / 256), (unsigned)nsplit);
+    const bool vec = (ldS % 4 == 0) && ((uintptr_t)S % (4 * sizeof(Tin)) == 0);
+    if (vec)
+        hipLaunchKernelGGL((k_stq<Tin, NT, true>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
+                           (const Tin*)Q, ldQ, Zp, nP, split_rows);
+    else
+        hipLaunchKernelGGL((k_stq<Tin, NT, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
+                           (const Tin*)Q, ldQ, Zp, nP, split_rows);
+    return hipGetLastError();
+}
+
+template <typename Tin>
+static hipError_t stq_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q,
+                               int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit,
+                               hipStream_t st) {
+    switch (nt) {
+#define RPOD_STQ_CASE(K) case K: return stq_nt<Tin, K>(S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+        RPOD_STQ_CASE(1) RPOD_STQ_CASE(2) RPOD_STQ_CASE(3) RPOD_STQ_CASE(4)
+        RPOD_STQ_CASE(5) RPOD_STQ_CASE(6) RPOD_STQ_CASE(7) RPOD_STQ_CASE(8)
+#undef RPOD_STQ_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stq(int tin, int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q,
+                      int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
+    if (tin == DT_F64) return stq_dispatch<double>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+    if (tin == DT_F32) return stq_dispatch<float>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_slabs(const double* Zp, int nsplit, int64_t count, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_slabs, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, Zp, nsplit,
+                       count, out);
+    return hipGetLastError();
+}
+
+}  // namespace rpod

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI (no GPU needed): symbols and argument validation."""
+
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+import paper_2504_15350_amd as rp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(rpod_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(rp.LIB_PATH), reason="librpod.so not built")
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    L = rp.lib()
+    syms = _declared_symbols()
+    assert {"rpod_compute", "rpod_plan_create", "rpod_workspace_size"} <= syms
+    for s in sorted(syms):
+        assert hasattr(L, s), s
+
+
+@needs_lib
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=0, n=10, r=1, p=0, q=0), 1),
+    (dict(m=10, n=10, r=0, p=0, q=0), 1),
+    (dict(m=10, n=10, r=2, p=-1, q=0), 1),
+    (dict(m=10, n=10, r=2, p=1, q=-1), 1),
+    (dict(m=10, n=10, r=8, p=3, q=0), 1),            # l > min(m, n)
+    (dict(m=1000, n=1000, r=100, p=29, q=0), 5),      # l > 128
+    (dict(m=100, n=100, r=4, p=2, q=1, ld=99), 1),     # ld < m
+])
+def test_workspace_size_rejects(kw, status):
+    ld = kw.pop("ld", None)
+    with pytest.raises(rp.RpodError) as e:
+        rp.workspace_size(dtype=torch.float32, ld=ld, **kw)
+    assert e.value.status == status
+    assert rp.lib().rpod_last_error().decode() != "no error"
+
+
+@needs_lib
+def test_workspace_size_accepts_edges():
+    a = rp.workspace_size(1000, 30, 20, 10, 0, torch.float64)      # l == n
+    b = rp.workspace_size(262144, 5000, 50, 10, 2, torch.float32)
+    c = rp.workspace_size(4096, 200, 100, 28, 1, torch.float32)     # l == 128
+    assert 0 < a < b and c > 0
+    assert b % 256 == 0
+
+
+@needs_lib
+def test_unsupported_dtype_is_reported():
+    with pytest.raises(rp.RpodError) as e:
+        rp.workspace_size(1000, 100, 10, 5, 1, torch.float16)
+    assert e.value.status in (0, 5)
+
+
+@needs_lib
+def test_plan_create_null_arguments():
+    L = rp.lib()
+    d = rp.make_desc(100, 50, 5, 5, 1, torch.float32)
+    h = ctypes.c_void_p()
+    assert L.rpod_plan_create(ctypes.byref(h), ctypes.byref(d), None, 1 << 20, None) == 1
+    assert L.rpod_plan_create(ctypes.byref(h), ctypes.byref(d), ctypes.c_void_p(256 * 3 + 8), 1 << 30, None) == 1
+    assert L.rpod_plan_create(ctypes.byref(h), ctypes.byref(d), ctypes.c_void_p(1 << 20), 16, None) == 3
+    assert L.rpod_compute(None, None, 0, None, None, None) == 1
+    assert L.rpod_status_query(None, None) == 1
+    assert L.rpod_plan_destroy(None) == 1
+    assert L.rpod_generate_omega(1, 0, 4, 0, None, 1, None) == 1
+    assert L.rpod_sketch_bits(1, 10, 4, None, None) == 1
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(rp, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(rp, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        rp.lib()
