@@ -144,6 +144,21 @@ rpod_status rpod_generate_omega(uint64_t seed, int64_t n, int32_t l, int32_t dty
 rpod_status rpod_sketch_bits(uint64_t seed, int64_t n, int32_t l, uint32_t* out,
                              void* hip_stream);
 
+/* Per-pass timing, for measurement. With enable != 0 the plan records a
+ * pair of HIP events on its stream around every pass over S issued by later
+ * compute calls (pass 0: the products S X of Alg. 1 steps 2-3; pass 1: the
+ * products S^T Q of steps 3 and 5), resetting earlier records; enable = 0
+ * stops recording. The first call with enable != 0 creates the events. */
+rpod_status rpod_plan_set_timing(rpod_plan plan, int32_t enable);
+
+/* Synchronise the plan's stream and report the recorded launches of one
+ * pass kind (0 or 1): their number, summed duration in milliseconds, and the
+ * algorithmic work of one launch: bytes = m n size(S) + n l size(S) + m l 4
+ * (S once, the n x l operand once, the m x l result or operand once) and
+ * flops = 2 m n l. Host pointers; any may be NULL. */
+rpod_status rpod_plan_get_timing(rpod_plan plan, int32_t pass, int64_t* launches, double* total_ms,
+                                 double* bytes_per_launch, double* flops_per_launch);
+
 /* Human-readable description of the last error on the calling thread
  * (static storage, valid until the next call on that thread). */
 const char* rpod_last_error(void);

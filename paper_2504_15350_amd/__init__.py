@@ -60,6 +60,9 @@ def lib():
             "rpod_status_query": [vp, ctypes.POINTER(i32)],
             "rpod_generate_omega": [u64, i64, i32, i32, vp, i64, vp],
             "rpod_sketch_bits": [u64, i64, i32, vp, vp],
+            "rpod_plan_set_timing": [vp, i32],
+            "rpod_plan_get_timing": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -149,6 +152,18 @@ class Plan:
         self.last_flags = fl.value
         _check(st)
         return fl.value
+
+    def set_timing(self, enable=True):
+        """Record HIP events around every pass over S of later compute calls."""
+        _check(lib().rpod_plan_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self, pass_kind):
+        """(launches, total_ms, bytes_per_launch, flops_per_launch) of pass 0 (S X) or 1 (S^T Q)."""
+        n = ctypes.c_int64(0)
+        t, b, f = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        _check(lib().rpod_plan_get_timing(self._h, int(pass_kind), ctypes.byref(n), ctypes.byref(t),
+                                          ctypes.byref(b), ctypes.byref(f)))
+        return n.value, t.value, b.value, f.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

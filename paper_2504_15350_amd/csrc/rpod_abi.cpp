@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/rpod.h"
 #include "internal.hpp"
@@ -134,9 +135,33 @@ struct rpod_plan_s {
     Layout L;
     char* ws;
     hipStream_t st;
+    // per-pass event timing (measurement only)
+    bool timing = false;
+    std::vector<hipEvent_t> ev[2];  // start/stop pairs, reused across resets
+    size_t used[2] = {0, 0};
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
+
+namespace {
+
+// Record the start (begin=true) or stop event of one pass over S.
+hipError_t mark(rpod_plan_s* P, int kind, bool begin) {
+    if (!P->timing) return hipSuccess;
+    std::vector<hipEvent_t>& v = P->ev[kind];
+    const size_t idx = begin ? 2 * P->used[kind] : 2 * P->used[kind] + 1;
+    if (idx >= v.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        v.push_back(e);
+    }
+    hipError_t err = hipEventRecord(v[idx], P->st);
+    if (!begin) ++P->used[kind];
+    return err;
+}
+
+}  // namespace
 
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
@@ -218,6 +243,8 @@ rpod_status rpod_plan_create(rpod_plan* plan, const rpod_desc* desc, void* works
 rpod_status rpod_plan_destroy(rpod_plan plan) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     hipError_t e = hipStreamSynchronize(plan->st);
+    for (int k = 0; k < 2; ++k)
+        for (hipEvent_t ev : plan->ev[k]) (void)hipEventDestroy(ev);
     delete plan;
     if (e != hipSuccess) return fail(RPOD_EHIP, "stream synchronisation failed: %s", hipGetErrorString(e));
     return RPOD_OK;
@@ -227,7 +254,7 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     if (S == nullptr || Phi == nullptr || sigma == nullptr || A == nullptr)
         return fail(RPOD_EINVAL, "S, Phi, sigma and A must be non-NULL");
-    const rpod_plan_s* P = plan;
+    rpod_plan_s* P = plan;
     const Layout& L = P->L;
     const rpod_desc& d = P->d;
     if ((uintptr_t)S % dt_size(L.tin) != 0) return fail(RPOD_EINVAL, "S is not aligned to its element size");
@@ -252,23 +279,31 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi
     // Alg. 1 step 1: Gaussian sketch
     HIP_TRY(launch_omega(L.tin, seed, n, L.l, lp, L.nP, X, L.nP, st));
     // step 2: Y = S Omega, then Q by CholeskyQR2
+    HIP_TRY(mark(P, 0, true));
     HIP_TRY(launch_sx(L.tin, L.tacc, nt, S, d.ld, m, n, X, L.nP, Y, L.mP, L.mP, nullptr, 0, st));
+    HIP_TRY(mark(P, 0, false));
     rpod_status s = orth(P, L.tacc, Y, Q1, L.mP, m, 1);
     if (s != RPOD_OK) return s;
     // step 3, one product at a time with re-orthonormalisation
     for (int it = 0; it < d.q; ++it) {
+        HIP_TRY(mark(P, 1, true));
         HIP_TRY(launch_stq(L.tin, nt, S, d.ld, m, n, Q1, L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
+        HIP_TRY(mark(P, 1, false));
         HIP_TRY(launch_reduce_slabs(Zp, L.nsplit, L.nP * lp, Zt, st));
         HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st));
         s = orth(P, DT_F64, Zw, Zw2, L.nP, n, 2);
         if (s != RPOD_OK) return s;
         HIP_TRY(launch_sx(DT_F64, L.tin, nt, Zw2, L.nP, n, lp, R64s, lp, X, L.nP, L.nP, nullptr, 0, st));
+        HIP_TRY(mark(P, 0, true));
         HIP_TRY(launch_sx(L.tin, L.tacc, nt, S, d.ld, m, n, X, L.nP, Y, L.mP, L.mP, nullptr, 0, st));
+        HIP_TRY(mark(P, 0, false));
         s = orth(P, L.tacc, Y, Q1, L.mP, m, 1);
         if (s != RPOD_OK) return s;
     }
     // step 5: T^T = S^T Q (Q = Q1 R^-1 applied on the small side)
+    HIP_TRY(mark(P, 1, true));
     HIP_TRY(launch_stq(L.tin, nt, S, d.ld, m, n, Q1, L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
+    HIP_TRY(mark(P, 1, false));
     HIP_TRY(launch_reduce_slabs(Zp, L.nsplit, L.nP * lp, Zt, st));
     HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st));
     // step 6: SVD of T through the eigenvectors of T T^T
@@ -305,6 +340,33 @@ rpod_status rpod_status_query(rpod_plan plan, int32_t* device_flags) {
     if (host_flags & RPOD_FLAG_NONFINITE) return fail(RPOD_EINVAL_DATA, "non-finite values in S");
     if (host_flags & RPOD_FLAG_BREAKDOWN)
         return fail(RPOD_EBREAKDOWN, "sketch rank-deficient after the shifted CholeskyQR retry");
+    return RPOD_OK;
+}
+
+rpod_status rpod_plan_set_timing(rpod_plan plan, int32_t enable) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    plan->timing = enable != 0;
+    plan->used[0] = plan->used[1] = 0;
+    return RPOD_OK;
+}
+
+rpod_status rpod_plan_get_timing(rpod_plan plan, int32_t pass, int64_t* launches, double* total_ms,
+                                 double* bytes_per_launch, double* flops_per_launch) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    if (pass < 0 || pass > 1) return fail(RPOD_EINVAL, "pass must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(plan->st));
+    double tot = 0.0;
+    for (size_t k = 0; k < plan->used[pass]; ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, plan->ev[pass][2 * k], plan->ev[pass][2 * k + 1]));
+        tot += ms;
+    }
+    const rpod_desc& d = plan->d;
+    const double s = (double)dt_size(plan->L.tin), l = (double)plan->L.l;
+    if (launches) *launches = (int64_t)plan->used[pass];
+    if (total_ms) *total_ms = tot;
+    if (bytes_per_launch) *bytes_per_launch = (double)d.m * d.n * s + (double)d.n * l * s + (double)d.m * l * 4.0;
+    if (flops_per_launch) *flops_per_launch = 2.0 * d.m * d.n * l;
     return RPOD_OK;
 }
 
