@@ -10,6 +10,14 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T> struct vec4_of;
 template <> struct vec4_of<float>  { typedef f32x4 type; };
 template <> struct vec4_of<double> { typedef f64x4 type; };
+template <> struct vec4_of<__bf16> { typedef __bf16 type __attribute__((ext_vector_type(4))); };
+template <> struct vec4_of<_Float16> { typedef _Float16 type __attribute__((ext_vector_type(4))); };
+
+// Narrowing used for every store into a 16-bit operand: through FP32, each
+// step rounding to nearest even.
+template <typename Tout, typename T>
+__device__ __forceinline__ Tout narrow(T x) { return (Tout)(float)x; }
+template <> __device__ __forceinline__ double narrow<double, double>(double x) { return x; }
 
 // One 16x16x4 matrix-core step, D = A*B + C, wave64 operand layout:
 //   lane l supplies A[l%16][l/16] and B[l/16][l%16];

@@ -13,7 +13,8 @@ enum DT : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
 //      rows >= m and columns >= n read as zero.
 //   X: n x 16*nt column-major (ldX >= roundup(n,16), multiple of 4), type tin,
 //      zero-padded rows up to roundup(n,16).
-//   Y: mstore x 16*nt column-major (ldY multiple of 4), type tout; rows
+//   Y: mstore x 16*nt column-major (ldY multiple of 4), type tout (F64, F32,
+//      or a 16-bit type when tin is F64, converted through FP32); rows
 //      [0, mstore) are written, mstore <= ldY.
 //   If cond != nullptr the kernel does nothing unless (*cond & cond_mask).
 hipError_t launch_sx(int tin, int tout, int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
@@ -28,6 +29,16 @@ hipError_t launch_sx(int tin, int tout, int nt, const void* S, int64_t ldS, int6
 hipError_t launch_stq(int tin, int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
                       const void* Q, int64_t ldQ, double* Zp, int64_t nP,
                       int64_t split_rows, int nsplit, hipStream_t st);
+
+// 16-bit (tin = DT_BF16 or DT_F16) versions on the 16x16x32 matrix cores:
+// Y (FP32) = S X with X in the same 16-bit type (ldX multiple of 8, zero rows
+// up to roundup(n, 32)); partial Z = S^T Q with Q in FP32 (zero rows up to
+// roundup(m, 32)), rounded to 16 bits on the fly, plus the rounding remainder
+// as a second product when lo is set. split_rows must be a multiple of 32.
+hipError_t launch_sx16(int tin, int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* X,
+                       int64_t ldX, float* Y, int64_t ldY, int64_t mstore, hipStream_t st);
+hipError_t launch_stq16(int tin, int nt, bool lo, const void* S, int64_t ldS, int64_t m, int64_t n, const float* Q,
+                        int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit, hipStream_t st);
 
 // out[e] = sum_s Zp[s * count + e], fixed order.
 hipError_t launch_reduce_slabs(const double* Zp, int nsplit, int64_t count, double* out, hipStream_t st);

@@ -64,8 +64,6 @@ rpod_status validate(const rpod_desc* d) {
     const int64_t mn = d->m < d->n ? d->m : d->n;
     if (l > mn) return fail(RPOD_EINVAL, "l = r + p = %lld exceeds min(m, n) = %lld", (long long)l, (long long)mn);
     if (l > 128) return fail(RPOD_EUNSUPPORTED, "l = r + p = %lld exceeds 128", (long long)l);
-    if (d->dtype != RPOD_F64 && d->dtype != RPOD_F32)
-        return fail(RPOD_EUNSUPPORTED, "dtype %d is not supported by this build", d->dtype);
     return RPOD_OK;
 }
 
@@ -78,7 +76,7 @@ Layout make_layout(const rpod_desc* d) {
     L.ntr = L.rp / 16;
     L.mP = roundup(d->m, 256);
     L.nP = roundup(d->n, 256);
-    L.tin = d->dtype == RPOD_F64 ? DT_F64 : DT_F32;
+    L.tin = d->dtype == RPOD_F64 ? DT_F64 : d->dtype == RPOD_F32 ? DT_F32 : d->dtype == RPOD_BF16 ? DT_BF16 : DT_F16;
     L.tacc = d->dtype == RPOD_F64 ? DT_F64 : DT_F32;
     // split-K over rows for S^T Q: about 1024 workgroups, at least 256 rows each
     const int64_t ncb = L.nP / 256;
@@ -87,7 +85,7 @@ Layout make_layout(const rpod_desc* d) {
     const int64_t maxs = (d->m + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
-    L.split_rows = roundup((d->m + ns - 1) / ns, 16);
+    L.split_rows = roundup((d->m + ns - 1) / ns, 32);
     L.nsplit = (int)((d->m + L.split_rows - 1) / L.split_rows);
     int64_t nc = d->m / 2048;
     L.nchunk = (int)(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
@@ -276,35 +274,47 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi
     const int lp = L.lp, nt = L.nt;
 
     HIP_TRY(launch_zero_ints(flags, 64, st));
+    const bool s16 = L.tin == DT_BF16 || L.tin == DT_F16;
+    // one pass Y = S X over S
+    auto pass_sx = [&]() -> rpod_status {
+        HIP_TRY(mark(P, 0, true));
+        if (s16)
+            HIP_TRY(launch_sx16(L.tin, nt, S, d.ld, m, n, X, L.nP, static_cast<float*>(Y), L.mP, L.mP, st));
+        else
+            HIP_TRY(launch_sx(L.tin, L.tacc, nt, S, d.ld, m, n, X, L.nP, Y, L.mP, L.mP, nullptr, 0, st));
+        HIP_TRY(mark(P, 0, false));
+        return RPOD_OK;
+    };
+    // one pass Z~ = S^T Q1 over S (lo: Q1 with ~16 significant bits on 16-bit paths)
+    auto pass_stq = [&](bool lo) -> rpod_status {
+        HIP_TRY(mark(P, 1, true));
+        if (s16)
+            HIP_TRY(launch_stq16(L.tin, nt, lo, S, d.ld, m, n, static_cast<const float*>(Q1), L.mP, Zp, L.nP,
+                                 L.split_rows, L.nsplit, st));
+        else
+            HIP_TRY(launch_stq(L.tin, nt, S, d.ld, m, n, Q1, L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
+        HIP_TRY(mark(P, 1, false));
+        HIP_TRY(launch_reduce_slabs(Zp, L.nsplit, L.nP * lp, Zt, st));
+        return RPOD_OK;
+    };
+    rpod_status s;
     // Alg. 1 step 1: Gaussian sketch
     HIP_TRY(launch_omega(L.tin, seed, n, L.l, lp, L.nP, X, L.nP, st));
     // step 2: Y = S Omega, then Q by CholeskyQR2
-    HIP_TRY(mark(P, 0, true));
-    HIP_TRY(launch_sx(L.tin, L.tacc, nt, S, d.ld, m, n, X, L.nP, Y, L.mP, L.mP, nullptr, 0, st));
-    HIP_TRY(mark(P, 0, false));
-    rpod_status s = orth(P, L.tacc, Y, Q1, L.mP, m, 1);
-    if (s != RPOD_OK) return s;
+    if ((s = pass_sx()) != RPOD_OK) return s;
+    if ((s = orth(P, L.tacc, Y, Q1, L.mP, m, 1)) != RPOD_OK) return s;
     // step 3, one product at a time with re-orthonormalisation
     for (int it = 0; it < d.q; ++it) {
-        HIP_TRY(mark(P, 1, true));
-        HIP_TRY(launch_stq(L.tin, nt, S, d.ld, m, n, Q1, L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
-        HIP_TRY(mark(P, 1, false));
-        HIP_TRY(launch_reduce_slabs(Zp, L.nsplit, L.nP * lp, Zt, st));
+        if ((s = pass_stq(false)) != RPOD_OK) return s;
         HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st));
-        s = orth(P, DT_F64, Zw, Zw2, L.nP, n, 2);
-        if (s != RPOD_OK) return s;
+        if ((s = orth(P, DT_F64, Zw, Zw2, L.nP, n, 2)) != RPOD_OK) return s;
         HIP_TRY(launch_sx(DT_F64, L.tin, nt, Zw2, L.nP, n, lp, R64s, lp, X, L.nP, L.nP, nullptr, 0, st));
-        HIP_TRY(mark(P, 0, true));
-        HIP_TRY(launch_sx(L.tin, L.tacc, nt, S, d.ld, m, n, X, L.nP, Y, L.mP, L.mP, nullptr, 0, st));
-        HIP_TRY(mark(P, 0, false));
-        s = orth(P, L.tacc, Y, Q1, L.mP, m, 1);
-        if (s != RPOD_OK) return s;
+        if ((s = pass_sx()) != RPOD_OK) return s;
+        if ((s = orth(P, L.tacc, Y, Q1, L.mP, m, 1)) != RPOD_OK) return s;
     }
-    // step 5: T^T = S^T Q (Q = Q1 R^-1 applied on the small side)
-    HIP_TRY(mark(P, 1, true));
-    HIP_TRY(launch_stq(L.tin, nt, S, d.ld, m, n, Q1, L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
-    HIP_TRY(mark(P, 1, false));
-    HIP_TRY(launch_reduce_slabs(Zp, L.nsplit, L.nP * lp, Zt, st));
+    // step 5: T^T = S^T Q (Q = Q1 R^-1 applied on the small side); on 16-bit
+    // paths this is the refinement pass with Q carried to ~16 bits
+    if ((s = pass_stq(true)) != RPOD_OK) return s;
     HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st));
     // step 6: SVD of T through the eigenvectors of T T^T
     double* G = P->at<double>(L.o_G);
@@ -375,8 +385,8 @@ rpod_status rpod_generate_omega(uint64_t seed, int64_t n, int32_t l, int32_t dty
     if (n < 1 || l < 1) return fail(RPOD_EINVAL, "n and l must be >= 1");
     if (ldo < n) return fail(RPOD_EINVAL, "ldo must be >= n");
     if (out == nullptr) return fail(RPOD_EINVAL, "out is NULL");
-    if (dtype != RPOD_F64 && dtype != RPOD_F32) return fail(RPOD_EUNSUPPORTED, "dtype must be RPOD_F64 or RPOD_F32");
-    const int dt = dtype == RPOD_F64 ? DT_F64 : DT_F32;
+    if (dtype < RPOD_F64 || dtype > RPOD_F16) return fail(RPOD_EINVAL, "unknown dtype %d", dtype);
+    const int dt = dtype;  // rpod_dtype and the internal codes coincide
     HIP_TRY(launch_omega(dt, seed, n, l, l, n, out, ldo, static_cast<hipStream_t>(hip_stream)));
     return RPOD_OK;
 }

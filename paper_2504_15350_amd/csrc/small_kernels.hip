@@ -46,8 +46,8 @@ __global__ void k_omega(uint64_t seed, int64_t n, int l, int lpad, int64_t rows_
         g0 = rho * cos(th);
         g1 = rho * sin(th);
     }
-    if (c0 < lpad) out[(int64_t)c0 * ldo + j] = (T)g0;
-    if (c1 < lpad) out[(int64_t)c1 * ldo + j] = (c1 < l) ? (T)g1 : (T)0;
+    if (c0 < lpad) out[(int64_t)c0 * ldo + j] = narrow<T>(g0);
+    if (c1 < lpad) out[(int64_t)c1 * ldo + j] = narrow<T>(c1 < l ? g1 : 0.0);
 }
 
 hipError_t launch_omega(int tout, uint64_t seed, int64_t n, int l, int lpad, int64_t rows_pad, void* out,
@@ -57,6 +57,11 @@ hipError_t launch_omega(int tout, uint64_t seed, int64_t n, int l, int lpad, int
         hipLaunchKernelGGL(k_omega<double>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (double*)out, ldo);
     else if (tout == DT_F32)
         hipLaunchKernelGGL(k_omega<float>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (float*)out, ldo);
+    else if (tout == DT_BF16)
+        hipLaunchKernelGGL(k_omega<__bf16>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (__bf16*)out, ldo);
+    else if (tout == DT_F16)
+        hipLaunchKernelGGL(k_omega<_Float16>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (_Float16*)out,
+                           ldo);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

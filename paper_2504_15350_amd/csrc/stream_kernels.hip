@@ -38,7 +38,7 @@ __device__ __forceinline__ V4<T> load_rows4(const T* S, int64_t ld, int64_t lim,
 template <typename Tout, typename T>
 __device__ __forceinline__ void store4(Tout* p, T a, T b, T c, T d) {
     typedef typename vec4_of<Tout>::type VO;
-    VO v = {(Tout)a, (Tout)b, (Tout)c, (Tout)d};
+    VO v = {narrow<Tout>(a), narrow<Tout>(b), narrow<Tout>(c), narrow<Tout>(d)};
     *reinterpret_cast<VO*>(p) = v;
 }
 
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m
             } else {
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    if (row + t < mstore) py[row + t] = (Tout)acc[t][c][v];
+                    if (row + t < mstore) py[row + t] = narrow<Tout>(acc[t][c][v]);
             }
         }
     }
@@ -206,6 +206,10 @@ hipError_t launch_sx(int tin, int tout, int nt, const void* S, int64_t ldS, int6
         return sx_dispatch<double, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
     if (tin == DT_F32 && tout == DT_F32)
         return sx_dispatch<float, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+    if (tin == DT_F64 && tout == DT_BF16)
+        return sx_dispatch<double, __bf16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+    if (tin == DT_F64 && tout == DT_F16)
+        return sx_dispatch<double, _Float16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
     return hipErrorInvalidValue;
 }
 

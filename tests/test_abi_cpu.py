@@ -62,10 +62,18 @@ def test_workspace_size_accepts_edges():
 
 
 @needs_lib
-def test_unsupported_dtype_is_reported():
-    with pytest.raises(rp.RpodError) as e:
-        rp.workspace_size(1000, 100, 10, 5, 1, torch.float16)
-    assert e.value.status in (0, 5)
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32, torch.bfloat16, torch.float16])
+def test_every_storage_dtype_has_a_plan(dt):
+    assert rp.workspace_size(1000, 100, 10, 5, 1, dt) > 0
+
+
+@needs_lib
+def test_unknown_dtype_code_rejected():
+    L = rp.lib()
+    d = rp.make_desc(100, 50, 5, 5, 1, torch.float32)
+    d.dtype = 7
+    out = ctypes.c_size_t(0)
+    assert L.rpod_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 1
 
 
 @needs_lib
