@@ -5,14 +5,17 @@ One step = one full rPOD call (Alg. 1 of Sec. 4.2: sketch, q subspace
 iterations with CholeskyQR2, T = Q^T S, small SVD, lift, coefficients and
 sign fix) on a synthetic snapshot matrix already resident in HBM.
 
-Default workload: the plain FP32 configuration, S = 262144 x 5000 (a 512 x
-512 cell-centred grid on [0,1] x [0,2], 5000 snapshots of a 200-mode
+Main workload (the JSON line's value): plain FP32, S = 262144 x 5000 (a
+512 x 512 cell-centred grid on [0,1] x [0,2], 5000 snapshots of a 200-mode
 Fourier field with |k|^-1.5 amplitudes and AR(1) time series, phi = 0.95,
 plus 1e-4 white noise), r = 50, p = 10, q = 2.
 
-Prints one JSON line (see the fields below). Per-kernel times of the passes
-over S come from HIP events recorded by the library on its stream around
-every pass during the timed steps.
+Also measured (unless --no-extra): the mixed-precision BF16 path against
+plain FP32 on S = 1048576 x 10000 (1024 x 1024 grid, same field), r = 100,
+p = 20, q = 2, reported under "mixed_vs_plain".
+
+Per-kernel times of the passes over S come from HIP events that the library
+records on its stream around every pass during the timed steps.
 """
 
 import argparse
@@ -33,10 +36,23 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
 WORKLOADS = {
     "fp32_262144x5000": dict(
         label="plain rPOD FP32, S 262144x5000 (512x512 grid), Fourier field, r=50 p=10 q=2",
-        nx=512, ny=512, n=5000, r=50, p=10, q=2, dtype="f32", gen_seed=2, seed=2, sample_rows=65536),
+        nx=512, ny=512, n=5000, r=50, p=10, q=2, dtype="f32", gen="host", gen_seed=2, seed=2,
+        sample_rows=65536),
     "fp64_4096x200": dict(
         label="plain rPOD FP64, S 4096x200, U diag(exp(-0.1k)) V^T + noise, r=20 p=10 q=1",
-        m=4096, n=200, r=20, p=10, q=1, dtype="f64", gen_seed=1, seed=1, sample_rows=4096),
+        m=4096, n=200, r=20, p=10, q=1, dtype="f64", gen="host", gen_seed=1, seed=1, sample_rows=4096),
+    "bf16_1048576x10000": dict(
+        label="mixed rPOD, S 1048576x10000 (1024x1024 grid) in BF16, Fourier field, r=100 p=20 q=2",
+        nx=1024, ny=1024, n=10000, r=100, p=20, q=2, dtype="bf16", gen="device", gen_seed=3, seed=3,
+        sample_rows=16384),
+    "f16_1048576x10000": dict(
+        label="mixed rPOD, S 1048576x10000 (1024x1024 grid) in FP16, Fourier field, r=100 p=20 q=2",
+        nx=1024, ny=1024, n=10000, r=100, p=20, q=2, dtype="f16", gen="device", gen_seed=3, seed=3,
+        sample_rows=16384),
+    "fp32_1048576x10000": dict(
+        label="plain rPOD FP32, S 1048576x10000 (1024x1024 grid), Fourier field, r=100 p=20 q=2",
+        nx=1024, ny=1024, n=10000, r=100, p=20, q=2, dtype="f32", gen="device", gen_seed=3, seed=3,
+        sample_rows=16384),
 }
 DEFAULT = "fp32_262144x5000"
 
@@ -45,20 +61,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_input(w):
+def torch_dtype(name):
+    import torch
+    return {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[name]
+
+
+def make_input(w, dev):
+    """Synthetic S as a device tensor St (n, m)."""
+    import torch
     import synth
+    if w["gen"] == "device":
+        return synth.fourier_field_device(w["nx"], w["ny"], w["n"], seed=w["gen_seed"],
+                                          dtype=torch_dtype(w["dtype"]), device=dev)["St"]
     npdt = np.float64 if w["dtype"] == "f64" else np.float32
     if "nx" in w:
         g = synth.fourier_field(w["nx"], w["ny"], w["n"], n_modes=200, beta=1.5, phi=0.95, noise_std=1e-4,
                                 seed=w["gen_seed"], dtype=npdt)
     else:
         g = synth.lowrank_exp(w["m"], w["n"], decay=0.1, noise_std=1e-4, seed=w["gen_seed"], dtype=npdt)
-    return g["St"]
+    return torch.from_numpy(g["St"]).to(dev)
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("stream_kernels.hip", "device_common.hpp"):
+    for f in ("stream_kernels.hip", "stream16_kernels.hip", "device_common.hpp"):
         with open(os.path.join(ROOT, "paper_2504_15350_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,25 +104,80 @@ def load_traffic(workload, kernel):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(St_host, w, seed):
+def measure(name, St, steps, warmup):
+    """Time `steps` rPOD calls; per-pass kernel times from the library's HIP events."""
+    import torch
+    import paper_2504_15350_amd as rp
+    w = WORKLOADS[name]
+    n, m = St.shape
+    dev = St.device
+    plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=St.dtype, device=dev)
+    out = (torch.empty((w["r"], m), dtype=plan.out_dtype, device=dev),
+           torch.empty((w["r"],), dtype=torch.float64, device=dev),
+           torch.empty((n, w["r"]), dtype=plan.out_dtype, device=dev))
+    for _ in range(warmup):
+        plan.compute(St, w["seed"], out=out, check=False)
+    plan.status()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.compute(St, w["seed"], out=out, check=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    flags = plan.status()
+    ms = wall * 1e3 / steps
+    kern = {}
+    for kind, kname in ((0, "S_X"), (1, "St_Q")):
+        nl, tot, bpl, fpl = plan.timing(kind)
+        kern[kname] = dict(launches=nl, avg_ms=tot / max(nl, 1), bytes=bpl, flops=fpl, total_ms=tot)
+    plan.set_timing(False)
+    sigma = out[1].cpu().numpy()
+    plan.close()
+    log(f"[bench] {name}: {ms:.3f} ms per rPOD over {steps} steps (flags {flags}); "
+        + ", ".join(f"{k} {v['avg_ms']:.3f} ms x{v['launches'] // steps}" for k, v in kern.items()))
+
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    kd = kern[dom]
+    fl = kd["flops"] / (kd["avg_ms"] * 1e-3) / 1e12
+    gbs = kd["bytes"] / (kd["avg_ms"] * 1e-3) / 1e9
+    peak = PEAK_TFLOPS[w["dtype"]]
+    if kd["flops"] / kd["bytes"] > peak * 1e3 / HBM_PEAK_GBS:
+        roof = dict(bound="mfma", achieved=round(fl, 2), peak=peak, unit="TFLOP/s", frac=round(fl / peak, 4))
+    else:
+        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(gbs / HBM_PEAK_GBS, 4))
+    roof.update(traffic=load_traffic(name, dom), kernel=dom, avg_launch_ms=round(kd["avg_ms"], 4),
+                algorithmic_bytes_per_launch=kd["bytes"], algorithmic_flops_per_launch=kd["flops"],
+                hbm_gbs_algorithmic=round(gbs, 1))
+    passes = sum(v["launches"] for v in kern.values()) / steps
+    s_bytes = passes * m * n * St.element_size()
+    return dict(ms=ms, roofline=roof, sigma=sigma, flags=flags,
+                hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
+                kernels={k: {"launches_per_step": v["launches"] // steps, "avg_ms": round(v["avg_ms"], 4)}
+                         for k, v in kern.items()})
+
+
+def cpu_baseline(St, w, seed):
     """The oracle's FP64 rPOD (as it stands) on a row sample, scaled to the full matrix."""
     from oracle import philox
     from oracle import rpod as orpod
+    import torch
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
-    n, m = St_host.shape
+    n, m = St.shape
     ms = min(m, w["sample_rows"])
-    S = St_host[:, :ms].T
-    npdt = np.float64 if w["dtype"] == "f64" else np.float32
-    om = philox.gaussian_sketch(seed, n, w["r"] + w["p"]).astype(npdt).astype(np.float64)
+    S = St[:, :ms].to(torch.float64).cpu().numpy().T
+    om = torch.from_numpy(philox.gaussian_sketch(seed, n, w["r"] + w["p"]).astype(np.float32))
+    om = om.to(St.dtype).double().numpy() if w["dtype"] != "f64" else philox.gaussian_sketch(seed, n, w["r"] + w["p"])
     t0 = time.perf_counter()
     orpod.rpod_stable(S, w["r"], om, w["q"])
     dt = time.perf_counter() - t0
     scale = m / ms
-    return dict(value=dt * scale * 1e3, unit="ms", cores=int(cores), kind="oracle",
+    return dict(value=round(dt * scale * 1e3, 1), unit="ms", cores=int(cores), kind="oracle",
                 sample=f"O2 (FP64 numpy rPOD, same algorithm and sketch) on the first {ms} of {m} rows, "
                        f"{dt:.2f} s measured, scaled x{scale:g} to the full matrix")
 
@@ -108,95 +189,73 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-vs-plain measurement")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU row-sharded "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the row-sharded multi-GPU "
               f"design is not built in this version", file=sys.stderr)
         sys.exit(2)
 
+    import torch
+    dev = torch.device("cuda", 0)
     w = WORKLOADS[args.workload]
     t0 = time.perf_counter()
-    St = make_input(w)
-    n, m = St.shape
-    log(f"[bench] generated S {m}x{n} {St.dtype} in {time.perf_counter() - t0:.1f} s")
-
-    import torch
-    import paper_2504_15350_amd as rp
-    dt = torch.float64 if w["dtype"] == "f64" else torch.float32
-    dev = torch.device("cuda", 0)
-    Sd = torch.from_numpy(St).to(dev)
+    St = make_input(w, dev)
     torch.cuda.synchronize()
-    plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=dt, device=dev)
-    out = (torch.empty((w["r"], m), dtype=plan.out_dtype, device=dev),
-           torch.empty((w["r"],), dtype=torch.float64, device=dev),
-           torch.empty((n, w["r"]), dtype=plan.out_dtype, device=dev))
-    for _ in range(args.warmup):
-        plan.compute(Sd, w["seed"], out=out, check=False)
-    plan.status()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-
-    plan.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.compute(Sd, w["seed"], out=out, check=False)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    flags = plan.status()
-    ms_per_step = wall * 1e3 / args.steps
-    log(f"[bench] {args.steps} steps in {wall:.3f} s: {ms_per_step:.3f} ms per rPOD (flags {flags})")
-
-    kern = {}
-    for kind, name in ((0, "k_sx"), (1, "k_stq")):
-        nl, tot, bpl, fpl = plan.timing(kind)
-        kern[name] = dict(launches=nl, avg_ms=tot / max(nl, 1), bytes=bpl, flops=fpl, total_ms=tot)
-    plan.set_timing(False)
-    dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    kd = kern[dom]
-    passes = kern["k_sx"]["launches"] + kern["k_stq"]["launches"]
-    s_bytes_per_call = (passes / args.steps) * m * n * St.dtype.itemsize
-    fl_achieved = kd["flops"] / (kd["avg_ms"] * 1e-3) / 1e12
-    gbs_achieved = kd["bytes"] / (kd["avg_ms"] * 1e-3) / 1e9
-    ridge = PEAK_TFLOPS[w["dtype"]] * 1e3 / HBM_PEAK_GBS
-    intensity = kd["flops"] / kd["bytes"]
-    if intensity > ridge:
-        roof = dict(bound="mfma", achieved=round(fl_achieved, 2), peak=PEAK_TFLOPS[w["dtype"]], unit="TFLOP/s",
-                    frac=round(fl_achieved / PEAK_TFLOPS[w["dtype"]], 4))
-    else:
-        roof = dict(bound="hbm", achieved=round(gbs_achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(gbs_achieved / HBM_PEAK_GBS, 4))
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = round(kd["avg_ms"], 4)
-    roof["algorithmic_bytes_per_launch"] = kd["bytes"]
-    roof["algorithmic_flops_per_launch"] = kd["flops"]
-    roof["hbm_gbs_algorithmic"] = round(gbs_achieved, 1)
-    roof["traffic"] = load_traffic(args.workload, dom)
+    log(f"[bench] generated S {St.shape[1]}x{St.shape[0]} {St.dtype} in {time.perf_counter() - t0:.1f} s")
+    main_res = measure(args.workload, St, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row sample ...")
         cpu = cpu_baseline(St, w, w["seed"])
         log(f"[bench] cpu baseline {cpu['value']:.0f} ms ({cpu['sample']})")
+    del St
+    torch.cuda.empty_cache()
+
+    extra = None
+    if not args.no_extra:
+        ext_steps, ext_warm = max(3, args.steps // 2), max(1, args.warmup // 2)
+        rows = {}
+        for name in ("bf16_1048576x10000", "fp32_1048576x10000"):
+            t0 = time.perf_counter()
+            Sx = make_input(WORKLOADS[name], dev)
+            torch.cuda.synchronize()
+            log(f"[bench] generated {name} in {time.perf_counter() - t0:.1f} s")
+            rows[name] = measure(name, Sx, ext_steps, ext_warm)
+            del Sx
+            torch.cuda.empty_cache()
+        mb, pf = rows["bf16_1048576x10000"], rows["fp32_1048576x10000"]
+        extra = {
+            "config": {"m": 1048576, "n": 10000, "r": 100, "p": 20, "q": 2, "steps": ext_steps},
+            "mixed_bf16_ms": round(mb["ms"], 3), "plain_fp32_ms": round(pf["ms"], 3),
+            "speedup": round(pf["ms"] / mb["ms"], 2),
+            "sigma_rel_diff_bf16_vs_fp32": float(np.max(np.abs(mb["sigma"] - pf["sigma"]) / pf["sigma"])),
+            "mixed_hbm_gbs_s_passes": mb["hbm_gbs_s_passes"], "mixed_roofline": mb["roofline"],
+            "mixed_kernels": mb["kernels"], "plain_roofline": pf["roofline"], "plain_kernels": pf["kernels"],
+        }
 
     res = {
         "metric": "rPOD time-to-r-modes",
-        "value": round(ms_per_step, 4),
+        "value": round(main_res["ms"], 4),
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(main_res["ms"], 4),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": w["dtype"],
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": w["label"], "m": m, "n": n, "r": w["r"],
-                   "p": w["p"], "q": w["q"], "parallelism": "single GPU"},
-        "hbm_gbs_s_passes": round(s_bytes_per_call / (ms_per_step * 1e-3) / 1e9, 1),
-        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4)} for k, v in kern.items()},
-        "roofline": roof,
+        "config": {"workload": args.workload, "description": w["label"],
+                   "m": w.get("m", w.get("nx", 0) * w.get("ny", 0)), "n": w["n"],
+                   "r": w["r"], "p": w["p"], "q": w["q"], "parallelism": "single GPU"},
+        "hbm_gbs_s_passes": main_res["hbm_gbs_s_passes"],
+        "kernels": main_res["kernels"],
+        "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
+        "mixed_vs_plain": extra,
     }
     print(json.dumps(res), flush=True)
 

@@ -17,9 +17,10 @@ enum DT : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
 //      or a 16-bit type when tin is F64, converted through FP32); rows
 //      [0, mstore) are written, mstore <= ldY.
 //   If cond != nullptr the kernel does nothing unless (*cond & cond_mask).
+//   upper: X is upper triangular (16 x 16 tiles below the diagonal skipped).
 hipError_t launch_sx(int tin, int tout, int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
                      const void* X, int64_t ldX, void* Y, int64_t ldY, int64_t mstore,
-                     const int* cond, int cond_mask, hipStream_t st);
+                     const int* cond, int cond_mask, hipStream_t st, bool upper = false);
 
 // Split-K transposed product: partial[s] = S[rows of split s]^T Q[rows of split s].
 //   S: m x n column-major (ldS), type tin; Q: m x 16*nt column-major (ldQ,
@@ -32,13 +33,17 @@ hipError_t launch_stq(int tin, int nt, const void* S, int64_t ldS, int64_t m, in
 
 // 16-bit (tin = DT_BF16 or DT_F16) versions on the 16x16x32 matrix cores:
 // Y (FP32) = S X with X in the same 16-bit type (ldX multiple of 8, zero rows
-// up to roundup(n, 32)); partial Z = S^T Q with Q in FP32 (zero rows up to
-// roundup(m, 32)), rounded to 16 bits on the fly, plus the rounding remainder
-// as a second product when lo is set. split_rows must be a multiple of 32.
+// up to roundup(n, 32)); partial Z = S^T Q with Q given as 16-bit hi and lo
+// parts (zero rows up to roundup(m, 64)); the lo product is added when lo is
+// set. split_rows must be a multiple of 64.
 hipError_t launch_sx16(int tin, int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* X,
                        int64_t ldX, float* Y, int64_t ldY, int64_t mstore, hipStream_t st);
-hipError_t launch_stq16(int tin, int nt, bool lo, const void* S, int64_t ldS, int64_t m, int64_t n, const float* Q,
-                        int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit, hipStream_t st);
+hipError_t launch_stq16(int tin, int nt, bool lo, const void* S, int64_t ldS, int64_t m, int64_t n,
+                        const unsigned short* Qh, const unsigned short* Ql, int64_t ldQ, double* Zp, int64_t nP,
+                        int64_t split_rows, int nsplit, hipStream_t st);
+// hi = round16(Q), lo = round16(Q - hi) elementwise (count a multiple of 4).
+hipError_t launch_split16(int tin, const float* Q, int64_t count, unsigned short* hi, unsigned short* lo,
+                          hipStream_t st);
 
 // out[e] = sum_s Zp[s * count + e], fixed order.
 hipError_t launch_reduce_slabs(const double* Zp, int nsplit, int64_t count, double* out, hipStream_t st);
@@ -66,7 +71,8 @@ hipError_t launch_chol_inv(const double* G, int l, int lp, int64_t M, double* Ri
 // by one-sided Jacobi (Hestenes) on its columns, one workgroup.
 //   UB: lp x lp column-major, column k = k-th eigenvector (= left singular
 //   vector of B) by descending eigenvalue; sig[k] = sqrt(eigenvalue).
-hipError_t launch_jacobi(const double* G, int l, int lp, double* UB, double* sig, int* flags,
+//   A pair is rotated while |w_p . w_q| > tol |w_p| |w_q|.
+hipError_t launch_jacobi(const double* G, int l, int lp, double* UB, double* sig, int* flags, double tol,
                          hipStream_t st);
 
 // M = Rinv * UB[:, :r] (lp x rp, column-major) in FP64 and FP32, and

@@ -45,7 +45,7 @@ struct Layout {
     int64_t split_rows;
     int nchunk;
     // byte offsets into the workspace
-    size_t o_flags, o_X, o_Y, o_Q1, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
+    size_t o_flags, o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
     size_t total;
 };
@@ -78,15 +78,19 @@ Layout make_layout(const rpod_desc* d) {
     L.nP = roundup(d->n, 256);
     L.tin = d->dtype == RPOD_F64 ? DT_F64 : d->dtype == RPOD_F32 ? DT_F32 : d->dtype == RPOD_BF16 ? DT_BF16 : DT_F16;
     L.tacc = d->dtype == RPOD_F64 ? DT_F64 : DT_F32;
-    // split-K over rows for S^T Q: about 1024 workgroups, at least 256 rows each
-    const int64_t ncb = L.nP / 256;
-    int64_t ns = (1024 + ncb - 1) / ncb;
+    // split-K over rows for S^T Q. FP32/FP64: ~1024 workgroups of 256
+    // columns, contiguous splits of >= 256 rows. 16-bit: ~4096 blocks of 128
+    // columns (up to 64 splits), splits interleaved in steps of R rows.
+    const bool s16k = d->dtype == RPOD_BF16 || d->dtype == RPOD_F16;
+    const int64_t ncb = s16k ? L.nP / 128 : L.nP / 256;
+    const int64_t target = s16k ? 4096 : 1024;
+    int64_t ns = (target + ncb - 1) / ncb;
     if (ns > 64) ns = 64;
-    const int64_t maxs = (d->m + 255) / 256;
+    const int64_t maxs = (d->m + (s16k ? 127 : 255)) / (s16k ? 128 : 256);
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
-    L.split_rows = roundup((d->m + ns - 1) / ns, 32);
-    L.nsplit = (int)((d->m + L.split_rows - 1) / L.split_rows);
+    L.split_rows = roundup((d->m + ns - 1) / ns, 64);
+    L.nsplit = s16k ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
     int64_t nc = d->m / 2048;
     L.nchunk = (int)(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
 
@@ -102,6 +106,9 @@ Layout make_layout(const rpod_desc* d) {
     L.o_X = take((size_t)L.nP * L.lp * si);
     L.o_Y = take((size_t)L.mP * L.lp * sa);
     L.o_Q1 = take((size_t)L.mP * L.lp * sa);
+    const bool s16 = L.tin == DT_BF16 || L.tin == DT_F16;
+    L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
+    L.o_Ql = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Zp = take((size_t)L.nsplit * L.nP * L.lp * 8);
     L.o_Zt = take((size_t)L.nP * L.lp * 8);
     L.o_Zw = take((size_t)L.nP * L.lp * 8);
@@ -188,13 +195,38 @@ rpod_status orth(const rpod_plan_s* P, int dt, const void* In, void* Out, int64_
     const void* Rf = dt == DT_F64 ? (const void*)R64f : (const void*)R32f;
     HIP_TRY(launch_gram(dt, L.nt, In, ld, M, Gp, G, nullptr, 0, P->st));
     HIP_TRY(launch_chol_inv(G, L.l, L.lp, M, R64a, R32a, flags, local, 0, P->st));
-    HIP_TRY(launch_sx(dt, dt, L.nt, In, ld, M, L.lp, Ra, L.lp, Out, ld, ld, nullptr, 0, P->st));
+    HIP_TRY(launch_sx(dt, dt, L.nt, In, ld, M, L.lp, Ra, L.lp, Out, ld, ld, nullptr, 0, P->st, true));
     HIP_TRY(launch_gram(dt, L.nt, Out, ld, M, Gp, G, nullptr, 0, P->st));
     HIP_TRY(launch_chol_inv(G, L.l, L.lp, M, R64f, R32f, flags, local, 1, P->st));
     // shifted retry: Out <- Out R^-1 in place, then re-factor (no-ops unless flagged)
-    HIP_TRY(launch_sx(dt, dt, L.nt, Out, ld, M, L.lp, Rf, L.lp, Out, ld, ld, local, 0x1, P->st));
+    HIP_TRY(launch_sx(dt, dt, L.nt, Out, ld, M, L.lp, Rf, L.lp, Out, ld, ld, local, 0x1, P->st, true));
     HIP_TRY(launch_gram(dt, L.nt, Out, ld, M, Gp, G, local, 0x1, P->st));
     HIP_TRY(launch_chol_inv(G, L.l, L.lp, M, R64f, R32f, flags, local, 2, P->st));
+    return RPOD_OK;
+}
+
+// Basis of the n x l iterate Zw (FP64) for the next product with S, written
+// to X in the S type: one CholeskyQR, X = Zw R^-1 (only the span matters
+// here; the orthonormality that the method needs is restored by the
+// CholeskyQR2 of the next S X). After a shifted factorisation a second
+// CholeskyQR step runs (no-ops otherwise).
+rpod_status basis_small(const rpod_plan_s* P, double* Zw, double* Zw2, void* X) {
+    const Layout& L = P->L;
+    int* flags = P->at<int>(L.o_flags);
+    int* local = flags + 1;
+    double* Gp = P->at<double>(L.o_Gpart);
+    double* G = P->at<double>(L.o_G);
+    double* Ra = P->at<double>(L.o_R64[0]);
+    double* Rb = P->at<double>(L.o_R64[2]);
+    hipStream_t st = P->st;
+    HIP_TRY(launch_gram(DT_F64, L.nt, Zw, L.nP, P->d.n, Gp, G, nullptr, 0, st));
+    HIP_TRY(launch_chol_inv(G, L.l, L.lp, P->d.n, Ra, P->at<float>(L.o_R32[0]), flags, local, 0, st));
+    HIP_TRY(launch_sx(DT_F64, L.tin, L.nt, Zw, L.nP, P->d.n, L.lp, Ra, L.lp, X, L.nP, L.nP, nullptr, 0, st, true));
+    // after a shift: Zw2 = Zw Ra^-1, refactor, X = Zw2 Rb^-1
+    HIP_TRY(launch_sx(DT_F64, DT_F64, L.nt, Zw, L.nP, P->d.n, L.lp, Ra, L.lp, Zw2, L.nP, L.nP, local, 0x1, st, true));
+    HIP_TRY(launch_gram(DT_F64, L.nt, Zw2, L.nP, P->d.n, Gp, G, local, 0x1, st));
+    HIP_TRY(launch_chol_inv(G, L.l, L.lp, P->d.n, Rb, P->at<float>(L.o_R32[2]), flags, local, 2, st));
+    HIP_TRY(launch_sx(DT_F64, L.tin, L.nt, Zw2, L.nP, P->d.n, L.lp, Rb, L.lp, X, L.nP, L.nP, local, 0x1, st, true));
     return RPOD_OK;
 }
 
@@ -269,7 +301,6 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi
     double* Zw = P->at<double>(L.o_Zw);
     double* Zw2 = P->at<double>(L.o_Zw2);
     double* R64t = P->at<double>(L.o_R64[1]);   // final factor of the tall orthonormalisation
-    double* R64s = P->at<double>(L.o_R64[2]);   // final factor of the short (S^T side) one
     const int64_t m = d.m, n = d.n;
     const int lp = L.lp, nt = L.nt;
 
@@ -289,12 +320,21 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi
     auto pass_stq = [&](bool lo) -> rpod_status {
         HIP_TRY(mark(P, 1, true));
         if (s16)
-            HIP_TRY(launch_stq16(L.tin, nt, lo, S, d.ld, m, n, static_cast<const float*>(Q1), L.mP, Zp, L.nP,
-                                 L.split_rows, L.nsplit, st));
+            HIP_TRY(launch_stq16(L.tin, nt, lo, S, d.ld, m, n, P->at<unsigned short>(L.o_Qh),
+                                 P->at<unsigned short>(L.o_Ql), L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
         else
             HIP_TRY(launch_stq(L.tin, nt, S, d.ld, m, n, Q1, L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
         HIP_TRY(mark(P, 1, false));
         HIP_TRY(launch_reduce_slabs(Zp, L.nsplit, L.nP * lp, Zt, st));
+        return RPOD_OK;
+    };
+    // CholeskyQR2 of Y into Q1; on 16-bit paths also the hi/lo parts of Q1
+    auto orth_tall = [&]() -> rpod_status {
+        rpod_status so = orth(P, L.tacc, Y, Q1, L.mP, m, 1);
+        if (so != RPOD_OK) return so;
+        if (s16)
+            HIP_TRY(launch_split16(L.tin, static_cast<const float*>(Q1), L.mP * lp, P->at<unsigned short>(L.o_Qh),
+                                   P->at<unsigned short>(L.o_Ql), st));
         return RPOD_OK;
     };
     rpod_status s;
@@ -302,26 +342,28 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi
     HIP_TRY(launch_omega(L.tin, seed, n, L.l, lp, L.nP, X, L.nP, st));
     // step 2: Y = S Omega, then Q by CholeskyQR2
     if ((s = pass_sx()) != RPOD_OK) return s;
-    if ((s = orth(P, L.tacc, Y, Q1, L.mP, m, 1)) != RPOD_OK) return s;
+    if ((s = orth_tall()) != RPOD_OK) return s;
     // step 3, one product at a time with re-orthonormalisation
     for (int it = 0; it < d.q; ++it) {
         if ((s = pass_stq(false)) != RPOD_OK) return s;
-        HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st));
-        if ((s = orth(P, DT_F64, Zw, Zw2, L.nP, n, 2)) != RPOD_OK) return s;
-        HIP_TRY(launch_sx(DT_F64, L.tin, nt, Zw2, L.nP, n, lp, R64s, lp, X, L.nP, L.nP, nullptr, 0, st));
+        HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st, true));
+        if ((s = basis_small(P, Zw, Zw2, X)) != RPOD_OK) return s;
         if ((s = pass_sx()) != RPOD_OK) return s;
-        if ((s = orth(P, L.tacc, Y, Q1, L.mP, m, 1)) != RPOD_OK) return s;
+        if ((s = orth_tall()) != RPOD_OK) return s;
     }
     // step 5: T^T = S^T Q (Q = Q1 R^-1 applied on the small side); on 16-bit
     // paths this is the refinement pass with Q carried to ~16 bits
     if ((s = pass_stq(true)) != RPOD_OK) return s;
-    HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st));
+    HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st, true));
     // step 6: SVD of T through the eigenvectors of T T^T
     double* G = P->at<double>(L.o_G);
     double* UB = P->at<double>(L.o_UB);
     double* sig = P->at<double>(L.o_sig);
     HIP_TRY(launch_gram(DT_F64, nt, Zw, L.nP, n, P->at<double>(L.o_Gpart), G, nullptr, 0, st));
-    HIP_TRY(launch_jacobi(G, L.l, lp, UB, sig, flags, st));
+    // rotation threshold: FP64 rounding level on the FP64 path; elsewhere far
+    // below the FP32 storage error of Q, which bounds the result anyway
+    const double jtol = L.tacc == DT_F64 ? (double)lp * 0x1.0p-53 : 1e-10;
+    HIP_TRY(launch_jacobi(G, L.l, lp, UB, sig, flags, jtol, st));
     // step 7: Phi = Q U_hat[:, :r] = Q1 (R^-1 U_hat[:, :r]); coefficients A = U_hat_r^T T
     double* M64 = P->at<double>(L.o_M64);
     float* M32 = P->at<float>(L.o_M32);

@@ -178,8 +178,16 @@ __global__ void k_gram_reduce(const double* __restrict__ Gpart, int nt, int nwg,
     int a = 0, q = p;
     while (q >= nt - a) { q -= nt - a; ++a; }
     const int b = a + q;
-    double s = 0.0;
-    for (int w = 0; w < nwg; ++w) s += Gpart[((int64_t)w * np + p) * 256 + (e % 256)];
+    // eight independent partial sums (loads in flight together), combined in a fixed order
+    double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double* src = Gpart + (int64_t)p * 256 + (e % 256);
+    const int64_t wstride = (int64_t)np * 256;
+    int w = 0;
+    for (; w + 8 <= nwg; w += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc8[u] += src[(w + u) * wstride];
+    for (; w < nwg; ++w) acc8[0] += src[w * wstride];
+    const double s = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
     const int lp = 16 * nt;
     G[(16 * a + mm) * lp + 16 * b + nn] = s;
     G[(16 * b + nn) * lp + 16 * a + mm] = s;
@@ -240,6 +248,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
     __shared__ int s_fail, s_nonfinite;
     __shared__ double s_trace;
     const int tid = threadIdx.x;
+    const int ti = tid & 15, tj = tid >> 4;  // 16 x 16 thread grid for the 2-D updates
 
     if (mode == 2 && !(*local & DEV_FLAG_SHIFTED)) return;
     if (tid == 0) {
@@ -267,28 +276,26 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
         for (int attempt = 0; attempt < 2; ++attempt) {
             const double shift =
                 attempt == 0 ? 0.0 : 11.0 * ((double)M * l + (double)l * (l + 1)) * 0x1.0p-53 * s_trace;
-            for (int e = tid; e < l * l; e += 256) {
-                const int i = e / l, j = e % l;
-                A[i * LDA + j] = G[i * lp + j] + (i == j ? shift : 0.0);
-            }
+            for (int i = tj; i < l; i += 16)
+                for (int j = ti; j < l; j += 16) A[i * LDA + j] = G[i * lp + j] + (i == j ? shift : 0.0);
             if (tid == 0) s_fail = 0;
             __syncthreads();
             for (int k = 0; k < l; ++k) {
                 const double d = A[k * LDA + k];
                 const double tol = (double)l * 0x1.0p-52 * gdiag[k];
-                if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot
+                if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot (uniform)
                     if (tid == 0) s_fail = 1;
-                    break;  // uniform: every thread reads the same d
+                    break;
                 }
-                const double rkk = sqrt(d);
+                const double rinv = 1.0 / sqrt(d);
+                __syncthreads();  // everyone has read the pivot
+                for (int j = k + tid; j < l; j += 256) A[k * LDA + j] *= rinv;  // row k of R
                 __syncthreads();
-                if (tid == 0) A[k * LDA + k] = rkk;
-                for (int j = k + 1 + tid; j < l; j += 256) A[k * LDA + j] /= rkk;
-                __syncthreads();
-                const int w = l - k - 1;
-                for (int e = tid; e < w * w; e += 256) {
-                    const int i = k + 1 + e % w, j = k + 1 + e / w;
-                    if (i <= j) A[i * LDA + j] -= A[k * LDA + i] * A[k * LDA + j];
+                // trailing update of the upper triangle, rows/columns k+1..l-1
+                for (int i = k + 1 + tj; i < l; i += 16) {
+                    const double rki = A[k * LDA + i];
+                    for (int j = i + ((ti - (i - k - 1)) % 16 + 16) % 16; j < l; j += 16)
+                        A[i * LDA + j] -= rki * A[k * LDA + j];
                 }
                 __syncthreads();
             }
@@ -308,24 +315,21 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
     }
 
     if (ok) {
-        // X = R^-1 by Gauss-Jordan from the last column
-        for (int e = tid; e < l * l; e += 256) {
-            const int i = e / l, j = e % l;
-            if (i > j) A[i * LDA + j] = 0.0;
-        }
+        // X = R^-1 by Gauss-Jordan from the last column; X[i][j] (i < j) is
+        // kept transposed in the strict lower triangle of A, X[k][k] in xd
+        for (int i = tj; i < l; i += 16)
+            for (int j = ti; j < i; j += 16) A[i * LDA + j] = 0.0;
         for (int k = tid; k < l; k += 256) xd[k] = 1.0;
         __syncthreads();
         for (int k = l - 1; k >= 0; --k) {
             const double inv = 1.0 / A[k * LDA + k];
-            // row k of X: X[k][k] = xd[k], X[k][j>k] at A[j][k]
             if (tid == 0) xd[k] *= inv;
             for (int j = k + 1 + tid; j < l; j += 256) A[j * LDA + k] *= inv;
             __syncthreads();
-            const int w = l - k;  // columns j = k..l-1
-            for (int e = tid; e < k * w; e += 256) {
-                const int i = e % k, j = k + e / k;
+            // rows i < k, columns j >= k: X[i][j] -= R[i][k] X[k][j]
+            for (int j = k + tj; j < l; j += 16) {
                 const double xkj = (j == k) ? xd[k] : A[j * LDA + k];
-                A[j * LDA + i] -= A[i * LDA + k] * xkj;
+                for (int i = ti; i < k; i += 16) A[j * LDA + i] -= A[i * LDA + k] * xkj;
             }
             __syncthreads();
         }
@@ -369,7 +373,8 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
 }
 
 __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, int l, int lp,
-                                                 double* __restrict__ UB, double* __restrict__ sig, int* flags) {
+                                                 double* __restrict__ UB, double* __restrict__ sig, int* flags,
+                                                 double tol) {
     __shared__ double W[LPMAX * JLD];  // column c at W[c * JLD + row]
     __shared__ double nrm[LPMAX];
     __shared__ int s_rot;
@@ -386,7 +391,6 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, i
 
     const int pr = tid / tpp;     // pair slot
     const int sub = tid % tpp;    // lane within the pair group
-    const double tol = (double)lp * 0x1.0p-53;
     int sweep = 0;
     const int max_sweeps = 40;
     for (; sweep < max_sweeps; ++sweep) {
@@ -442,12 +446,13 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, i
     }
 }
 
-hipError_t launch_jacobi(const double* G, int l, int lp, double* UB, double* sig, int* flags, hipStream_t st) {
+hipError_t launch_jacobi(const double* G, int l, int lp, double* UB, double* sig, int* flags, double tol,
+                         hipStream_t st) {
     if (lp > LPMAX || lp % 16) return hipErrorInvalidValue;
     const int npair = lp / 2;
     int tpp = 64;  // threads per column pair: a power of two that divides the wave
     while (tpp * npair > 1024) tpp /= 2;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(tpp * npair), 0, st, G, l, lp, UB, sig, flags);
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(tpp * npair), 0, st, G, l, lp, UB, sig, flags, tol);
     return hipGetLastError();
 }
 

@@ -1,11 +1,12 @@
 // Passes over a 16-bit snapshot matrix (bfloat16 or IEEE half) on the
 // 16x16x32 matrix cores of gfx950, FP32 accumulation.
 //
-//   k_sx16   Y = S X    (X stored in the same 16-bit type)
-//   k_stq16  Z = S^T Q  (Q stored in FP32, rounded to the 16-bit type on the
-//                        fly; with LO the rounding remainder is applied as a
-//                        second product, so Q carries ~16 significant bits:
-//                        the refinement pass for T = Q^T S)
+//   k_sx16    Y = S X    (X stored in the same 16-bit type)
+//   k_stq16   Z = S^T Q  (Q given as 16-bit hi = round(Q) and, with LO, also
+//                         lo = round(Q - hi) applied as a second product, so
+//                         Q carries ~16 significant bits: the refinement pass
+//                         for T = Q^T S)
+//   k_split16 the hi/lo split of an FP32 Q
 //
 // MFMA operand layout (measured on gfx950 for 16x16x32 bf16/f16): lane l
 // supplies A[l%16][8*(l/16) + i] and B[8*(l/16) + i][l%16], i = 0..7, and
@@ -59,7 +60,7 @@ __device__ __forceinline__ u16x8 load_rows8(const unsigned short* S, int64_t ld,
     if (j < n) {
         const unsigned short* p = S + j * ld + i;
         if (VEC && i + 7 < lim) {
-            v = *reinterpret_cast<const u16x8*>(p);
+            v = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(p));  // streamed once
         } else {
 #pragma unroll
             for (int t = 0; t < 8; ++t)
@@ -71,23 +72,30 @@ __device__ __forceinline__ u16x8 load_rows8(const unsigned short* S, int64_t ld,
 
 // ---------------------------------------------------------------------------
 // Y = S X, 16-bit S and X, FP32 Y. Workgroup: 256 rows, columns in chunks of
-// 32 (one MFMA K). Each chunk of S is staged in LDS column-major (row runs
-// of 16 bytes written by each thread, coalesced 512-byte column reads from
-// HBM) and read back transposed: lane (r, kg) of m-tile mt gathers row
-// 64 w + 16 mt + r of columns 8 kg .. 8 kg + 7. X is column-major, so its
-// operand is one 16-byte load per output tile.
+// 32 (one MFMA K). Each chunk of S is staged in LDS column-major (every
+// thread moves a 16-byte run of 8 rows; a column of the tile is one
+// 512-byte coalesced read from HBM) and read back transposed: lane (r, kg)
+// of m-tile mt gathers row 64 w + 16 mt + r of columns 8 kg .. 8 kg + 7. The
+// chunk of X (32 rows x 16 NT columns, column-major) is staged next to it and
+// read as one 16-byte operand per output tile. The next chunk's global loads
+// are issued before the current chunk's matrix-core work.
 // ---------------------------------------------------------------------------
-constexpr int SX16_BM = 256, SX16_BK = 32, SX16_LDR = SX16_BM + 4;  // LDS column stride (elements)
+constexpr int SX16_BM = 256, SX16_BK = 32;
+constexpr int SX16_LDR = SX16_BM + 4;   // S tile column stride (elements): conflict-free gathers
+constexpr int SX16_LDX = SX16_BK + 8;   // X tile column stride (elements): conflict-free 16-byte reads
 
 template <typename T16, int NT, bool VEC>
-__global__ __launch_bounds__(256) void k_sx16(const unsigned short* __restrict__ S, int64_t ldS, int64_t m,
-                                              int64_t n, const unsigned short* __restrict__ X, int64_t ldX,
-                                              float* __restrict__ Y, int64_t ldY, int64_t mstore) {
+__global__ __launch_bounds__(256, 2) void k_sx16(const unsigned short* __restrict__ S, int64_t ldS, int64_t m,
+                                                 int64_t n, const unsigned short* __restrict__ X, int64_t ldX,
+                                                 float* __restrict__ Y, int64_t ldY, int64_t mstore) {
     __shared__ unsigned short tile[SX16_BK * SX16_LDR];
+    __shared__ __attribute__((aligned(16))) unsigned short xt[16 * NT * SX16_LDX];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * SX16_BM;
-    const int rg = tid & 31, cc = tid >> 5;  // staging: rows 8 rg..+7 of columns cc + 8 q
+    const int rg = tid & 31, cc = tid >> 5;  // S staging: rows 8 rg..+7 of columns cc + 8 q
+    constexpr int XCH = 16 * NT * (SX16_BK / 8);  // 16-byte chunks of the X tile
+    constexpr int XPT = (XCH + 255) / 256;
 
     f32x4 acc[4][NT];
 #pragma unroll
@@ -95,31 +103,52 @@ __global__ __launch_bounds__(256) void k_sx16(const unsigned short* __restrict__
 #pragma unroll
         for (int c = 0; c < NT; ++c) acc[mt][c] = f32x4{0, 0, 0, 0};
 
-    const bool active = i0 < m;
-    for (int64_t j0 = 0; active && j0 < n; j0 += SX16_BK) {
-        u16x8 st[4];
+    if (i0 < m) {
+        u16x8 st[4], xr[XPT];
+        auto fetch = [&](int64_t j0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st[q] = load_rows8<VEC>(S, ldS, m, n, i0 + 8 * rg, j0 + cc + 8 * q);
-        u16x8 b[NT];
+            for (int q = 0; q < 4; ++q) st[q] = load_rows8<VEC>(S, ldS, m, n, i0 + 8 * rg, j0 + cc + 8 * q);
 #pragma unroll
-        for (int c = 0; c < NT; ++c)
-            b[c] = *reinterpret_cast<const u16x8*>(X + (int64_t)(16 * c + r16) * ldX + j0 + 8 * kg);
-        __syncthreads();  // previous chunk fully consumed
+            for (int q = 0; q < XPT; ++q) {
+                const int ch = tid + 256 * q;
+                if (ch < XCH) {
+                    const int c = ch / (SX16_BK / 8), part = ch % (SX16_BK / 8);
+                    xr[q] = *reinterpret_cast<const u16x8*>(X + (int64_t)c * ldX + j0 + 8 * part);
+                }
+            }
+        };
+        fetch(0);
+        for (int64_t j0 = 0; j0 < n; j0 += SX16_BK) {
+            __syncthreads();  // previous chunk fully consumed
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            unsigned short* dst = tile + (cc + 8 * q) * SX16_LDR + 8 * rg;
-            *reinterpret_cast<u16x4*>(dst) = u16x4{st[q][0], st[q][1], st[q][2], st[q][3]};
-            *reinterpret_cast<u16x4*>(dst + 4) = u16x4{st[q][4], st[q][5], st[q][6], st[q][7]};
-        }
-        __syncthreads();
+            for (int q = 0; q < 4; ++q) {
+                unsigned short* dst = tile + (cc + 8 * q) * SX16_LDR + 8 * rg;
+                *reinterpret_cast<u16x4*>(dst) = u16x4{st[q][0], st[q][1], st[q][2], st[q][3]};
+                *reinterpret_cast<u16x4*>(dst + 4) = u16x4{st[q][4], st[q][5], st[q][6], st[q][7]};
+            }
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const unsigned short* src = tile + (8 * kg) * SX16_LDR + wave * 64 + 16 * mt + r16;
-            u16x8 a;
+            for (int q = 0; q < XPT; ++q) {
+                const int ch = tid + 256 * q;
+                if (ch < XCH) {
+                    const int c = ch / (SX16_BK / 8), part = ch % (SX16_BK / 8);
+                    *reinterpret_cast<u16x8*>(xt + c * SX16_LDX + 8 * part) = xr[q];
+                }
+            }
+            __syncthreads();
+            if (j0 + SX16_BK < n) fetch(j0 + SX16_BK);  // in flight during the matrix-core work
+            u16x8 b[NT];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) a[i] = src[i * SX16_LDR];
+            for (int c = 0; c < NT; ++c)
+                b[c] = *reinterpret_cast<const u16x8*>(xt + (16 * c + r16) * SX16_LDX + 8 * kg);
 #pragma unroll
-            for (int c = 0; c < NT; ++c) acc[mt][c] = mma16<T16>::run(a, b[c], acc[mt][c]);
+            for (int mt = 0; mt < 4; ++mt) {
+                const unsigned short* src = tile + (8 * kg) * SX16_LDR + wave * 64 + 16 * mt + r16;
+                u16x8 a;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a[i] = src[i * SX16_LDR];
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[mt][c] = mma16<T16>::run(a, b[c], acc[mt][c]);
+            }
         }
     }
 #pragma unroll
@@ -139,61 +168,157 @@ __global__ __launch_bounds__(256) void k_sx16(const unsigned short* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Z_s = S_s^T Q_s, 16-bit S, FP32 Q. Workgroup: 256 columns (4 waves x 4
-// tiles of 16), rows of split s in steps of 32 (one MFMA K):
-//   A[mm][8 kg + i] = S[i0 + 8 kg + i][jw + 16 u + mm]  (one 16-byte load)
-//   B[8 kg + i][nn] = round16(Q[i0 + 8 kg + i][16 c + nn])  (+ remainder if LO)
+// Z_s = S_s^T Q_s, 16-bit S, Q given as 16-bit hi (and lo) parts.
+// Workgroup: G blocks of 128 columns of S over the rows of split s, R rows
+// per step (R = 128; 64 when the lo part doubles the Q block). Per step the
+// Q block (R x 16 NT) is staged in LDS once and serves the G column blocks,
+// whose S blocks (R x 128) pass through one LDS buffer in turn; global reads
+// cover 4 columns x 256 bytes (R = 128) per wave instruction, the shape that
+// streams near the HBM peak, and are non-temporal. Operands are plain
+// 16-byte LDS reads (K along rows):
+//   A[mm][8 kg + i] = S[i0 + 32 k + 8 kg + i][j0 + 128 g + 32 w + 16 u + mm]
+//   B[8 kg + i][nn] = Q[i0 + 32 k + 8 kg + i][16 c + nn]   (hi, then lo)
+// Loads of the next S block (and of the next step's Q block) are in flight
+// during each matrix-core phase. Splits are interleaved (step t of split s
+// covers rows R (t nsplit + s) .. +R-1), so the workgroups of one column
+// block read neighbouring pieces of every column.
 // ---------------------------------------------------------------------------
-template <typename T16, int NT, bool VEC, bool LO>
-__global__ __launch_bounds__(256) void k_stq16(const unsigned short* __restrict__ S, int64_t ldS, int64_t m,
-                                               int64_t n, const float* __restrict__ Q, int64_t ldQ,
-                                               double* __restrict__ Zp, int64_t nP, int64_t split_rows) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+constexpr int STQ16_HB = 128;  // columns per block
+
+template <typename T16, int NT, bool VEC, bool LO, int G>
+__global__ __launch_bounds__(256, 2) void k_stq16(const unsigned short* __restrict__ S, int64_t ldS, int64_t m,
+                                                  int64_t n, const unsigned short* __restrict__ Qh,
+                                                  const unsigned short* __restrict__ Ql, int64_t ldQ,
+                                                  double* __restrict__ Zp, int64_t nP, int nsplit, int ncb,
+                                                  int ntiles) {
+    constexpr int R = LO ? 64 : 128;
+    constexpr int LDS_ = R + 8;   // column stride (elements) of the LDS blocks
+    constexpr int LPC = R / 8;    // 16-byte chunks per column of a block
+    constexpr int NQ = LO ? 2 : 1;
+    constexpr int HB = STQ16_HB;
+    __shared__ __attribute__((aligned(16))) unsigned short ss[HB * LDS_];
+    __shared__ __attribute__((aligned(16))) unsigned short qs[NQ * 16 * NT * LDS_];
+    const int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const int cb = tile % ncb, sp = tile / ncb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
-    const int64_t jw = (int64_t)blockIdx.x * 256 + wave * 64;
-    const int64_t ib = (int64_t)blockIdx.y * split_rows;
-    const int64_t ie = (ib + split_rows < m) ? ib + split_rows : m;
+    const int64_t j0 = (int64_t)cb * (G * HB);
+    const int64_t ib = (int64_t)sp * R, stride = (int64_t)nsplit * R;
+    constexpr int SCH = HB * LPC / 256;                // S chunks per thread and half
+    constexpr int QCH = 16 * NT * LPC;                 // Q chunks per block
+    constexpr int QPT = (QCH + 255) / 256;
 
-    f32x4 acc[4][NT];
+    f32x4 acc[G][2][NT];  // [block][u][c]
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int c = 0; c < NT; ++c) acc[u][c] = f32x4{0, 0, 0, 0};
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[g][u][c] = f32x4{0, 0, 0, 0};
 
-    if (jw < n) {
-        for (int64_t i0 = ib; i0 < ie; i0 += 32) {
-            u16x8 a[4];
+    u16x8 sr[SCH], qr[NQ][QPT];
+    auto fetch_s = [&](int64_t i0, int g) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = load_rows8<VEC>(S, ldS, ie, n, i0 + 8 * kg, jw + 16 * u + r16);
+        for (int q = 0; q < SCH; ++q) {
+            const int ch = tid + 256 * q;
+            sr[q] = load_rows8<VEC>(S, ldS, m, n, i0 + 8 * (ch % LPC), j0 + HB * g + ch / LPC);
+        }
+    };
+    auto fetch_q = [&](int64_t i0) {
 #pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                const float* pq = Q + (int64_t)(16 * c + r16) * ldQ + i0 + 8 * kg;
-                const f32x4 q0 = *reinterpret_cast<const f32x4*>(pq);
-                const f32x4 q1 = *reinterpret_cast<const f32x4*>(pq + 4);
-                u16x8 hi, lo;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const float x = i < 4 ? q0[i] : q1[i - 4];
-                    hi[i] = mma16<T16>::from_float(x);
-                    if (LO) lo[i] = mma16<T16>::from_float(x - mma16<T16>::to_float(hi[i]));
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    acc[u][c] = mma16<T16>::run(a[u], hi, acc[u][c]);
-                    if (LO) acc[u][c] = mma16<T16>::run(a[u], lo, acc[u][c]);
-                }
+        for (int q = 0; q < QPT; ++q) {
+            const int ch = tid + 256 * q;
+            if (ch < QCH) {
+                const int64_t off = (int64_t)(ch / LPC) * ldQ + i0 + 8 * (ch % LPC);
+                qr[0][q] = *reinterpret_cast<const u16x8*>(Qh + off);
+                if (LO) qr[NQ - 1][q] = *reinterpret_cast<const u16x8*>(Ql + off);
             }
         }
-    }
-    double* zp = Zp + (int64_t)blockIdx.y * nP * (16 * NT);
+    };
+    auto put_s = [&]() {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            double* pz = zp + (int64_t)(16 * c + r16) * nP + jw + 16 * u + 4 * kg;
-            typedef double d4 __attribute__((ext_vector_type(4)));
-            *reinterpret_cast<d4*>(pz) = d4{acc[u][c][0], acc[u][c][1], acc[u][c][2], acc[u][c][3]};
+        for (int q = 0; q < SCH; ++q) {
+            const int ch = tid + 256 * q;
+            *reinterpret_cast<u16x8*>(ss + (ch / LPC) * LDS_ + 8 * (ch % LPC)) = sr[q];
         }
+    };
+    auto compute = [&](int g) {
+#pragma unroll
+        for (int k = 0; k < R / 32; ++k) {
+            u16x8 a[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                a[u] = *reinterpret_cast<const u16x8*>(ss + (32 * wave + 16 * u + r16) * LDS_ + 32 * k + 8 * kg);
+#pragma unroll
+            for (int h = 0; h < NQ; ++h)  // hi and lo far apart: no back-to-back dependence
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const u16x8 b =
+                        *reinterpret_cast<const u16x8*>(qs + (h * 16 * NT + 16 * c + r16) * LDS_ + 32 * k + 8 * kg);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) acc[g][u][c] = mma16<T16>::run(a[u], b, acc[g][u][c]);
+                }
+        }
+    };
+    if (ib < m) {
+        fetch_q(ib);
+        fetch_s(ib, 0);
+    }
+    for (int64_t i0 = ib; i0 < m; i0 += stride) {
+        __syncthreads();  // previous step fully consumed
+        put_s();
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) {
+            const int ch = tid + 256 * q;
+            if (ch < QCH) {
+#pragma unroll
+                for (int h = 0; h < NQ; ++h)
+                    *reinterpret_cast<u16x8*>(qs + (h * 16 * NT + ch / LPC) * LDS_ + 8 * (ch % LPC)) = qr[h][q];
+            }
+        }
+        __syncthreads();
+        if constexpr (G == 2) {
+            fetch_s(i0, 1);  // second block of this step, in flight during the first block's work
+            compute(0);
+            __syncthreads();
+            put_s();
+            __syncthreads();
+        }
+        if (i0 + stride < m) {  // next step, in flight during the last block's work
+            fetch_q(i0 + stride);
+            fetch_s(i0 + stride, 0);
+        }
+        compute(G - 1);
+    }
+    double* zp = Zp + (int64_t)sp * nP * (16 * NT);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                double* pz = zp + (int64_t)(16 * c + r16) * nP + j0 + HB * g + 32 * wave + 16 * u + 4 * kg;
+                typedef double d4 __attribute__((ext_vector_type(4)));
+                *reinterpret_cast<d4*>(pz) = d4{acc[g][u][c][0], acc[g][u][c][1], acc[g][u][c][2], acc[g][u][c][3]};
+            }
+}
+
+// Split an FP32 tall matrix into 16-bit hi = round(q) and lo = round(q - hi).
+template <typename T16>
+__global__ void k_split16(const float* __restrict__ Q, int64_t count, unsigned short* __restrict__ hi,
+                          unsigned short* __restrict__ lo) {
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (e >= count) return;
+    const f32x4 q = *reinterpret_cast<const f32x4*>(Q + e);
+    u16x4 h, l;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[i] = mma16<T16>::from_float(q[i]);
+        l[i] = mma16<T16>::from_float(q[i] - mma16<T16>::to_float(h[i]));
+    }
+    *reinterpret_cast<u16x4*>(hi + e) = h;
+    *reinterpret_cast<u16x4*>(lo + e) = l;
 }
 
 // ---------------------------------------------------------------------------
@@ -215,16 +340,21 @@ static hipError_t sx16_nt(const void* S, int64_t ldS, int64_t m, int64_t n, cons
 }
 
 template <typename T16, int NT, bool LO>
-static hipError_t stq16_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q, int64_t ldQ, double* Zp,
-                           int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
-    dim3 grid((unsigned)(nP / 256), (unsigned)nsplit);
+static hipError_t stq16_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const unsigned short* Qh,
+                           const unsigned short* Ql, int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows,
+                           int nsplit, hipStream_t st) {
+    (void)split_rows;  // splits are interleaved in steps of R rows
+    constexpr int G = LO ? 2 : 1;  // measured: one Q block per 128 columns (hi), per 256 (hi + lo)
+    const int ncb = (int)(nP / (G * STQ16_HB));
+    const int ntiles = ncb * nsplit;
+    dim3 grid((unsigned)ntiles);
     const bool vec = (ldS % 8 == 0) && ((uintptr_t)S % 16 == 0);
     if (vec)
-        hipLaunchKernelGGL((k_stq16<T16, NT, true, LO>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS, m,
-                           n, (const float*)Q, ldQ, Zp, nP, split_rows);
+        hipLaunchKernelGGL((k_stq16<T16, NT, true, LO, G>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS,
+                           m, n, Qh, Ql, ldQ, Zp, nP, nsplit, ncb, ntiles);
     else
-        hipLaunchKernelGGL((k_stq16<T16, NT, false, LO>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS, m,
-                           n, (const float*)Q, ldQ, Zp, nP, split_rows);
+        hipLaunchKernelGGL((k_stq16<T16, NT, false, LO, G>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS,
+                           m, n, Qh, Ql, ldQ, Zp, nP, nsplit, ncb, ntiles);
     return hipGetLastError();
 }
 
@@ -240,11 +370,11 @@ static hipError_t sx16_dispatch(int nt, const void* S, int64_t ldS, int64_t m, i
 }
 
 template <typename T16, bool LO>
-static hipError_t stq16_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q,
-                                 int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit,
-                                 hipStream_t st) {
+static hipError_t stq16_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
+                                 const unsigned short* Qh, const unsigned short* Ql, int64_t ldQ, double* Zp,
+                                 int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
     switch (nt) {
-#define RPOD_C(K) case K: return stq16_nt<T16, K, LO>(S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+#define RPOD_C(K) case K: return stq16_nt<T16, K, LO>(S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st);
         RPOD_C(1) RPOD_C(2) RPOD_C(3) RPOD_C(4) RPOD_C(5) RPOD_C(6) RPOD_C(7) RPOD_C(8)
 #undef RPOD_C
         default: return hipErrorInvalidValue;
@@ -258,15 +388,29 @@ hipError_t launch_sx16(int tin, int nt, const void* S, int64_t ldS, int64_t m, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stq16(int tin, int nt, bool lo, const void* S, int64_t ldS, int64_t m, int64_t n, const float* Q,
-                        int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
+hipError_t launch_stq16(int tin, int nt, bool lo, const void* S, int64_t ldS, int64_t m, int64_t n,
+                        const unsigned short* Qh, const unsigned short* Ql, int64_t ldQ, double* Zp, int64_t nP,
+                        int64_t split_rows, int nsplit, hipStream_t st) {
     if (tin == DT_BF16)
-        return lo ? stq16_dispatch<__bf16, true>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st)
-                  : stq16_dispatch<__bf16, false>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+        return lo ? stq16_dispatch<__bf16, true>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st)
+                  : stq16_dispatch<__bf16, false>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st);
     if (tin == DT_F16)
-        return lo ? stq16_dispatch<_Float16, true>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st)
-                  : stq16_dispatch<_Float16, false>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+        return lo ? stq16_dispatch<_Float16, true>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st)
+                  : stq16_dispatch<_Float16, false>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_split16(int tin, const float* Q, int64_t count, unsigned short* hi, unsigned short* lo,
+                          hipStream_t st) {
+    if (count % 4) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((count / 4 + 255) / 256));
+    if (tin == DT_BF16)
+        hipLaunchKernelGGL(k_split16<__bf16>, grid, dim3(256), 0, st, Q, count, hi, lo);
+    else if (tin == DT_F16)
+        hipLaunchKernelGGL(k_split16<_Float16>, grid, dim3(256), 0, st, Q, count, hi, lo);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 }  // namespace rpod

@@ -50,7 +50,7 @@ __device__ __forceinline__ void store4(Tout* p, T a, T b, T c, T d) {
 //   A[mm][k] = S[iw + 4 mm + t][j0 + 4 k + s],  B[k][nn] = X[j0 + 4 k + s][16 c + nn]
 // so output row mm of MFMA t is global row iw + 4 mm + t.
 // ---------------------------------------------------------------------------
-template <typename Tin, typename Tout, int NT, bool VEC>
+template <typename Tin, typename Tout, int NT, bool VEC, bool UPPER>
 __global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m, int64_t n,
                                             const Tin* __restrict__ X, int64_t ldX, Tout* Y,
                                             int64_t ldY, int64_t mstore, const int* cond,
@@ -80,7 +80,10 @@ __global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
-                    for (int c = 0; c < NT; ++c) acc[t][c] = mfma_16x16x4(a[s][t], b[c][s], acc[t][c]);
+                    for (int c = 0; c < NT; ++c) {
+                        if (UPPER && j0 > 16 * c) continue;  // X upper triangular: tile is zero
+                        acc[t][c] = mfma_16x16x4(a[s][t], b[c][s], acc[t][c]);
+                    }
         }
     }
     // component v of acc[t][c] is MFMA row mm = mfma_row(kg, v), i.e. global
@@ -169,16 +172,19 @@ __global__ void k_reduce_slabs(const double* __restrict__ Zp, int nsplit, int64_
 // ---------------------------------------------------------------------------
 template <typename Tin, typename Tout, int NT>
 static hipError_t sx_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const void* X, int64_t ldX,
-                        void* Y, int64_t ldY, int64_t mstore, const int* cond, int cond_mask,
+                        void* Y, int64_t ldY, int64_t mstore, const int* cond, int cond_mask, bool upper,
                         hipStream_t st) {
     const int64_t rows = mstore > m ? mstore : m;
     dim3 grid((unsigned)((rows + 255) / 256));
     const bool vec = (ldS % 4 == 0) && ((uintptr_t)S % (4 * sizeof(Tin)) == 0);
-    if (vec)
-        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
+    if (upper)  // internal operands only: always vector-aligned
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true, true>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
+                           (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
+    else if (vec)
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
                            (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
     else
-        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, false, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
                            (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
     return hipGetLastError();
 }
@@ -186,10 +192,10 @@ static hipError_t sx_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const 
 template <typename Tin, typename Tout>
 static hipError_t sx_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* X,
                               int64_t ldX, void* Y, int64_t ldY, int64_t mstore, const int* cond,
-                              int cond_mask, hipStream_t st) {
+                              int cond_mask, bool upper, hipStream_t st) {
     switch (nt) {
 #define RPOD_SX_CASE(K) \
-    case K: return sx_nt<Tin, Tout, K>(S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+    case K: return sx_nt<Tin, Tout, K>(S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
         RPOD_SX_CASE(1) RPOD_SX_CASE(2) RPOD_SX_CASE(3) RPOD_SX_CASE(4)
         RPOD_SX_CASE(5) RPOD_SX_CASE(6) RPOD_SX_CASE(7) RPOD_SX_CASE(8)
 #undef RPOD_SX_CASE
@@ -199,17 +205,17 @@ static hipError_t sx_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int
 
 hipError_t launch_sx(int tin, int tout, int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
                      const void* X, int64_t ldX, void* Y, int64_t ldY, int64_t mstore, const int* cond,
-                     int cond_mask, hipStream_t st) {
+                     int cond_mask, hipStream_t st, bool upper) {
     if (tin == DT_F64 && tout == DT_F64)
-        return sx_dispatch<double, double>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+        return sx_dispatch<double, double>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
     if (tin == DT_F64 && tout == DT_F32)
-        return sx_dispatch<double, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+        return sx_dispatch<double, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
     if (tin == DT_F32 && tout == DT_F32)
-        return sx_dispatch<float, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+        return sx_dispatch<float, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
     if (tin == DT_F64 && tout == DT_BF16)
-        return sx_dispatch<double, __bf16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+        return sx_dispatch<double, __bf16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
     if (tin == DT_F64 && tout == DT_F16)
-        return sx_dispatch<double, _Float16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, st);
+        return sx_dispatch<double, _Float16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
     return hipErrorInvalidValue;
 }
 

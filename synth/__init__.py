@@ -142,3 +142,39 @@ def fourier_field(nx, ny, n, n_modes=200, beta=1.5, phi=0.95, noise_std=1e-4, se
         St[t0:t1] = blk
     return dict(St=St, modes=modes, kmag=kmag, amp=amp, T=T, nx=nx, ny=ny)
 
+
+
+def fourier_field_device(nx, ny, n, n_modes=200, beta=1.5, phi=0.95, noise_std=1e-4, seed=3,
+                         dtype=None, device="cuda", col_block=512):
+    """fourier_field() built on the GPU with torch (FP32 arithmetic), for sizes
+    too large to generate on the host. Same modes, amplitudes and AR(1) series
+    (drawn on the host from the same streams); the white noise comes from a
+    seeded torch generator on the device, so the matrix equals the host
+    generator's only up to the noise draw. Returns St (n, nx*ny) on device.
+    """
+    import torch
+
+    dtype = torch.float32 if dtype is None else dtype
+    m = nx * ny
+    modes, kmag = fourier_modes(nx, ny, n_modes)
+    amp = kmag ** (-beta)
+    T = ar1_series(n, n_modes, phi, seed)
+    dev = torch.device(device)
+    ix = torch.arange(nx, dtype=torch.float64, device=dev) + 0.5
+    iy = torch.arange(ny, dtype=torch.float64, device=dev) + 0.5
+    ma = torch.as_tensor(modes[:, 0], dtype=torch.float64, device=dev)
+    mb = torch.as_tensor(modes[:, 1], dtype=torch.float64, device=dev)
+    sx = torch.sin(torch.pi * ma[:, None] * ix[None, :] / nx)
+    sy = torch.sin(torch.pi * mb[:, None] * iy[None, :] / ny)
+    F = (sy[:, :, None] * sx[:, None, :]).reshape(n_modes, m).to(torch.float32)     # (K, m)
+    C = torch.as_tensor(T * amp[None, :], dtype=torch.float32, device=dev)          # (n, K)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed) * 1000003 + _S_NOISE)
+    St = torch.empty((n, m), dtype=dtype, device=dev)
+    for t0 in range(0, n, col_block):
+        t1 = min(n, t0 + col_block)
+        blk = C[t0:t1] @ F
+        if noise_std:
+            blk += noise_std * torch.randn((t1 - t0, m), generator=gen, device=dev, dtype=torch.float32)
+        St[t0:t1] = blk.to(dtype)
+    return dict(St=St, modes=modes, kmag=kmag, amp=amp, T=T, nx=nx, ny=ny)
