@@ -14,6 +14,12 @@ Also measured (unless --no-extra): the mixed-precision BF16 path against
 plain FP32 on S = 1048576 x 10000 (1024 x 1024 grid, same field), r = 100,
 p = 20, q = 2, reported under "mixed_vs_plain".
 
+Also measured (unless --no-batch): the uneven batch of 64 snapshot matrices
+(m in {2^16, 2^17, 2^18}, n in [500, 4000], r in {10, 25, 50, 100}, p = 10,
+q = 2, spectral decay in [0.05, 0.2], all drawn per matrix from the seed):
+one batched plan in BF16 and in FP32 against 64 single plain FP32 plans run
+one after another, reported under "batched_vs_plain".
+
 Per-kernel times of the passes over S come from HIP events that the library
 records on its stream around every pass during the timed steps.
 """
@@ -118,6 +124,13 @@ def measure(name, St, steps, warmup):
     for _ in range(warmup):
         plan.compute(St, w["seed"], out=out, check=False)
     plan.status()
+    # graph replays, no per-pass events
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.compute(St, w["seed"], out=out, check=False)
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
     plan.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,6 +140,7 @@ def measure(name, St, steps, warmup):
     wall = time.perf_counter() - t0
     flags = plan.status()
     ms = wall * 1e3 / steps
+    log(f"[bench] {name}: graph replay {ms_graph:.3f} ms per rPOD")
     kern = {}
     for kind, kname in ((0, "S_X"), (1, "St_Q")):
         nl, tot, bpl, fpl = plan.timing(kind)
@@ -152,10 +166,118 @@ def measure(name, St, steps, warmup):
                 hbm_gbs_algorithmic=round(gbs, 1))
     passes = sum(v["launches"] for v in kern.values()) / steps
     s_bytes = passes * m * n * St.element_size()
-    return dict(ms=ms, roofline=roof, sigma=sigma, flags=flags,
+    return dict(ms=ms, ms_graph=ms_graph, roofline=roof, sigma=sigma, flags=flags,
                 hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
                 kernels={k: {"launches_per_step": v["launches"] // steps, "avg_ms": round(v["avg_ms"], 4)}
                          for k, v in kern.items()})
+
+
+BATCH = dict(count=64, shape_seed=4, p=10, q=2, seed0=1000)
+
+
+def make_batch(dev):
+    """The 64 uneven matrices as FP32 device tensors (St (n, m) each) and their shapes."""
+    import synth
+    shapes = synth.batch_shapes(BATCH["count"], seed=BATCH["shape_seed"])
+    mats = [synth.lowrank_exp_device(m, n, a, noise_std=1e-4, seed=BATCH["seed0"] + i, device=dev)
+            for i, (m, n, r, a) in enumerate(shapes)]
+    return shapes, mats
+
+
+def measure_batch(mats, shapes, steps, warmup, batched=True):
+    """Time one batched plan over all matrices (or one plan per matrix in
+    sequence); per-pass kernel times from the library's HIP events."""
+    import torch
+    import paper_2504_15350_amd as rp
+    p, q = BATCH["p"], BATCH["q"]
+    seeds = [BATCH["seed0"] + 7 * i for i in range(len(mats))]
+    dt = mats[0].dtype
+    if batched:
+        plans = [rp.BatchPlan([(m, n, r, p) for (m, n, r, _a) in shapes], q, dtype=dt, device=mats[0].device)]
+        outs = [plans[0].alloc_outputs()]
+        run = lambda: plans[0].compute(mats, seeds, outs=outs[0], check=False)
+    else:
+        plans = [rp.Plan(m, n, r, p, q, dtype=dt, device=mats[0].device) for (m, n, r, _a) in shapes]
+        outs = [(torch.empty((r, m), dtype=pl.out_dtype, device=mats[0].device),
+                 torch.empty((r,), dtype=torch.float64, device=mats[0].device),
+                 torch.empty((n, r), dtype=pl.out_dtype, device=mats[0].device))
+                for pl, (m, n, r, _a) in zip(plans, shapes)]
+
+        def run():
+            for pl, St, sd, o in zip(plans, mats, seeds, outs):
+                pl.compute(St, sd, out=o, check=False)
+    for _ in range(warmup):
+        run()
+    for pl in plans:
+        pl.status()
+        pl.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    flags = [pl.status() for pl in plans]
+    tot = {0: [0, 0.0, 0.0], 1: [0, 0.0, 0.0]}
+    for pl in plans:
+        for kind in (0, 1):
+            nl, t, bpl, _fpl = pl.timing(kind)
+            tot[kind][0] += nl
+            tot[kind][1] += t
+            tot[kind][2] += bpl * nl
+        pl.set_timing(False)
+    if batched:
+        sig = [o[1].cpu().numpy() for o in outs[0]]
+    else:
+        sig = [o[1].cpu().numpy() for o in outs]
+    for pl in plans:
+        pl.close()
+    kern = {}
+    for kind, kname in ((0, "S_X"), (1, "St_Q")):
+        nl, t, b = tot[kind]
+        kern[kname] = dict(launches_per_step=nl // steps, avg_ms=round(t / max(nl, 1), 4),
+                           hbm_gbs_algorithmic=round(b / (t * 1e-3) / 1e9, 1) if t > 0 else None)
+    s_bytes = sum(m * n for (m, n, _r, _a) in shapes) * mats[0].element_size() * (2 * q + 2)
+    log(f"[bench] batch {'batched' if batched else 'sequential'} {dt}: {ms:.2f} ms per batch "
+        f"({len(mats)} matrices), flags {flags}, " + ", ".join(f"{k} {v}" for k, v in kern.items()))
+    return dict(ms=ms, sigma=sig, kernels=kern, hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
+                flags=flags)
+
+
+def batch_block(dev, steps, warmup):
+    import torch
+    t0 = time.perf_counter()
+    shapes, mats = make_batch(dev)
+    torch.cuda.synchronize()
+    elems = sum(m * n for (m, n, _r, _a) in shapes)
+    log(f"[bench] generated the 64-matrix batch ({elems / 1e9:.2f} G elements) in {time.perf_counter() - t0:.1f} s")
+    plain = measure_batch(mats, shapes, steps, warmup, batched=False)
+    b32 = measure_batch(mats, shapes, steps, warmup, batched=True)
+    mats16 = [St.to(torch.bfloat16) for St in mats]
+    del mats
+    torch.cuda.empty_cache()
+    b16 = measure_batch(mats16, shapes, steps, warmup, batched=True)
+    del mats16
+    torch.cuda.empty_cache()
+
+    def err(a, b):
+        return float(max(np.max(np.abs(x - y) / y) for x, y in zip(a["sigma"], b["sigma"])))
+    return {
+        "config": {"count": len(shapes), "elements": elems, "p": BATCH["p"], "q": BATCH["q"],
+                   "m_values": sorted({s[0] for s in shapes}), "n_range": [min(s[1] for s in shapes),
+                                                                           max(s[1] for s in shapes)],
+                   "r_values": sorted({s[2] for s in shapes}), "steps": steps},
+        "plain_fp32_sequential_ms": round(plain["ms"], 3),
+        "batched_fp32_ms": round(b32["ms"], 3),
+        "batched_bf16_ms": round(b16["ms"], 3),
+        "speedup_batched_fp32": round(plain["ms"] / b32["ms"], 2),
+        "speedup_batched_bf16": round(plain["ms"] / b16["ms"], 2),
+        "sigma_rel_diff_batched_fp32_vs_plain": err(b32, plain),
+        "sigma_rel_diff_batched_bf16_vs_plain": err(b16, plain),
+        "hbm_gbs_s_passes": {"plain_fp32": plain["hbm_gbs_s_passes"], "batched_fp32": b32["hbm_gbs_s_passes"],
+                             "batched_bf16": b16["hbm_gbs_s_passes"]},
+        "kernels": {"plain_fp32": plain["kernels"], "batched_fp32": b32["kernels"], "batched_bf16": b16["kernels"]},
+    }
 
 
 def cpu_baseline(St, w, seed):
@@ -190,6 +312,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-vs-plain measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batch measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the row-sharded multi-GPU "
@@ -235,6 +358,10 @@ def main():
             "mixed_kernels": mb["kernels"], "plain_roofline": pf["roofline"], "plain_kernels": pf["kernels"],
         }
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_block(dev, max(3, args.steps // 4), max(1, args.warmup // 2))
+
     res = {
         "metric": "rPOD time-to-r-modes",
         "value": round(main_res["ms"], 4),
@@ -252,10 +379,12 @@ def main():
                    "m": w.get("m", w.get("nx", 0) * w.get("ny", 0)), "n": w["n"],
                    "r": w["r"], "p": w["p"], "q": w["q"], "parallelism": "single GPU"},
         "hbm_gbs_s_passes": main_res["hbm_gbs_s_passes"],
+        "ms_graph_replay": round(main_res["ms_graph"], 4),
         "kernels": main_res["kernels"],
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
         "mixed_vs_plain": extra,
+        "batched_vs_plain": batch,
     }
     print(json.dumps(res), flush=True)
 

@@ -99,7 +99,12 @@ rpod_status rpod_workspace_size(const rpod_desc* desc, size_t* bytes);
 /* Create a plan bound to `hip_stream` (a hipStream_t; NULL = default stream).
  * `workspace` is a device buffer of at least rpod_workspace_size() bytes,
  * 256-byte aligned, owned by the caller and used exclusively by this plan
- * until rpod_plan_destroy(). The workspace is cleared on `hip_stream` here.
+ * until rpod_plan_destroy(). The workspace is cleared and the plan's launch
+ * program is uploaded into it on `hip_stream`; the call synchronises that
+ * stream. The whole launch sequence of a compute call is captured once here
+ * into a HIP graph (on private streams) that every compute call replays;
+ * environment variable RPOD_NO_GRAPH=1 makes compute calls launch the kernels
+ * one by one instead (same kernels, same results).
  * The plan object itself is host memory owned by the library. */
 rpod_status rpod_plan_create(rpod_plan* plan, const rpod_desc* desc,
                              void* workspace, size_t workspace_bytes, void* hip_stream);
@@ -110,7 +115,9 @@ rpod_status rpod_plan_destroy(rpod_plan plan);
 
 /* Randomized POD of S (Alg. 1 of Sec. 4.2 with re-orthonormalisation after
  * every product with S or S^T), enqueued on the plan's stream.
- *   S      device, m x n column-major, leading dimension desc.ld, desc.dtype.
+ *   S      device, m x n column-major, leading dimension desc.ld, desc.dtype;
+ *          16-byte aligned when ld is a multiple of 4 (FP64, FP32) or of 8
+ *          (BF16, FP16), else aligned to its element size.
  *   seed   selects the Gaussian sketch (rpod_generate_omega with this seed).
  *   Phi    device, m x r column-major (ld = m), output.
  *   sigma  device, r doubles, output, descending.
@@ -124,6 +131,37 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed,
  * Returns RPOD_EINVAL_DATA if RPOD_FLAG_NONFINITE is set, RPOD_EBREAKDOWN if
  * RPOD_FLAG_BREAKDOWN is set, RPOD_EHIP on a runtime error, else RPOD_OK. */
 rpod_status rpod_status_query(rpod_plan plan, int32_t* device_flags);
+
+/* Batches: several independent rPOD problems (Sec. 4.2 applied to each
+ * snapshot matrix) in one plan. Matrices may differ in m, n, ld, r and p;
+ * they must share dtype and q. Matrices whose padded sketch widths
+ * (roundup(r + p, 16)) and padded ranks (roundup(r, 16)) agree form a class;
+ * every step of Alg. 1 is one kernel launch per class, covering all its
+ * matrices (each launch walks a per-matrix table of arguments and workgroup
+ * offsets kept in the workspace), and the classes run as independent
+ * branches of the plan's graph. Results equal those of single plans for the
+ * same matrices and seeds, up to the row-split of the S^T Q products (the
+ * split count is chosen per matrix from the batch size, which changes the
+ * FP64 summation order of that product only).
+ *   descs  host, `count` descriptions, 1 <= count <= 4096.
+ * rpod_workspace_size_batched / rpod_plan_create_batched behave as their
+ * single-matrix counterparts (which are the count = 1 case). */
+rpod_status rpod_workspace_size_batched(const rpod_desc* descs, int32_t count, size_t* bytes);
+rpod_status rpod_plan_create_batched(rpod_plan* plan, const rpod_desc* descs, int32_t count,
+                                     void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Compute every matrix of a batched plan, enqueued on the plan's stream.
+ * S, seeds, Phi, sigma, A: host arrays of `count` entries (the plan's
+ * count), entry i being the argument of rpod_compute for matrix i (device
+ * pointers, same layout, alignment and ownership rules). Also accepts a
+ * plan of one matrix. */
+rpod_status rpod_compute_batched(rpod_plan plan, const void* const* S, const uint64_t* seeds,
+                                 void* const* Phi, double* const* sigma, void* const* A);
+
+/* As rpod_status_query for every matrix: per_matrix_flags (host, `count`
+ * entries, may be NULL) receives each matrix's status word; the return
+ * value reflects the OR of all of them. */
+rpod_status rpod_status_query_batched(rpod_plan plan, int32_t* per_matrix_flags);
 
 /* The Gaussian sketch of Alg. 1 step 1 (entries N(0,1), Sec. 4.2), drawn on
  * the GPU: out (device) receives the n x l matrix column-major with leading
@@ -155,7 +193,9 @@ rpod_status rpod_plan_set_timing(rpod_plan plan, int32_t enable);
  * pass kind (0 or 1): their number, summed duration in milliseconds, and the
  * algorithmic work of one launch: bytes = m n size(S) + n l size(S) + m l 4
  * (S once, the n x l operand once, the m x l result or operand once) and
- * flops = 2 m n l. Host pointers; any may be NULL. */
+ * flops = 2 m n l, summed over the matrices the launch covers (a batched
+ * plan times its classes' launches; timing replays the kernels one by one
+ * instead of the graph). Host pointers; any may be NULL. */
 rpod_status rpod_plan_get_timing(rpod_plan plan, int32_t pass, int64_t* launches, double* total_ms,
                                  double* bytes_per_launch, double* flops_per_launch);
 

@@ -16,7 +16,7 @@ import os
 
 import torch
 
-__all__ = ["RpodError", "Plan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
+__all__ = ["RpodError", "Plan", "BatchPlan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
            "STATUS", "FLAG_SHIFTED", "FLAG_BREAKDOWN", "FLAG_NONFINITE", "FLAG_JACOBI_SLOW"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -63,6 +63,11 @@ def lib():
             "rpod_plan_set_timing": [vp, i32],
             "rpod_plan_get_timing": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+            "rpod_workspace_size_batched": [ctypes.POINTER(_Desc), i32, ctypes.POINTER(ctypes.c_size_t)],
+            "rpod_plan_create_batched": [ctypes.POINTER(vp), ctypes.POINTER(_Desc), i32, vp, ctypes.c_size_t, vp],
+            "rpod_compute_batched": [vp, ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), ctypes.POINTER(vp)],
+            "rpod_status_query_batched": [vp, ctypes.POINTER(i32)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -101,58 +106,14 @@ def workspace_size(m, n, r, p, q, dtype, ld=None):
     return out.value
 
 
-class Plan:
-    """A plan for one matrix shape: rpod_plan_create / rpod_compute / rpod_status_query."""
+def workspace_size_batched(descs):
+    arr = (_Desc * len(descs))(*descs)
+    out = ctypes.c_size_t(0)
+    _check(lib().rpod_workspace_size_batched(arr, len(descs), ctypes.byref(out)))
+    return out.value
 
-    def __init__(self, m, n, r, p, q, dtype=torch.float32, ld=None, device="cuda", stream=None):
-        self.device = torch.device(device)
-        if self.device.type == "cuda" and self.device.index is None:
-            self.device = torch.device("cuda", torch.cuda.current_device())
-        self.m, self.n, self.r, self.p, self.q = int(m), int(n), int(r), int(p), int(q)
-        self.ld = self.m if ld is None else int(ld)
-        self.dtype = dtype
-        self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
-        self._desc = make_desc(m, n, r, p, q, dtype, ld)
-        nbytes = workspace_size(m, n, r, p, q, dtype, ld)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        sptr, self.stream = _stream_ptr(stream, self.device)
-        h = ctypes.c_void_p()
-        _check(lib().rpod_plan_create(ctypes.byref(h), ctypes.byref(self._desc), _dev_ptr(self.workspace),
-                                      nbytes, sptr))
-        self._h = h
 
-    def compute(self, St, seed, out=None, check=True):
-        """rPOD of the column-major S given as St (n, ld) -> (Phi_t (r, m), sigma (r,), A_t (n, r)).
-
-        With check=True the stream is synchronised and the device status
-        word is turned into an exception; check=False only enqueues.
-        """
-        if St.dtype != self.dtype or St.device != self.device:
-            raise TypeError("St must be a tensor of the plan's dtype on the plan's device")
-        if St.dim() != 2 or St.shape[0] != self.n or St.shape[1] < self.m:
-            raise ValueError(f"St must have shape ({self.n}, >= {self.m})")
-        if St.stride(1) != 1 or St.stride(0) != self.ld:
-            raise ValueError("St must be row-major with row stride equal to the plan's ld")
-        if out is None:
-            Phi = torch.empty((self.r, self.m), dtype=self.out_dtype, device=self.device)
-            sigma = torch.empty((self.r,), dtype=torch.float64, device=self.device)
-            A = torch.empty((self.n, self.r), dtype=self.out_dtype, device=self.device)
-        else:
-            Phi, sigma, A = out
-        _check(lib().rpod_compute(self._h, _dev_ptr(St), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
-                                  _dev_ptr(Phi), _dev_ptr(sigma), _dev_ptr(A)))
-        if check:
-            self.status()
-        return Phi, sigma, A
-
-    def status(self):
-        """Synchronise and return the device flags; raise on an error status."""
-        fl = ctypes.c_int32(0)
-        st = lib().rpod_status_query(self._h, ctypes.byref(fl))
-        self.last_flags = fl.value
-        _check(st)
-        return fl.value
-
+class _PlanBase:
     def set_timing(self, enable=True):
         """Record HIP events around every pass over S of later compute calls."""
         _check(lib().rpod_plan_set_timing(self._h, 1 if enable else 0))
@@ -175,6 +136,133 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _check_St(St, dtype, device, m, n, ld):
+    if St.dtype != dtype or St.device != device:
+        raise TypeError("St must be a tensor of the plan's dtype on the plan's device")
+    if St.dim() != 2 or St.shape[0] != n or St.shape[1] < m:
+        raise ValueError(f"St must have shape ({n}, >= {m})")
+    if St.stride(1) != 1 or St.stride(0) != ld:
+        raise ValueError("St must be row-major with row stride equal to the plan's ld")
+
+
+def _norm_device(device):
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
+class Plan(_PlanBase):
+    """A plan for one matrix shape: rpod_plan_create / rpod_compute / rpod_status_query."""
+
+    def __init__(self, m, n, r, p, q, dtype=torch.float32, ld=None, device="cuda", stream=None):
+        self.device = _norm_device(device)
+        self.m, self.n, self.r, self.p, self.q = int(m), int(n), int(r), int(p), int(q)
+        self.ld = self.m if ld is None else int(ld)
+        self.dtype = dtype
+        self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
+        self._desc = make_desc(m, n, r, p, q, dtype, ld)
+        nbytes = workspace_size(m, n, r, p, q, dtype, ld)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        sptr, self.stream = _stream_ptr(stream, self.device)
+        h = ctypes.c_void_p()
+        _check(lib().rpod_plan_create(ctypes.byref(h), ctypes.byref(self._desc), _dev_ptr(self.workspace),
+                                      nbytes, sptr))
+        self._h = h
+
+    def compute(self, St, seed, out=None, check=True):
+        """rPOD of the column-major S given as St (n, ld) -> (Phi_t (r, m), sigma (r,), A_t (n, r)).
+
+        With check=True the stream is synchronised and the device status
+        word is turned into an exception; check=False only enqueues.
+        """
+        _check_St(St, self.dtype, self.device, self.m, self.n, self.ld)
+        if out is None:
+            Phi = torch.empty((self.r, self.m), dtype=self.out_dtype, device=self.device)
+            sigma = torch.empty((self.r,), dtype=torch.float64, device=self.device)
+            A = torch.empty((self.n, self.r), dtype=self.out_dtype, device=self.device)
+        else:
+            Phi, sigma, A = out
+        _check(lib().rpod_compute(self._h, _dev_ptr(St), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                  _dev_ptr(Phi), _dev_ptr(sigma), _dev_ptr(A)))
+        if check:
+            self.status()
+        return Phi, sigma, A
+
+    def status(self):
+        """Synchronise and return the device flags; raise on an error status."""
+        fl = ctypes.c_int32(0)
+        st = lib().rpod_status_query(self._h, ctypes.byref(fl))
+        self.last_flags = fl.value
+        _check(st)
+        return fl.value
+
+
+
+class BatchPlan(_PlanBase):
+    """A plan for a batch of matrices: rpod_plan_create_batched / rpod_compute_batched.
+
+    shapes: list of (m, n, r, p) or (m, n, r, p, ld); all share dtype and q.
+    """
+
+    def __init__(self, shapes, q, dtype=torch.float32, device="cuda", stream=None):
+        self.device = _norm_device(device)
+        self.dtype = dtype
+        self.q = int(q)
+        self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
+        self.shapes = []
+        descs = []
+        for sh in shapes:
+            m, n, r, p = (int(x) for x in sh[:4])
+            ld = int(sh[4]) if len(sh) > 4 else m
+            self.shapes.append((m, n, r, p, ld))
+            descs.append(make_desc(m, n, r, p, q, dtype, ld))
+        self.count = len(descs)
+        self._descs = (_Desc * self.count)(*descs)
+        nbytes = workspace_size_batched(descs)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        sptr, self.stream = _stream_ptr(stream, self.device)
+        h = ctypes.c_void_p()
+        _check(lib().rpod_plan_create_batched(ctypes.byref(h), self._descs, self.count, _dev_ptr(self.workspace),
+                                              nbytes, sptr))
+        self._h = h
+
+    def alloc_outputs(self):
+        outs = []
+        for (m, n, r, _p, _ld) in self.shapes:
+            outs.append((torch.empty((r, m), dtype=self.out_dtype, device=self.device),
+                         torch.empty((r,), dtype=torch.float64, device=self.device),
+                         torch.empty((n, r), dtype=self.out_dtype, device=self.device)))
+        return outs
+
+    def compute(self, Sts, seeds, outs=None, check=True):
+        """rPOD of every matrix; Sts[i] is (n_i, ld_i). Returns a list of (Phi_t, sigma, A_t)."""
+        if len(Sts) != self.count or len(seeds) != self.count:
+            raise ValueError(f"expected {self.count} matrices and seeds")
+        for St, (m, n, _r, _p, ld) in zip(Sts, self.shapes):
+            _check_St(St, self.dtype, self.device, m, n, ld)
+        if outs is None:
+            outs = self.alloc_outputs()
+        vp = ctypes.c_void_p
+        S_arr = (vp * self.count)(*[St.data_ptr() for St in Sts])
+        seed_arr = (ctypes.c_uint64 * self.count)(*[int(s) & (2 ** 64 - 1) for s in seeds])
+        P_arr = (vp * self.count)(*[o[0].data_ptr() for o in outs])
+        s_arr = (vp * self.count)(*[o[1].data_ptr() for o in outs])
+        A_arr = (vp * self.count)(*[o[2].data_ptr() for o in outs])
+        _check(lib().rpod_compute_batched(self._h, S_arr, seed_arr, P_arr, s_arr, A_arr))
+        if check:
+            self.status()
+        return outs
+
+    def status(self):
+        """Synchronise; per-matrix device flags (list); raise on an error status."""
+        fl = (ctypes.c_int32 * self.count)()
+        st = lib().rpod_status_query_batched(self._h, fl)
+        self.last_flags = list(fl)
+        _check(st)
+        return list(fl)
 
 
 def rpod(St, r, p, q, seed, stream=None):

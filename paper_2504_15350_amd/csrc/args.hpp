@@ -1,0 +1,158 @@
+// Argument records of the grouped kernels (host and device).
+//
+// Every kernel is launched "grouped": one launch serves a group of matrices.
+// The launch receives a device array of per-matrix argument records and a
+// tile-offset table tstart[0..count]; workgroup b belongs to the matrix i with
+// tstart[i] <= b < tstart[i+1] and handles local tile b - tstart[i]. A single
+// matrix is a group of one. Per-call pointers (S, the outputs, the seed) live
+// in a call table written before every compute call; records that need them
+// say so (from_call) and carry the matrix's index into that table.
+#pragma once
+
+#include <stdint.h>
+
+namespace rpod {
+
+struct CallDesc {  // written per compute call
+    const void* S;
+    void* Phi;
+    double* sigma;
+    void* A;
+    uint64_t seed;
+};
+
+struct SxArgs {  // Y = S X
+    const void* S;
+    int64_t ldS, m, n;
+    const void* X;
+    int64_t ldX;
+    void* Y;
+    int64_t ldY, mstore;
+    const int* cond;
+    int cond_mask;
+    int call;  // >= 0: S comes from call table entry `call`
+};
+
+struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)
+    const void* S;
+    int64_t ldS, m, n;
+    const void* Q;   // FP32/FP64 Q, or the 16-bit hi part
+    const void* Ql;  // 16-bit lo part
+    int64_t ldQ;
+    double* Zp;
+    int64_t nP, split_rows;
+    int nsplit, ncb;
+    int call;
+};
+
+struct ReduceArgs {  // out = sum of nsplit slabs
+    const double* Zp;
+    int64_t count;
+    double* out;
+    int nsplit;
+};
+
+struct GramArgs {  // G = Y^T Y, FP64
+    const void* Y;
+    int64_t ld, M;
+    double* Gpart;
+    double* G;
+    const int* cond;
+    int cond_mask;
+    int nwg;
+};
+
+struct CholArgs {  // Cholesky + inverse
+    const double* G;
+    int64_t M;
+    double* R64;
+    float* R32;
+    int* flags;
+    int* local;
+    int l, lp, mode;
+};
+
+struct JacobiArgs {  // eigenvectors of the small Gram matrix
+    const double* G;
+    double* UB;
+    double* sig;
+    int* flags;
+    double tol;
+    int l, lp;
+};
+
+struct LiftArgs {  // M = Rinv UB[:, :r], Ur = UB[:, :r]
+    const double* Rinv;
+    const double* UB;
+    double* M64;
+    float* M32;
+    double* Ur;
+    int lp, r, rp;
+};
+
+struct ColmaxArgs {  // per-chunk argmax |Phi|
+    const void* Phi;
+    int64_t ld, m, chunk;
+    double* pval;
+    int64_t* pidx;
+    int r, nchunk;
+};
+
+struct SignArgs {
+    const double* pval;
+    const int64_t* pidx;
+    double* signs;
+    int r, nchunk;
+};
+
+struct FinArgs {  // outputs (Phi, A, sigma) from call table entry `call`
+    const void* Phi_int;
+    int64_t ldP, m;
+    const double* At;
+    int64_t ldA, n;
+    const double* signs;
+    const double* sig;
+    int r, call;
+};
+
+struct OmegaArgs {  // Gaussian sketch; seed from call table entry `call` (or `seed` if call < 0)
+    void* out;
+    int64_t n, rows_pad, ldo;
+    uint64_t seed;
+    int l, lpad, call;
+};
+
+struct SplitArgs {  // 16-bit hi/lo split
+    const float* Q;
+    int64_t count;
+    unsigned short* hi;
+    unsigned short* lo;
+};
+
+struct ZeroArgs {
+    int* p;
+    int count;
+};
+
+// Workgroup -> (item, local tile) for grouped launches.
+#ifdef __HIPCC__
+__device__ __forceinline__ int group_item(const int* tstart, int count, int b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {  // last i with tstart[i] <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if (tstart[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+#endif
+
+// One grouped launch as seen by a kernel.
+template <typename A>
+struct Group {
+    const A* args;
+    const int* tstart;
+    const CallDesc* calls;
+    int count;
+};
+
+}  // namespace rpod

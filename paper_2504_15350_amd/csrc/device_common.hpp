@@ -15,6 +15,13 @@ template <> struct vec4_of<_Float16> { typedef _Float16 type __attribute__((ext_
 
 // Narrowing used for every store into a 16-bit operand: through FP32, each
 // step rounding to nearest even.
+// Global-memory (address space 1) pointers. Operands reached through
+// argument records in memory are generic pointers to the compiler, which
+// would access them with flat instructions; the hot kernels convert them once.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gbl(T* p) { return (GLOBAL T*)p; }
+
 template <typename Tout, typename T>
 __device__ __forceinline__ Tout narrow(T x) { return (Tout)(float)x; }
 template <> __device__ __forceinline__ double narrow<double, double>(double x) { return x; }

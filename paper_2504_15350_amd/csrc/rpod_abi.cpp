@@ -1,10 +1,16 @@
-// C ABI of the randomized POD library: validation, workspace layout, plans
-// and the launch sequence of one rPOD call (Alg. 1 of Sec. 4.2).
+// C ABI of the randomized POD library: validation, workspace layout, the
+// recorded launch program of a plan (one matrix or a batch), its hipGraph,
+// and the entry points. The program is the launch sequence of one rPOD call
+// (Alg. 1 of Sec. 4.2), every launch grouped over the matrices of a class
+// (same padded sketch width, rank tiles and storage type).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -36,16 +42,18 @@ size_t dt_size(int dt) {
     }
 }
 
-// Everything the launch sequence needs, derived from the description.
+bool is16(int dt) { return dt == DT_BF16 || dt == DT_F16; }
+
+// Buffers and sizes of one matrix, derived from its description.
 struct Layout {
     int l, lp, nt, rp, ntr;
     int64_t mP, nP;
     int tin, tacc;
-    int nsplit;
+    int nsplit, ncb_lo;
     int64_t split_rows;
     int nchunk;
-    // byte offsets into the workspace
-    size_t o_flags, o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
+    // byte offsets into the matrix's workspace region
+    size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
     size_t total;
 };
@@ -67,7 +75,9 @@ rpod_status validate(const rpod_desc* d) {
     return RPOD_OK;
 }
 
-Layout make_layout(const rpod_desc* d) {
+// wg_target: workgroups wanted for one S^T Q pass of this matrix (the row
+// split count follows from it).
+Layout make_layout(const rpod_desc* d, int64_t wg_target) {
     Layout L{};
     L.l = d->r + d->p;
     L.lp = (int)roundup(L.l, 16);
@@ -76,21 +86,22 @@ Layout make_layout(const rpod_desc* d) {
     L.ntr = L.rp / 16;
     L.mP = roundup(d->m, 256);
     L.nP = roundup(d->n, 256);
-    L.tin = d->dtype == RPOD_F64 ? DT_F64 : d->dtype == RPOD_F32 ? DT_F32 : d->dtype == RPOD_BF16 ? DT_BF16 : DT_F16;
+    L.tin = d->dtype;  // rpod_dtype and the internal codes coincide
     L.tacc = d->dtype == RPOD_F64 ? DT_F64 : DT_F32;
-    // split-K over rows for S^T Q. FP32/FP64: ~1024 workgroups of 256
-    // columns, contiguous splits of >= 256 rows. 16-bit: ~4096 blocks of 128
-    // columns (up to 64 splits), splits interleaved in steps of R rows.
-    const bool s16k = d->dtype == RPOD_BF16 || d->dtype == RPOD_F16;
-    const int64_t ncb = s16k ? L.nP / 128 : L.nP / 256;
-    const int64_t target = s16k ? 4096 : 1024;
+    // split-K over rows for S^T Q. FP32/FP64: blocks of 256 columns and
+    // contiguous splits of >= 256 rows. 16-bit: blocks of 128 columns (256
+    // with the lo part), splits interleaved in steps of 128 rows.
+    const bool s16 = is16(L.tin);
+    const int64_t ncb = s16 ? L.nP / stq16_block_cols(false) : L.nP / 256;
+    const int64_t target = s16 ? wg_target : std::max<int64_t>(64, wg_target / 4);
     int64_t ns = (target + ncb - 1) / ncb;
     if (ns > 64) ns = 64;
-    const int64_t maxs = (d->m + (s16k ? 127 : 255)) / (s16k ? 128 : 256);
+    const int64_t maxs = s16 ? (d->m + 127) / 128 : (d->m + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
     L.split_rows = roundup((d->m + ns - 1) / ns, 64);
-    L.nsplit = s16k ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
+    L.nsplit = s16 ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
+    L.ncb_lo = (int)(L.nP / stq16_block_cols(true));
     int64_t nc = d->m / 2048;
     L.nchunk = (int)(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
 
@@ -102,11 +113,9 @@ Layout make_layout(const rpod_desc* d) {
         return o;
     };
     const size_t lp2 = (size_t)L.lp * L.lp;
-    L.o_flags = take(64 * sizeof(int));
     L.o_X = take((size_t)L.nP * L.lp * si);
     L.o_Y = take((size_t)L.mP * L.lp * sa);
     L.o_Q1 = take((size_t)L.mP * L.lp * sa);
-    const bool s16 = L.tin == DT_BF16 || L.tin == DT_F16;
     L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Ql = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Zp = take((size_t)L.nsplit * L.nP * L.lp * 8);
@@ -133,40 +142,88 @@ Layout make_layout(const rpod_desc* d) {
     return L;
 }
 
+// ---------------------------------------------------------------------------
+// Recorded program
+// ---------------------------------------------------------------------------
+enum Kind { K_ZERO, K_OMEGA, K_SX, K_SX16, K_STQ, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT, K_SIGNS,
+            K_FIN, K_SPLIT };
+
+struct Step {
+    Kind kind;
+    int tin = 0, tout = 0, nt = 0, lp = 0;
+    bool vec = true, upper = false, lo = false;
+    int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S (timed)
+    size_t a1 = 0, t1 = 0, a2 = 0, t2 = 0;  // program-blob offsets of the argument / tile tables
+    int count = 0, tiles1 = 0, tiles2 = 0;
+    double bytes = 0, flops = 0;  // algorithmic work of the launch (passes over S)
+};
+
+struct Item {
+    rpod_desc d;
+    Layout L;
+    size_t off;  // workspace offset of the matrix's region
+    int idx;     // index in the batch (call table, flags region)
+};
+
+struct Builder {
+    std::vector<char> blob;
+    size_t put(const void* p, size_t bytes) {
+        const size_t o = (size_t)roundup((int64_t)blob.size(), 16);
+        blob.resize(o + bytes);
+        std::memcpy(blob.data() + o, p, bytes);
+        return o;
+    }
+    template <typename A>
+    void add(Step& s, const std::vector<A>& args, const std::vector<int>& tiles, bool second = false) {
+        std::vector<int> ts(args.size() + 1, 0);
+        for (size_t i = 0; i < args.size(); ++i) ts[i + 1] = ts[i] + tiles[i];
+        const size_t ao = put(args.data(), sizeof(A) * args.size());
+        const size_t to = put(ts.data(), sizeof(int) * ts.size());
+        s.count = (int)args.size();
+        if (!second) {
+            s.a1 = ao; s.t1 = to; s.tiles1 = ts.back();
+        } else {
+            s.a2 = ao; s.t2 = to; s.tiles2 = ts.back();
+        }
+    }
+};
+
+constexpr int FLAG_INTS = 64;  // status words per matrix (0: status, 1: orthonormalisation-local)
+
 }  // namespace
 
 struct rpod_plan_s {
-    rpod_desc d;
-    Layout L;
-    char* ws;
-    hipStream_t st;
+    std::vector<Item> items;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t st = nullptr;
+    size_t o_flags = 0, o_calls = 0, o_prog = 0;
+    std::vector<std::vector<Step>> programs;  // one per class
+    // graph of the whole program
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
     // per-pass event timing (measurement only)
     bool timing = false;
-    std::vector<hipEvent_t> ev[2];  // start/stop pairs, reused across resets
+    std::vector<hipEvent_t> ev[2];
+    std::vector<double> evbytes[2], evflops[2];
     size_t used[2] = {0, 0};
+    std::vector<CallDesc> host_calls;
+
+    int* flags(const Item& it) const { return reinterpret_cast<int*>(ws + o_flags) + FLAG_INTS * it.idx; }
     template <typename T>
-    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-};
-
-namespace {
-
-// Record the start (begin=true) or stop event of one pass over S.
-hipError_t mark(rpod_plan_s* P, int kind, bool begin) {
-    if (!P->timing) return hipSuccess;
-    std::vector<hipEvent_t>& v = P->ev[kind];
-    const size_t idx = begin ? 2 * P->used[kind] : 2 * P->used[kind] + 1;
-    if (idx >= v.size()) {
-        hipEvent_t e;
-        hipError_t err = hipEventCreate(&e);
-        if (err != hipSuccess) return err;
-        v.push_back(e);
+    T* at(const Item& it, size_t off) const { return reinterpret_cast<T*>(ws + it.off + off); }
+    CallDesc* calls() const { return reinterpret_cast<CallDesc*>(ws + o_calls); }
+    template <typename A>
+    GroupLaunch<A> gl(const Step& s, bool second) const {
+        GroupLaunch<A> g;
+        g.args = reinterpret_cast<const A*>(ws + o_prog + (second ? s.a2 : s.a1));
+        g.tstart = reinterpret_cast<const int*>(ws + o_prog + (second ? s.t2 : s.t1));
+        g.calls = calls();
+        g.count = s.count;
+        g.tiles = second ? s.tiles2 : s.tiles1;
+        return g;
     }
-    hipError_t err = hipEventRecord(v[idx], P->st);
-    if (!begin) ++P->used[kind];
-    return err;
-}
-
-}  // namespace
+};
 
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
@@ -176,57 +233,540 @@ hipError_t mark(rpod_plan_s* P, int kind, bool begin) {
 
 namespace {
 
-// CholeskyQR2 of a tall matrix In (rows M, leading dim ld, type dt) into Out:
-// Out = In R1^-1 is written, the final factor R2^-1 (or R3^-1 after the
-// shifted retry) is left in R64[k]/R32[k] so that Q = Out R^-1 implicitly.
-// If the first Cholesky needed a shift, a third pass Out <- Out R2^-1 runs
-// (shifted CholeskyQR3, Fukaya et al., SISC 2020).
-rpod_status orth(const rpod_plan_s* P, int dt, const void* In, void* Out, int64_t ld, int64_t M, int kfin) {
-    const Layout& L = P->L;
-    int* flags = P->at<int>(L.o_flags);
-    int* local = flags + 1;
-    double* Gp = P->at<double>(L.o_Gpart);
-    double* G = P->at<double>(L.o_G);
-    double* R64a = P->at<double>(L.o_R64[0]);
-    float* R32a = P->at<float>(L.o_R32[0]);
-    double* R64f = P->at<double>(L.o_R64[kfin]);
-    float* R32f = P->at<float>(L.o_R32[kfin]);
-    const void* Ra = dt == DT_F64 ? (const void*)R64a : (const void*)R32a;
-    const void* Rf = dt == DT_F64 ? (const void*)R64f : (const void*)R32f;
-    HIP_TRY(launch_gram(dt, L.nt, In, ld, M, Gp, G, nullptr, 0, P->st));
-    HIP_TRY(launch_chol_inv(G, L.l, L.lp, M, R64a, R32a, flags, local, 0, P->st));
-    HIP_TRY(launch_sx(dt, dt, L.nt, In, ld, M, L.lp, Ra, L.lp, Out, ld, ld, nullptr, 0, P->st, true));
-    HIP_TRY(launch_gram(dt, L.nt, Out, ld, M, Gp, G, nullptr, 0, P->st));
-    HIP_TRY(launch_chol_inv(G, L.l, L.lp, M, R64f, R32f, flags, local, 1, P->st));
-    // shifted retry: Out <- Out R^-1 in place, then re-factor (no-ops unless flagged)
-    HIP_TRY(launch_sx(dt, dt, L.nt, Out, ld, M, L.lp, Rf, L.lp, Out, ld, ld, local, 0x1, P->st, true));
-    HIP_TRY(launch_gram(dt, L.nt, Out, ld, M, Gp, G, local, 0x1, P->st));
-    HIP_TRY(launch_chol_inv(G, L.l, L.lp, M, R64f, R32f, flags, local, 2, P->st));
+// ---------------------------------------------------------------------------
+// Recording one class (matrices sharing lp, rp, the storage type and q)
+// ---------------------------------------------------------------------------
+struct Recorder {
+    const rpod_plan_s* P;
+    Builder& B;
+    std::vector<const Item*> C;
+    std::vector<Step>& out;
+    const Layout& L0() const { return C[0]->L; }
+
+    template <typename F>
+    auto each(F f) -> std::vector<decltype(f(*C[0]))> {
+        std::vector<decltype(f(*C[0]))> v;
+        for (const Item* it : C) v.push_back(f(*it));
+        return v;
+    }
+    template <typename F>
+    std::vector<int> tiles(F f) {
+        std::vector<int> v;
+        for (const Item* it : C) v.push_back(f(*it));
+        return v;
+    }
+
+    void zero() {
+        Step s{K_ZERO};
+        B.add(s, each([&](const Item& it) { return ZeroArgs{P->flags(it), FLAG_INTS}; }),
+              tiles([](const Item&) { return 1; }));
+        out.push_back(s);
+    }
+    void omega() {
+        Step s{K_OMEGA};
+        s.tout = L0().tin;
+        B.add(s, each([&](const Item& it) {
+                  OmegaArgs a{};
+                  a.out = P->at<char>(it, it.L.o_X);
+                  a.n = it.d.n; a.rows_pad = it.L.nP; a.ldo = it.L.nP;
+                  a.seed = 0; a.l = it.L.l; a.lpad = it.L.lp; a.call = it.idx;
+                  return a;
+              }),
+              tiles([](const Item& it) { return (int)((it.L.nP + 255) / 256) * ((it.L.lp + 1) / 2); }));
+        out.push_back(s);
+    }
+    // generic tall x small product (internal operands)
+    void sx(int tin, int tout, int nt, bool upper, std::vector<SxArgs> args) {
+        Step s{K_SX};
+        s.tin = tin; s.tout = tout; s.nt = nt; s.upper = upper; s.vec = true;
+        std::vector<int> t;
+        for (const SxArgs& a : args) t.push_back((int)((std::max(a.mstore, a.m) + 255) / 256));
+        B.add(s, args, t);
+        out.push_back(s);
+    }
+    // pass over S: Y = S X
+    void pass_sx() {
+        const bool s16 = is16(L0().tin);
+        Step s{s16 ? K_SX16 : K_SX};
+        s.tin = L0().tin; s.tout = L0().tacc; s.nt = L0().nt; s.pass = 0;
+        s.vec = true;
+        for (const Item* it : C) {
+            s.vec = s.vec && (it->d.ld % (s16 ? 8 : 4) == 0);
+            const double sz = (double)dt_size(it->L.tin);
+            s.bytes += (double)it->d.m * it->d.n * sz + (double)it->d.n * it->L.l * sz + (double)it->d.m * it->L.l * 4.0;
+            s.flops += 2.0 * it->d.m * it->d.n * it->L.l;
+        }
+        std::vector<SxArgs> args = each([&](const Item& it) {
+            return SxArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, it.L.o_X), it.L.nP,
+                          P->at<char>(it, it.L.o_Y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
+        });
+        B.add(s, args, tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
+        out.push_back(s);
+    }
+    // pass over S: slabs of S^T Q1 (lo: Q1 carried as hi + lo on 16-bit paths), then their sum Zt
+    void pass_stq(bool lo) {
+        const bool s16 = is16(L0().tin);
+        Step s{s16 ? K_STQ16 : K_STQ};
+        s.tin = L0().tin; s.nt = L0().nt; s.pass = 1; s.lo = s16 && lo;
+        s.vec = true;
+        for (const Item* it : C) {
+            s.vec = s.vec && (it->d.ld % (s16 ? 8 : 4) == 0);
+            const double sz = (double)dt_size(it->L.tin);
+            s.bytes += (double)it->d.m * it->d.n * sz + (double)it->d.n * it->L.l * sz + (double)it->d.m * it->L.l * 4.0;
+            s.flops += 2.0 * it->d.m * it->d.n * it->L.l;
+        }
+        std::vector<StqArgs> args = each([&](const Item& it) {
+            StqArgs a{};
+            a.S = nullptr; a.ldS = it.d.ld; a.m = it.d.m; a.n = it.d.n;
+            a.Q = s16 ? (const void*)P->at<char>(it, it.L.o_Qh) : (const void*)P->at<char>(it, it.L.o_Q1);
+            a.Ql = s16 ? (const void*)P->at<char>(it, it.L.o_Ql) : nullptr;
+            a.ldQ = it.L.mP; a.Zp = P->at<double>(it, it.L.o_Zp); a.nP = it.L.nP;
+            a.split_rows = it.L.split_rows; a.nsplit = it.L.nsplit;
+            a.ncb = s16 ? (int)(it.L.nP / stq16_block_cols(s.lo)) : (int)(it.L.nP / 256);
+            a.call = it.idx;
+            return a;
+        });
+        std::vector<int> t;
+        for (const StqArgs& a : args) t.push_back(a.ncb * a.nsplit);
+        B.add(s, args, t);
+        out.push_back(s);
+        Step r{K_REDUCE};
+        B.add(r, each([&](const Item& it) {
+                  return ReduceArgs{P->at<double>(it, it.L.o_Zp), it.L.nP * it.L.lp, P->at<double>(it, it.L.o_Zt),
+                                    it.L.nsplit};
+              }),
+              tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
+        out.push_back(r);
+    }
+    void gram(int dt, std::vector<GramArgs> args) {
+        Step s{K_GRAM};
+        s.tin = dt; s.nt = L0().nt;
+        std::vector<int> t1, t2;
+        for (const GramArgs& a : args) {
+            t1.push_back(gram_tiles(s.nt, a.nwg));
+            t2.push_back(gram_reduce_tiles(s.nt));
+        }
+        B.add(s, args, t1);
+        B.add(s, args, t2, true);
+        out.push_back(s);
+    }
+    void chol(std::vector<CholArgs> args) {
+        Step s{K_CHOL};
+        B.add(s, args, std::vector<int>(args.size(), 1));
+        out.push_back(s);
+    }
+    // CholeskyQR2 of the tall In (ld, M rows, type dt) into Out; the final
+    // factor R^-1 is left in R[kfin] so that Q = Out R^-1. Shifted CholeskyQR3
+    // (Fukaya et al., SISC 2020) after a shifted first factorisation.
+    void orth_tall(int kfin) {
+        const int dt = L0().tacc;
+        auto In = [&](const Item& it) { return (void*)P->at<char>(it, it.L.o_Y); };
+        auto Out = [&](const Item& it) { return (void*)P->at<char>(it, it.L.o_Q1); };
+        auto Rx = [&](const Item& it, int k) {
+            return dt == DT_F64 ? (const void*)P->at<char>(it, it.L.o_R64[k]) : (const void*)P->at<char>(it, it.L.o_R32[k]);
+        };
+        auto gargs = [&](auto buf, bool cond) {
+            return each([&](const Item& it) {
+                return GramArgs{buf(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m)};
+            });
+        };
+        auto cargs = [&](int k, int mode) {
+            return each([&](const Item& it) {
+                return CholArgs{P->at<double>(it, it.L.o_G), it.d.m, P->at<double>(it, it.L.o_R64[k]),
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+            });
+        };
+        auto apply = [&](auto src, auto dst, int k, bool cond) {
+            return each([&](const Item& it) {
+                return SxArgs{src(it), it.L.mP, it.d.m, it.L.lp, Rx(it, k), it.L.lp, dst(it), it.L.mP, it.L.mP,
+                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+            });
+        };
+        gram(dt, gargs(In, false));
+        chol(cargs(0, 0));
+        sx(dt, dt, L0().nt, true, apply(In, Out, 0, false));
+        gram(dt, gargs(Out, false));
+        chol(cargs(kfin, 1));
+        sx(dt, dt, L0().nt, true, apply(Out, Out, kfin, true));  // shifted retry, in place (no-op otherwise)
+        gram(dt, gargs(Out, true));
+        chol(cargs(kfin, 2));
+        if (is16(L0().tin)) {
+            Step s{K_SPLIT};
+            s.tin = L0().tin;
+            B.add(s, each([&](const Item& it) {
+                      return SplitArgs{P->at<float>(it, it.L.o_Q1), it.L.mP * it.L.lp,
+                                       P->at<unsigned short>(it, it.L.o_Qh), P->at<unsigned short>(it, it.L.o_Ql)};
+                  }),
+                  tiles([](const Item& it) { return (int)((it.L.mP * it.L.lp / 4 + 255) / 256); }));
+            out.push_back(s);
+        }
+    }
+    // Zw = Zt R^-1 (R from the last tall orthonormalisation): Zw = S^T Q
+    void small_from_slabs() {
+        sx(DT_F64, DT_F64, L0().nt, true, each([&](const Item& it) {
+               return SxArgs{P->at<char>(it, it.L.o_Zt), it.L.nP, it.d.n, it.L.lp, P->at<char>(it, it.L.o_R64[1]),
+                             it.L.lp, P->at<char>(it, it.L.o_Zw), it.L.nP, it.L.nP, nullptr, 0, -1};
+           }));
+    }
+    // Basis X of the n x l iterate Zw for the next product with S: one
+    // CholeskyQR, X = Zw R^-1 (only its span matters; the CholeskyQR2 of the
+    // next S X restores orthonormality); a second step after a shift.
+    void basis_small() {
+        const int tin = L0().tin;
+        auto gargs = [&](bool second, bool cond) {
+            return each([&](const Item& it) {
+                return GramArgs{P->at<char>(it, second ? it.L.o_Zw2 : it.L.o_Zw), it.L.nP, it.d.n,
+                                P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.n)};
+            });
+        };
+        auto app = [&](size_t Layout::*src, size_t Layout::*dst, int k, bool cond) {
+            return each([&](const Item& it) {
+                return SxArgs{P->at<char>(it, it.L.*src), it.L.nP, it.d.n, it.L.lp, P->at<char>(it, it.L.o_R64[k]),
+                              it.L.lp, P->at<char>(it, it.L.*dst), it.L.nP, it.L.nP, cond ? P->flags(it) + 1 : nullptr,
+                              cond ? 1 : 0, -1};
+            });
+        };
+        auto cargs = [&](int k, int mode) {
+            return each([&](const Item& it) {
+                return CholArgs{P->at<double>(it, it.L.o_G), it.d.n, P->at<double>(it, it.L.o_R64[k]),
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+            });
+        };
+        gram(DT_F64, gargs(false, false));
+        chol(cargs(0, 0));
+        sx(DT_F64, tin, L0().nt, true, app(&Layout::o_Zw, &Layout::o_X, 0, false));
+        sx(DT_F64, DT_F64, L0().nt, true, app(&Layout::o_Zw, &Layout::o_Zw2, 0, true));
+        gram(DT_F64, gargs(true, true));
+        chol(cargs(2, 2));
+        sx(DT_F64, tin, L0().nt, true, app(&Layout::o_Zw2, &Layout::o_X, 2, true));
+    }
+    void finish() {
+        const Layout& L = L0();
+        // step 6: SVD of T through the eigenvectors of T T^T
+        gram(DT_F64, each([&](const Item& it) {
+                 return GramArgs{P->at<char>(it, it.L.o_Zw), it.L.nP, it.d.n, P->at<double>(it, it.L.o_Gpart),
+                                 P->at<double>(it, it.L.o_G), nullptr, 0, gram_nwg(it.d.n)};
+             }));
+        Step j{K_JACOBI};
+        j.lp = L.lp;
+        // rotation threshold: FP64 rounding level on the FP64 path; elsewhere far
+        // below the FP32 storage error of Q, which bounds the result anyway
+        const double jtol = L.tacc == DT_F64 ? (double)L.lp * 0x1.0p-53 : 1e-10;
+        B.add(j, each([&](const Item& it) {
+                  return JacobiArgs{P->at<double>(it, it.L.o_G), P->at<double>(it, it.L.o_UB),
+                                    P->at<double>(it, it.L.o_sig), P->flags(it), jtol, it.L.l, it.L.lp};
+              }),
+              tiles([](const Item&) { return 1; }));
+        out.push_back(j);
+        // step 7: Phi = Q U_hat[:, :r] = Q1 (R^-1 U_hat[:, :r]); A = U_hat_r^T T
+        Step lf{K_LIFT};
+        B.add(lf, each([&](const Item& it) {
+                  return LiftArgs{P->at<double>(it, it.L.o_R64[1]), P->at<double>(it, it.L.o_UB),
+                                  P->at<double>(it, it.L.o_M64), P->at<float>(it, it.L.o_M32),
+                                  P->at<double>(it, it.L.o_Ur), it.L.lp, it.d.r, it.L.rp};
+              }),
+              tiles([](const Item& it) { return (it.L.lp * it.L.rp + 255) / 256; }));
+        out.push_back(lf);
+        sx(L.tacc, L.tacc, L.ntr, false, each([&](const Item& it) {
+               const void* Mx = it.L.tacc == DT_F64 ? (const void*)P->at<char>(it, it.L.o_M64)
+                                                    : (const void*)P->at<char>(it, it.L.o_M32);
+               return SxArgs{P->at<char>(it, it.L.o_Q1), it.L.mP, it.d.m, it.L.lp, Mx, it.L.lp,
+                             P->at<char>(it, it.L.o_Phi), it.L.mP, it.L.mP, nullptr, 0, -1};
+           }));
+        sx(DT_F64, DT_F64, L.ntr, false, each([&](const Item& it) {
+               return SxArgs{P->at<char>(it, it.L.o_Zw), it.L.nP, it.d.n, it.L.lp, P->at<char>(it, it.L.o_Ur), it.L.lp,
+                             P->at<char>(it, it.L.o_At), it.L.nP, it.L.nP, nullptr, 0, -1};
+           }));
+        // sign convention and outputs
+        Step sg{K_SIGNS};
+        sg.tin = L.tacc;
+        B.add(sg, each([&](const Item& it) {
+                  return ColmaxArgs{P->at<char>(it, it.L.o_Phi), it.L.mP, it.d.m,
+                                    (it.d.m + it.L.nchunk - 1) / it.L.nchunk, P->at<double>(it, it.L.o_pval),
+                                    P->at<int64_t>(it, it.L.o_pidx), it.d.r, it.L.nchunk};
+              }),
+              tiles([](const Item& it) { return it.L.nchunk * it.d.r; }));
+        B.add(sg, each([&](const Item& it) {
+                  return SignArgs{P->at<double>(it, it.L.o_pval), P->at<int64_t>(it, it.L.o_pidx),
+                                  P->at<double>(it, it.L.o_signs), it.d.r, it.L.nchunk};
+              }),
+              tiles([](const Item& it) { return (it.d.r + 63) / 64; }), true);
+        out.push_back(sg);
+        Step fn{K_FIN};
+        fn.tin = L.tacc;
+        auto fargs = each([&](const Item& it) {
+            return FinArgs{P->at<char>(it, it.L.o_Phi), it.L.mP, it.d.m, P->at<double>(it, it.L.o_At), it.L.nP,
+                           it.d.n, P->at<double>(it, it.L.o_signs), P->at<double>(it, it.L.o_sig), it.d.r, it.idx};
+        });
+        B.add(fn, fargs, tiles([](const Item& it) { return fin_phi_tiles(it.d.m, it.d.r); }));
+        B.add(fn, fargs, tiles([](const Item& it) { return fin_a_tiles(it.d.n, it.d.r); }), true);
+        out.push_back(fn);
+    }
+    void record() {
+        zero();
+        omega();         // Alg. 1 step 1
+        pass_sx();       // step 2
+        orth_tall(1);    // step 4 (Q of the sketch)
+        for (int it = 0; it < C[0]->d.q; ++it) {  // step 3, re-orthonormalised after every product
+            pass_stq(false);
+            small_from_slabs();
+            basis_small();
+            pass_sx();
+            orth_tall(1);
+        }
+        pass_stq(true);  // step 5 (refinement on 16-bit paths)
+        small_from_slabs();
+        finish();        // steps 6, 7 and the coefficients
+    }
+};
+
+// Classes: matrices sharing the kernel template parameters of every step.
+std::vector<std::vector<const Item*>> classes_of(const std::vector<Item>& items) {
+    std::map<std::pair<int, int>, std::vector<const Item*>> m;
+    for (const Item& it : items) m[{it.L.nt, it.L.ntr}].push_back(&it);
+    std::vector<std::vector<const Item*>> out;
+    for (auto& kv : m) out.push_back(kv.second);
+    return out;
+}
+
+hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
+    switch (s.kind) {
+        case K_ZERO: return launch_zero_ints(P->gl<ZeroArgs>(s, false), st);
+        case K_OMEGA: return launch_omega(s.tout, P->gl<OmegaArgs>(s, false), st);
+        case K_SX: return launch_sx(s.tin, s.tout, s.nt, s.vec, s.upper, P->gl<SxArgs>(s, false), st);
+        case K_SX16: return launch_sx16(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
+        case K_STQ: return launch_stq(s.tin, s.nt, s.vec, P->gl<StqArgs>(s, false), st);
+        case K_STQ16: return launch_stq16(s.tin, s.nt, s.lo, s.vec, P->gl<StqArgs>(s, false), st);
+        case K_REDUCE: return launch_reduce_slabs(P->gl<ReduceArgs>(s, false), st);
+        case K_GRAM: return launch_gram(s.tin, s.nt, P->gl<GramArgs>(s, false), P->gl<GramArgs>(s, true), st);
+        case K_CHOL: return launch_chol_inv(P->gl<CholArgs>(s, false), st);
+        case K_JACOBI: return launch_jacobi(s.lp, P->gl<JacobiArgs>(s, false), st);
+        case K_LIFT: return launch_lift_coef(P->gl<LiftArgs>(s, false), st);
+        case K_SIGNS: return launch_signs(s.tin, P->gl<ColmaxArgs>(s, false), P->gl<SignArgs>(s, true), st);
+        case K_FIN: return launch_finalize(s.tin, P->gl<FinArgs>(s, false), P->gl<FinArgs>(s, true), st);
+        case K_SPLIT: return launch_split16(s.tin, P->gl<SplitArgs>(s, false), st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Record the start (begin=true) or stop event of one pass over S.
+hipError_t mark(rpod_plan_s* P, const Step& s, bool begin, hipStream_t st) {
+    if (!P->timing || s.pass < 0) return hipSuccess;
+    const int kind = s.pass;
+    std::vector<hipEvent_t>& v = P->ev[kind];
+    const size_t idx = begin ? 2 * P->used[kind] : 2 * P->used[kind] + 1;
+    if (idx >= v.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        v.push_back(e);
+    }
+    hipError_t err = hipEventRecord(v[idx], st);
+    if (!begin) {
+        if (P->evbytes[kind].size() <= P->used[kind]) {
+            P->evbytes[kind].push_back(0);
+            P->evflops[kind].push_back(0);
+        }
+        P->evbytes[kind][P->used[kind]] = s.bytes;
+        P->evflops[kind][P->used[kind]] = s.flops;
+        ++P->used[kind];
+    }
+    return err;
+}
+
+hipError_t replay(rpod_plan_s* P, hipStream_t st) {
+    for (const std::vector<Step>& prog : P->programs)
+        for (const Step& s : prog) {
+            hipError_t e = mark(P, s, true, st);
+            if (e == hipSuccess) e = run_step(P, s, st);
+            if (e == hipSuccess) e = mark(P, s, false, st);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+// Capture the whole program into a hipGraph on private streams, one branch per
+// class (branches are independent).
+hipError_t capture(rpod_plan_s* P) {
+    hipStream_t cs = nullptr;
+    std::vector<hipStream_t> fs;
+    std::vector<hipEvent_t> evs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    const size_t nb = P->programs.size();
+    for (size_t k = 0; e == hipSuccess && k < nb; ++k) {
+        hipStream_t s;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) fs.push_back(s);
+    }
+    for (size_t k = 0; e == hipSuccess && k < nb + 1; ++k) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) evs.push_back(ev);
+    }
+    bool capturing = false;
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) capturing = true;
+    if (e == hipSuccess) e = hipEventRecord(evs[nb], cs);
+    for (size_t k = 0; e == hipSuccess && k < nb; ++k) {
+        e = hipStreamWaitEvent(fs[k], evs[nb], 0);
+        for (size_t i = 0; e == hipSuccess && i < P->programs[k].size(); ++i) e = run_step(P, P->programs[k][i], fs[k]);
+        if (e == hipSuccess) e = hipEventRecord(evs[k], fs[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, evs[k], 0);
+    }
+    if (capturing) {
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) P->graph = g;
+        else if (g) (void)hipGraphDestroy(g);
+    }
+    for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+    for (hipStream_t s : fs) (void)hipStreamDestroy(s);
+    if (cs) (void)hipStreamDestroy(cs);
+    return e;
+}
+
+// Layout of a batch: flags, call table, matrix regions, then the program.
+struct BatchLayout {
+    std::vector<Item> items;
+    size_t o_flags, o_calls, o_items_end;
+};
+
+rpod_status batch_layout(const rpod_desc* descs, int32_t count, BatchLayout& bl) {
+    if (descs == nullptr) return fail(RPOD_EINVAL, "descs is NULL");
+    if (count < 1 || count > 4096) return fail(RPOD_EINVAL, "count must be in [1, 4096] (got %d)", count);
+    for (int i = 0; i < count; ++i) {
+        rpod_status s = validate(&descs[i]);
+        if (s != RPOD_OK) return s;
+        if (descs[i].dtype != descs[0].dtype) return fail(RPOD_EINVAL, "all matrices of a batch must share dtype");
+        if (descs[i].q != descs[0].q) return fail(RPOD_EINVAL, "all matrices of a batch must share q");
+    }
+    const int64_t wg = count == 1 ? 4096 : std::max<int64_t>(256, 8192 / count);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    bl.o_flags = take((size_t)count * FLAG_INTS * sizeof(int));
+    bl.o_calls = take((size_t)count * sizeof(CallDesc));
+    bl.items.clear();
+    for (int i = 0; i < count; ++i) {
+        Item it;
+        it.d = descs[i];
+        it.L = make_layout(&descs[i], wg);
+        it.off = take(it.L.total);
+        it.idx = i;
+        bl.items.push_back(it);
+    }
+    bl.o_items_end = off;
     return RPOD_OK;
 }
 
-// Basis of the n x l iterate Zw (FP64) for the next product with S, written
-// to X in the S type: one CholeskyQR, X = Zw R^-1 (only the span matters
-// here; the orthonormality that the method needs is restored by the
-// CholeskyQR2 of the next S X). After a shifted factorisation a second
-// CholeskyQR step runs (no-ops otherwise).
-rpod_status basis_small(const rpod_plan_s* P, double* Zw, double* Zw2, void* X) {
-    const Layout& L = P->L;
-    int* flags = P->at<int>(L.o_flags);
-    int* local = flags + 1;
-    double* Gp = P->at<double>(L.o_Gpart);
-    double* G = P->at<double>(L.o_G);
-    double* Ra = P->at<double>(L.o_R64[0]);
-    double* Rb = P->at<double>(L.o_R64[2]);
-    hipStream_t st = P->st;
-    HIP_TRY(launch_gram(DT_F64, L.nt, Zw, L.nP, P->d.n, Gp, G, nullptr, 0, st));
-    HIP_TRY(launch_chol_inv(G, L.l, L.lp, P->d.n, Ra, P->at<float>(L.o_R32[0]), flags, local, 0, st));
-    HIP_TRY(launch_sx(DT_F64, L.tin, L.nt, Zw, L.nP, P->d.n, L.lp, Ra, L.lp, X, L.nP, L.nP, nullptr, 0, st, true));
-    // after a shift: Zw2 = Zw Ra^-1, refactor, X = Zw2 Rb^-1
-    HIP_TRY(launch_sx(DT_F64, DT_F64, L.nt, Zw, L.nP, P->d.n, L.lp, Ra, L.lp, Zw2, L.nP, L.nP, local, 0x1, st, true));
-    HIP_TRY(launch_gram(DT_F64, L.nt, Zw2, L.nP, P->d.n, Gp, G, local, 0x1, st));
-    HIP_TRY(launch_chol_inv(G, L.l, L.lp, P->d.n, Rb, P->at<float>(L.o_R32[2]), flags, local, 2, st));
-    HIP_TRY(launch_sx(DT_F64, L.tin, L.nt, Zw2, L.nP, P->d.n, L.lp, Rb, L.lp, X, L.nP, L.nP, local, 0x1, st, true));
+// Record every class; returns the program blob.
+std::vector<char> record_all(rpod_plan_s* P) {
+    Builder B;
+    P->programs.clear();
+    for (const std::vector<const Item*>& cls : classes_of(P->items)) {
+        P->programs.emplace_back();
+        Recorder R{P, B, cls, P->programs.back()};
+        R.record();
+    }
+    return B.blob;
+}
+
+rpod_status workspace_bytes(const rpod_desc* descs, int32_t count, size_t* bytes) {
+    BatchLayout bl;
+    rpod_status s = batch_layout(descs, count, bl);
+    if (s != RPOD_OK) return s;
+    rpod_plan_s tmp;
+    tmp.items = bl.items;
+    tmp.o_flags = bl.o_flags;
+    tmp.o_calls = bl.o_calls;
+    tmp.o_prog = bl.o_items_end;
+    const std::vector<char> blob = record_all(&tmp);
+    *bytes = bl.o_items_end + (blob.size() + 255) / 256 * 256;
+    return RPOD_OK;
+}
+
+void destroy_plan(rpod_plan_s* P) {
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    for (int k = 0; k < 2; ++k)
+        for (hipEvent_t ev : P->ev[k]) (void)hipEventDestroy(ev);
+    delete P;
+}
+
+rpod_status create_plan(rpod_plan* plan, const rpod_desc* descs, int32_t count, void* workspace, size_t ws_bytes,
+                        void* hip_stream) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    BatchLayout bl;
+    rpod_status s = batch_layout(descs, count, bl);
+    if (s != RPOD_OK) return s;
+    if (workspace == nullptr) return fail(RPOD_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256 != 0) return fail(RPOD_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    s = workspace_bytes(descs, count, &need);
+    if (s != RPOD_OK) return s;
+    if (ws_bytes < need) return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    rpod_plan_s* P = new (std::nothrow) rpod_plan_s;
+    if (P == nullptr) return fail(RPOD_ENOMEM, "host allocation of the plan failed");
+    P->items = bl.items;
+    P->ws = static_cast<char*>(workspace);
+    P->ws_bytes = ws_bytes;
+    P->st = static_cast<hipStream_t>(hip_stream);
+    P->o_flags = bl.o_flags;
+    P->o_calls = bl.o_calls;
+    P->o_prog = bl.o_items_end;
+    P->host_calls.resize(count);
+    const std::vector<char> blob = record_all(P);
+    hipError_t e = hipMemsetAsync(workspace, 0, need, P->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->ws + P->o_prog, blob.data(), blob.size(), hipMemcpyHostToDevice, P->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->st);  // the blob is host memory of this frame
+    if (e != hipSuccess) {
+        destroy_plan(P);
+        return fail(RPOD_EHIP, "initialising the workspace failed: %s", hipGetErrorString(e));
+    }
+    const char* ng = std::getenv("RPOD_NO_GRAPH");
+    if (!(ng && ng[0] == '1')) {
+        e = capture(P);
+        if (e != hipSuccess) {
+            destroy_plan(P);
+            return fail(RPOD_EHIP, "capturing the launch graph failed: %s", hipGetErrorString(e));
+        }
+    }
+    *plan = P;
+    return RPOD_OK;
+}
+
+rpod_status compute_impl(rpod_plan_s* P, const void* const* S, const uint64_t* seeds, void* const* Phi,
+                         double* const* sigma, void* const* A) {
+    const int count = (int)P->items.size();
+    for (int i = 0; i < count; ++i) {
+        const Item& it = P->items[i];
+        if (S[i] == nullptr || Phi[i] == nullptr || sigma[i] == nullptr || A[i] == nullptr)
+            return fail(RPOD_EINVAL, "matrix %d: S, Phi, sigma and A must be non-NULL", i);
+        // vector loads of S need 16-byte alignment when ld allows them
+        const int64_t vq = is16(it.L.tin) ? 8 : 4;
+        if (it.d.ld % vq == 0 && (uintptr_t)S[i] % 16 != 0)
+            return fail(RPOD_EINVAL, "matrix %d: S must be 16-byte aligned when ld is a multiple of %lld", i,
+                        (long long)vq);
+        if ((uintptr_t)S[i] % dt_size(it.L.tin) != 0)
+            return fail(RPOD_EINVAL, "matrix %d: S is not aligned to its element size", i);
+        const size_t so = dt_size(it.L.tacc);
+        if ((uintptr_t)Phi[i] % so || (uintptr_t)A[i] % so || (uintptr_t)sigma[i] % 8)
+            return fail(RPOD_EINVAL, "matrix %d: Phi, A or sigma is not aligned to its element size", i);
+        P->host_calls[i] = CallDesc{S[i], Phi[i], sigma[i], A[i], seeds[i]};
+    }
+    HIP_TRY(launch_set_calls(P->calls(), P->host_calls.data(), count, P->st));
+    if (P->exec != nullptr && !P->timing)
+        HIP_TRY(hipGraphLaunch(P->exec, P->st));
+    else
+        HIP_TRY(replay(P, P->st));
     return RPOD_OK;
 }
 
@@ -237,162 +777,75 @@ extern "C" {
 const char* rpod_last_error(void) { return g_err; }
 
 rpod_status rpod_workspace_size(const rpod_desc* desc, size_t* bytes) {
-    rpod_status s = validate(desc);
-    if (s != RPOD_OK) return s;
     if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
-    *bytes = make_layout(desc).total;
-    return RPOD_OK;
+    return workspace_bytes(desc, 1, bytes);
+}
+
+rpod_status rpod_workspace_size_batched(const rpod_desc* descs, int32_t count, size_t* bytes) {
+    if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
+    return workspace_bytes(descs, count, bytes);
 }
 
 rpod_status rpod_plan_create(rpod_plan* plan, const rpod_desc* desc, void* workspace, size_t workspace_bytes,
                              void* hip_stream) {
-    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
-    *plan = nullptr;
-    rpod_status s = validate(desc);
-    if (s != RPOD_OK) return s;
-    if (workspace == nullptr) return fail(RPOD_EINVAL, "workspace is NULL");
-    if ((uintptr_t)workspace % 256 != 0) return fail(RPOD_EINVAL, "workspace must be 256-byte aligned");
-    Layout L = make_layout(desc);
-    if (workspace_bytes < L.total)
-        return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
-    rpod_plan_s* P = new (std::nothrow) rpod_plan_s;
-    if (P == nullptr) return fail(RPOD_ENOMEM, "host allocation of the plan failed");
-    P->d = *desc;
-    P->L = L;
-    P->ws = static_cast<char*>(workspace);
-    P->st = static_cast<hipStream_t>(hip_stream);
-    hipError_t e = hipMemsetAsync(workspace, 0, L.total, P->st);
-    if (e != hipSuccess) {
-        delete P;
-        return fail(RPOD_EHIP, "clearing the workspace failed: %s", hipGetErrorString(e));
-    }
-    *plan = P;
-    return RPOD_OK;
+    return create_plan(plan, desc, 1, workspace, workspace_bytes, hip_stream);
+}
+
+rpod_status rpod_plan_create_batched(rpod_plan* plan, const rpod_desc* descs, int32_t count, void* workspace,
+                                     size_t workspace_bytes, void* hip_stream) {
+    return create_plan(plan, descs, count, workspace, workspace_bytes, hip_stream);
 }
 
 rpod_status rpod_plan_destroy(rpod_plan plan) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     hipError_t e = hipStreamSynchronize(plan->st);
-    for (int k = 0; k < 2; ++k)
-        for (hipEvent_t ev : plan->ev[k]) (void)hipEventDestroy(ev);
-    delete plan;
+    destroy_plan(plan);
     if (e != hipSuccess) return fail(RPOD_EHIP, "stream synchronisation failed: %s", hipGetErrorString(e));
     return RPOD_OK;
 }
 
 rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi, double* sigma, void* A) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
-    if (S == nullptr || Phi == nullptr || sigma == nullptr || A == nullptr)
-        return fail(RPOD_EINVAL, "S, Phi, sigma and A must be non-NULL");
-    rpod_plan_s* P = plan;
-    const Layout& L = P->L;
-    const rpod_desc& d = P->d;
-    if ((uintptr_t)S % dt_size(L.tin) != 0) return fail(RPOD_EINVAL, "S is not aligned to its element size");
-    const size_t so = dt_size(L.tacc);
-    if ((uintptr_t)Phi % so || (uintptr_t)A % so || (uintptr_t)sigma % 8)
-        return fail(RPOD_EINVAL, "Phi, A or sigma is not aligned to its element size");
-    hipStream_t st = P->st;
-    int* flags = P->at<int>(L.o_flags);
-    void* X = P->at<void>(L.o_X);
-    void* Y = P->at<void>(L.o_Y);
-    void* Q1 = P->at<void>(L.o_Q1);
-    double* Zp = P->at<double>(L.o_Zp);
-    double* Zt = P->at<double>(L.o_Zt);
-    double* Zw = P->at<double>(L.o_Zw);
-    double* Zw2 = P->at<double>(L.o_Zw2);
-    double* R64t = P->at<double>(L.o_R64[1]);   // final factor of the tall orthonormalisation
-    const int64_t m = d.m, n = d.n;
-    const int lp = L.lp, nt = L.nt;
+    if (plan->items.size() != 1) return fail(RPOD_EINVAL, "plan holds a batch: use rpod_compute_batched");
+    return compute_impl(plan, &S, &seed, &Phi, &sigma, &A);
+}
 
-    HIP_TRY(launch_zero_ints(flags, 64, st));
-    const bool s16 = L.tin == DT_BF16 || L.tin == DT_F16;
-    // one pass Y = S X over S
-    auto pass_sx = [&]() -> rpod_status {
-        HIP_TRY(mark(P, 0, true));
-        if (s16)
-            HIP_TRY(launch_sx16(L.tin, nt, S, d.ld, m, n, X, L.nP, static_cast<float*>(Y), L.mP, L.mP, st));
-        else
-            HIP_TRY(launch_sx(L.tin, L.tacc, nt, S, d.ld, m, n, X, L.nP, Y, L.mP, L.mP, nullptr, 0, st));
-        HIP_TRY(mark(P, 0, false));
-        return RPOD_OK;
-    };
-    // one pass Z~ = S^T Q1 over S (lo: Q1 with ~16 significant bits on 16-bit paths)
-    auto pass_stq = [&](bool lo) -> rpod_status {
-        HIP_TRY(mark(P, 1, true));
-        if (s16)
-            HIP_TRY(launch_stq16(L.tin, nt, lo, S, d.ld, m, n, P->at<unsigned short>(L.o_Qh),
-                                 P->at<unsigned short>(L.o_Ql), L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
-        else
-            HIP_TRY(launch_stq(L.tin, nt, S, d.ld, m, n, Q1, L.mP, Zp, L.nP, L.split_rows, L.nsplit, st));
-        HIP_TRY(mark(P, 1, false));
-        HIP_TRY(launch_reduce_slabs(Zp, L.nsplit, L.nP * lp, Zt, st));
-        return RPOD_OK;
-    };
-    // CholeskyQR2 of Y into Q1; on 16-bit paths also the hi/lo parts of Q1
-    auto orth_tall = [&]() -> rpod_status {
-        rpod_status so = orth(P, L.tacc, Y, Q1, L.mP, m, 1);
-        if (so != RPOD_OK) return so;
-        if (s16)
-            HIP_TRY(launch_split16(L.tin, static_cast<const float*>(Q1), L.mP * lp, P->at<unsigned short>(L.o_Qh),
-                                   P->at<unsigned short>(L.o_Ql), st));
-        return RPOD_OK;
-    };
-    rpod_status s;
-    // Alg. 1 step 1: Gaussian sketch
-    HIP_TRY(launch_omega(L.tin, seed, n, L.l, lp, L.nP, X, L.nP, st));
-    // step 2: Y = S Omega, then Q by CholeskyQR2
-    if ((s = pass_sx()) != RPOD_OK) return s;
-    if ((s = orth_tall()) != RPOD_OK) return s;
-    // step 3, one product at a time with re-orthonormalisation
-    for (int it = 0; it < d.q; ++it) {
-        if ((s = pass_stq(false)) != RPOD_OK) return s;
-        HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st, true));
-        if ((s = basis_small(P, Zw, Zw2, X)) != RPOD_OK) return s;
-        if ((s = pass_sx()) != RPOD_OK) return s;
-        if ((s = orth_tall()) != RPOD_OK) return s;
+rpod_status rpod_compute_batched(rpod_plan plan, const void* const* S, const uint64_t* seeds, void* const* Phi,
+                                 double* const* sigma, void* const* A) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    if (S == nullptr || seeds == nullptr || Phi == nullptr || sigma == nullptr || A == nullptr)
+        return fail(RPOD_EINVAL, "pointer arrays must be non-NULL");
+    return compute_impl(plan, S, seeds, Phi, sigma, A);
+}
+
+rpod_status rpod_status_query_batched(rpod_plan plan, int32_t* per_matrix_flags) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    const size_t count = plan->items.size();
+    std::vector<int> host(count * FLAG_INTS, 0);
+    hipError_t e = hipMemcpyAsync(host.data(), plan->ws + plan->o_flags, host.size() * sizeof(int),
+                                  hipMemcpyDeviceToHost, plan->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->st);
+    if (e != hipSuccess) return fail(RPOD_EHIP, "reading the status words failed: %s", hipGetErrorString(e));
+    int all = 0;
+    for (size_t i = 0; i < count; ++i) {
+        all |= host[i * FLAG_INTS];
+        if (per_matrix_flags) per_matrix_flags[i] = host[i * FLAG_INTS];
     }
-    // step 5: T^T = S^T Q (Q = Q1 R^-1 applied on the small side); on 16-bit
-    // paths this is the refinement pass with Q carried to ~16 bits
-    if ((s = pass_stq(true)) != RPOD_OK) return s;
-    HIP_TRY(launch_sx(DT_F64, DT_F64, nt, Zt, L.nP, n, lp, R64t, lp, Zw, L.nP, L.nP, nullptr, 0, st, true));
-    // step 6: SVD of T through the eigenvectors of T T^T
-    double* G = P->at<double>(L.o_G);
-    double* UB = P->at<double>(L.o_UB);
-    double* sig = P->at<double>(L.o_sig);
-    HIP_TRY(launch_gram(DT_F64, nt, Zw, L.nP, n, P->at<double>(L.o_Gpart), G, nullptr, 0, st));
-    // rotation threshold: FP64 rounding level on the FP64 path; elsewhere far
-    // below the FP32 storage error of Q, which bounds the result anyway
-    const double jtol = L.tacc == DT_F64 ? (double)lp * 0x1.0p-53 : 1e-10;
-    HIP_TRY(launch_jacobi(G, L.l, lp, UB, sig, flags, jtol, st));
-    // step 7: Phi = Q U_hat[:, :r] = Q1 (R^-1 U_hat[:, :r]); coefficients A = U_hat_r^T T
-    double* M64 = P->at<double>(L.o_M64);
-    float* M32 = P->at<float>(L.o_M32);
-    double* Ur = P->at<double>(L.o_Ur);
-    HIP_TRY(launch_lift_coef(R64t, UB, lp, d.r, L.rp, M64, M32, Ur, st));
-    void* Phi_int = P->at<void>(L.o_Phi);
-    const void* Mx = L.tacc == DT_F64 ? (const void*)M64 : (const void*)M32;
-    HIP_TRY(launch_sx(L.tacc, L.tacc, L.ntr, Q1, L.mP, m, lp, Mx, lp, Phi_int, L.mP, L.mP, nullptr, 0, st));
-    double* At = P->at<double>(L.o_At);
-    HIP_TRY(launch_sx(DT_F64, DT_F64, L.ntr, Zw, L.nP, n, lp, Ur, lp, At, L.nP, L.nP, nullptr, 0, st));
-    double* signs = P->at<double>(L.o_signs);
-    HIP_TRY(launch_signs(L.tacc, Phi_int, L.mP, m, d.r, L.nchunk, P->at<double>(L.o_pval),
-                         P->at<int64_t>(L.o_pidx), signs, st));
-    HIP_TRY(launch_finalize(L.tacc, Phi_int, L.mP, m, d.r, At, L.nP, n, signs, sig, Phi, A, sigma, st));
+    if (all & RPOD_FLAG_NONFINITE) return fail(RPOD_EINVAL_DATA, "non-finite values in S");
+    if (all & RPOD_FLAG_BREAKDOWN) return fail(RPOD_EBREAKDOWN, "sketch rank-deficient after the shifted CholeskyQR retry");
     return RPOD_OK;
 }
 
 rpod_status rpod_status_query(rpod_plan plan, int32_t* device_flags) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
-    int host_flags = 0;
-    hipError_t e = hipMemcpyAsync(&host_flags, plan->at<int>(plan->L.o_flags), sizeof(int), hipMemcpyDeviceToHost,
-                                  plan->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(plan->st);
-    if (e != hipSuccess) return fail(RPOD_EHIP, "reading the status word failed: %s", hipGetErrorString(e));
-    if (device_flags) *device_flags = host_flags;
-    if (host_flags & RPOD_FLAG_NONFINITE) return fail(RPOD_EINVAL_DATA, "non-finite values in S");
-    if (host_flags & RPOD_FLAG_BREAKDOWN)
-        return fail(RPOD_EBREAKDOWN, "sketch rank-deficient after the shifted CholeskyQR retry");
-    return RPOD_OK;
+    std::vector<int32_t> f(plan->items.size(), 0);
+    rpod_status s = rpod_status_query_batched(plan, f.data());
+    if (device_flags) {
+        int32_t all = 0;
+        for (int32_t v : f) all |= v;
+        *device_flags = all;
+    }
+    return s;
 }
 
 rpod_status rpod_plan_set_timing(rpod_plan plan, int32_t enable) {
@@ -407,18 +860,19 @@ rpod_status rpod_plan_get_timing(rpod_plan plan, int32_t pass, int64_t* launches
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     if (pass < 0 || pass > 1) return fail(RPOD_EINVAL, "pass must be 0 or 1");
     HIP_TRY(hipStreamSynchronize(plan->st));
-    double tot = 0.0;
+    double tot = 0.0, b = 0.0, f = 0.0;
     for (size_t k = 0; k < plan->used[pass]; ++k) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, plan->ev[pass][2 * k], plan->ev[pass][2 * k + 1]));
         tot += ms;
+        b += plan->evbytes[pass][k];
+        f += plan->evflops[pass][k];
     }
-    const rpod_desc& d = plan->d;
-    const double s = (double)dt_size(plan->L.tin), l = (double)plan->L.l;
+    const double nl = (double)std::max<size_t>(plan->used[pass], 1);
     if (launches) *launches = (int64_t)plan->used[pass];
     if (total_ms) *total_ms = tot;
-    if (bytes_per_launch) *bytes_per_launch = (double)d.m * d.n * s + (double)d.n * l * s + (double)d.m * l * 4.0;
-    if (flops_per_launch) *flops_per_launch = 2.0 * d.m * d.n * l;
+    if (bytes_per_launch) *bytes_per_launch = b / nl;
+    if (flops_per_launch) *flops_per_launch = f / nl;
     return RPOD_OK;
 }
 
@@ -428,8 +882,7 @@ rpod_status rpod_generate_omega(uint64_t seed, int64_t n, int32_t l, int32_t dty
     if (ldo < n) return fail(RPOD_EINVAL, "ldo must be >= n");
     if (out == nullptr) return fail(RPOD_EINVAL, "out is NULL");
     if (dtype < RPOD_F64 || dtype > RPOD_F16) return fail(RPOD_EINVAL, "unknown dtype %d", dtype);
-    const int dt = dtype;  // rpod_dtype and the internal codes coincide
-    HIP_TRY(launch_omega(dt, seed, n, l, l, n, out, ldo, static_cast<hipStream_t>(hip_stream)));
+    HIP_TRY(launch_omega_direct(dtype, seed, n, l, out, ldo, static_cast<hipStream_t>(hip_stream)));
     return RPOD_OK;
 }
 

@@ -14,23 +14,61 @@ namespace rpod {
 template <typename T>
 using V4 = typename vec4_of<T>::type;
 
-__global__ void k_zero_ints(int* p, int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0;
+template <typename A>
+static Group<A> mkg(const GroupLaunch<A>& L) {
+    Group<A> g;
+    g.args = L.args;
+    g.tstart = L.tstart;
+    g.calls = L.calls;
+    g.count = L.count;
+    return g;
 }
 
-hipError_t launch_zero_ints(int* p, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_ints, dim3((count + 255) / 256), dim3(256), 0, st, p, count);
+__global__ void k_zero_ints(Group<ZeroArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const ZeroArgs& a = g.args[it];
+    const int i = (blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
+    if (i < a.count) a.p[i] = 0;
+}
+
+hipError_t launch_zero_ints(const GroupLaunch<ZeroArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_ints, dim3(L.tiles), dim3(256), 0, st, mkg(L));
     return hipGetLastError();
+}
+
+// Per-call table: one entry per matrix, written from kernel arguments so
+// that it needs no host staging buffer (and may precede a graph launch).
+constexpr int CALLS_PER_LAUNCH = 16;
+struct CallBatch {
+    CallDesc d[CALLS_PER_LAUNCH];
+    int first, count;
+};
+
+__global__ void k_set_calls(CallDesc* table, CallBatch b) {
+    const int i = threadIdx.x;
+    if (i < b.count) table[b.first + i] = b.d[i];
+}
+
+hipError_t launch_set_calls(CallDesc* table, const CallDesc* host, int count, hipStream_t st) {
+    for (int first = 0; first < count; first += CALLS_PER_LAUNCH) {
+        CallBatch b;
+        b.first = first;
+        b.count = count - first < CALLS_PER_LAUNCH ? count - first : CALLS_PER_LAUNCH;
+        for (int i = 0; i < b.count; ++i) b.d[i] = host[first + i];
+        hipLaunchKernelGGL(k_set_calls, dim3(1), dim3(CALLS_PER_LAUNCH), 0, st, table, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
 // Gaussian sketch. Thread per (row j, column pair t).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_omega(uint64_t seed, int64_t n, int l, int lpad, int64_t rows_pad, T* out, int64_t ldo) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = blockIdx.y;  // column pair
+__device__ __forceinline__ void omega_body(uint64_t seed, int64_t n, int l, int lpad, int64_t rows_pad, GLOBAL T* out,
+                                           int64_t ldo, int64_t bx, int t /* column pair */) {
+    const int64_t j = bx * blockDim.x + threadIdx.x;
     if (j >= rows_pad) return;
     const int c0 = 2 * t, c1 = 2 * t + 1;
     double g0 = 0.0, g1 = 0.0;
@@ -50,18 +88,46 @@ __global__ void k_omega(uint64_t seed, int64_t n, int l, int lpad, int64_t rows_
     if (c1 < lpad) out[(int64_t)c1 * ldo + j] = narrow<T>(c1 < l ? g1 : 0.0);
 }
 
-hipError_t launch_omega(int tout, uint64_t seed, int64_t n, int l, int lpad, int64_t rows_pad, void* out,
-                        int64_t ldo, hipStream_t st) {
-    dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)((lpad + 1) / 2));
+// grouped: local tile t covers rows 256 (t % nb) .. and column pair t / nb
+template <typename T>
+__global__ void k_omega(Group<OmegaArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const OmegaArgs& a = g.args[it];
+    const int t = blockIdx.x - g.tstart[it];
+    const int nb = (int)((a.rows_pad + 255) / 256);
+    const uint64_t seed = a.call >= 0 ? g.calls[a.call].seed : a.seed;
+    omega_body<T>(seed, a.n, a.l, a.lpad, a.rows_pad, gbl((T*)a.out), a.ldo, t % nb, t / nb);
+}
+
+template <typename T>
+__global__ void k_omega_direct(uint64_t seed, int64_t n, int l, int64_t ldo, T* out) {
+    omega_body<T>(seed, n, l, l, n, gbl(out), ldo, blockIdx.x, blockIdx.y);
+}
+
+hipError_t launch_omega(int tout, const GroupLaunch<OmegaArgs>& L, hipStream_t st) {
     if (tout == DT_F64)
-        hipLaunchKernelGGL(k_omega<double>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (double*)out, ldo);
+        hipLaunchKernelGGL(k_omega<double>, dim3(L.tiles), dim3(256), 0, st, mkg(L));
     else if (tout == DT_F32)
-        hipLaunchKernelGGL(k_omega<float>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (float*)out, ldo);
+        hipLaunchKernelGGL(k_omega<float>, dim3(L.tiles), dim3(256), 0, st, mkg(L));
     else if (tout == DT_BF16)
-        hipLaunchKernelGGL(k_omega<__bf16>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (__bf16*)out, ldo);
+        hipLaunchKernelGGL(k_omega<__bf16>, dim3(L.tiles), dim3(256), 0, st, mkg(L));
     else if (tout == DT_F16)
-        hipLaunchKernelGGL(k_omega<_Float16>, grid, dim3(256), 0, st, seed, n, l, lpad, rows_pad, (_Float16*)out,
-                           ldo);
+        hipLaunchKernelGGL(k_omega<_Float16>, dim3(L.tiles), dim3(256), 0, st, mkg(L));
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_omega_direct(int tout, uint64_t seed, int64_t n, int l, void* out, int64_t ldo, hipStream_t st) {
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((l + 1) / 2));
+    if (tout == DT_F64)
+        hipLaunchKernelGGL(k_omega_direct<double>, grid, dim3(256), 0, st, seed, n, l, ldo, (double*)out);
+    else if (tout == DT_F32)
+        hipLaunchKernelGGL(k_omega_direct<float>, grid, dim3(256), 0, st, seed, n, l, ldo, (float*)out);
+    else if (tout == DT_BF16)
+        hipLaunchKernelGGL(k_omega_direct<__bf16>, grid, dim3(256), 0, st, seed, n, l, ldo, (__bf16*)out);
+    else if (tout == DT_F16)
+        hipLaunchKernelGGL(k_omega_direct<_Float16>, grid, dim3(256), 0, st, seed, n, l, ldo, (_Float16*)out);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -90,8 +156,8 @@ hipError_t launch_sketch_bits(uint64_t seed, int64_t n, int l, uint32_t* out, hi
 // lane loads rows 4*(l/16)..+3 of column 16a + l%16 for every tile a, and
 // MFMA (pair, s) uses row slot s of that vector as the K index.
 // Pairs [PLO, PHI) of the NT(NT+1)/2 upper-triangle tile pairs belong to one
-// blockIdx.y group; partials are reduced over the 4 waves in LDS in a fixed
-// order and written per workgroup.
+// pair group of the launch; partials are reduced over the 4 waves in LDS in a
+// fixed order and written per workgroup.
 // ---------------------------------------------------------------------------
 constexpr int GRAM_WGS = 256;
 
@@ -104,8 +170,8 @@ __host__ __device__ constexpr int gram_pg(int nt) {
 int64_t gram_partial_count(int nt) { return (int64_t)GRAM_WGS * npairs_of(nt) * 256; }
 
 template <typename Tin, int NT, int PLO, int PHI>
-__device__ __forceinline__ void gram_body(const Tin* __restrict__ Y, int64_t ld, int64_t M,
-                                          double* __restrict__ Gpart, double* red) {
+__device__ __forceinline__ void gram_body(const GLOBAL Tin* __restrict__ Y, int64_t ld, int64_t M,
+                                          GLOBAL double* __restrict__ Gpart, double* red, int bx, int nwg) {
     constexpr int PG = PHI - PLO;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -114,12 +180,12 @@ __device__ __forceinline__ void gram_body(const Tin* __restrict__ Y, int64_t ld,
     for (int p = 0; p < PG; ++p) acc[p] = f64x4{0, 0, 0, 0};
 
     const int64_t nrb = (M + 15) / 16;
-    for (int64_t rb = (int64_t)blockIdx.x * 4 + wave; rb < nrb; rb += (int64_t)gridDim.x * 4) {
+    for (int64_t rb = (int64_t)bx * 4 + wave; rb < nrb; rb += (int64_t)nwg * 4) {
         const int64_t i0 = rb * 16 + 4 * kg;
         double x[NT][4];
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
-            const V4<Tin> v = *reinterpret_cast<const V4<Tin>*>(Y + (int64_t)(16 * a + r16) * ld + i0);
+            const V4<Tin> v = *reinterpret_cast<const GLOBAL V4<Tin>*>(Y + (int64_t)(16 * a + r16) * ld + i0);
 #pragma unroll
             for (int s = 0; s < 4; ++s) x[a][s] = (double)v[s];
         }
@@ -151,28 +217,36 @@ __device__ __forceinline__ void gram_body(const Tin* __restrict__ Y, int64_t ld,
     constexpr int NP = npairs_of(NT);
     for (int e = threadIdx.x; e < PG * 256; e += 256) {
         const int p = PLO + e / 256;
-        Gpart[((int64_t)blockIdx.x * NP + p) * 256 + (e % 256)] = red[e];
+        Gpart[((int64_t)bx * NP + p) * 256 + (e % 256)] = red[e];
     }
 }
 
+// grouped: local tile t is partial workgroup t % nwg of pair group t / nwg
 template <typename Tin, int NT>
-__global__ __launch_bounds__(256) void k_gram(const Tin* __restrict__ Y, int64_t ld, int64_t M,
-                                              double* __restrict__ Gpart, const int* cond, int cond_mask) {
-    if (cond != nullptr && !(*cond & cond_mask)) return;
+__global__ __launch_bounds__(256) void k_gram(Group<GramArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const GramArgs& a = g.args[it];
+    if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
+    const int t = blockIdx.x - g.tstart[it];
+    const int bx = t % a.nwg, grp = t / a.nwg;
     constexpr int NP = npairs_of(NT), PG = gram_pg(NT);
     __shared__ double red[PG * 256];
-    if (blockIdx.y == 0) gram_body<Tin, NT, 0, (PG < NP ? PG : NP)>(Y, ld, M, Gpart, red);
+    const GLOBAL Tin* Y = gbl((const Tin*)a.Y);
+    GLOBAL double* Gp = gbl(a.Gpart);
+    if (grp == 0) gram_body<Tin, NT, 0, (PG < NP ? PG : NP)>(Y, a.ld, a.M, Gp, red, bx, a.nwg);
     if constexpr (gram_groups(NT) > 1) {
-        if (blockIdx.y == 1) gram_body<Tin, NT, PG, (2 * PG < NP ? 2 * PG : NP)>(Y, ld, M, Gpart, red);
-        if (blockIdx.y == 2) gram_body<Tin, NT, 2 * PG, NP>(Y, ld, M, Gpart, red);
+        if (grp == 1) gram_body<Tin, NT, PG, (2 * PG < NP ? 2 * PG : NP)>(Y, a.ld, a.M, Gp, red, bx, a.nwg);
+        if (grp == 2) gram_body<Tin, NT, 2 * PG, NP>(Y, a.ld, a.M, Gp, red, bx, a.nwg);
     }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ Gpart, int nt, int nwg, double* __restrict__ G,
-                              const int* cond, int cond_mask) {
-    if (cond != nullptr && !(*cond & cond_mask)) return;
+// grouped: npairs(nt) tiles of 256 elements per matrix
+__global__ void k_gram_reduce(Group<GramArgs> g, int nt) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const GramArgs& ga = g.args[it];
+    if (ga.cond != nullptr && !(*ga.cond & ga.cond_mask)) return;
     const int np = nt * (nt + 1) / 2;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = (blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
     if (e >= np * 256) return;
     const int p = e / 256, mm = (e % 256) / 16, nn = e % 16;
     int a = 0, q = p;
@@ -180,8 +254,9 @@ __global__ void k_gram_reduce(const double* __restrict__ Gpart, int nt, int nwg,
     const int b = a + q;
     // eight independent partial sums (loads in flight together), combined in a fixed order
     double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const double* src = Gpart + (int64_t)p * 256 + (e % 256);
+    const GLOBAL double* src = gbl(ga.Gpart) + (int64_t)p * 256 + (e % 256);
     const int64_t wstride = (int64_t)np * 256;
+    const int nwg = ga.nwg;
     int w = 0;
     for (; w + 8 <= nwg; w += 8)
 #pragma unroll
@@ -189,32 +264,36 @@ __global__ void k_gram_reduce(const double* __restrict__ Gpart, int nt, int nwg,
     for (; w < nwg; ++w) acc8[0] += src[w * wstride];
     const double s = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
     const int lp = 16 * nt;
+    GLOBAL double* G = gbl(ga.G);
     G[(16 * a + mm) * lp + 16 * b + nn] = s;
     G[(16 * b + nn) * lp + 16 * a + mm] = s;
 }
 
-template <typename Tin, int NT>
-static hipError_t gram_nt(const void* Y, int64_t ld, int64_t M, double* Gpart, double* G, const int* cond,
-                          int cond_mask, hipStream_t st) {
-    int64_t nrb = (M + 15) / 16;
-    int nwg = (int)((nrb + 3) / 4);
+int gram_nwg(int64_t M) {
+    const int64_t nrb = (M + 15) / 16;
+    int64_t nwg = (nrb + 3) / 4;
     if (nwg > GRAM_WGS) nwg = GRAM_WGS;
     if (nwg < 1) nwg = 1;
-    hipLaunchKernelGGL((k_gram<Tin, NT>), dim3(nwg, gram_groups(NT)), dim3(256), 0, st, (const Tin*)Y, ld, M,
-                       Gpart, cond, cond_mask);
+    return (int)nwg;
+}
+
+int gram_tiles(int nt, int nwg) { return nwg * gram_groups(nt); }
+int gram_reduce_tiles(int nt) { return npairs_of(nt); }
+
+template <typename Tin, int NT>
+static hipError_t gram_nt(const GroupLaunch<GramArgs>& L, const GroupLaunch<GramArgs>& R, hipStream_t st) {
+    hipLaunchKernelGGL((k_gram<Tin, NT>), dim3(L.tiles), dim3(256), 0, st, mkg(L));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int cnt = npairs_of(NT) * 256;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((cnt + 255) / 256), dim3(256), 0, st, Gpart, NT, nwg, G, cond,
-                       cond_mask);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(R.tiles), dim3(256), 0, st, mkg(R), NT);
     return hipGetLastError();
 }
 
 template <typename Tin>
-static hipError_t gram_dispatch(int nt, const void* Y, int64_t ld, int64_t M, double* Gpart, double* G,
-                                const int* cond, int cond_mask, hipStream_t st) {
+static hipError_t gram_dispatch(int nt, const GroupLaunch<GramArgs>& L, const GroupLaunch<GramArgs>& R,
+                                hipStream_t st) {
     switch (nt) {
-#define RPOD_GRAM_CASE(K) case K: return gram_nt<Tin, K>(Y, ld, M, Gpart, G, cond, cond_mask, st);
+#define RPOD_GRAM_CASE(K) case K: return gram_nt<Tin, K>(L, R, st);
         RPOD_GRAM_CASE(1) RPOD_GRAM_CASE(2) RPOD_GRAM_CASE(3) RPOD_GRAM_CASE(4)
         RPOD_GRAM_CASE(5) RPOD_GRAM_CASE(6) RPOD_GRAM_CASE(7) RPOD_GRAM_CASE(8)
 #undef RPOD_GRAM_CASE
@@ -222,10 +301,10 @@ static hipError_t gram_dispatch(int nt, const void* Y, int64_t ld, int64_t M, do
     }
 }
 
-hipError_t launch_gram(int tin, int nt, const void* Y, int64_t ld, int64_t M, double* Gpart, double* G,
-                       const int* cond, int cond_mask, hipStream_t st) {
-    if (tin == DT_F64) return gram_dispatch<double>(nt, Y, ld, M, Gpart, G, cond, cond_mask, st);
-    if (tin == DT_F32) return gram_dispatch<float>(nt, Y, ld, M, Gpart, G, cond, cond_mask, st);
+hipError_t launch_gram(int tin, int nt, const GroupLaunch<GramArgs>& L, const GroupLaunch<GramArgs>& R,
+                       hipStream_t st) {
+    if (tin == DT_F64) return gram_dispatch<double>(nt, L, R, st);
+    if (tin == DT_F32) return gram_dispatch<float>(nt, L, R, st);
     return hipErrorInvalidValue;
 }
 
@@ -239,9 +318,9 @@ hipError_t launch_gram(int tin, int nt, const void* Y, int64_t ld, int64_t M, do
 constexpr int LPMAX = 128;
 constexpr int LDA = LPMAX + 1;
 
-__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int l, int lp, int64_t M,
-                                                  double* __restrict__ Rinv64, float* __restrict__ Rinv32,
-                                                  int* flags, int* local, int mode) {
+__device__ __forceinline__ void chol_body(const double* __restrict__ G, int l, int lp, int64_t M,
+                                          double* __restrict__ Rinv64, float* __restrict__ Rinv32, int* flags,
+                                          int* local, int mode) {
     __shared__ double A[LPMAX * LDA];
     __shared__ double xd[LPMAX];
     __shared__ double gdiag[LPMAX];
@@ -352,10 +431,13 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
     }
 }
 
-hipError_t launch_chol_inv(const double* G, int l, int lp, int64_t M, double* Rinv64, float* Rinv32, int* flags,
-                           int* local, int mode, hipStream_t st) {
-    if (lp > LPMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, st, G, l, lp, M, Rinv64, Rinv32, flags, local, mode);
+__global__ __launch_bounds__(256) void k_chol_inv(Group<CholArgs> g) {
+    const CholArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
+    chol_body(a.G, a.l, a.lp, a.M, a.R64, a.R32, a.flags, a.local, a.mode);
+}
+
+hipError_t launch_chol_inv(const GroupLaunch<CholArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_chol_inv, dim3(L.count), dim3(256), 0, st, mkg(L));
     return hipGetLastError();
 }
 
@@ -372,9 +454,8 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
     return __shfl_xor(v, mask, 64);
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, int l, int lp,
-                                                 double* __restrict__ UB, double* __restrict__ sig, int* flags,
-                                                 double tol) {
+__device__ __forceinline__ void jacobi_body(const double* __restrict__ G, int l, int lp, double* __restrict__ UB,
+                                            double* __restrict__ sig, int* flags, double tol) {
     __shared__ double W[LPMAX * JLD];  // column c at W[c * JLD + row]
     __shared__ double nrm[LPMAX];
     __shared__ int s_rot;
@@ -446,20 +527,35 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, i
     }
 }
 
-hipError_t launch_jacobi(const double* G, int l, int lp, double* UB, double* sig, int* flags, double tol,
-                         hipStream_t st) {
-    if (lp > LPMAX || lp % 16) return hipErrorInvalidValue;
+__global__ __launch_bounds__(1024) void k_jacobi(Group<JacobiArgs> g) {
+    const JacobiArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
+    jacobi_body(a.G, a.l, a.lp, a.UB, a.sig, a.flags, a.tol);
+}
+
+int jacobi_threads(int lp) {
     const int npair = lp / 2;
     int tpp = 64;  // threads per column pair: a power of two that divides the wave
     while (tpp * npair > 1024) tpp /= 2;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(tpp * npair), 0, st, G, l, lp, UB, sig, flags, tol);
+    return tpp * npair;
+}
+
+hipError_t launch_jacobi(int lp, const GroupLaunch<JacobiArgs>& L, hipStream_t st) {
+    if (lp > LPMAX || lp % 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi, dim3(L.count), dim3(jacobi_threads(lp)), 0, st, mkg(L));
     return hipGetLastError();
 }
 
 // M = Rinv * UB[:, :r] and Ur = UB[:, :r], both lp x rp column-major (zero pad).
-__global__ void k_lift_coef(const double* __restrict__ Rinv, const double* __restrict__ UB, int lp, int r, int rp,
-                            double* __restrict__ M64, float* __restrict__ M32, double* __restrict__ Ur) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_lift_coef(Group<LiftArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const LiftArgs& la = g.args[it];
+    const double* __restrict__ Rinv = la.Rinv;
+    const double* __restrict__ UB = la.UB;
+    double* __restrict__ M64 = la.M64;
+    float* __restrict__ M32 = la.M32;
+    double* __restrict__ Ur = la.Ur;
+    const int lp = la.lp, r = la.r, rp = la.rp;
+    const int e = (blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
     if (e >= lp * rp) return;
     const int k = e % lp, c = e / lp;
     double s = 0.0, u = 0.0;
@@ -472,9 +568,8 @@ __global__ void k_lift_coef(const double* __restrict__ Rinv, const double* __res
     Ur[e] = u;
 }
 
-hipError_t launch_lift_coef(const double* Rinv, const double* UB, int lp, int r, int rp, double* M64, float* M32,
-                            double* Ur, hipStream_t st) {
-    hipLaunchKernelGGL(k_lift_coef, dim3((lp * rp + 255) / 256), dim3(256), 0, st, Rinv, UB, lp, r, rp, M64, M32, Ur);
+hipError_t launch_lift_coef(const GroupLaunch<LiftArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_lift_coef, dim3(L.tiles), dim3(256), 0, st, mkg(L));
     return hipGetLastError();
 }
 
@@ -483,18 +578,22 @@ hipError_t launch_lift_coef(const double* Rinv, const double* UB, int lp, int r,
 // ties) is made positive. Partial argmax per (column, row chunk), then one
 // thread per column combines chunks in order.
 // ---------------------------------------------------------------------------
+// grouped: local tile t covers row chunk t % nchunk of column t / nchunk
 template <typename T>
-__global__ __launch_bounds__(256) void k_colmax(const T* __restrict__ Phi, int64_t ld, int64_t m, int64_t chunk,
-                                                double* __restrict__ pval, int64_t* __restrict__ pidx) {
-    const int c = blockIdx.y, ch = blockIdx.x;
-    const int64_t i0 = (int64_t)ch * chunk;
-    const int64_t i1 = (i0 + chunk < m) ? i0 + chunk : m;
+__global__ __launch_bounds__(256) void k_colmax(Group<ColmaxArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const ColmaxArgs& a = g.args[it];
+    const int t = blockIdx.x - g.tstart[it];
+    const int c = t / a.nchunk, ch = t % a.nchunk;
+    const GLOBAL T* __restrict__ Phi = gbl((const T*)a.Phi);
+    const int64_t i0 = (int64_t)ch * a.chunk;
+    const int64_t i1 = (i0 + a.chunk < a.m) ? i0 + a.chunk : a.m;
     double best = -1.0, bval = 0.0;
     int64_t bidx = INT64_MAX;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-        const double v = (double)Phi[(int64_t)c * ld + i];
-        const double a = fabs(v);
-        if (a > best) { best = a; bidx = i; bval = v; }  // increasing i: strict > keeps first
+        const double v = (double)Phi[(int64_t)c * a.ld + i];
+        const double av = fabs(v);
+        if (av > best) { best = av; bidx = i; bval = v; }  // increasing i: strict > keeps first
     }
     __shared__ double sb[256], sv[256];
     __shared__ int64_t si[256];
@@ -510,75 +609,77 @@ __global__ __launch_bounds__(256) void k_colmax(const T* __restrict__ Phi, int64
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const int64_t slot = (int64_t)c * gridDim.x + ch;
-        pval[slot] = (sb[0] < 0.0) ? 0.0 : sv[0];
-        pidx[slot] = si[0];
+        const int64_t slot = (int64_t)c * a.nchunk + ch;
+        a.pval[slot] = (sb[0] < 0.0) ? 0.0 : sv[0];
+        a.pidx[slot] = si[0];
     }
 }
 
-__global__ void k_signs(const double* __restrict__ pval, const int64_t* __restrict__ pidx, int nchunk, int r,
-                        double* __restrict__ signs) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= r) return;
+__global__ void k_signs(Group<SignArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const SignArgs& a = g.args[it];
+    const int c = (blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
+    if (c >= a.r) return;
     double best = -1.0, bval = 0.0;
     int64_t bidx = INT64_MAX;
-    for (int k = 0; k < nchunk; ++k) {
-        const double v = pval[(int64_t)c * nchunk + k];
-        const int64_t ix = pidx[(int64_t)c * nchunk + k];
-        const double a = fabs(v);
-        if (a > best || (a == best && ix < bidx)) { best = a; bval = v; bidx = ix; }
+    for (int k = 0; k < a.nchunk; ++k) {
+        const double v = a.pval[(int64_t)c * a.nchunk + k];
+        const int64_t ix = a.pidx[(int64_t)c * a.nchunk + k];
+        const double av = fabs(v);
+        if (av > best || (av == best && ix < bidx)) { best = av; bval = v; bidx = ix; }
     }
-    signs[c] = (bval < 0.0) ? -1.0 : 1.0;
+    a.signs[c] = (bval < 0.0) ? -1.0 : 1.0;
 }
 
-hipError_t launch_signs(int tphi, const void* Phi, int64_t ld, int64_t m, int r, int nchunk, double* part_val,
-                        int64_t* part_idx, double* signs, hipStream_t st) {
-    const int64_t chunk = (m + nchunk - 1) / nchunk;
-    dim3 grid(nchunk, r);
+hipError_t launch_signs(int tphi, const GroupLaunch<ColmaxArgs>& C, const GroupLaunch<SignArgs>& S, hipStream_t st) {
     if (tphi == DT_F64)
-        hipLaunchKernelGGL(k_colmax<double>, grid, dim3(256), 0, st, (const double*)Phi, ld, m, chunk, part_val, part_idx);
+        hipLaunchKernelGGL(k_colmax<double>, dim3(C.tiles), dim3(256), 0, st, mkg(C));
     else
-        hipLaunchKernelGGL(k_colmax<float>, grid, dim3(256), 0, st, (const float*)Phi, ld, m, chunk, part_val, part_idx);
+        hipLaunchKernelGGL(k_colmax<float>, dim3(C.tiles), dim3(256), 0, st, mkg(C));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_signs, dim3((r + 63) / 64), dim3(64), 0, st, part_val, part_idx, nchunk, r, signs);
+    hipLaunchKernelGGL(k_signs, dim3(S.tiles), dim3(64), 0, st, mkg(S));
     return hipGetLastError();
 }
 
+// grouped: Phi tiles (rows 256 (t % nb).., column t / nb); outputs from the call table
 template <typename T>
-__global__ void k_fin_phi(const T* __restrict__ Pin, int64_t ldP, int64_t m, int r, const double* __restrict__ signs,
-                          T* __restrict__ Pout) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (i >= m) return;
-    Pout[(int64_t)c * m + i] = (T)(signs[c] * (double)Pin[(int64_t)c * ldP + i]);
+__global__ void k_fin_phi(Group<FinArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const FinArgs& a = g.args[it];
+    const int t = blockIdx.x - g.tstart[it];
+    const int nb = (int)((a.m + 255) / 256);
+    const int c = t / nb;
+    const int64_t i = (int64_t)(t % nb) * blockDim.x + threadIdx.x;
+    if (i >= a.m) return;
+    GLOBAL T* Pout = gbl((T*)g.calls[a.call].Phi);
+    const GLOBAL T* Pin = gbl((const T*)a.Phi_int);
+    Pout[(int64_t)c * a.m + i] = (T)(a.signs[c] * (double)Pin[(int64_t)c * a.ldP + i]);
 }
 
 template <typename T>
-__global__ void k_fin_a(const double* __restrict__ At, int64_t ldA, int64_t n, int r, const double* __restrict__ signs,
-                        const double* __restrict__ sig, T* __restrict__ Aout, double* __restrict__ sigma_out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < (int64_t)r && blockIdx.y == 0) sigma_out[e] = sig[e];
-    if (e >= n * r) return;
-    const int64_t j = e / r;
-    const int k = (int)(e % r);
-    Aout[e] = (T)(signs[k] * At[(int64_t)k * ldA + j]);
+__global__ void k_fin_a(Group<FinArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const FinArgs& a = g.args[it];
+    const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
+    const CallDesc& cd = g.calls[a.call];
+    if (e < (int64_t)a.r) cd.sigma[e] = a.sig[e];
+    if (e >= a.n * a.r) return;
+    const int64_t j = e / a.r;
+    const int k = (int)(e % a.r);
+    gbl((T*)cd.A)[e] = (T)(a.signs[k] * gbl(a.At)[(int64_t)k * a.ldA + j]);
 }
 
-hipError_t launch_finalize(int tphi, const void* Phi_int, int64_t ldP, int64_t m, int r, const double* At,
-                           int64_t ldA, int64_t n, const double* signs, const double* sig, void* Phi_out,
-                           void* A_out, double* sigma_out, hipStream_t st) {
-    dim3 gp((unsigned)((m + 255) / 256), r);
-    const int64_t na = n * r > r ? n * r : r;
-    dim3 ga((unsigned)((na + 255) / 256));
+int fin_phi_tiles(int64_t m, int r) { return (int)((m + 255) / 256) * r; }
+int fin_a_tiles(int64_t n, int r) { return (int)(((n * r > r ? n * r : r) + 255) / 256); }
+
+hipError_t launch_finalize(int tphi, const GroupLaunch<FinArgs>& P, const GroupLaunch<FinArgs>& A, hipStream_t st) {
     if (tphi == DT_F64) {
-        hipLaunchKernelGGL(k_fin_phi<double>, gp, dim3(256), 0, st, (const double*)Phi_int, ldP, m, r, signs,
-                           (double*)Phi_out);
-        hipLaunchKernelGGL(k_fin_a<double>, ga, dim3(256), 0, st, At, ldA, n, r, signs, sig, (double*)A_out, sigma_out);
+        hipLaunchKernelGGL(k_fin_phi<double>, dim3(P.tiles), dim3(256), 0, st, mkg(P));
+        hipLaunchKernelGGL(k_fin_a<double>, dim3(A.tiles), dim3(256), 0, st, mkg(A));
     } else {
-        hipLaunchKernelGGL(k_fin_phi<float>, gp, dim3(256), 0, st, (const float*)Phi_int, ldP, m, r, signs,
-                           (float*)Phi_out);
-        hipLaunchKernelGGL(k_fin_a<float>, ga, dim3(256), 0, st, At, ldA, n, r, signs, sig, (float*)A_out, sigma_out);
+        hipLaunchKernelGGL(k_fin_phi<float>, dim3(P.tiles), dim3(256), 0, st, mkg(P));
+        hipLaunchKernelGGL(k_fin_a<float>, dim3(A.tiles), dim3(256), 0, st, mkg(A));
     }
     return hipGetLastError();
 }

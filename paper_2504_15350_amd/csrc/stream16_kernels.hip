@@ -54,13 +54,13 @@ template <> struct mma16<_Float16> {
 
 // Eight consecutive rows i..i+7 of column j (16-bit), zero outside [0,lim) x [0,n).
 template <bool VEC>
-__device__ __forceinline__ u16x8 load_rows8(const unsigned short* S, int64_t ld, int64_t lim, int64_t n,
+__device__ __forceinline__ u16x8 load_rows8(const GLOBAL unsigned short* S, int64_t ld, int64_t lim, int64_t n,
                                             int64_t i, int64_t j) {
     u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
     if (j < n) {
-        const unsigned short* p = S + j * ld + i;
+        const GLOBAL unsigned short* p = S + j * ld + i;
         if (VEC && i + 7 < lim) {
-            v = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(p));  // streamed once
+            v = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL u16x8*>(p));  // streamed once
         } else {
 #pragma unroll
             for (int t = 0; t < 8; ++t)
@@ -85,14 +85,14 @@ constexpr int SX16_LDR = SX16_BM + 4;   // S tile column stride (elements): conf
 constexpr int SX16_LDX = SX16_BK + 8;   // X tile column stride (elements): conflict-free 16-byte reads
 
 template <typename T16, int NT, bool VEC>
-__global__ __launch_bounds__(256, 2) void k_sx16(const unsigned short* __restrict__ S, int64_t ldS, int64_t m,
-                                                 int64_t n, const unsigned short* __restrict__ X, int64_t ldX,
-                                                 float* __restrict__ Y, int64_t ldY, int64_t mstore) {
+__device__ __forceinline__ void sx16_body(const GLOBAL unsigned short* __restrict__ S, int64_t ldS, int64_t m,
+                                          int64_t n, const GLOBAL unsigned short* __restrict__ X, int64_t ldX,
+                                          GLOBAL float* __restrict__ Y, int64_t ldY, int64_t mstore, int64_t bx) {
     __shared__ unsigned short tile[SX16_BK * SX16_LDR];
     __shared__ __attribute__((aligned(16))) unsigned short xt[16 * NT * SX16_LDX];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
-    const int64_t i0 = (int64_t)blockIdx.x * SX16_BM;
+    const int64_t i0 = bx * SX16_BM;
     const int rg = tid & 31, cc = tid >> 5;  // S staging: rows 8 rg..+7 of columns cc + 8 q
     constexpr int XCH = 16 * NT * (SX16_BK / 8);  // 16-byte chunks of the X tile
     constexpr int XPT = (XCH + 255) / 256;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256, 2) void k_sx16(const unsigned short* __restric
                 const int ch = tid + 256 * q;
                 if (ch < XCH) {
                     const int c = ch / (SX16_BK / 8), part = ch % (SX16_BK / 8);
-                    xr[q] = *reinterpret_cast<const u16x8*>(X + (int64_t)c * ldX + j0 + 8 * part);
+                    xr[q] = *reinterpret_cast<const GLOBAL u16x8*>(X + (int64_t)c * ldX + j0 + 8 * part);
                 }
             }
         };
@@ -156,15 +156,24 @@ __global__ __launch_bounds__(256, 2) void k_sx16(const unsigned short* __restric
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             const int64_t row = i0 + wave * 64 + 16 * mt + 4 * kg;
-            float* py = Y + (int64_t)(16 * c + r16) * ldY + row;
+            GLOBAL float* py = Y + (int64_t)(16 * c + r16) * ldY + row;
             if (row + 3 < mstore) {
-                *reinterpret_cast<f32x4*>(py) = acc[mt][c];
+                *reinterpret_cast<GLOBAL f32x4*>(py) = acc[mt][c];
             } else {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     if (row + v < mstore) py[v] = acc[mt][c][v];
             }
         }
+}
+
+template <typename T16, int NT, bool VEC>
+__global__ __launch_bounds__(256, 2) void k_sx16(Group<SxArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const SxArgs& a = g.args[it];
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    sx16_body<T16, NT, VEC>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.X), a.ldX,
+                            gbl((float*)a.Y), a.ldY, a.mstore, blockIdx.x - g.tstart[it]);
 }
 
 // ---------------------------------------------------------------------------
@@ -186,11 +195,10 @@ __global__ __launch_bounds__(256, 2) void k_sx16(const unsigned short* __restric
 constexpr int STQ16_HB = 128;  // columns per block
 
 template <typename T16, int NT, bool VEC, bool LO, int G>
-__global__ __launch_bounds__(256, 2) void k_stq16(const unsigned short* __restrict__ S, int64_t ldS, int64_t m,
-                                                  int64_t n, const unsigned short* __restrict__ Qh,
-                                                  const unsigned short* __restrict__ Ql, int64_t ldQ,
-                                                  double* __restrict__ Zp, int64_t nP, int nsplit, int ncb,
-                                                  int ntiles) {
+__device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restrict__ S, int64_t ldS, int64_t m,
+                                           int64_t n, const GLOBAL unsigned short* __restrict__ Qh,
+                                           const GLOBAL unsigned short* __restrict__ Ql, int64_t ldQ,
+                                           GLOBAL double* __restrict__ Zp, int64_t nP, int nsplit, int ncb, int tile) {
     constexpr int R = LO ? 64 : 128;
     constexpr int LDS_ = R + 8;   // column stride (elements) of the LDS blocks
     constexpr int LPC = R / 8;    // 16-byte chunks per column of a block
@@ -198,8 +206,6 @@ __global__ __launch_bounds__(256, 2) void k_stq16(const unsigned short* __restri
     constexpr int HB = STQ16_HB;
     __shared__ __attribute__((aligned(16))) unsigned short ss[HB * LDS_];
     __shared__ __attribute__((aligned(16))) unsigned short qs[NQ * 16 * NT * LDS_];
-    const int tile = blockIdx.x;
-    if (tile >= ntiles) return;
     const int cb = tile % ncb, sp = tile / ncb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -231,8 +237,8 @@ __global__ __launch_bounds__(256, 2) void k_stq16(const unsigned short* __restri
             const int ch = tid + 256 * q;
             if (ch < QCH) {
                 const int64_t off = (int64_t)(ch / LPC) * ldQ + i0 + 8 * (ch % LPC);
-                qr[0][q] = *reinterpret_cast<const u16x8*>(Qh + off);
-                if (LO) qr[NQ - 1][q] = *reinterpret_cast<const u16x8*>(Ql + off);
+                qr[0][q] = *reinterpret_cast<const GLOBAL u16x8*>(Qh + off);
+                if (LO) qr[NQ - 1][q] = *reinterpret_cast<const GLOBAL u16x8*>(Ql + off);
             }
         }
     };
@@ -291,78 +297,87 @@ __global__ __launch_bounds__(256, 2) void k_stq16(const unsigned short* __restri
         }
         compute(G - 1);
     }
-    double* zp = Zp + (int64_t)sp * nP * (16 * NT);
+    GLOBAL double* zp = Zp + (int64_t)sp * nP * (16 * NT);
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
-                double* pz = zp + (int64_t)(16 * c + r16) * nP + j0 + HB * g + 32 * wave + 16 * u + 4 * kg;
+                GLOBAL double* pz = zp + (int64_t)(16 * c + r16) * nP + j0 + HB * g + 32 * wave + 16 * u + 4 * kg;
                 typedef double d4 __attribute__((ext_vector_type(4)));
-                *reinterpret_cast<d4*>(pz) = d4{acc[g][u][c][0], acc[g][u][c][1], acc[g][u][c][2], acc[g][u][c][3]};
+                *reinterpret_cast<GLOBAL d4*>(pz) = d4{acc[g][u][c][0], acc[g][u][c][1], acc[g][u][c][2], acc[g][u][c][3]};
             }
+}
+
+// grouped launch: local tile t covers column block t % ncb of split t / ncb
+template <typename T16, int NT, bool VEC, bool LO, int G>
+__global__ __launch_bounds__(256, 2) void k_stq16(Group<StqArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const StqArgs& a = g.args[it];
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    stq16_body<T16, NT, VEC, LO, G>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q),
+                                    gbl((const unsigned short*)a.Ql), a.ldQ, gbl(a.Zp), a.nP, a.nsplit, a.ncb,
+                                    blockIdx.x - g.tstart[it]);
 }
 
 // Split an FP32 tall matrix into 16-bit hi = round(q) and lo = round(q - hi).
 template <typename T16>
-__global__ void k_split16(const float* __restrict__ Q, int64_t count, unsigned short* __restrict__ hi,
-                          unsigned short* __restrict__ lo) {
-    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (e >= count) return;
-    const f32x4 q = *reinterpret_cast<const f32x4*>(Q + e);
+__global__ void k_split16(Group<SplitArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const SplitArgs& sa = g.args[it];
+    const GLOBAL float* __restrict__ Q = gbl(sa.Q);
+    GLOBAL unsigned short* __restrict__ hi = gbl(sa.hi);
+    GLOBAL unsigned short* __restrict__ lo = gbl(sa.lo);
+    const int64_t e = ((int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x) * 4;
+    if (e >= sa.count) return;
+    const f32x4 q = *reinterpret_cast<const GLOBAL f32x4*>(Q + e);
     u16x4 h, l;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         h[i] = mma16<T16>::from_float(q[i]);
         l[i] = mma16<T16>::from_float(q[i] - mma16<T16>::to_float(h[i]));
     }
-    *reinterpret_cast<u16x4*>(hi + e) = h;
-    *reinterpret_cast<u16x4*>(lo + e) = l;
+    *reinterpret_cast<GLOBAL u16x4*>(hi + e) = h;
+    *reinterpret_cast<GLOBAL u16x4*>(lo + e) = l;
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <typename A>
+static Group<A> mkgroup16(const GroupLaunch<A>& L) {
+    Group<A> g;
+    g.args = L.args;
+    g.tstart = L.tstart;
+    g.calls = L.calls;
+    g.count = L.count;
+    return g;
+}
+
 template <typename T16, int NT>
-static hipError_t sx16_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const void* X, int64_t ldX, void* Y,
-                          int64_t ldY, int64_t mstore, hipStream_t st) {
-    const int64_t rows = mstore > m ? mstore : m;
-    dim3 grid((unsigned)((rows + SX16_BM - 1) / SX16_BM));
-    const bool vec = (ldS % 8 == 0) && ((uintptr_t)S % 16 == 0);
+static hipError_t sx16_nt(const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st) {
     if (vec)
-        hipLaunchKernelGGL((k_sx16<T16, NT, true>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS, m, n,
-                           (const unsigned short*)X, ldX, (float*)Y, ldY, mstore);
+        hipLaunchKernelGGL((k_sx16<T16, NT, true>), dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
     else
-        hipLaunchKernelGGL((k_sx16<T16, NT, false>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS, m, n,
-                           (const unsigned short*)X, ldX, (float*)Y, ldY, mstore);
+        hipLaunchKernelGGL((k_sx16<T16, NT, false>), dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
     return hipGetLastError();
 }
 
 template <typename T16, int NT, bool LO>
-static hipError_t stq16_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const unsigned short* Qh,
-                           const unsigned short* Ql, int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows,
-                           int nsplit, hipStream_t st) {
-    (void)split_rows;  // splits are interleaved in steps of R rows
+static hipError_t stq16_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
     constexpr int G = LO ? 2 : 1;  // measured: one Q block per 128 columns (hi), per 256 (hi + lo)
-    const int ncb = (int)(nP / (G * STQ16_HB));
-    const int ntiles = ncb * nsplit;
-    dim3 grid((unsigned)ntiles);
-    const bool vec = (ldS % 8 == 0) && ((uintptr_t)S % 16 == 0);
     if (vec)
-        hipLaunchKernelGGL((k_stq16<T16, NT, true, LO, G>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS,
-                           m, n, Qh, Ql, ldQ, Zp, nP, nsplit, ncb, ntiles);
+        hipLaunchKernelGGL((k_stq16<T16, NT, true, LO, G>), dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
     else
-        hipLaunchKernelGGL((k_stq16<T16, NT, false, LO, G>), grid, dim3(256), 0, st, (const unsigned short*)S, ldS,
-                           m, n, Qh, Ql, ldQ, Zp, nP, nsplit, ncb, ntiles);
+        hipLaunchKernelGGL((k_stq16<T16, NT, false, LO, G>), dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
     return hipGetLastError();
 }
 
 template <typename T16>
-static hipError_t sx16_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* X,
-                                int64_t ldX, void* Y, int64_t ldY, int64_t mstore, hipStream_t st) {
+static hipError_t sx16_dispatch(int nt, const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st) {
     switch (nt) {
-#define RPOD_C(K) case K: return sx16_nt<T16, K>(S, ldS, m, n, X, ldX, Y, ldY, mstore, st);
+#define RPOD_C(K) case K: return sx16_nt<T16, K>(L, vec, st);
         RPOD_C(1) RPOD_C(2) RPOD_C(3) RPOD_C(4) RPOD_C(5) RPOD_C(6) RPOD_C(7) RPOD_C(8)
 #undef RPOD_C
         default: return hipErrorInvalidValue;
@@ -370,44 +385,37 @@ static hipError_t sx16_dispatch(int nt, const void* S, int64_t ldS, int64_t m, i
 }
 
 template <typename T16, bool LO>
-static hipError_t stq16_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
-                                 const unsigned short* Qh, const unsigned short* Ql, int64_t ldQ, double* Zp,
-                                 int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
+static hipError_t stq16_dispatch(int nt, const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
     switch (nt) {
-#define RPOD_C(K) case K: return stq16_nt<T16, K, LO>(S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st);
+#define RPOD_C(K) case K: return stq16_nt<T16, K, LO>(L, vec, st);
         RPOD_C(1) RPOD_C(2) RPOD_C(3) RPOD_C(4) RPOD_C(5) RPOD_C(6) RPOD_C(7) RPOD_C(8)
 #undef RPOD_C
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sx16(int tin, int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* X,
-                       int64_t ldX, float* Y, int64_t ldY, int64_t mstore, hipStream_t st) {
-    if (tin == DT_BF16) return sx16_dispatch<__bf16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, st);
-    if (tin == DT_F16) return sx16_dispatch<_Float16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, st);
+int stq16_block_cols(bool lo) { return (lo ? 2 : 1) * STQ16_HB; }
+int stq16_rows_per_step(bool lo) { return lo ? 64 : 128; }
+
+hipError_t launch_sx16(int tin, int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st) {
+    if (tin == DT_BF16) return sx16_dispatch<__bf16>(nt, L, vec, st);
+    if (tin == DT_F16) return sx16_dispatch<_Float16>(nt, L, vec, st);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stq16(int tin, int nt, bool lo, const void* S, int64_t ldS, int64_t m, int64_t n,
-                        const unsigned short* Qh, const unsigned short* Ql, int64_t ldQ, double* Zp, int64_t nP,
-                        int64_t split_rows, int nsplit, hipStream_t st) {
+hipError_t launch_stq16(int tin, int nt, bool lo, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st) {
     if (tin == DT_BF16)
-        return lo ? stq16_dispatch<__bf16, true>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st)
-                  : stq16_dispatch<__bf16, false>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st);
+        return lo ? stq16_dispatch<__bf16, true>(nt, L, vec, st) : stq16_dispatch<__bf16, false>(nt, L, vec, st);
     if (tin == DT_F16)
-        return lo ? stq16_dispatch<_Float16, true>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st)
-                  : stq16_dispatch<_Float16, false>(nt, S, ldS, m, n, Qh, Ql, ldQ, Zp, nP, split_rows, nsplit, st);
+        return lo ? stq16_dispatch<_Float16, true>(nt, L, vec, st) : stq16_dispatch<_Float16, false>(nt, L, vec, st);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_split16(int tin, const float* Q, int64_t count, unsigned short* hi, unsigned short* lo,
-                          hipStream_t st) {
-    if (count % 4) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((count / 4 + 255) / 256));
+hipError_t launch_split16(int tin, const GroupLaunch<SplitArgs>& L, hipStream_t st) {
     if (tin == DT_BF16)
-        hipLaunchKernelGGL(k_split16<__bf16>, grid, dim3(256), 0, st, Q, count, hi, lo);
+        hipLaunchKernelGGL(k_split16<__bf16>, dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
     else if (tin == DT_F16)
-        hipLaunchKernelGGL(k_split16<_Float16>, grid, dim3(256), 0, st, Q, count, hi, lo);
+        hipLaunchKernelGGL(k_split16<_Float16>, dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -19,13 +19,13 @@ using V4 = typename vec4_of<T>::type;
 
 // Four consecutive rows i..i+3 of column j, rows >= lim or columns >= n read 0.
 template <bool VEC, typename T>
-__device__ __forceinline__ V4<T> load_rows4(const T* S, int64_t ld, int64_t lim, int64_t n,
+__device__ __forceinline__ V4<T> load_rows4(const GLOBAL T* S, int64_t ld, int64_t lim, int64_t n,
                                             int64_t i, int64_t j) {
     V4<T> v = {0, 0, 0, 0};
     if (j < n) {
-        const T* p = S + j * ld + i;
+        const GLOBAL T* p = S + j * ld + i;
         if (VEC && i + 3 < lim) {
-            v = *reinterpret_cast<const V4<T>*>(p);
+            v = *reinterpret_cast<const GLOBAL V4<T>*>(p);
         } else {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
@@ -36,10 +36,10 @@ __device__ __forceinline__ V4<T> load_rows4(const T* S, int64_t ld, int64_t lim,
 }
 
 template <typename Tout, typename T>
-__device__ __forceinline__ void store4(Tout* p, T a, T b, T c, T d) {
+__device__ __forceinline__ void store4(GLOBAL Tout* p, T a, T b, T c, T d) {
     typedef typename vec4_of<Tout>::type VO;
     VO v = {narrow<Tout>(a), narrow<Tout>(b), narrow<Tout>(c), narrow<Tout>(d)};
-    *reinterpret_cast<VO*>(p) = v;
+    *reinterpret_cast<GLOBAL VO*>(p) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -51,14 +51,12 @@ __device__ __forceinline__ void store4(Tout* p, T a, T b, T c, T d) {
 // so output row mm of MFMA t is global row iw + 4 mm + t.
 // ---------------------------------------------------------------------------
 template <typename Tin, typename Tout, int NT, bool VEC, bool UPPER>
-__global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m, int64_t n,
-                                            const Tin* __restrict__ X, int64_t ldX, Tout* Y,
-                                            int64_t ldY, int64_t mstore, const int* cond,
-                                            int cond_mask) {
-    if (cond != nullptr && !(*cond & cond_mask)) return;
+__device__ __forceinline__ void sx_body(const GLOBAL Tin* S, int64_t ldS, int64_t m, int64_t n,
+                                        const GLOBAL Tin* __restrict__ X, int64_t ldX, GLOBAL Tout* Y, int64_t ldY,
+                                        int64_t mstore, int64_t bx) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
-    const int64_t iw = (int64_t)blockIdx.x * 256 + wave * 64;
+    const int64_t iw = bx * 256 + wave * 64;
     const int64_t irow = iw + 4 * r16;
 
     V4<Tin> acc[4][NT];
@@ -74,7 +72,7 @@ __global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m
             for (int s = 0; s < 4; ++s) a[s] = load_rows4<VEC>(S, ldS, m, n, irow, j0 + 4 * kg + s);
 #pragma unroll
             for (int c = 0; c < NT; ++c)
-                b[c] = *reinterpret_cast<const V4<Tin>*>(X + (int64_t)(16 * c + r16) * ldX + j0 + 4 * kg);
+                b[c] = *reinterpret_cast<const GLOBAL V4<Tin>*>(X + (int64_t)(16 * c + r16) * ldX + j0 + 4 * kg);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -90,7 +88,7 @@ __global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m
     // row iw + 4 mm + t: rows t = 0..3 are contiguous
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
-        Tout* py = Y + (int64_t)(16 * c + r16) * ldY;
+        GLOBAL Tout* py = Y + (int64_t)(16 * c + r16) * ldY;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = iw + 4 * mfma_row<Tin>(kg, v);
@@ -105,6 +103,16 @@ __global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m
     }
 }
 
+template <typename Tin, typename Tout, int NT, bool VEC, bool UPPER>
+__global__ __launch_bounds__(256) void k_sx(Group<SxArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const SxArgs& a = g.args[it];
+    if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    sx_body<Tin, Tout, NT, VEC, UPPER>(gbl((const Tin*)S), a.ldS, a.m, a.n, gbl((const Tin*)a.X), a.ldX,
+                                       gbl((Tout*)a.Y), a.ldY, a.mstore, blockIdx.x - g.tstart[it]);
+}
+
 // ---------------------------------------------------------------------------
 // Z_s = S_s^T Q_s for row split s. Workgroup = 4 waves = 256 columns of S
 // (each wave 4 tiles of 16 columns), streaming its split of rows 16 at a
@@ -112,13 +120,14 @@ __global__ __launch_bounds__(256) void k_sx(const Tin* S, int64_t ldS, int64_t m
 //   A[mm][k] = S[i0 + 4 k + s][jw + 16 u + mm],  B[k][nn] = Q[i0 + 4 k + s][16 c + nn].
 // ---------------------------------------------------------------------------
 template <typename Tin, int NT, bool VEC>
-__global__ __launch_bounds__(256) void k_stq(const Tin* __restrict__ S, int64_t ldS, int64_t m,
-                                             int64_t n, const Tin* __restrict__ Q, int64_t ldQ,
-                                             double* __restrict__ Zp, int64_t nP, int64_t split_rows) {
+__device__ __forceinline__ void stq_body(const GLOBAL Tin* __restrict__ S, int64_t ldS, int64_t m, int64_t n,
+                                         const GLOBAL Tin* __restrict__ Q, int64_t ldQ, GLOBAL double* __restrict__ Zp,
+                                         int64_t nP,
+                                         int64_t split_rows, int64_t bx, int64_t by) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
-    const int64_t jw = (int64_t)blockIdx.x * 256 + wave * 64;
-    const int64_t ib = (int64_t)blockIdx.y * split_rows;
+    const int64_t jw = bx * 256 + wave * 64;
+    const int64_t ib = by * split_rows;
     const int64_t ie = (ib + split_rows < m) ? ib + split_rows : m;
 
     V4<Tin> acc[4][NT];
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(256) void k_stq(const Tin* __restrict__ S, int64_t 
             for (int u = 0; u < 4; ++u) a[u] = load_rows4<VEC>(S, ldS, ie, n, i0 + 4 * kg, jw + 16 * u + r16);
 #pragma unroll
             for (int c = 0; c < NT; ++c)
-                b[c] = *reinterpret_cast<const V4<Tin>*>(Q + (int64_t)(16 * c + r16) * ldQ + i0 + 4 * kg);
+                b[c] = *reinterpret_cast<const GLOBAL V4<Tin>*>(Q + (int64_t)(16 * c + r16) * ldQ + i0 + 4 * kg);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -143,12 +152,12 @@ __global__ __launch_bounds__(256) void k_stq(const Tin* __restrict__ S, int64_t 
                     for (int c = 0; c < NT; ++c) acc[u][c] = mfma_16x16x4(a[u][s], b[c][s], acc[u][c]);
         }
     }
-    double* zp = Zp + (int64_t)blockIdx.y * nP * (16 * NT);
+    GLOBAL double* zp = Zp + by * nP * (16 * NT);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            double* pz = zp + (int64_t)(16 * c + r16) * nP + jw + 16 * u;
+            GLOBAL double* pz = zp + (int64_t)(16 * c + r16) * nP + jw + 16 * u;
             if constexpr (sizeof(Tin) == 4) {
                 store4<double>(pz + 4 * kg, acc[u][c][0], acc[u][c][1], acc[u][c][2], acc[u][c][3]);
             } else {
@@ -158,44 +167,58 @@ __global__ __launch_bounds__(256) void k_stq(const Tin* __restrict__ S, int64_t 
         }
 }
 
-__global__ void k_reduce_slabs(const double* __restrict__ Zp, int nsplit, int64_t count,
-                               double* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
+// grouped launch: local tile t covers column block t % ncb of split t / ncb
+template <typename Tin, int NT, bool VEC>
+__global__ __launch_bounds__(256) void k_stq(Group<StqArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const StqArgs& a = g.args[it];
+    const int t = blockIdx.x - g.tstart[it];
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    stq_body<Tin, NT, VEC>(gbl((const Tin*)S), a.ldS, a.m, a.n, gbl((const Tin*)a.Q), a.ldQ, gbl(a.Zp), a.nP,
+                           a.split_rows, t % a.ncb, t / a.ncb);
+}
+
+// out[e] = sum of the nsplit slabs, fixed order; 256 elements per workgroup
+__global__ void k_reduce_slabs(Group<ReduceArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const ReduceArgs& a = g.args[it];
+    const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
+    if (e >= a.count) return;
+    const GLOBAL double* Zp = gbl(a.Zp);
     double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += Zp[(int64_t)k * count + e];
-    out[e] = s;
+    for (int k = 0; k < a.nsplit; ++k) s += Zp[(int64_t)k * a.count + e];
+    *gbl(a.out + e) = s;
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <typename A>
+static Group<A> mkgroup(const A* args, const int* ts, int count, const CallDesc* calls) {
+    Group<A> g;
+    g.args = args;
+    g.tstart = ts;
+    g.calls = calls;
+    g.count = count;
+    return g;
+}
+
 template <typename Tin, typename Tout, int NT>
-static hipError_t sx_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const void* X, int64_t ldX,
-                        void* Y, int64_t ldY, int64_t mstore, const int* cond, int cond_mask, bool upper,
-                        hipStream_t st) {
-    const int64_t rows = mstore > m ? mstore : m;
-    dim3 grid((unsigned)((rows + 255) / 256));
-    const bool vec = (ldS % 4 == 0) && ((uintptr_t)S % (4 * sizeof(Tin)) == 0);
-    if (upper)  // internal operands only: always vector-aligned
-        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true, true>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
-                           (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
+static hipError_t sx_nt(const GroupLaunch<SxArgs>& L, bool vec, bool upper, hipStream_t st) {
+    const Group<SxArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
+    if (upper)
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true, true>), dim3(L.tiles), dim3(256), 0, st, g);
     else if (vec)
-        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
-                           (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true, false>), dim3(L.tiles), dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, false, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
-                           (const Tin*)X, ldX, (Tout*)Y, ldY, mstore, cond, cond_mask);
+        hipLaunchKernelGGL((k_sx<Tin, Tout, NT, false, false>), dim3(L.tiles), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
 template <typename Tin, typename Tout>
-static hipError_t sx_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* X,
-                              int64_t ldX, void* Y, int64_t ldY, int64_t mstore, const int* cond,
-                              int cond_mask, bool upper, hipStream_t st) {
+static hipError_t sx_dispatch(int nt, const GroupLaunch<SxArgs>& L, bool vec, bool upper, hipStream_t st) {
     switch (nt) {
-#define RPOD_SX_CASE(K) \
-    case K: return sx_nt<Tin, Tout, K>(S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
+#define RPOD_SX_CASE(K) case K: return sx_nt<Tin, Tout, K>(L, vec, upper, st);
         RPOD_SX_CASE(1) RPOD_SX_CASE(2) RPOD_SX_CASE(3) RPOD_SX_CASE(4)
         RPOD_SX_CASE(5) RPOD_SX_CASE(6) RPOD_SX_CASE(7) RPOD_SX_CASE(8)
 #undef RPOD_SX_CASE
@@ -203,42 +226,29 @@ static hipError_t sx_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int
     }
 }
 
-hipError_t launch_sx(int tin, int tout, int nt, const void* S, int64_t ldS, int64_t m, int64_t n,
-                     const void* X, int64_t ldX, void* Y, int64_t ldY, int64_t mstore, const int* cond,
-                     int cond_mask, hipStream_t st, bool upper) {
-    if (tin == DT_F64 && tout == DT_F64)
-        return sx_dispatch<double, double>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
-    if (tin == DT_F64 && tout == DT_F32)
-        return sx_dispatch<double, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
-    if (tin == DT_F32 && tout == DT_F32)
-        return sx_dispatch<float, float>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
-    if (tin == DT_F64 && tout == DT_BF16)
-        return sx_dispatch<double, __bf16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
-    if (tin == DT_F64 && tout == DT_F16)
-        return sx_dispatch<double, _Float16>(nt, S, ldS, m, n, X, ldX, Y, ldY, mstore, cond, cond_mask, upper, st);
+hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const GroupLaunch<SxArgs>& L, hipStream_t st) {
+    if (tin == DT_F64 && tout == DT_F64) return sx_dispatch<double, double>(nt, L, vec, upper, st);
+    if (tin == DT_F64 && tout == DT_F32) return sx_dispatch<double, float>(nt, L, vec, upper, st);
+    if (tin == DT_F32 && tout == DT_F32) return sx_dispatch<float, float>(nt, L, vec, upper, st);
+    if (tin == DT_F64 && tout == DT_BF16) return sx_dispatch<double, __bf16>(nt, L, vec, upper, st);
+    if (tin == DT_F64 && tout == DT_F16) return sx_dispatch<double, _Float16>(nt, L, vec, upper, st);
     return hipErrorInvalidValue;
 }
 
 template <typename Tin, int NT>
-static hipError_t stq_nt(const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q, int64_t ldQ,
-                         double* Zp, int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
-    dim3 grid((unsigned)(nP / 256), (unsigned)nsplit);
-    const bool vec = (ldS % 4 == 0) && ((uintptr_t)S % (4 * sizeof(Tin)) == 0);
+static hipError_t stq_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
+    const Group<StqArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
     if (vec)
-        hipLaunchKernelGGL((k_stq<Tin, NT, true>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
-                           (const Tin*)Q, ldQ, Zp, nP, split_rows);
+        hipLaunchKernelGGL((k_stq<Tin, NT, true>), dim3(L.tiles), dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL((k_stq<Tin, NT, false>), grid, dim3(256), 0, st, (const Tin*)S, ldS, m, n,
-                           (const Tin*)Q, ldQ, Zp, nP, split_rows);
+        hipLaunchKernelGGL((k_stq<Tin, NT, false>), dim3(L.tiles), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
 template <typename Tin>
-static hipError_t stq_dispatch(int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q,
-                               int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit,
-                               hipStream_t st) {
+static hipError_t stq_dispatch(int nt, const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
     switch (nt) {
-#define RPOD_STQ_CASE(K) case K: return stq_nt<Tin, K>(S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+#define RPOD_STQ_CASE(K) case K: return stq_nt<Tin, K>(L, vec, st);
         RPOD_STQ_CASE(1) RPOD_STQ_CASE(2) RPOD_STQ_CASE(3) RPOD_STQ_CASE(4)
         RPOD_STQ_CASE(5) RPOD_STQ_CASE(6) RPOD_STQ_CASE(7) RPOD_STQ_CASE(8)
 #undef RPOD_STQ_CASE
@@ -246,16 +256,14 @@ static hipError_t stq_dispatch(int nt, const void* S, int64_t ldS, int64_t m, in
     }
 }
 
-hipError_t launch_stq(int tin, int nt, const void* S, int64_t ldS, int64_t m, int64_t n, const void* Q,
-                      int64_t ldQ, double* Zp, int64_t nP, int64_t split_rows, int nsplit, hipStream_t st) {
-    if (tin == DT_F64) return stq_dispatch<double>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
-    if (tin == DT_F32) return stq_dispatch<float>(nt, S, ldS, m, n, Q, ldQ, Zp, nP, split_rows, nsplit, st);
+hipError_t launch_stq(int tin, int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st) {
+    if (tin == DT_F64) return stq_dispatch<double>(nt, L, vec, st);
+    if (tin == DT_F32) return stq_dispatch<float>(nt, L, vec, st);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_slabs(const double* Zp, int nsplit, int64_t count, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_slabs, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, Zp, nsplit,
-                       count, out);
+hipError_t launch_reduce_slabs(const GroupLaunch<ReduceArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_slabs, dim3(L.tiles), dim3(256), 0, st, mkgroup(L.args, L.tstart, L.count, L.calls));
     return hipGetLastError();
 }
 

@@ -20,6 +20,9 @@ fourier_field   a QG-like field on a cell-centred nx x ny grid of
                 lowest Dirichlet modes sin(kx x) sin(ky y),
                 kx = pi a, ky = pi b / 2, with amplitude |k|^-beta times a
                 stationary unit-variance AR(1) series, plus white noise.
+batch_shapes    the shapes of an uneven batch: m in {2^16, 2^17, 2^18},
+                n in [500, 4000], r in {10, 25, 50, 100}, decay in
+                [0.05, 0.2], all drawn per matrix from the seed.
 """
 
 import os
@@ -178,3 +181,69 @@ def fourier_field_device(nx, ny, n, n_modes=200, beta=1.5, phi=0.95, noise_std=1
             blk += noise_std * torch.randn((t1 - t0, m), generator=gen, device=dev, dtype=torch.float32)
         St[t0:t1] = blk.to(dtype)
     return dict(St=St, modes=modes, kmag=kmag, amp=amp, T=T, nx=nx, ny=ny)
+
+
+# ---------------------------------------------------------------------------
+# uneven batches
+# ---------------------------------------------------------------------------
+
+BATCH_RANKS = (10, 25, 50, 100)
+
+
+def batch_shapes(count=64, seed=4):
+    """Shapes of an uneven batch of snapshot matrices, drawn from stream 5.
+
+    Per matrix (m, n, r, alpha): m = 2^k with k uniform in {16, 17, 18},
+    n a uniform integer in [500, 4000], r uniform in {10, 25, 50, 100} and
+    the spectral decay alpha uniform in [0.05, 0.2]. r + 10 <= n always.
+    """
+    g = rng(seed, _S_SHAPE)
+    out = []
+    for _ in range(count):
+        m = 1 << int(g.integers(16, 19))
+        n = int(g.integers(500, 4001))
+        r = int(BATCH_RANKS[int(g.integers(0, len(BATCH_RANKS)))])
+        alpha = float(g.uniform(0.05, 0.2))
+        out.append((m, n, r, alpha))
+    return out
+
+
+def lowrank_exp_device(m, n, decay, noise_std=1e-4, seed=1, K=256, dtype=None, device="cuda"):
+    """S = U diag(exp(-decay k)) V^T + noise built on the GPU with torch, as
+    St (n, m): U (m x K) and V (n x K) orthonormalised from seeded Gaussian
+    matrices by CholeskyQR twice (FP32 products on the device, the K x K
+    Cholesky factor and its inverse in FP64 on the host), noise
+    N(0, noise_std^2) from a seeded torch generator. Only plain FP32 matrix
+    products run on the device. For sizes too large for the host; not
+    bitwise equal to lowrank_exp()."""
+    import torch
+
+    dtype = torch.float32 if dtype is None else dtype
+    dev = torch.device(device)
+    K = min(K, n, m)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed) * 1000003 + _S_U)
+
+    def orth(rows):
+        X = torch.randn((rows, K), generator=gen, device=dev, dtype=torch.float32)
+        for _ in range(2):
+            G = (X.T.contiguous() @ X).to("cpu", torch.float64)
+            Rinv = np.linalg.inv(np.linalg.cholesky(G.numpy()).T)
+            X = X @ torch.from_numpy(Rinv.astype(np.float32)).to(dev)
+        return X
+
+    U = orth(m)
+    V = orth(n)
+    sig = torch.from_numpy(np.exp(-decay * np.arange(1, K + 1)).astype(np.float32)).to(dev)
+    C = V * sig[None, :]                              # (n, K)
+    U32 = U.T.contiguous()                            # (K, m)
+    del U, V
+    St = torch.empty((n, m), dtype=dtype, device=dev)
+    gen.manual_seed(int(seed) * 1000003 + _S_NOISE)
+    for t0 in range(0, n, 512):
+        t1 = min(n, t0 + 512)
+        blk = C[t0:t1] @ U32
+        if noise_std:
+            blk += noise_std * torch.randn((t1 - t0, m), generator=gen, device=dev, dtype=torch.float32)
+        St[t0:t1] = blk.to(dtype)
+    return St

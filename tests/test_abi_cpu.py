@@ -96,3 +96,40 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(rp, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         rp.lib()
+
+
+@needs_lib
+def test_batched_workspace_validation():
+    f32, f64 = torch.float32, torch.float64
+    a = rp.make_desc(3000, 300, 10, 10, 2, f32)
+    b = rp.make_desc(5000, 260, 25, 10, 2, f32)
+    # a batch of one is the single-matrix plan
+    assert rp.workspace_size_batched([a]) == rp.workspace_size(3000, 300, 10, 10, 2, f32)
+    two = rp.workspace_size_batched([a, b])
+    assert two > rp.workspace_size(3000, 300, 10, 10, 2, f32) + rp.workspace_size(5000, 260, 25, 10, 2, f32) // 2
+    with pytest.raises(rp.RpodError) as e:
+        rp.workspace_size_batched([a, rp.make_desc(3000, 300, 10, 10, 2, f64)])  # mixed dtype
+    assert e.value.status == 1
+    with pytest.raises(rp.RpodError) as e:
+        rp.workspace_size_batched([a, rp.make_desc(3000, 300, 10, 10, 1, f32)])  # mixed q
+    assert e.value.status == 1
+    with pytest.raises(rp.RpodError) as e:
+        rp.workspace_size_batched([a, rp.make_desc(3000, 300, 100, 29, 2, f32)])  # l > 128 in one member
+    assert e.value.status == 5
+    L = rp.lib()
+    out = ctypes.c_size_t(0)
+    arr = (rp._Desc * 1)(a)
+    assert L.rpod_workspace_size_batched(arr, 0, ctypes.byref(out)) == 1
+    assert L.rpod_workspace_size_batched(None, 1, ctypes.byref(out)) == 1
+    assert L.rpod_compute_batched(None, None, None, None, None, None) == 1
+    assert L.rpod_status_query_batched(None, None) == 1
+
+
+@needs_lib
+def test_batched_workspace_of_the_64_matrix_workload_fits_hbm():
+    """The 64-matrix uneven batch: workspace well under the 288 GB of one GPU."""
+    import synth
+    shapes = synth.batch_shapes(64, seed=4)
+    descs = [rp.make_desc(m, n, r, 10, 2, torch.bfloat16) for (m, n, r, _a) in shapes]
+    ws = rp.workspace_size_batched(descs)
+    assert 0 < ws < 40e9

@@ -1,0 +1,183 @@
+"""GPU parity of batched plans (rpod_plan_create_batched / rpod_compute_batched).
+
+A batch is several independent rPOD problems (Sec. 4.2 applied per matrix)
+of uneven shape in one plan whose launches each cover a whole class of
+matrices. Every matrix of a batch must match the FP64 oracle on its own
+sketch at the tolerances of its precision, exactly as a single plan does;
+the graph replay must equal the kernel-by-kernel launch bit for bit.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_15350_amd as rp
+import synth
+from oracle import rpod as orpod
+
+from test_gpu_parity import DEV, compare, say, sketch_for, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch_inputs(shapes, dtype, seed0, noise_std=1e-4):
+    """shapes: (m, n, r, p[, ld]) -> device tensors, oracle matrices, seeds."""
+    Sds, S64s, seeds = [], [], []
+    for i, sh in enumerate(shapes):
+        m, n, r, p = sh[:4]
+        ld = sh[4] if len(sh) > 4 else None
+        g = synth.lowrank_exp(m, n, decay=0.05 + 0.15 * (i % 4) / 3, noise_std=noise_std, seed=seed0 + i)
+        Sd, S64 = upload(g["St"], dtype, ld)
+        Sds.append(Sd)
+        S64s.append(S64)
+        seeds.append(1000 + 17 * i)
+    return Sds, S64s, seeds
+
+
+def _shapes_with_ld(shapes, Sds):
+    return [(m, n, r, p, Sd.stride(0)) for (m, n, r, p, *_), Sd in zip(shapes, Sds)]
+
+
+def _to_host(outs):
+    return [(P.double().cpu().numpy().T, s.cpu().numpy(), A.double().cpu().numpy().T) for P, s, A in outs]
+
+
+def _check_batch(shapes, q, dtype, seed0, name, noise_std=1e-4):
+    say(f"[batch] {name} count={len(shapes)} q={q} dtype={dtype}")
+    Sds, S64s, seeds = _batch_inputs(shapes, dtype, seed0, noise_std)
+    plan = rp.BatchPlan(_shapes_with_ld(shapes, Sds), q, dtype=dtype, device=DEV)
+    outs = _to_host(plan.compute(Sds, seeds))
+    say(f"[batch] {name} flags={plan.last_flags}")
+    results = []
+    for i, ((m, n, r, p, *_), S64) in enumerate(zip(shapes, S64s)):
+        om = sketch_for(seeds[i], n, r + p, dtype)
+        P2, s2, A2, ex = orpod.rpod_stable(S64, r, om, q)
+        res = compare(outs[i], (P2, s2, A2), dtype, r, ex["ritz"])
+        say(f"[batch] {name} matrix {i} m={m} n={n} r={r} p={p} ok {res}")
+        results.append(res)
+    plan.close()
+    return Sds, S64s, seeds, outs
+
+
+# four classes (padded sketch width / padded rank 32/16, 48/32, 32/32,
+# 112/112), ragged m and n, one odd leading dimension
+SHAPES = [
+    (3000, 300, 10, 10),
+    (5000, 260, 25, 10),
+    (1537, 411, 20, 5, 1541),
+    (4096, 500, 100, 10),
+    (2200, 333, 10, 12),
+    (6001, 290, 25, 8),
+]
+
+
+def test_batched_fp64_matches_oracle():
+    _check_batch(SHAPES, 1, torch.float64, 40, "fp64")
+
+
+def test_batched_fp32_matches_oracle_and_single_plans():
+    Sds, S64s, seeds, outs = _check_batch(SHAPES, 2, torch.float32, 50, "fp32")
+    for i, ((m, n, r, p, *_), Sd) in enumerate(zip(SHAPES, Sds)):
+        plan = rp.Plan(m, n, r, p, 2, dtype=torch.float32, ld=Sd.stride(0), device=DEV)
+        P1, s1, A1 = plan.compute(Sd, seeds[i])
+        plan.close()
+        s1 = s1.cpu().numpy()
+        # only the row split of S^T Q differs (FP64 summation order)
+        assert np.max(np.abs(outs[i][1] - s1) / s1) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+def test_batched_16bit_matches_oracle(dtype):
+    # white noise below the 16-bit rounding of S, so that the spectrum keeps
+    # a clear gap after mode r (the subspace angle scales with error / gap)
+    shapes = [(4096, 400, 25, 10), (3001, 350, 50, 10), (5120, 301, 10, 10, 5128)]
+    _check_batch(shapes, 2, dtype, 60, f"{dtype}", noise_std=1e-6)
+
+
+def test_graph_replay_equals_direct_launches():
+    """Replays of the captured graph, with unrelated eager work in between,
+    against the same plan built with RPOD_NO_GRAPH=1 (kernels launched one by one)."""
+    shapes = SHAPES[:4]
+    Sds, _, seeds = _batch_inputs(shapes, torch.float32, 70)
+    sh = _shapes_with_ld(shapes, Sds)
+    os.environ["RPOD_NO_GRAPH"] = "1"
+    try:
+        direct = rp.BatchPlan(sh, 2, dtype=torch.float32, device=DEV)
+    finally:
+        del os.environ["RPOD_NO_GRAPH"]
+    ref = _to_host(direct.compute(Sds, seeds))
+    direct.close()
+    graph = rp.BatchPlan(sh, 2, dtype=torch.float32, device=DEV)
+    outs = graph.alloc_outputs()
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=DEV)
+        junk.mul_(2.0).add_(1.0).sum().item()  # eager work and a synchronisation between replays
+        for o in outs:
+            for t in o:
+                t.fill_(float("nan"))
+        got = _to_host(graph.compute(Sds, seeds, outs=outs))
+        for i in range(len(shapes)):
+            for a, b in zip(got[i], ref[i]):
+                assert np.array_equal(a, b), f"replay {rep} matrix {i} differs from direct launches"
+        say(f"[graph] replay {rep} bitwise equal")
+    graph.close()
+
+
+def test_single_plan_graph_replay_equals_direct():
+    m, n, r, p, q = 3000, 280, 20, 10, 2
+    g = synth.lowrank_exp(m, n, decay=0.1, noise_std=1e-4, seed=80)
+    Sd, _ = upload(g["St"], torch.float32)
+    os.environ["RPOD_NO_GRAPH"] = "1"
+    try:
+        direct = rp.Plan(m, n, r, p, q, dtype=torch.float32, device=DEV)
+    finally:
+        del os.environ["RPOD_NO_GRAPH"]
+    ref = [t.cpu() for t in direct.compute(Sd, 5)]
+    direct.close()
+    plan = rp.Plan(m, n, r, p, q, dtype=torch.float32, device=DEV)
+    for rep in range(3):
+        torch.randn(1 << 18, device=DEV).sum().item()
+        got = [t.cpu() for t in plan.compute(Sd, 5)]
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), f"replay {rep}"
+    plan.close()
+
+
+def test_batched_breakdown_is_reported_per_matrix():
+    """A zero matrix inside a batch breaks down alone; the others stay correct."""
+    shapes = [(3000, 300, 10, 10), (2000, 200, 10, 6), (4000, 310, 25, 10)]
+    Sds, S64s, seeds = _batch_inputs(shapes, torch.float32, 90)
+    Sds[1].zero_()
+    plan = rp.BatchPlan(_shapes_with_ld(shapes, Sds), 1, dtype=torch.float32, device=DEV)
+    with pytest.raises(rp.RpodError) as ei:
+        plan.compute(Sds, seeds)
+    assert ei.value.status == 6
+    flags = plan.last_flags
+    assert flags[1] & rp.FLAG_BREAKDOWN
+    assert not (flags[0] & rp.FLAG_BREAKDOWN) and not (flags[2] & rp.FLAG_BREAKDOWN)
+    outs = _to_host(plan.compute(Sds, seeds, check=False))
+    torch.cuda.synchronize()
+    for i in (0, 2):
+        m, n, r, p = shapes[i]
+        om = sketch_for(seeds[i], n, r + p, torch.float32)
+        P2, s2, A2, ex = orpod.rpod_stable(S64s[i], r, om, 1)
+        compare(outs[i], (P2, s2, A2), torch.float32, r, ex["ritz"])
+    plan.close()
+
+
+def test_batched_plan_reuse_with_new_inputs():
+    """A batched plan reused with other matrices of the same shapes and other seeds."""
+    shapes = SHAPES[:3]
+    Sa, _, seeds = _batch_inputs(shapes, torch.float32, 100)
+    Sb, S64b, _ = _batch_inputs(shapes, torch.float32, 200)
+    plan = rp.BatchPlan(_shapes_with_ld(shapes, Sa), 1, dtype=torch.float32, device=DEV)
+    plan.compute(Sa, seeds)
+    seeds_b = [s + 1 for s in seeds]
+    outs = _to_host(plan.compute(Sb, seeds_b))
+    for i, (m, n, r, p, *_) in enumerate(shapes):
+        om = sketch_for(seeds_b[i], n, r + p, torch.float32)
+        P2, s2, A2, ex = orpod.rpod_stable(S64b[i], r, om, 1)
+        compare(outs[i], (P2, s2, A2), torch.float32, r, ex["ritz"])
+    plan.close()
