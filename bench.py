@@ -184,7 +184,7 @@ def make_batch(dev):
     return shapes, mats
 
 
-def measure_batch(mats, shapes, steps, warmup, batched=True):
+def measure_batch(mats, shapes, steps, warmup, batched=True, tuning=None):
     """Time one batched plan over all matrices (or one plan per matrix in
     sequence); per-pass kernel times from the library's HIP events."""
     import torch
@@ -193,7 +193,8 @@ def measure_batch(mats, shapes, steps, warmup, batched=True):
     seeds = [BATCH["seed0"] + 7 * i for i in range(len(mats))]
     dt = mats[0].dtype
     if batched:
-        plans = [rp.BatchPlan([(m, n, r, p) for (m, n, r, _a) in shapes], q, dtype=dt, device=mats[0].device)]
+        plans = [rp.BatchPlan([(m, n, r, p) for (m, n, r, _a) in shapes], q, dtype=dt, device=mats[0].device,
+                              tuning=tuning)]
         outs = [plans[0].alloc_outputs()]
         run = lambda: plans[0].compute(mats, seeds, outs=outs[0], check=False)
     else:
@@ -210,13 +211,22 @@ def measure_batch(mats, shapes, steps, warmup, batched=True):
         run()
     for pl in plans:
         pl.status()
-        pl.set_timing(True)
+    # graph replays (classes of a batch run as concurrent graph branches)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         run()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    # the same steps again, kernels launched one by one with per-pass events
+    for pl in plans:
+        pl.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ms_timed = (time.perf_counter() - t0) * 1e3 / steps
     flags = [pl.status() for pl in plans]
     tot = {0: [0, 0.0, 0.0], 1: [0, 0.0, 0.0]}
     for pl in plans:
@@ -239,8 +249,9 @@ def measure_batch(mats, shapes, steps, warmup, batched=True):
                            hbm_gbs_algorithmic=round(b / (t * 1e-3) / 1e9, 1) if t > 0 else None)
     s_bytes = sum(m * n for (m, n, _r, _a) in shapes) * mats[0].element_size() * (2 * q + 2)
     log(f"[bench] batch {'batched' if batched else 'sequential'} {dt}: {ms:.2f} ms per batch "
-        f"({len(mats)} matrices), flags {flags}, " + ", ".join(f"{k} {v}" for k, v in kern.items()))
-    return dict(ms=ms, sigma=sig, kernels=kern, hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
+        f"(kernel by kernel with events: {ms_timed:.2f} ms) "
+        f"({len(mats)} matrices), flags {sorted(set(sum(([f] if isinstance(f, int) else f for f in flags), [])))}, " + ", ".join(f"{k} {v}" for k, v in kern.items()))
+    return dict(ms=ms, ms_timed=ms_timed, sigma=sig, kernels=kern, hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
                 flags=flags)
 
 
@@ -251,12 +262,21 @@ def batch_block(dev, steps, warmup):
     torch.cuda.synchronize()
     elems = sum(m * n for (m, n, _r, _a) in shapes)
     log(f"[bench] generated the 64-matrix batch ({elems / 1e9:.2f} G elements) in {time.perf_counter() - t0:.1f} s")
+    import paper_2504_15350_amd as rp
+    bshapes = [(m, n, r, BATCH["p"]) for (m, n, r, _a) in shapes]
     plain = measure_batch(mats, shapes, steps, warmup, batched=False)
-    b32 = measure_batch(mats, shapes, steps, warmup, batched=True)
+    t0 = time.perf_counter()
+    tune32, tms32 = rp.autotune(bshapes, BATCH["q"], mats, repeats=2)
+    log(f"[bench] autotuned the FP32 batch in {time.perf_counter() - t0:.1f} s: {tune32} ({tms32:.2f} ms per call)")
+    b32 = measure_batch(mats, shapes, steps, warmup, batched=True, tuning=tune32)
     mats16 = [St.to(torch.bfloat16) for St in mats]
     del mats
     torch.cuda.empty_cache()
-    b16 = measure_batch(mats16, shapes, steps, warmup, batched=True)
+    b16d = measure_batch(mats16, shapes, steps, warmup, batched=True)
+    t0 = time.perf_counter()
+    tune16, tms16 = rp.autotune(bshapes, BATCH["q"], mats16, repeats=2)
+    log(f"[bench] autotuned the BF16 batch in {time.perf_counter() - t0:.1f} s: {tune16} ({tms16:.2f} ms per call)")
+    b16 = measure_batch(mats16, shapes, steps, warmup, batched=True, tuning=tune16)
     del mats16
     torch.cuda.empty_cache()
 
@@ -270,6 +290,11 @@ def batch_block(dev, steps, warmup):
         "plain_fp32_sequential_ms": round(plain["ms"], 3),
         "batched_fp32_ms": round(b32["ms"], 3),
         "batched_bf16_ms": round(b16["ms"], 3),
+        "batched_bf16_default_tuning_ms": round(b16d["ms"], 3),
+        "tuning": {"fp32": {"stq_workgroups": tune32.stq_workgroups, "gram_workgroups": tune32.gram_workgroups},
+                   "bf16": {"stq_workgroups": tune16.stq_workgroups, "gram_workgroups": tune16.gram_workgroups}},
+        "kernel_by_kernel_ms": {"plain_fp32": round(plain["ms_timed"], 3), "batched_fp32": round(b32["ms_timed"], 3),
+                                "batched_bf16": round(b16["ms_timed"], 3)},
         "speedup_batched_fp32": round(plain["ms"] / b32["ms"], 2),
         "speedup_batched_bf16": round(plain["ms"] / b16["ms"], 2),
         "sigma_rel_diff_batched_fp32_vs_plain": err(b32, plain),

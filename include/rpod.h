@@ -150,6 +150,50 @@ rpod_status rpod_workspace_size_batched(const rpod_desc* descs, int32_t count, s
 rpod_status rpod_plan_create_batched(rpod_plan* plan, const rpod_desc* descs, int32_t count,
                                      void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Launch-shape knobs of a plan (0 = the library's default for the field).
+ *   stq_workgroups   workgroups wanted per matrix for one S^T Q pass; the
+ *                    row-split count of that split-K product follows from it
+ *                    (at most 64 splits, at least 128 rows each).
+ *   gram_workgroups  most workgroups per matrix of a tall Gram matrix, <= 256.
+ *   reserved         must be 0.
+ * Results depend on the knobs only through the FP64 summation order of the
+ * split-K partial sums. */
+typedef struct {
+    int32_t stq_workgroups;
+    int32_t gram_workgroups;
+    int32_t reserved[6];
+} rpod_tuning;
+
+/* As rpod_workspace_size_batched / rpod_plan_create_batched with explicit
+ * knobs (tuning may be NULL: defaults). */
+rpod_status rpod_workspace_size_tuned(const rpod_desc* descs, int32_t count, const rpod_tuning* tuning,
+                                      size_t* bytes);
+rpod_status rpod_plan_create_tuned(rpod_plan* plan, const rpod_desc* descs, int32_t count,
+                                   const rpod_tuning* tuning, void* workspace, size_t workspace_bytes,
+                                   void* hip_stream);
+
+/* Autotuner of the knobs for a batch (count = 1 for one matrix): times
+ * whole compute calls (graph replays, HIP events on hip_stream) on the given
+ * matrices for a coordinate search over stq_workgroups in {128, 256, ...,
+ * 8192} and then gram_workgroups in {32, 64, 128, 256}, the defaults
+ * included, and returns the fastest in *best (host) with its time per call
+ * in milliseconds in *best_ms (host, may be NULL). Synchronous: returns
+ * after the last trial.
+ *   S          host array of `count` device pointers, as for rpod_compute_batched.
+ *   workspace  device, at least rpod_autotune_workspace_size() bytes, 256-byte
+ *              aligned; overwritten (trial plans and their outputs live there).
+ *   repeats    timed calls per candidate (>= 1), after one untimed call.
+ *   cache_path host string or NULL. If the file holds an entry for this batch
+ *              (a hash of the descriptions, the device name and its compute
+ *              unit count) it is returned without timing anything; otherwise
+ *              the result is appended to the file as one text line
+ *              "<key hex> <stq_workgroups> <gram_workgroups> <ms>". An
+ *              unreadable or unwritable file is ignored. */
+rpod_status rpod_autotune_workspace_size(const rpod_desc* descs, int32_t count, size_t* bytes);
+rpod_status rpod_autotune(const rpod_desc* descs, int32_t count, const void* const* S, void* workspace,
+                          size_t workspace_bytes, void* hip_stream, int32_t repeats, const char* cache_path,
+                          rpod_tuning* best, double* best_ms);
+
 /* Compute every matrix of a batched plan, enqueued on the plan's stream.
  * S, seeds, Phi, sigma, A: host arrays of `count` entries (the plan's
  * count), entry i being the argument of rpod_compute for matrix i (device

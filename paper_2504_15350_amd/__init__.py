@@ -16,7 +16,7 @@ import os
 
 import torch
 
-__all__ = ["RpodError", "Plan", "BatchPlan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
+__all__ = ["RpodError", "Plan", "BatchPlan", "Tuning", "autotune", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
            "STATUS", "FLAG_SHIFTED", "FLAG_BREAKDOWN", "FLAG_NONFINITE", "FLAG_JACOBI_SLOW"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,6 +39,15 @@ class _Desc(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("dtype", ctypes.c_int32), ("r", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    """Launch-shape knobs of a plan (rpod_tuning); 0 = library default."""
+    _fields_ = [("stq_workgroups", ctypes.c_int32), ("gram_workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+    def __repr__(self):
+        return f"Tuning(stq_workgroups={self.stq_workgroups}, gram_workgroups={self.gram_workgroups})"
 
 
 _lib = None
@@ -68,6 +77,13 @@ def lib():
             "rpod_compute_batched": [vp, ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), ctypes.POINTER(vp)],
             "rpod_status_query_batched": [vp, ctypes.POINTER(i32)],
+            "rpod_workspace_size_tuned": [ctypes.POINTER(_Desc), i32, ctypes.POINTER(Tuning),
+                                          ctypes.POINTER(ctypes.c_size_t)],
+            "rpod_plan_create_tuned": [ctypes.POINTER(vp), ctypes.POINTER(_Desc), i32, ctypes.POINTER(Tuning), vp,
+                                       ctypes.c_size_t, vp],
+            "rpod_autotune_workspace_size": [ctypes.POINTER(_Desc), i32, ctypes.POINTER(ctypes.c_size_t)],
+            "rpod_autotune": [ctypes.POINTER(_Desc), i32, ctypes.POINTER(vp), vp, ctypes.c_size_t, vp, i32,
+                              ctypes.c_char_p, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -106,11 +122,47 @@ def workspace_size(m, n, r, p, q, dtype, ld=None):
     return out.value
 
 
-def workspace_size_batched(descs):
+def workspace_size_batched(descs, tuning=None):
     arr = (_Desc * len(descs))(*descs)
     out = ctypes.c_size_t(0)
-    _check(lib().rpod_workspace_size_batched(arr, len(descs), ctypes.byref(out)))
+    if tuning is None:
+        _check(lib().rpod_workspace_size_batched(arr, len(descs), ctypes.byref(out)))
+    else:
+        _check(lib().rpod_workspace_size_tuned(arr, len(descs), ctypes.byref(tuning), ctypes.byref(out)))
     return out.value
+
+
+def _shape_descs(shapes, q, dtype):
+    out = []
+    for sh in shapes:
+        m, n, r, p = (int(x) for x in sh[:4])
+        ld = int(sh[4]) if len(sh) > 4 else m
+        out.append(((m, n, r, p, ld), make_desc(m, n, r, p, q, dtype, ld)))
+    return out
+
+
+def autotune(shapes, q, Sts, dtype=None, repeats=3, cache=None, device=None, stream=None):
+    """rpod_autotune over a batch given as shapes (m, n, r, p[, ld]) and the
+    device tensors Sts; returns (Tuning, ms per call). cache: a text file
+    path (default: environment variable RPOD_TUNE_CACHE, if set)."""
+    dtype = Sts[0].dtype if dtype is None else dtype
+    dev = _norm_device(Sts[0].device if device is None else device)
+    sd = _shape_descs(shapes, q, dtype)
+    for St, ((m, n, _r, _p, ld), _d) in zip(Sts, sd):
+        _check_St(St, dtype, dev, m, n, ld)
+    arr = (_Desc * len(sd))(*[d for _, d in sd])
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().rpod_autotune_workspace_size(arr, len(sd), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    sptr, _s = _stream_ptr(stream, dev)
+    S_arr = (ctypes.c_void_p * len(sd))(*[St.data_ptr() for St in Sts])
+    cache = os.environ.get("RPOD_TUNE_CACHE") if cache is None else cache
+    best = Tuning()
+    ms = ctypes.c_double(0)
+    _check(lib().rpod_autotune(arr, len(sd), S_arr, _dev_ptr(ws), nbytes.value, sptr, int(repeats),
+                               None if cache is None else str(cache).encode(), ctypes.byref(best), ctypes.byref(ms)))
+    del ws
+    return best, ms.value
 
 
 class _PlanBase:
@@ -207,26 +259,27 @@ class BatchPlan(_PlanBase):
     shapes: list of (m, n, r, p) or (m, n, r, p, ld); all share dtype and q.
     """
 
-    def __init__(self, shapes, q, dtype=torch.float32, device="cuda", stream=None):
+    def __init__(self, shapes, q, dtype=torch.float32, device="cuda", stream=None, tuning=None):
         self.device = _norm_device(device)
         self.dtype = dtype
         self.q = int(q)
         self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
-        self.shapes = []
-        descs = []
-        for sh in shapes:
-            m, n, r, p = (int(x) for x in sh[:4])
-            ld = int(sh[4]) if len(sh) > 4 else m
-            self.shapes.append((m, n, r, p, ld))
-            descs.append(make_desc(m, n, r, p, q, dtype, ld))
+        sd = _shape_descs(shapes, q, dtype)
+        self.shapes = [sh for sh, _ in sd]
+        descs = [d for _, d in sd]
         self.count = len(descs)
+        self.tuning = tuning
         self._descs = (_Desc * self.count)(*descs)
-        nbytes = workspace_size_batched(descs)
+        nbytes = workspace_size_batched(descs, tuning)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         sptr, self.stream = _stream_ptr(stream, self.device)
         h = ctypes.c_void_p()
-        _check(lib().rpod_plan_create_batched(ctypes.byref(h), self._descs, self.count, _dev_ptr(self.workspace),
-                                              nbytes, sptr))
+        if tuning is None:
+            _check(lib().rpod_plan_create_batched(ctypes.byref(h), self._descs, self.count,
+                                                  _dev_ptr(self.workspace), nbytes, sptr))
+        else:
+            _check(lib().rpod_plan_create_tuned(ctypes.byref(h), self._descs, self.count, ctypes.byref(tuning),
+                                                _dev_ptr(self.workspace), nbytes, sptr))
         self._h = h
 
     def alloc_outputs(self):

@@ -52,6 +52,7 @@ struct Layout {
     int nsplit, ncb_lo;
     int64_t split_rows;
     int nchunk;
+    int gram_cap;
     // byte offsets into the matrix's workspace region
     size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
@@ -76,9 +77,10 @@ rpod_status validate(const rpod_desc* d) {
 }
 
 // wg_target: workgroups wanted for one S^T Q pass of this matrix (the row
-// split count follows from it).
-Layout make_layout(const rpod_desc* d, int64_t wg_target) {
+// split count follows from it); gram_cap: most workgroups of a tall Gram.
+Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     Layout L{};
+    L.gram_cap = gram_cap;
     L.l = d->r + d->p;
     L.lp = (int)roundup(L.l, 16);
     L.nt = L.lp / 16;
@@ -368,7 +370,7 @@ struct Recorder {
         auto gargs = [&](auto buf, bool cond) {
             return each([&](const Item& it) {
                 return GramArgs{buf(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m)};
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap)};
             });
         };
         auto cargs = [&](int k, int mode) {
@@ -418,7 +420,7 @@ struct Recorder {
             return each([&](const Item& it) {
                 return GramArgs{P->at<char>(it, second ? it.L.o_Zw2 : it.L.o_Zw), it.L.nP, it.d.n,
                                 P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.n)};
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.n, it.L.gram_cap)};
             });
         };
         auto app = [&](size_t Layout::*src, size_t Layout::*dst, int k, bool cond) {
@@ -447,7 +449,7 @@ struct Recorder {
         // step 6: SVD of T through the eigenvectors of T T^T
         gram(DT_F64, each([&](const Item& it) {
                  return GramArgs{P->at<char>(it, it.L.o_Zw), it.L.nP, it.d.n, P->at<double>(it, it.L.o_Gpart),
-                                 P->at<double>(it, it.L.o_G), nullptr, 0, gram_nwg(it.d.n)};
+                                 P->at<double>(it, it.L.o_G), nullptr, 0, gram_nwg(it.d.n, it.L.gram_cap)};
              }));
         Step j{K_JACOBI};
         j.lp = L.lp;
@@ -635,7 +637,18 @@ struct BatchLayout {
     size_t o_flags, o_calls, o_items_end;
 };
 
-rpod_status batch_layout(const rpod_desc* descs, int32_t count, BatchLayout& bl) {
+rpod_status check_tuning(const rpod_tuning* t) {
+    if (t == nullptr) return RPOD_OK;
+    if (t->stq_workgroups < 0 || t->stq_workgroups > (1 << 20) || t->gram_workgroups < 0 ||
+        t->gram_workgroups > 256)
+        return fail(RPOD_EINVAL, "tuning values out of range (stq_workgroups %d, gram_workgroups %d)",
+                    t->stq_workgroups, t->gram_workgroups);
+    for (int k = 0; k < 6; ++k)
+        if (t->reserved[k] != 0) return fail(RPOD_EINVAL, "tuning.reserved must be 0");
+    return RPOD_OK;
+}
+
+rpod_status batch_layout(const rpod_desc* descs, int32_t count, const rpod_tuning* tune, BatchLayout& bl) {
     if (descs == nullptr) return fail(RPOD_EINVAL, "descs is NULL");
     if (count < 1 || count > 4096) return fail(RPOD_EINVAL, "count must be in [1, 4096] (got %d)", count);
     for (int i = 0; i < count; ++i) {
@@ -644,7 +657,11 @@ rpod_status batch_layout(const rpod_desc* descs, int32_t count, BatchLayout& bl)
         if (descs[i].dtype != descs[0].dtype) return fail(RPOD_EINVAL, "all matrices of a batch must share dtype");
         if (descs[i].q != descs[0].q) return fail(RPOD_EINVAL, "all matrices of a batch must share q");
     }
-    const int64_t wg = count == 1 ? 4096 : std::max<int64_t>(256, 8192 / count);
+    rpod_status ts = check_tuning(tune);
+    if (ts != RPOD_OK) return ts;
+    int64_t wg = count == 1 ? 4096 : std::max<int64_t>(256, 8192 / count);
+    if (tune && tune->stq_workgroups > 0) wg = tune->stq_workgroups;
+    const int gcap = (tune && tune->gram_workgroups > 0) ? tune->gram_workgroups : 256;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -657,7 +674,7 @@ rpod_status batch_layout(const rpod_desc* descs, int32_t count, BatchLayout& bl)
     for (int i = 0; i < count; ++i) {
         Item it;
         it.d = descs[i];
-        it.L = make_layout(&descs[i], wg);
+        it.L = make_layout(&descs[i], wg, gcap);
         it.off = take(it.L.total);
         it.idx = i;
         bl.items.push_back(it);
@@ -678,9 +695,9 @@ std::vector<char> record_all(rpod_plan_s* P) {
     return B.blob;
 }
 
-rpod_status workspace_bytes(const rpod_desc* descs, int32_t count, size_t* bytes) {
+rpod_status workspace_bytes(const rpod_desc* descs, int32_t count, const rpod_tuning* tune, size_t* bytes) {
     BatchLayout bl;
-    rpod_status s = batch_layout(descs, count, bl);
+    rpod_status s = batch_layout(descs, count, tune, bl);
     if (s != RPOD_OK) return s;
     rpod_plan_s tmp;
     tmp.items = bl.items;
@@ -700,17 +717,17 @@ void destroy_plan(rpod_plan_s* P) {
     delete P;
 }
 
-rpod_status create_plan(rpod_plan* plan, const rpod_desc* descs, int32_t count, void* workspace, size_t ws_bytes,
-                        void* hip_stream) {
+rpod_status create_plan(rpod_plan* plan, const rpod_desc* descs, int32_t count, const rpod_tuning* tune,
+                        void* workspace, size_t ws_bytes, void* hip_stream) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     *plan = nullptr;
     BatchLayout bl;
-    rpod_status s = batch_layout(descs, count, bl);
+    rpod_status s = batch_layout(descs, count, tune, bl);
     if (s != RPOD_OK) return s;
     if (workspace == nullptr) return fail(RPOD_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(RPOD_EINVAL, "workspace must be 256-byte aligned");
     size_t need = 0;
-    s = workspace_bytes(descs, count, &need);
+    s = workspace_bytes(descs, count, tune, &need);
     if (s != RPOD_OK) return s;
     if (ws_bytes < need) return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
     rpod_plan_s* P = new (std::nothrow) rpod_plan_s;
@@ -770,6 +787,182 @@ rpod_status compute_impl(rpod_plan_s* P, const void* const* S, const uint64_t* s
     return RPOD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+const int STQ_CANDIDATES[] = {128, 256, 512, 1024, 2048, 4096, 8192};
+const int GRAM_CANDIDATES[] = {32, 64, 128, 256};
+
+// Output buffers of the trial calls, placed after the largest trial plan.
+struct TrialOutputs {
+    size_t plan_bytes;
+    std::vector<size_t> phi, sig, a;
+    size_t total;
+};
+
+rpod_status autotune_bytes(const rpod_desc* descs, int32_t count, size_t* bytes, TrialOutputs* to) {
+    BatchLayout bl;
+    rpod_status s = batch_layout(descs, count, nullptr, bl);
+    if (s != RPOD_OK) return s;
+    size_t pb = 0;
+    s = workspace_bytes(descs, count, nullptr, &pb);
+    if (s != RPOD_OK) return s;
+    for (int c : STQ_CANDIDATES) {
+        rpod_tuning t{};
+        t.stq_workgroups = c;
+        size_t b = 0;
+        s = workspace_bytes(descs, count, &t, &b);
+        if (s != RPOD_OK) return s;
+        pb = std::max(pb, b);
+    }
+    TrialOutputs o;
+    o.plan_bytes = (pb + 255) / 256 * 256;
+    size_t off = o.plan_bytes;
+    for (int i = 0; i < count; ++i) {
+        const size_t so = descs[i].dtype == RPOD_F64 ? 8 : 4;
+        o.phi.push_back(off);
+        off += ((size_t)descs[i].m * descs[i].r * so + 255) / 256 * 256;
+        o.sig.push_back(off);
+        off += ((size_t)descs[i].r * 8 + 255) / 256 * 256;
+        o.a.push_back(off);
+        off += ((size_t)descs[i].r * descs[i].n * so + 255) / 256 * 256;
+    }
+    o.total = off;
+    *bytes = off;
+    if (to) *to = o;
+    return RPOD_OK;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+bool cache_lookup(const char* path, uint64_t key, rpod_tuning* best, double* ms) {
+    if (path == nullptr) return false;
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return false;
+    unsigned long long k = 0;
+    int a = 0, b = 0;
+    double t = 0;
+    bool found = false;
+    while (std::fscanf(f, "%llx %d %d %lf", &k, &a, &b, &t) == 4) {
+        if (k == key && a >= 0 && b >= 0 && b <= 256) {
+            *best = rpod_tuning{};
+            best->stq_workgroups = a;
+            best->gram_workgroups = b;
+            *ms = t;
+            found = true;  // the last entry for a key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+rpod_status autotune(const rpod_desc* descs, int32_t count, const void* const* S, void* workspace, size_t ws_bytes,
+                     hipStream_t st, int32_t repeats, const char* cache_path, rpod_tuning* best, double* best_ms) {
+    if (best == nullptr || S == nullptr) return fail(RPOD_EINVAL, "S and best must be non-NULL");
+    if (repeats < 1) return fail(RPOD_EINVAL, "repeats must be >= 1");
+    TrialOutputs to;
+    size_t need = 0;
+    rpod_status s = autotune_bytes(descs, count, &need, &to);
+    if (s != RPOD_OK) return s;
+    if (workspace == nullptr || (uintptr_t)workspace % 256 != 0)
+        return fail(RPOD_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < need) return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    uint64_t key = fnv1a(1469598103934665603ull, descs, sizeof(rpod_desc) * (size_t)count);
+    key = fnv1a(key, prop.gcnArchName, std::strlen(prop.gcnArchName));
+    key = fnv1a(key, &prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+    double ms = 0;
+    if (cache_lookup(cache_path, key, best, &ms)) {
+        if (best_ms) *best_ms = ms;
+        return RPOD_OK;
+    }
+    char* ws = static_cast<char*>(workspace);
+    std::vector<void*> Phi(count), A(count);
+    std::vector<double*> sig(count);
+    std::vector<uint64_t> seeds(count);
+    for (int i = 0; i < count; ++i) {
+        Phi[i] = ws + to.phi[i];
+        A[i] = ws + to.a[i];
+        sig[i] = reinterpret_cast<double*>(ws + to.sig[i]);
+        seeds[i] = 0x5EED0000ull + (uint64_t)i;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RPOD_EHIP, "hipEventCreate failed: %s", hipGetErrorString(he));
+    }
+    // time one candidate: ms per call, or a negative value on failure
+    auto trial = [&](const rpod_tuning& t, rpod_status& err) -> double {
+        rpod_plan p = nullptr;
+        err = create_plan(&p, descs, count, &t, workspace, to.plan_bytes, st);
+        if (err != RPOD_OK) return -1.0;
+        err = compute_impl(p, S, seeds.data(), Phi.data(), sig.data(), A.data());
+        hipError_t e = hipSuccess;
+        for (int r = 0; err == RPOD_OK && e == hipSuccess && r < repeats; ++r) {
+            if (r == 0) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) err = compute_impl(p, S, seeds.data(), Phi.data(), sig.data(), A.data());
+        }
+        if (err == RPOD_OK && e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float el = -1.f;
+        if (err == RPOD_OK && e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+        (void)hipStreamSynchronize(st);
+        destroy_plan(p);
+        if (err == RPOD_OK && e != hipSuccess) err = fail(RPOD_EHIP, "autotune timing failed: %s", hipGetErrorString(e));
+        return err == RPOD_OK ? (double)el / repeats : -1.0;
+    };
+    rpod_tuning cur{};
+    rpod_status err = RPOD_OK;
+    double tbest = trial(cur, err);  // defaults
+    if (err != RPOD_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return err;
+    }
+    rpod_tuning bt = cur;
+    for (int c : STQ_CANDIDATES) {
+        rpod_tuning t{};
+        t.stq_workgroups = c;
+        const double v = trial(t, err);
+        if (err != RPOD_OK) break;
+        if (v < tbest) { tbest = v; bt = t; }
+    }
+    for (int g : GRAM_CANDIDATES) {
+        if (err != RPOD_OK) break;
+        rpod_tuning t = bt;
+        t.gram_workgroups = g;
+        const double v = trial(t, err);
+        if (err != RPOD_OK) break;
+        if (v < tbest) { tbest = v; bt = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != RPOD_OK) return err;
+    *best = bt;
+    if (best_ms) *best_ms = tbest;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f, "%016llx %d %d %.6f\n", (unsigned long long)key, bt.stq_workgroups, bt.gram_workgroups,
+                         tbest);
+            std::fclose(f);
+        }
+    }
+    return RPOD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -778,22 +971,46 @@ const char* rpod_last_error(void) { return g_err; }
 
 rpod_status rpod_workspace_size(const rpod_desc* desc, size_t* bytes) {
     if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
-    return workspace_bytes(desc, 1, bytes);
+    return workspace_bytes(desc, 1, nullptr, bytes);
 }
 
 rpod_status rpod_workspace_size_batched(const rpod_desc* descs, int32_t count, size_t* bytes) {
     if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
-    return workspace_bytes(descs, count, bytes);
+    return workspace_bytes(descs, count, nullptr, bytes);
 }
 
 rpod_status rpod_plan_create(rpod_plan* plan, const rpod_desc* desc, void* workspace, size_t workspace_bytes,
                              void* hip_stream) {
-    return create_plan(plan, desc, 1, workspace, workspace_bytes, hip_stream);
+    return create_plan(plan, desc, 1, nullptr, workspace, workspace_bytes, hip_stream);
 }
 
 rpod_status rpod_plan_create_batched(rpod_plan* plan, const rpod_desc* descs, int32_t count, void* workspace,
                                      size_t workspace_bytes, void* hip_stream) {
-    return create_plan(plan, descs, count, workspace, workspace_bytes, hip_stream);
+    return create_plan(plan, descs, count, nullptr, workspace, workspace_bytes, hip_stream);
+}
+
+rpod_status rpod_workspace_size_tuned(const rpod_desc* descs, int32_t count, const rpod_tuning* tuning,
+                                      size_t* bytes) {
+    if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
+    return workspace_bytes(descs, count, tuning, bytes);
+}
+
+rpod_status rpod_plan_create_tuned(rpod_plan* plan, const rpod_desc* descs, int32_t count,
+                                   const rpod_tuning* tuning, void* workspace, size_t workspace_bytes,
+                                   void* hip_stream) {
+    return create_plan(plan, descs, count, tuning, workspace, workspace_bytes, hip_stream);
+}
+
+rpod_status rpod_autotune_workspace_size(const rpod_desc* descs, int32_t count, size_t* bytes) {
+    if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
+    return autotune_bytes(descs, count, bytes, nullptr);
+}
+
+rpod_status rpod_autotune(const rpod_desc* descs, int32_t count, const void* const* S, void* workspace,
+                          size_t workspace_bytes, void* hip_stream, int32_t repeats, const char* cache_path,
+                          rpod_tuning* best, double* best_ms) {
+    return autotune(descs, count, S, workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream), repeats,
+                    cache_path, best, best_ms);
 }
 
 rpod_status rpod_plan_destroy(rpod_plan plan) {

@@ -269,10 +269,11 @@ __global__ void k_gram_reduce(Group<GramArgs> g, int nt) {
     G[(16 * b + nn) * lp + 16 * a + mm] = s;
 }
 
-int gram_nwg(int64_t M) {
+int gram_nwg(int64_t M, int cap) {
     const int64_t nrb = (M + 15) / 16;
     int64_t nwg = (nrb + 3) / 4;
-    if (nwg > GRAM_WGS) nwg = GRAM_WGS;
+    if (cap < 1 || cap > GRAM_WGS) cap = GRAM_WGS;
+    if (nwg > cap) nwg = cap;
     if (nwg < 1) nwg = 1;
     return (int)nwg;
 }

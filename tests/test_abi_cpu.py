@@ -133,3 +133,28 @@ def test_batched_workspace_of_the_64_matrix_workload_fits_hbm():
     descs = [rp.make_desc(m, n, r, 10, 2, torch.bfloat16) for (m, n, r, _a) in shapes]
     ws = rp.workspace_size_batched(descs)
     assert 0 < ws < 40e9
+
+
+@needs_lib
+def test_tuning_validation_and_workspace():
+    f32 = torch.float32
+    descs = [rp.make_desc(3000, 300, 10, 10, 2, f32), rp.make_desc(5000, 2600, 25, 10, 2, f32)]
+    base = rp.workspace_size_batched(descs)
+    assert rp.workspace_size_batched(descs, rp.Tuning()) == base      # all-zero knobs are the defaults
+    small = rp.workspace_size_batched(descs, rp.Tuning(128, 64))
+    large = rp.workspace_size_batched(descs, rp.Tuning(8192, 256))
+    assert small <= base <= large                                      # more row splits, more slab memory
+    for bad in (rp.Tuning(-1, 0), rp.Tuning(0, 257), rp.Tuning(0, -3)):
+        with pytest.raises(rp.RpodError) as e:
+            rp.workspace_size_batched(descs, bad)
+        assert e.value.status == 1
+    t = rp.Tuning(256, 64)
+    t.reserved[2] = 1
+    with pytest.raises(rp.RpodError):
+        rp.workspace_size_batched(descs, t)
+    arr = (rp._Desc * 2)(*descs)
+    need = ctypes.c_size_t(0)
+    assert rp.lib().rpod_autotune_workspace_size(arr, 2, ctypes.byref(need)) == 0
+    assert need.value > large                                          # trial plans plus their outputs
+    best = rp.Tuning()
+    assert rp.lib().rpod_autotune(arr, 2, None, None, 0, None, 1, None, ctypes.byref(best), None) == 1

@@ -44,10 +44,10 @@ def _to_host(outs):
     return [(P.double().cpu().numpy().T, s.cpu().numpy(), A.double().cpu().numpy().T) for P, s, A in outs]
 
 
-def _check_batch(shapes, q, dtype, seed0, name, noise_std=1e-4):
-    say(f"[batch] {name} count={len(shapes)} q={q} dtype={dtype}")
+def _check_batch(shapes, q, dtype, seed0, name, noise_std=1e-4, tuning=None):
+    say(f"[batch] {name} count={len(shapes)} q={q} dtype={dtype} tuning={tuning}")
     Sds, S64s, seeds = _batch_inputs(shapes, dtype, seed0, noise_std)
-    plan = rp.BatchPlan(_shapes_with_ld(shapes, Sds), q, dtype=dtype, device=DEV)
+    plan = rp.BatchPlan(_shapes_with_ld(shapes, Sds), q, dtype=dtype, device=DEV, tuning=tuning)
     outs = _to_host(plan.compute(Sds, seeds))
     say(f"[batch] {name} flags={plan.last_flags}")
     results = []
@@ -181,3 +181,31 @@ def test_batched_plan_reuse_with_new_inputs():
         P2, s2, A2, ex = orpod.rpod_stable(S64b[i], r, om, 1)
         compare(outs[i], (P2, s2, A2), torch.float32, r, ex["ritz"])
     plan.close()
+
+
+@pytest.mark.parametrize("stq,gram", [(128, 32), (8192, 256), (512, 0)])
+def test_explicit_tunings_match_oracle(stq, gram):
+    _check_batch(SHAPES[:4], 2, torch.float32, 110, f"tuned{stq}/{gram}", tuning=rp.Tuning(stq, gram))
+
+
+def test_autotune_and_cache(tmp_path):
+    shapes = [(20000, 700, 25, 10), (9000, 1200, 50, 10), (30001, 500, 10, 10)]
+    Sds, S64s, seeds = _batch_inputs(shapes, torch.bfloat16, 120, noise_std=1e-6)
+    sh = _shapes_with_ld(shapes, Sds)
+    cache = tmp_path / "tune.txt"
+    best, ms = rp.autotune(sh, 2, Sds, repeats=2, cache=str(cache))
+    say(f"[autotune] best {best} {ms:.3f} ms per call")
+    assert ms > 0 and best.stq_workgroups in (0, 128, 256, 512, 1024, 2048, 4096, 8192)
+    assert best.gram_workgroups in (0, 32, 64, 128, 256)
+    lines = cache.read_text().split("\n")
+    assert len([x for x in lines if x.strip()]) == 1
+    again, ms2 = rp.autotune(sh, 2, Sds, repeats=2, cache=str(cache))   # served from the cache
+    assert (again.stq_workgroups, again.gram_workgroups) == (best.stq_workgroups, best.gram_workgroups)
+    assert abs(ms2 - ms) < 1e-5
+    plan = rp.BatchPlan(sh, 2, dtype=torch.bfloat16, device=DEV, tuning=best)
+    outs = _to_host(plan.compute(Sds, seeds))
+    plan.close()
+    for i, (m, n, r, p) in enumerate(shapes):
+        om = sketch_for(seeds[i], n, r + p, torch.bfloat16)
+        P2, s2, A2, ex = orpod.rpod_stable(S64s[i], r, om, 2)
+        compare(outs[i], (P2, s2, A2), torch.bfloat16, r, ex["ritz"])
