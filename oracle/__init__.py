@@ -15,6 +15,10 @@ pod      O1: deterministic POD by the thin SVD of the snapshot matrix
 rpod     O2: randomized POD, Alg. 1 of Sec. 4.2 (stable form with
          re-orthonormalisation after every product), and the literal form.
 metrics  sign-invariant comparison metrics (principal angles, sigma errors).
+warm     the learned warm start (an extension of Alg. 1, not in the paper):
+         network forward, loss, analytic gradient and Adam step, the bank
+         Grams and targets, the predicted subspace and the warm-started
+         rPOD with its residual check.
 
 Parity status: every function here is pinned by a CPU test against a closed
 form, a published known-answer vector, brute force or a theorem's bound.

@@ -1,0 +1,160 @@
+"""Learned warm start for randomized POD, CPU FP64 oracle (test infrastructure only).
+
+The paper has no warm start; this is an extension of its Alg. 1 (Sec. 4.2):
+a small network maps a parameter vector to a predicted subspace of the
+snapshot matrix, which takes the place of most Gaussian sketch columns.
+Everything here follows the plain definitions below; it shares no code with
+the GPU library.
+
+Definitions
+-----------
+Bank: K orthonormal bases Phi_1..Phi_K (m x r each), [Phi] = [Phi_1 .. Phi_K].
+  G_W = [Phi]^T [Phi] (Kr x Kr), G8[k, l] = ||Phi_k^T Phi_l||_F^2.
+Network (4 -> 256 -> 256 -> K, tanh, softmax):
+  h1 = tanh(W1 mu + b1), h2 = tanh(W2 h1 + b2), z = W3 h2 + b3, c = softmax(z).
+Loss of a training pair (mu_i, Phi_i), with P(c) = sum_k c_k Phi_k Phi_k^T:
+  L_i = ||Phi_i Phi_i^T - P(c)||_F^2 = r - 2 b_i^T c + c^T G8 c,
+  b_ik = ||Phi_k^T Phi_i||_F^2; the training loss is the mean over pairs.
+Optimiser: Adam with L2 weight decay added to the gradient (the convention
+  of torch.optim.Adam), bias-corrected moments.
+Predicted subspace: W = P(c)^j Phi_k*, k* = argmax c (lowest index on ties):
+  j steps of subspace iteration on P(c) started from the bank basis of
+  largest weight. In the bank's coordinates W = [Phi] Z with
+  Z_0 = E_k* (the columns of block k*) and Z <- C (G_W Z), C = diag(c (x) 1_r).
+  A one-hot c gives W = Phi_k exactly.
+Warm rPOD: Y = [W, S Omega_p] (Omega_p the first p columns of the Gaussian
+  sketch), Q = orth(Y), q subspace iterations as in Alg. 1 (stable form),
+  then steps 5-7 of Alg. 1 and the coefficients.
+Residual of the returned modes: rho = max_k ||S v_k - sigma_k phi_k|| / sigma_k,
+  zero for an exact singular triplet.
+"""
+
+import numpy as np
+
+from .rpod import _finish, _orth, s_times, st_times
+
+IN, HIDDEN = 4, 256
+PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def param_shapes(K=8):
+    return {"W1": (HIDDEN, IN), "b1": (HIDDEN,), "W2": (HIDDEN, HIDDEN), "b2": (HIDDEN,),
+            "W3": (K, HIDDEN), "b3": (K,)}
+
+
+def softmax(z):
+    z = z - np.max(z, axis=-1, keepdims=True)
+    e = np.exp(z)
+    return e / np.sum(e, axis=-1, keepdims=True)
+
+
+def mlp_forward(P, X):
+    """X (N x 4) -> dict(h1, h2, z, c), all FP64."""
+    X = np.asarray(X, dtype=np.float64)
+    h1 = np.tanh(X @ P["W1"].T + P["b1"])
+    h2 = np.tanh(h1 @ P["W2"].T + P["b2"])
+    z = h2 @ P["W3"].T + P["b3"]
+    return dict(h1=h1, h2=h2, z=z, c=softmax(z))
+
+
+def bank_gram(bases):
+    Phi = np.hstack([np.asarray(b, dtype=np.float64) for b in bases])
+    return Phi.T @ Phi
+
+
+def block_gram(GW, K, r):
+    """G8[k, l] = ||Phi_k^T Phi_l||_F^2 from the blocks of G_W."""
+    G8 = np.empty((K, K))
+    for k in range(K):
+        for l in range(K):
+            G8[k, l] = np.sum(GW[k * r:(k + 1) * r, l * r:(l + 1) * r] ** 2)
+    return G8
+
+
+def targets(bases, Phi_i):
+    Phi_i = np.asarray(Phi_i, dtype=np.float64)
+    return np.array([np.sum((np.asarray(b, dtype=np.float64).T @ Phi_i) ** 2) for b in bases])
+
+
+def loss(P, X, B, G8, r):
+    """Mean loss and per-pair losses."""
+    c = mlp_forward(P, X)["c"]
+    B = np.asarray(B, dtype=np.float64)
+    per = r - 2.0 * np.sum(B * c, axis=1) + np.einsum("ik,kl,il->i", c, G8, c)
+    return float(np.mean(per)), per
+
+
+def backward(P, X, B, G8):
+    """Analytic gradient of the mean loss with respect to every parameter."""
+    X = np.asarray(X, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    N = X.shape[0]
+    f = mlp_forward(P, X)
+    c, h1, h2 = f["c"], f["h1"], f["h2"]
+    dc = (2.0 / N) * (c @ G8.T - B)                      # dL/dc (G8 is symmetric)
+    dz = c * (dc - np.sum(c * dc, axis=1, keepdims=True))  # softmax Jacobian
+    g = {"W3": dz.T @ h2, "b3": dz.sum(axis=0)}
+    da2 = (dz @ P["W3"]) * (1.0 - h2 * h2)
+    g["W2"] = da2.T @ h1
+    g["b2"] = da2.sum(axis=0)
+    da1 = (da2 @ P["W2"]) * (1.0 - h1 * h1)
+    g["W1"] = da1.T @ X
+    g["b1"] = da1.sum(axis=0)
+    return g
+
+
+def adam_step(P, g, state, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-5):
+    """One Adam step in place on P; state holds t and the moments m, v."""
+    state["t"] = state.get("t", 0) + 1
+    t = state["t"]
+    for k in PARAM_ORDER:
+        gk = g[k] + weight_decay * P[k]
+        m = state.setdefault("m", {}).setdefault(k, np.zeros_like(P[k]))
+        v = state.setdefault("v", {}).setdefault(k, np.zeros_like(P[k]))
+        m *= beta1
+        m += (1.0 - beta1) * gk
+        v *= beta2
+        v += (1.0 - beta2) * gk * gk
+        mh = m / (1.0 - beta1 ** t)
+        vh = v / (1.0 - beta2 ** t)
+        P[k] = P[k] - lr * mh / (np.sqrt(vh) + eps)
+    return P
+
+
+def argmax_first(c):
+    c = np.asarray(c)
+    return int(np.flatnonzero(c == np.max(c))[0])
+
+
+def assemble(GW, c, kstar, r, j=2):
+    """Z (Kr x r) with W = [Phi] Z = P(c)^j Phi_k*."""
+    Kr = GW.shape[0]
+    Z = np.zeros((Kr, r))
+    Z[kstar * r:(kstar + 1) * r, :] = np.eye(r)
+    w = np.repeat(np.asarray(c, dtype=np.float64), r)
+    for _ in range(j):
+        Z = w[:, None] * (GW @ Z)
+    return Z
+
+
+def residual(S, Phi, sigma, Vt):
+    """max_k ||S v_k - sigma_k phi_k|| / sigma_k over the returned modes."""
+    SV = s_times(S, np.asarray(Vt).T)
+    R = SV - Phi * sigma[None, :]
+    return float(np.max(np.linalg.norm(R, axis=0) / sigma))
+
+
+def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2):
+    """Warm-started rPOD; returns (Phi, sigma, A, extras) with extras['rho']."""
+    Phi_b = np.hstack([np.asarray(b, dtype=np.float64) for b in bases])
+    Z = assemble(Phi_b.T @ Phi_b, c, kstar, r, j)
+    W = Phi_b @ Z
+    Y = np.hstack([W, s_times(S, np.asarray(omega_p, dtype=np.float64))])
+    Q = _orth(Y)
+    for _ in range(q):
+        Zs = _orth(st_times(S, Q))
+        Q = _orth(s_times(S, Zs))
+    Phi, s, A, ex = _finish(S, Q, r, 65536)
+    ex["rho"] = residual(S, Phi, s, ex["Vt_r"])
+    ex["W"] = W
+    return Phi, s, A, ex

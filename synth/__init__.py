@@ -247,3 +247,120 @@ def lowrank_exp_device(m, n, decay, noise_std=1e-4, seed=1, K=256, dtype=None, d
             blk += noise_std * torch.randn((t1 - t0, m), generator=gen, device=dev, dtype=torch.float32)
         St[t0:t1] = blk.to(dtype)
     return St
+
+
+# ---------------------------------------------------------------------------
+# parametric family for the learned warm start
+# ---------------------------------------------------------------------------
+# stream ids: 6 = skew generators, 7 = parameter draws, 8 = train/test split
+_S_SKEW, _S_MU, _S_SPLIT = 6, 7, 8
+
+# physical box of the parameter vector (delta, sigma, Fr, alpha), mapped to [-1, 1]^4
+PARAM_BOX = np.array([[0.2, 0.6], [0.006, 0.01], [0.07, 0.11], [0.05, 0.2]])
+
+
+def normalise_mu(mu):
+    mu = np.asarray(mu, dtype=np.float64)
+    return 2.0 * (mu - PARAM_BOX[:, 0]) / (PARAM_BOX[:, 1] - PARAM_BOX[:, 0]) - 1.0
+
+
+def draw_params(count=128, seed=5):
+    """count parameter vectors uniform in PARAM_BOX: (physical (count, 4), normalised (count, 4))."""
+    g = rng(seed, _S_MU)
+    u = g.uniform(size=(count, 4))
+    mu = PARAM_BOX[:, 0] + u * (PARAM_BOX[:, 1] - PARAM_BOX[:, 0])
+    return mu, normalise_mu(mu)
+
+
+def train_test_split(count=128, n_train=96, seed=5):
+    perm = rng(seed, _S_SPLIT).permutation(count)
+    return np.sort(perm[:n_train]), np.sort(perm[n_train:])
+
+
+def farthest_points(X, k):
+    """k row indices of X by farthest-point sampling, starting nearest the origin."""
+    X = np.asarray(X, dtype=np.float64)
+    idx = [int(np.argmin(np.sum(X * X, axis=1)))]
+    d = np.sum((X - X[idx[0]]) ** 2, axis=1)
+    while len(idx) < k:
+        j = int(np.argmax(d))
+        idx.append(j)
+        d = np.minimum(d, np.sum((X - X[j]) ** 2, axis=1))
+    return idx
+
+
+class ParamFamily:
+    """S(mu) = U(mu) diag(exp(-alpha k)) V^T + noise on an nx x ny grid.
+
+    U(mu) = F expm(sum_j mu_j G_j)[:, :K]: F holds the n_cand lowest
+    orthonormal Dirichlet sine modes of the grid (fourier_basis scaled to unit
+    norm), G_j are seeded skew-symmetric n_cand x n_cand matrices (stream 6)
+    scaled by `angle`/||G_j||_2 (so that the leading 50-dimensional subspaces
+    at opposite corners of the box are about 30 degrees apart), mu is the
+    normalised parameter vector in [-1, 1]^4 and alpha its physical fourth
+    component. U(mu) is orthonormal
+    and smooth in mu. V (n x K) is the Q factor of a seeded Gaussian matrix
+    per matrix seed; the noise is N(0, noise_std^2) per column stream.
+    """
+
+    def __init__(self, nx, ny, n_cand=400, K=100, angle=0.205, family_seed=5):
+        self.nx, self.ny, self.K = nx, ny, K
+        modes, _ = fourier_modes(nx, ny, n_cand)
+        self.F = fourier_basis(nx, ny, modes) / np.sqrt(nx * ny / 4.0)    # (m, n_cand), orthonormal
+        g = rng(family_seed, _S_SKEW)
+        self.G = []
+        for _ in range(4):
+            A = g.standard_normal((n_cand, n_cand))
+            Sk = 0.5 * (A - A.T)
+            self.G.append(Sk * (angle / np.linalg.norm(Sk, 2)))
+
+    @property
+    def m(self):
+        return self.nx * self.ny
+
+    def rotation(self, mu_hat):
+        from scipy.linalg import expm
+        M = sum(float(a) * Gj for a, Gj in zip(mu_hat, self.G))
+        return expm(M)
+
+    def U(self, mu_hat):
+        return self.F @ self.rotation(mu_hat)[:, :self.K]
+
+    @staticmethod
+    def spectrum(alpha, K):
+        return np.exp(-alpha * np.arange(1, K + 1))
+
+    def matrix(self, mu, n, noise_std=1e-7, seed=0, dtype=np.float64):
+        """Host St (n, m) for the physical parameter vector mu; also U, V, sigma."""
+        mu = np.asarray(mu, dtype=np.float64)
+        U = self.U(normalise_mu(mu))
+        V = _orthonormal(n, self.K, seed, _S_V)
+        s = self.spectrum(mu[3], self.K)
+        St = np.ascontiguousarray((V * s[None, :]) @ U.T)
+        _add_noise(St, noise_std, seed)
+        return dict(St=St.astype(dtype, copy=False), U=U, V=V, sigma=s)
+
+    def matrix_device(self, mu, n, noise_std=1e-7, seed=0, dtype=None, device="cuda", F_dev=None):
+        """matrix() built on the GPU with FP32 products (U from the host
+        rotation); the noise comes from a seeded torch generator."""
+        import torch
+        dtype = torch.float32 if dtype is None else dtype
+        dev = torch.device(device)
+        mu = np.asarray(mu, dtype=np.float64)
+        if F_dev is None:
+            F_dev = torch.from_numpy(self.F.astype(np.float32)).to(dev)
+        R = self.rotation(normalise_mu(mu))[:, :self.K]
+        s = self.spectrum(mu[3], self.K)
+        V = _orthonormal(n, self.K, seed, _S_V)
+        U32t = (F_dev @ torch.from_numpy(R.astype(np.float32)).to(dev)).T.contiguous()   # (K, m)
+        C = torch.from_numpy((V * s[None, :]).astype(np.float32)).to(dev)                 # (n, K)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(seed) * 1000003 + _S_NOISE)
+        St = torch.empty((n, self.m), dtype=dtype, device=dev)
+        for t0 in range(0, n, 512):
+            t1 = min(n, t0 + 512)
+            blk = C[t0:t1] @ U32t
+            if noise_std:
+                blk += noise_std * torch.randn((t1 - t0, self.m), generator=gen, device=dev, dtype=torch.float32)
+            St[t0:t1] = blk.to(dtype)
+        return St

@@ -1,0 +1,149 @@
+"""Pins of the warm-start oracle (CPU only): every function is checked
+against something other than itself (finite differences, brute-force
+matrices, closed forms, the exact SVD)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import metrics, pod
+from oracle import warm as ow
+
+
+def _params(K=8, seed=0, scale=0.3):
+    g = np.random.default_rng(seed)
+    return {k: scale * g.standard_normal(sh) for k, sh in ow.param_shapes(K).items()}
+
+
+def _bank(m=60, r=5, K=8, seed=1):
+    g = np.random.default_rng(seed)
+    return [np.linalg.qr(g.standard_normal((m, r)))[0] for _ in range(K)]
+
+
+def test_loss_equals_projector_distance():
+    """L(c) = ||Phi_i Phi_i^T - sum_k c_k Phi_k Phi_k^T||_F^2, written out with m x m matrices."""
+    bases = _bank()
+    r = bases[0].shape[1]
+    G8 = ow.block_gram(ow.bank_gram(bases), 8, r)
+    g = np.random.default_rng(2)
+    Phi_i = np.linalg.qr(g.standard_normal((60, r)))[0]
+    b = ow.targets(bases, Phi_i)
+    for _ in range(5):
+        c = ow.softmax(g.standard_normal(8))
+        Pc = sum(ck * B @ B.T for ck, B in zip(c, bases))
+        brute = np.sum((Phi_i @ Phi_i.T - Pc) ** 2)
+        formula = r - 2 * b @ c + c @ G8 @ c
+        assert abs(brute - formula) < 1e-12 * max(1.0, brute)
+
+
+def test_backward_matches_central_differences():
+    P = _params(seed=3)
+    bases = _bank(seed=4)
+    G8 = ow.block_gram(ow.bank_gram(bases), 8, 5)
+    g = np.random.default_rng(5)
+    X = g.uniform(-1, 1, (6, 4))
+    B = np.stack([ow.targets(bases, np.linalg.qr(g.standard_normal((60, 5)))[0]) for _ in range(6)])
+    grads = ow.backward(P, X, B, G8)
+    h = 1e-6
+    for name in ow.PARAM_ORDER:
+        flat = P[name].reshape(-1)
+        idx = g.choice(flat.size, size=min(12, flat.size), replace=False)
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + h
+            lp, _ = ow.loss(P, X, B, G8, 5)
+            flat[i] = old - h
+            lm, _ = ow.loss(P, X, B, G8, 5)
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            an = grads[name].reshape(-1)[i]
+            assert abs(fd - an) <= 1e-6 * max(1e-3, abs(fd)), (name, i, fd, an)
+
+
+def test_adam_first_step_is_a_sign_step():
+    """At t = 1 the bias-corrected Adam update is lr * g / (|g| + eps) (no weight decay)."""
+    P = _params(seed=6)
+    g = {k: np.random.default_rng(7).standard_normal(v.shape) for k, v in P.items()}
+    P0 = {k: v.copy() for k, v in P.items()}
+    ow.adam_step(P, g, {}, lr=1e-2, eps=1e-8, weight_decay=0.0)
+    for k in P:
+        want = P0[k] - 1e-2 * g[k] / (np.abs(g[k]) + 1e-8)
+        assert np.allclose(P[k], want, rtol=0, atol=1e-15)
+
+
+def test_adam_weight_decay_enters_the_gradient():
+    P = {k: np.ones(s) for k, s in ow.param_shapes().items()}
+    g = {k: np.zeros(s) for k, s in ow.param_shapes().items()}
+    ow.adam_step(P, g, {}, lr=1e-3, weight_decay=0.5)
+    # gradient 0.5 * theta = 0.5 > 0: one sign step down
+    for k in P:
+        assert np.allclose(P[k], 1.0 - 1e-3 * 0.5 / (0.5 + 1e-8))
+
+
+def test_assemble_one_hot_returns_the_bank_basis():
+    bases = _bank(seed=8)
+    GW = ow.bank_gram(bases)
+    Phi_b = np.hstack(bases)
+    for k in (0, 5, 7):
+        c = np.zeros(8)
+        c[k] = 1.0
+        for j in (1, 2, 3):
+            W = Phi_b @ ow.assemble(GW, c, k, 5, j)
+            assert np.allclose(W, bases[k], atol=1e-13)
+
+
+def test_assemble_is_power_iteration_on_the_weighted_projector():
+    bases = _bank(seed=9)
+    GW = ow.bank_gram(bases)
+    c = ow.softmax(np.random.default_rng(10).standard_normal(8))
+    k = ow.argmax_first(c)
+    Pc = sum(ck * B @ B.T for ck, B in zip(c, bases))
+    for j in (1, 2):
+        W = np.hstack(bases) @ ow.assemble(GW, c, k, 5, j)
+        brute = np.linalg.matrix_power(Pc, j) @ bases[k]
+        assert np.allclose(W, brute, atol=1e-13)
+
+
+def test_argmax_takes_lowest_index_on_ties():
+    assert ow.argmax_first([0.1, 0.4, 0.4, 0.1]) == 1
+
+
+def test_residual_is_zero_for_exact_triplets_and_not_otherwise():
+    g = synth.lowrank_exp(500, 80, decay=0.1, noise_std=0.0, seed=11)
+    S = g["St"].T
+    U, s, Vt = np.linalg.svd(S, full_matrices=False)
+    assert ow.residual(S, U[:, :10], s[:10], Vt[:10]) < 1e-13
+    Ub = U[:, :10].copy()
+    Ub[:, 9] = np.cos(1e-3) * U[:, 9] + np.sin(1e-3) * U[:, 20]
+    assert ow.residual(S, Ub, s[:10], Vt[:10]) > 1e-4
+
+
+def test_warm_start_with_the_exact_basis_equals_exact_pod():
+    """W = the exact leading basis (one-hot c on it): q = 0 already gives O1."""
+    fam = synth.ParamFamily(32, 64, K=100)
+    mu, _ = synth.draw_params(3, seed=12)
+    d = fam.matrix(mu[0], 300, noise_std=0.0, seed=13)
+    S = d["St"].T
+    r = 20
+    bases = _bank(m=S.shape[0], r=r, seed=14)
+    bases[2] = d["U"][:, :r]
+    c = np.full(8, 1e-30)
+    c[2] = 1.0
+    om = np.random.default_rng(15).standard_normal((300, 10))
+    Phi, s, A, ex = ow.warm_rpod(S, bases, c / c.sum(), 2, r, om, q=0)
+    P1, s1, A1, _ = pod.pod_svd(S, r)
+    assert metrics.sigma_rel_err(s, s1) < 1e-12
+    assert metrics.sin_theta_max(Phi, P1) < 1e-10
+    assert ex["rho"] < 1e-10
+
+
+def test_parameter_family_is_smooth_and_orthonormal():
+    fam = synth.ParamFamily(32, 64)
+    U0 = fam.U(np.zeros(4))
+    assert np.abs(U0.T @ U0 - np.eye(fam.K)).max() < 1e-12
+    # nearby parameters give nearby leading subspaces, opposite corners about 30 degrees
+    d = np.array([1e-3, 0, 0, 0])
+    small = metrics.sin_theta_max(fam.U(d)[:, :50], U0[:, :50])
+    corner = metrics.sin_theta_max(fam.U(np.ones(4))[:, :50], fam.U(-np.ones(4))[:, :50])
+    assert small < 1e-3
+    assert 0.4 < corner < 0.6
