@@ -226,6 +226,103 @@ rpod_status rpod_generate_omega(uint64_t seed, int64_t n, int32_t l, int32_t dty
 rpod_status rpod_sketch_bits(uint64_t seed, int64_t n, int32_t l, uint32_t* out,
                              void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (an extension of Alg. 1 of Sec. 4.2; the paper has no
+ * warm start). A small network maps the normalised parameter vector mu of a
+ * snapshot matrix (4 components in [-1, 1]) to weights c over a bank of 8
+ * orthonormal bases Phi_1..Phi_8 (m x r each, typically computed by rPOD at
+ * other parameter values):
+ *   c = softmax(W3 tanh(W2 tanh(W1 mu + b1) + b2) + b3),  4 -> 256 -> 256 -> 8,
+ * FP32, 69,128 parameters packed in this order: W1 (256 x 4, row-major), b1
+ * (256), W2 (256 x 256), b2 (256), W3 (8 x 256), b3 (8).
+ * The predicted subspace is W = P(c)^j Phi_k*, P(c) = sum_k c_k Phi_k Phi_k^T,
+ * k* = argmax c (lowest index on ties), j = 2: two steps of subspace
+ * iteration on the weighted projector from the bank basis of largest weight
+ * (a one-hot c gives Phi_k exactly; the result does not depend on the signs
+ * or rotations of the bank bases). It is formed from the cached FP64 bank
+ * Gram G_W = [Phi]^T [Phi] and one product with the bank.
+ * Training loss of a pair (mu_i, Phi_i), mean over the pairs:
+ *   L_i = ||Phi_i Phi_i^T - P(c)||_F^2 = r - 2 b_i^T c + c^T G8 c,
+ *   b_ik = ||Phi_k^T Phi_i||_F^2 (rpod_warm_targets), G8_kl = ||Phi_k^T Phi_l||_F^2;
+ * optimiser Adam with L2 weight decay added to the gradient. Every step
+ * (forward, loss, backward, Adam, bank Grams) runs in the library's kernels.
+ * ------------------------------------------------------------------------ */
+#define RPOD_FLAG_RESIDUAL 0x10  /* warm start: residual above tolerance (informational) */
+#define RPOD_WARM_PARAMS 69128
+
+typedef struct {
+    int64_t m;          /* rows of the bank bases and of the snapshot matrices, >= 1 */
+    int32_t r;          /* columns of each bank basis, 1..128 (= the rank of warm plans) */
+    int32_t max_train;  /* largest batch of pairs for training / prediction, 1..4096 */
+    uint64_t seed;      /* initial weights: Glorot-uniform from Philox4x32-10 */
+} rpod_warm_desc;
+
+/* Byte offsets into the model workspace (for reading or writing the
+ * parameters and their gradient directly; FP32 arrays of RPOD_WARM_PARAMS). */
+typedef struct {
+    size_t params, grads, adam_m, adam_v;
+    size_t bank;   /* FP32, column-major, leading dimension roundup(m, 256), 8 r columns */
+    size_t gram;   /* FP64 G_W, 8r x 8r row-major */
+    size_t gram8;  /* FP64 G8, 8 x 8 row-major */
+    size_t total;  /* bytes of the model workspace */
+} rpod_warm_layout;
+
+typedef struct rpod_warm_s* rpod_warm;
+
+rpod_status rpod_warm_layout_of(const rpod_warm_desc* desc, rpod_warm_layout* layout);
+
+/* Create a model on `workspace` (device, layout.total bytes, 256-byte
+ * aligned, owned by the caller): cleared, weights initialised from the seed,
+ * Adam state zero. Every model call enqueues on hip_stream and those that
+ * upload launch arguments (set_bank, targets) synchronise it. */
+rpod_status rpod_warm_create(rpod_warm* model, const rpod_warm_desc* desc, void* workspace, size_t workspace_bytes,
+                             void* hip_stream);
+rpod_status rpod_warm_destroy(rpod_warm model);
+
+/* Store the bank: bases = host array of 8 device pointers, each m x r FP32
+ * column-major with leading dimension m (orthonormal columns expected); then
+ * G_W and G8 in FP64. Synchronous. */
+rpod_status rpod_warm_set_bank(rpod_warm model, const float* const* bases);
+
+/* b (device, 8 doubles) = ||Phi_k^T basis||_F^2 for the m x r FP32 basis
+ * (device, leading dimension m). Synchronous. */
+rpod_status rpod_warm_targets(rpod_warm model, const float* basis, double* b);
+
+/* Mean loss over N pairs (mu: device N x 4 FP32 row-major; b: device N x 8
+ * FP64 targets) into *loss (device FP32, may be NULL) and its gradient into
+ * the model's gradient array. N <= max_train. Enqueued. */
+rpod_status rpod_warm_loss_grad(rpod_warm model, const float* mu, const double* b, int32_t N, float* loss);
+
+/* `epochs` full-batch Adam steps on the N pairs (lr, beta1, beta2, eps,
+ * weight_decay as in Adam with L2 decay); losses (device FP32, epochs
+ * entries, may be NULL) receives the loss before each step. The step count
+ * of the bias correction continues across calls. Enqueued. */
+rpod_status rpod_warm_train(rpod_warm model, const float* mu, const double* b, int32_t N, int32_t epochs,
+                            float lr, float beta1, float beta2, float eps, float weight_decay, float* losses);
+
+/* c (device N x 8 FP32) = the network's weights for N parameter vectors. Enqueued. */
+rpod_status rpod_warm_predict(rpod_warm model, const float* mu, int32_t N, float* c);
+
+/* Warm plans. desc: dtype RPOD_F32, RPOD_BF16 or RPOD_F16, m = the model's
+ * m, r = the model's r, p >= 1 Gaussian columns next to the predicted
+ * subspace (l = r + p <= 128), q >= 0 subspace iterations after it. A
+ * compute call runs Y = [W, S Omega_p] (Omega_p: the first p columns of the
+ * sketch of `seed`), CholeskyQR2, q iterations, T = Q^T S and steps 6-7 of
+ * Alg. 1, then the residual of the returned modes
+ *   rho = max_{k <= r} ||S v_k - sigma_k phi_k|| / sigma_k   (FP64 products);
+ * if rho > tol (or the warm run broke down) the plain rPOD with q_fallback
+ * iterations and the full sketch of `seed` recomputes the outputs. The model
+ * must outlive the plan; its weights and bank are read at every call. */
+rpod_status rpod_workspace_size_warm(const rpod_desc* desc, rpod_warm model, int32_t q_fallback, size_t* bytes);
+rpod_status rpod_plan_create_warm(rpod_plan* plan, const rpod_desc* desc, rpod_warm model, int32_t q_fallback,
+                                  double tol, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* mu: host, 4 floats (normalised parameter vector). fell_back, rho: host,
+ * may be NULL. Synchronises the plan's stream once (to read rho) before it
+ * decides on the fallback, which is then only enqueued. */
+rpod_status rpod_compute_warm(rpod_plan plan, const void* S, const float* mu, uint64_t seed, void* Phi,
+                              double* sigma, void* A, int32_t* fell_back, double* rho);
+
 /* Per-pass timing, for measurement. With enable != 0 the plan records a
  * pair of HIP events on its stream around every pass over S issued by later
  * compute calls (pass 0: the products S X of Alg. 1 steps 2-3; pass 1: the

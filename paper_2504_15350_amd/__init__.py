@@ -16,7 +16,7 @@ import os
 
 import torch
 
-__all__ = ["RpodError", "Plan", "BatchPlan", "Tuning", "autotune", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
+__all__ = ["RpodError", "Plan", "BatchPlan", "Tuning", "autotune", "WarmModel", "WarmPlan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
            "STATUS", "FLAG_SHIFTED", "FLAG_BREAKDOWN", "FLAG_NONFINITE", "FLAG_JACOBI_SLOW"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +49,20 @@ class Tuning(ctypes.Structure):
     def __repr__(self):
         return f"Tuning(stq_workgroups={self.stq_workgroups}, gram_workgroups={self.gram_workgroups})"
 
+
+class _WarmDesc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("r", ctypes.c_int32), ("max_train", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _WarmLayout(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_size_t) for k in ("params", "grads", "adam_m", "adam_v", "bank", "gram", "gram8",
+                                                "total")]
+
+
+WARM_PARAMS = 69128
+WARM_BANK = 8
+FLAG_RESIDUAL = 0x10
 
 _lib = None
 
@@ -84,6 +98,20 @@ def lib():
             "rpod_autotune_workspace_size": [ctypes.POINTER(_Desc), i32, ctypes.POINTER(ctypes.c_size_t)],
             "rpod_autotune": [ctypes.POINTER(_Desc), i32, ctypes.POINTER(vp), vp, ctypes.c_size_t, vp, i32,
                               ctypes.c_char_p, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)],
+            "rpod_warm_layout_of": [ctypes.POINTER(_WarmDesc), ctypes.POINTER(_WarmLayout)],
+            "rpod_warm_create": [ctypes.POINTER(vp), ctypes.POINTER(_WarmDesc), vp, ctypes.c_size_t, vp],
+            "rpod_warm_destroy": [vp],
+            "rpod_warm_set_bank": [vp, ctypes.POINTER(vp)],
+            "rpod_warm_targets": [vp, vp, vp],
+            "rpod_warm_loss_grad": [vp, vp, vp, i32, vp],
+            "rpod_warm_train": [vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, vp],
+            "rpod_warm_predict": [vp, vp, i32, vp],
+            "rpod_workspace_size_warm": [ctypes.POINTER(_Desc), vp, i32, ctypes.POINTER(ctypes.c_size_t)],
+            "rpod_plan_create_warm": [ctypes.POINTER(vp), ctypes.POINTER(_Desc), vp, i32, ctypes.c_double, vp,
+                                      ctypes.c_size_t, vp],
+            "rpod_compute_warm": [vp, vp, ctypes.POINTER(ctypes.c_float), u64, vp, vp, vp, ctypes.POINTER(i32),
+                                  ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -316,6 +344,149 @@ class BatchPlan(_PlanBase):
         self.last_flags = list(fl)
         _check(st)
         return list(fl)
+
+
+class WarmModel:
+    """The learned warm start's network and basis bank (rpod_warm_*).
+
+    Bases, parameter vectors and targets are device tensors; a basis of m
+    rows and r columns is passed as an (r, m) tensor (column-major m x r).
+    """
+
+    def __init__(self, m, r, max_train=128, seed=0, device="cuda", stream=None):
+        self.device = _norm_device(device)
+        self.m, self.r, self.max_train = int(m), int(r), int(max_train)
+        self._desc = _WarmDesc(self.m, self.r, self.max_train, int(seed) & (2 ** 64 - 1))
+        self.layout = _WarmLayout()
+        _check(lib().rpod_warm_layout_of(ctypes.byref(self._desc), ctypes.byref(self.layout)))
+        self.workspace = torch.empty(self.layout.total, dtype=torch.uint8, device=self.device)
+        sptr, self.stream = _stream_ptr(stream, self.device)
+        h = ctypes.c_void_p()
+        _check(lib().rpod_warm_create(ctypes.byref(h), ctypes.byref(self._desc), _dev_ptr(self.workspace),
+                                      self.layout.total, sptr))
+        self._h = h
+
+    def _view(self, off, count, dtype):
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return self.workspace[off:off + nbytes].view(dtype)
+
+    def params(self):
+        return self._view(self.layout.params, WARM_PARAMS, torch.float32)
+
+    def grads(self):
+        return self._view(self.layout.grads, WARM_PARAMS, torch.float32)
+
+    def gram(self):
+        k = WARM_BANK * self.r
+        return self._view(self.layout.gram, k * k, torch.float64).view(k, k)
+
+    def gram8(self):
+        return self._view(self.layout.gram8, WARM_BANK * WARM_BANK, torch.float64).view(WARM_BANK, WARM_BANK)
+
+    def _basis_ok(self, B):
+        if B.dtype != torch.float32 or B.device != self.device or tuple(B.shape) != (self.r, self.m) \
+                or not B.is_contiguous():
+            raise ValueError(f"a basis must be a contiguous float32 ({self.r}, {self.m}) tensor on {self.device}")
+
+    def set_bank(self, bases):
+        if len(bases) != WARM_BANK:
+            raise ValueError(f"the bank holds {WARM_BANK} bases")
+        for B in bases:
+            self._basis_ok(B)
+        arr = (ctypes.c_void_p * WARM_BANK)(*[B.data_ptr() for B in bases])
+        _check(lib().rpod_warm_set_bank(self._h, arr))
+
+    def targets(self, basis):
+        self._basis_ok(basis)
+        b = torch.empty(WARM_BANK, dtype=torch.float64, device=self.device)
+        _check(lib().rpod_warm_targets(self._h, _dev_ptr(basis), _dev_ptr(b)))
+        return b
+
+    def _pairs_ok(self, mu, b=None):
+        if mu.dtype != torch.float32 or mu.dim() != 2 or mu.shape[1] != 4 or not mu.is_contiguous() \
+                or mu.device != self.device:
+            raise ValueError("mu must be a contiguous float32 (N, 4) device tensor")
+        if b is not None and (b.dtype != torch.float64 or tuple(b.shape) != (mu.shape[0], WARM_BANK)
+                              or not b.is_contiguous() or b.device != self.device):
+            raise ValueError("b must be a contiguous float64 (N, 8) device tensor")
+
+    def loss_grad(self, mu, b):
+        self._pairs_ok(mu, b)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().rpod_warm_loss_grad(self._h, _dev_ptr(mu), _dev_ptr(b), mu.shape[0], _dev_ptr(loss)))
+        return loss
+
+    def train(self, mu, b, epochs, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-5):
+        self._pairs_ok(mu, b)
+        losses = torch.empty(max(1, int(epochs)), dtype=torch.float32, device=self.device)
+        _check(lib().rpod_warm_train(self._h, _dev_ptr(mu), _dev_ptr(b), mu.shape[0], int(epochs), lr, beta1,
+                                     beta2, eps, weight_decay, _dev_ptr(losses)))
+        return losses[:int(epochs)]
+
+    def predict(self, mu):
+        self._pairs_ok(mu)
+        c = torch.empty((mu.shape[0], WARM_BANK), dtype=torch.float32, device=self.device)
+        _check(lib().rpod_warm_predict(self._h, _dev_ptr(mu), mu.shape[0], _dev_ptr(c)))
+        return c
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rpod_warm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class WarmPlan(_PlanBase):
+    """A warm-started plan for one matrix shape (rpod_plan_create_warm / rpod_compute_warm)."""
+
+    def __init__(self, model, n, p, q, q_fallback=2, tol=1e-3, dtype=torch.float32, ld=None, device="cuda",
+                 stream=None):
+        self.model = model  # must outlive the plan
+        self.device = _norm_device(device)
+        self.m, self.n, self.r, self.p, self.q = model.m, int(n), model.r, int(p), int(q)
+        self.ld = self.m if ld is None else int(ld)
+        self.dtype = dtype
+        self.out_dtype = torch.float32
+        self._desc = make_desc(self.m, self.n, self.r, self.p, self.q, dtype, self.ld)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().rpod_workspace_size_warm(ctypes.byref(self._desc), model._h, int(q_fallback),
+                                              ctypes.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        sptr, self.stream = _stream_ptr(stream, self.device)
+        h = ctypes.c_void_p()
+        _check(lib().rpod_plan_create_warm(ctypes.byref(h), ctypes.byref(self._desc), model._h, int(q_fallback),
+                                           float(tol), _dev_ptr(self.workspace), nbytes.value, sptr))
+        self._h = h
+
+    def compute(self, St, mu, seed, out=None, check=True):
+        """-> (Phi_t (r, m), sigma (r,), A_t (n, r), fell_back, rho)."""
+        _check_St(St, self.dtype, self.device, self.m, self.n, self.ld)
+        if out is None:
+            out = (torch.empty((self.r, self.m), dtype=torch.float32, device=self.device),
+                   torch.empty((self.r,), dtype=torch.float64, device=self.device),
+                   torch.empty((self.n, self.r), dtype=torch.float32, device=self.device))
+        Phi, sigma, A = out
+        mu_arr = (ctypes.c_float * 4)(*[float(x) for x in mu])
+        fb = ctypes.c_int32(0)
+        rho = ctypes.c_double(0)
+        _check(lib().rpod_compute_warm(self._h, _dev_ptr(St), mu_arr, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                       _dev_ptr(Phi), _dev_ptr(sigma), _dev_ptr(A), ctypes.byref(fb),
+                                       ctypes.byref(rho)))
+        if check:
+            self.status()
+        return Phi, sigma, A, bool(fb.value), rho.value
+
+    def status(self):
+        fl = ctypes.c_int32(0)
+        st = lib().rpod_status_query(self._h, ctypes.byref(fl))
+        self.last_flags = fl.value
+        _check(st)
+        return fl.value
 
 
 def rpod(St, r, p, q, seed, stream=None):

@@ -7,7 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librpod.so")
-SOURCES = ["stream_kernels.hip", "stream16_kernels.hip", "small_kernels.hip", "rpod_abi.cpp"]
+SOURCES = ["stream_kernels.hip", "stream16_kernels.hip", "small_kernels.hip", "warm_kernels.hip", "rpod_abi.cpp",
+           "warm_abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -24,7 +25,8 @@ FLAGS = [
 
 def build(verbose=True):
     """Compile every source into librpod.so (always rebuilds)."""
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -32,8 +34,12 @@ def build(verbose=True):
             cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "6"))))
+    with ThreadPoolExecutor(workers) as ex:
+        for fut in [ex.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
+            fut.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

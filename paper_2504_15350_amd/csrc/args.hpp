@@ -19,6 +19,7 @@ struct CallDesc {  // written per compute call
     double* sigma;
     void* A;
     uint64_t seed;
+    float mu[4];  // parameter vector of a warm-started call
 };
 
 struct SxArgs {  // Y = S X
@@ -31,6 +32,7 @@ struct SxArgs {  // Y = S X
     const int* cond;
     int cond_mask;
     int call;  // >= 0: S comes from call table entry `call`
+    int cmax;  // > 0: only output columns < cmax are stored
 };
 
 struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)
@@ -132,6 +134,50 @@ struct SplitArgs {  // 16-bit hi/lo split
 struct ZeroArgs {
     int* p;
     int count;
+};
+
+// ---- learned warm start ----
+struct WarmFwdArgs {  // network forward of the call's parameter vector
+    const float* params;
+    double* c;     // K weights (FP64 copy of the FP32 softmax)
+    int* kstar;    // argmax of c, lowest index on ties
+    int call;
+};
+
+struct WarmZArgs {  // coordinates Z of the predicted subspace in the bank, FP32 out
+    const double* GW;   // Kr x Kr row-major
+    const double* c;
+    const int* kstar;
+    float* X;           // ldX x lp column-major
+    int64_t ldX;
+    int r, Kr, lp, iters;
+};
+
+struct VscaleArgs {  // Xv[:, k] = At[:, k] / sig[k] (k < r), zero elsewhere
+    const double* At;
+    int64_t ldA, n, nP;
+    const double* sig;
+    double* Xv;
+    int r, rp;
+};
+
+struct ResidArgs {  // per (mode, row chunk) partial sums of ||Yres_k - sig_k Phi_k||^2
+    const double* Yres;
+    int64_t ldY, m, chunk;
+    const void* Phi;    // FP32 or FP64 (tphi)
+    int64_t ldP;
+    const double* sig;
+    double* part;
+    int r, nchunk;
+};
+
+struct ResidFinalArgs {
+    const double* part;
+    const double* sig;
+    double* rho;
+    int* flags;
+    double tol;
+    int r, nchunk;
 };
 
 // Workgroup -> (item, local tile) for grouped launches.

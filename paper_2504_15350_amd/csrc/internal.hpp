@@ -34,6 +34,10 @@ struct GroupLaunch {
 //   multiple of 4 (vector loads). upper: X is upper triangular (16 x 16 tiles
 //   below the diagonal skipped).
 hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const GroupLaunch<SxArgs>& L, hipStream_t st);
+// The same product with X and Y in FP64 and S of any storage type tin,
+// converted to FP64 in registers (FP64 matrix cores; vec: 8-byte-or-wider
+// aligned vector loads as for launch_sx with that storage type).
+hipError_t launch_sx_wide(int tin, int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st);
 
 // Split-K transposed product: slab s = S[rows of split s]^T Q[rows of split s]
 // (FP64 slabs nP x 16*nt, column-major). S: m x n (ldS); Q: m x 16*nt (ldQ,
@@ -113,6 +117,53 @@ hipError_t launch_omega_direct(int tout, uint64_t seed, int64_t n, int l, void* 
 hipError_t launch_sketch_bits(uint64_t seed, int64_t n, int l, uint32_t* out, hipStream_t st);
 
 hipError_t launch_zero_ints(const GroupLaunch<ZeroArgs>& L, hipStream_t st);
+
+// ---- learned warm start (warm_kernels.hip) ----
+// Network 4 -> 256 -> 256 -> K (tanh, tanh, softmax), FP32 parameters packed
+// as W1 (256 x 4, row-major), b1, W2 (256 x 256), b2, W3 (K x 256), b3.
+constexpr int WARM_IN = 4, WARM_H = 256, WARM_K = 8;
+constexpr int WP_W1 = 0, WP_B1 = WP_W1 + WARM_H * WARM_IN, WP_W2 = WP_B1 + WARM_H,
+              WP_B2 = WP_W2 + WARM_H * WARM_H, WP_W3 = WP_B2 + WARM_H, WP_B3 = WP_W3 + WARM_K * WARM_H,
+              WP_COUNT = WP_B3 + WARM_K;
+constexpr int DEV_FLAG_RESIDUAL = 0x10;
+
+// Glorot-uniform weights from Philox4x32-10 (key = seed, counter = element
+// index), zero biases.
+hipError_t launch_warm_init(float* params, uint64_t seed, hipStream_t st);
+// Forward of N parameter vectors (N x 4, row-major): hidden layers H1, H2
+// (N x 256), softmax weights C (N x K).
+hipError_t launch_warm_forward_batch(const float* params, const float* mu, int N, float* H1, float* H2, float* C,
+                                     hipStream_t st);
+// Loss of every pair (r - 2 b^T c + c^T G8 c) into loss_n, and dZ = dL/dz of
+// the mean loss (N x K), from C; then the mean into *loss.
+hipError_t launch_warm_loss(const float* C, const double* B, const double* G8, int N, int r, float* dZ,
+                            double* loss_n, float* loss, hipStream_t st);
+// Backward through the three layers into grads (same packing as params).
+hipError_t launch_warm_backward(const float* params, const float* mu, int N, const float* H1, const float* H2,
+                                const float* dZ, float* dA2, float* dA1, float* grads, hipStream_t st);
+// One Adam step (L2 weight decay in the gradient); bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
+hipError_t launch_warm_adam(float* params, const float* grads, float* m, float* v, float lr, float beta1,
+                            float beta2, float eps, float wd, float bc1, float bc2, hipStream_t st);
+// dst (ldd x cols_pad, FP32) = src (lds x cols) on rows < rows, zero on rows
+// [rows, rows_pad) and columns [cols, cols_pad).
+hipError_t launch_copy_pad(float* dst, int64_t ldd, const float* src, int64_t lds, int64_t rows, int64_t rows_pad,
+                           int cols, int cols_pad, hipStream_t st);
+// G[a][c0 + col] = Z[col * ldz + a] for a < Kr, col < ncol (G row-major, ld Kr).
+hipError_t launch_gather_cols(double* G, int Kr, int c0, int ncol, const double* Z, int64_t ldz, hipStream_t st);
+// out[k * KB + l] = sum over a in block k, b in block l (blocks of r) of
+// src[a * sa + b * sb]^2; KA x KB outputs.
+hipError_t launch_block_sumsq(const double* src, int64_t sa, int64_t sb, int r, int KA, int KB, double* out,
+                              hipStream_t st);
+// Plan steps (grouped): network forward of the call's parameter vector, the
+// predicted subspace's coordinates (tiles: lp per matrix), the scaled right
+// vectors (tiles: ceil(nP rp / 256)), the residual partials (tiles: r x
+// nchunk) and the residual rho = max_k ||S v_k - sigma_k phi_k|| / sigma_k
+// (one workgroup per matrix; DEV_FLAG_RESIDUAL when rho > tol).
+hipError_t launch_warm_plan_forward(const GroupLaunch<WarmFwdArgs>& L, hipStream_t st);
+hipError_t launch_warm_z(const GroupLaunch<WarmZArgs>& L, hipStream_t st);
+hipError_t launch_warm_vscale(const GroupLaunch<VscaleArgs>& L, hipStream_t st);
+hipError_t launch_warm_resid(int tphi, const GroupLaunch<ResidArgs>& P, const GroupLaunch<ResidFinalArgs>& F,
+                             hipStream_t st);
 
 // Write count call-table entries from host values (through kernel arguments).
 hipError_t launch_set_calls(CallDesc* table, const CallDesc* host, int count, hipStream_t st);

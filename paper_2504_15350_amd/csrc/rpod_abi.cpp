@@ -16,6 +16,7 @@
 
 #include "../../include/rpod.h"
 #include "internal.hpp"
+#include "warm_model.hpp"
 
 using namespace rpod;
 
@@ -32,6 +33,18 @@ rpod_status fail(rpod_status s, const char* fmt, ...) {
 }
 
 int64_t roundup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+rpod_status rpod_internal_fail(rpod_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+namespace {
 
 size_t dt_size(int dt) {
     switch (dt) {
@@ -148,7 +161,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // Recorded program
 // ---------------------------------------------------------------------------
 enum Kind { K_ZERO, K_OMEGA, K_SX, K_SX16, K_STQ, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT, K_SIGNS,
-            K_FIN, K_SPLIT };
+            K_FIN, K_SPLIT, K_WFWD, K_WZ, K_VSCALE, K_SXW, K_RESID };
 
 struct Step {
     Kind kind;
@@ -210,7 +223,18 @@ struct rpod_plan_s {
     std::vector<double> evbytes[2], evflops[2];
     size_t used[2] = {0, 0};
     std::vector<CallDesc> host_calls;
+    // warm plans: the model, the fallback program and its graph, the warm region
+    rpod_warm_s* model = nullptr;
+    std::vector<std::vector<Step>> fb_programs;
+    hipGraph_t fb_graph = nullptr;
+    hipGraphExec_t fb_exec = nullptr;
+    size_t o_warm = 0, w_Xw = 0, w_c = 0, w_kstar = 0, w_Xv = 0, w_Yres = 0, w_part = 0, w_rho = 0;
+    int64_t ldXw = 0;
+    double tol = 0.0;
+    int q_fb = 0;
 
+    template <typename T>
+    T* wat(size_t off) const { return reinterpret_cast<T*>(ws + o_warm + off); }
     int* flags(const Item& it) const { return reinterpret_cast<int*>(ws + o_flags) + FLAG_INTS * it.idx; }
     template <typename T>
     T* at(const Item& it, size_t off) const { return reinterpret_cast<T*>(ws + it.off + off); }
@@ -506,6 +530,83 @@ struct Recorder {
         B.add(fn, fargs, tiles([](const Item& it) { return fin_a_tiles(it.d.n, it.d.r); }), true);
         out.push_back(fn);
     }
+    // Warm-started program (single matrix): Y = [W, S Omega_p], then as
+    // record(), then the residual of the returned modes.
+    void record_warm() {
+        const Item& it = *C[0];
+        const Layout& L = it.L;
+        const rpod_warm_s* M = P->model;
+        const bool s16 = is16(L.tin);
+        const int p = it.d.p, r = it.d.r;
+        const int lpad = (int)roundup(p, 16);
+        zero();
+        Step f{K_WFWD};
+        B.add(f, std::vector<WarmFwdArgs>{{M->at<float>(M->L.params), P->wat<double>(P->w_c), P->wat<int>(P->w_kstar),
+                                           it.idx}},
+              std::vector<int>{1});
+        out.push_back(f);
+        Step z{K_WZ};
+        B.add(z, std::vector<WarmZArgs>{{M->at<double>(M->L.gram), P->wat<double>(P->w_c), P->wat<int>(P->w_kstar),
+                                         P->wat<float>(P->w_Xw), P->ldXw, r, M->Kr, L.lp, 2}},
+              std::vector<int>{L.lp});
+        out.push_back(z);
+        Step o{K_OMEGA};
+        o.tout = L.tin;
+        OmegaArgs oa{};
+        oa.out = P->at<char>(it, L.o_X);
+        oa.n = it.d.n; oa.rows_pad = L.nP; oa.ldo = L.nP; oa.seed = 0; oa.l = p; oa.lpad = lpad; oa.call = it.idx;
+        B.add(o, std::vector<OmegaArgs>{oa}, std::vector<int>{(int)((L.nP + 255) / 256) * (lpad / 2)});
+        out.push_back(o);
+        // pass over S: the Gaussian columns, stored after the r predicted ones
+        Step g{s16 ? K_SX16 : K_SX};
+        g.tin = L.tin; g.tout = L.tacc; g.nt = lpad / 16; g.pass = 0;
+        g.vec = it.d.ld % (s16 ? 8 : 4) == 0;
+        const double sz = (double)dt_size(L.tin);
+        g.bytes = (double)it.d.m * it.d.n * sz + (double)it.d.n * p * sz + (double)it.d.m * p * 4.0;
+        g.flops = 2.0 * it.d.m * it.d.n * p;
+        SxArgs ga{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, L.o_X), L.nP,
+                  P->at<char>(it, L.o_Y) + (size_t)r * L.mP * dt_size(L.tacc), L.mP, L.mP, nullptr, 0, it.idx, p};
+        B.add(g, std::vector<SxArgs>{ga}, std::vector<int>{(int)(L.mP / 256)});
+        out.push_back(g);
+        // the predicted subspace W = bank Z into the first r columns
+        sx(DT_F32, DT_F32, L.nt, false,
+           std::vector<SxArgs>{{M->at<float>(M->L.bank), M->mP, it.d.m, M->Kr, P->wat<float>(P->w_Xw), P->ldXw,
+                                P->at<char>(it, L.o_Y), L.mP, L.mP, nullptr, 0, -1, r}});
+        orth_tall(1);
+        for (int i = 0; i < it.d.q; ++i) {
+            pass_stq(false);
+            small_from_slabs();
+            basis_small();
+            pass_sx();
+            orth_tall(1);
+        }
+        pass_stq(true);
+        small_from_slabs();
+        finish();
+        // residual: Yres = S V_r (FP64 products), then rho
+        Step v{K_VSCALE};
+        B.add(v, std::vector<VscaleArgs>{{P->at<double>(it, L.o_At), L.nP, it.d.n, L.nP, P->at<double>(it, L.o_sig),
+                                          P->wat<double>(P->w_Xv), r, L.rp}},
+              std::vector<int>{(int)((L.nP * L.rp + 255) / 256)});
+        out.push_back(v);
+        Step w{K_SXW};
+        w.tin = L.tin; w.nt = L.ntr;
+        w.vec = it.d.ld % (s16 ? 8 : 4) == 0;
+        B.add(w, std::vector<SxArgs>{{nullptr, it.d.ld, it.d.m, it.d.n, P->wat<double>(P->w_Xv), L.nP,
+                                      P->wat<double>(P->w_Yres), L.mP, L.mP, nullptr, 0, it.idx, 0}},
+              std::vector<int>{(int)(L.mP / 256)});
+        out.push_back(w);
+        Step rs{K_RESID};
+        rs.tin = L.tacc;
+        const int64_t chunk = (it.d.m + L.nchunk - 1) / L.nchunk;
+        B.add(rs, std::vector<ResidArgs>{{P->wat<double>(P->w_Yres), L.mP, it.d.m, chunk, P->at<char>(it, L.o_Phi), L.mP,
+                                          P->at<double>(it, L.o_sig), P->wat<double>(P->w_part), r, L.nchunk}},
+              std::vector<int>{r * L.nchunk});
+        B.add(rs, std::vector<ResidFinalArgs>{{P->wat<double>(P->w_part), P->at<double>(it, L.o_sig),
+                                               P->wat<double>(P->w_rho), P->flags(it), P->tol, r, L.nchunk}},
+              std::vector<int>{1}, true);
+        out.push_back(rs);
+    }
     void record() {
         zero();
         omega();         // Alg. 1 step 1
@@ -549,6 +650,11 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_SIGNS: return launch_signs(s.tin, P->gl<ColmaxArgs>(s, false), P->gl<SignArgs>(s, true), st);
         case K_FIN: return launch_finalize(s.tin, P->gl<FinArgs>(s, false), P->gl<FinArgs>(s, true), st);
         case K_SPLIT: return launch_split16(s.tin, P->gl<SplitArgs>(s, false), st);
+        case K_WFWD: return launch_warm_plan_forward(P->gl<WarmFwdArgs>(s, false), st);
+        case K_WZ: return launch_warm_z(P->gl<WarmZArgs>(s, false), st);
+        case K_VSCALE: return launch_warm_vscale(P->gl<VscaleArgs>(s, false), st);
+        case K_SXW: return launch_sx_wide(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
+        case K_RESID: return launch_warm_resid(s.tin, P->gl<ResidArgs>(s, false), P->gl<ResidFinalArgs>(s, true), st);
     }
     return hipErrorInvalidValue;
 }
@@ -578,8 +684,8 @@ hipError_t mark(rpod_plan_s* P, const Step& s, bool begin, hipStream_t st) {
     return err;
 }
 
-hipError_t replay(rpod_plan_s* P, hipStream_t st) {
-    for (const std::vector<Step>& prog : P->programs)
+hipError_t replay(rpod_plan_s* P, const std::vector<std::vector<Step>>& programs, hipStream_t st) {
+    for (const std::vector<Step>& prog : programs)
         for (const Step& s : prog) {
             hipError_t e = mark(P, s, true, st);
             if (e == hipSuccess) e = run_step(P, s, st);
@@ -591,12 +697,13 @@ hipError_t replay(rpod_plan_s* P, hipStream_t st) {
 
 // Capture the whole program into a hipGraph on private streams, one branch per
 // class (branches are independent).
-hipError_t capture(rpod_plan_s* P) {
+hipError_t capture(rpod_plan_s* P, const std::vector<std::vector<Step>>& programs, hipGraph_t* graph,
+                   hipGraphExec_t* exec) {
     hipStream_t cs = nullptr;
     std::vector<hipStream_t> fs;
     std::vector<hipEvent_t> evs;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    const size_t nb = P->programs.size();
+    const size_t nb = programs.size();
     for (size_t k = 0; e == hipSuccess && k < nb; ++k) {
         hipStream_t s;
         e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -613,7 +720,7 @@ hipError_t capture(rpod_plan_s* P) {
     if (e == hipSuccess) e = hipEventRecord(evs[nb], cs);
     for (size_t k = 0; e == hipSuccess && k < nb; ++k) {
         e = hipStreamWaitEvent(fs[k], evs[nb], 0);
-        for (size_t i = 0; e == hipSuccess && i < P->programs[k].size(); ++i) e = run_step(P, P->programs[k][i], fs[k]);
+        for (size_t i = 0; e == hipSuccess && i < programs[k].size(); ++i) e = run_step(P, programs[k][i], fs[k]);
         if (e == hipSuccess) e = hipEventRecord(evs[k], fs[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, evs[k], 0);
     }
@@ -621,8 +728,8 @@ hipError_t capture(rpod_plan_s* P) {
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) P->graph = g;
+        if (e == hipSuccess) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) *graph = g;
         else if (g) (void)hipGraphDestroy(g);
     }
     for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
@@ -712,6 +819,8 @@ rpod_status workspace_bytes(const rpod_desc* descs, int32_t count, const rpod_tu
 void destroy_plan(rpod_plan_s* P) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->fb_exec) (void)hipGraphExecDestroy(P->fb_exec);
+    if (P->fb_graph) (void)hipGraphDestroy(P->fb_graph);
     for (int k = 0; k < 2; ++k)
         for (hipEvent_t ev : P->ev[k]) (void)hipEventDestroy(ev);
     delete P;
@@ -750,7 +859,7 @@ rpod_status create_plan(rpod_plan* plan, const rpod_desc* descs, int32_t count, 
     }
     const char* ng = std::getenv("RPOD_NO_GRAPH");
     if (!(ng && ng[0] == '1')) {
-        e = capture(P);
+        e = capture(P, P->programs, &P->graph, &P->exec);
         if (e != hipSuccess) {
             destroy_plan(P);
             return fail(RPOD_EHIP, "capturing the launch graph failed: %s", hipGetErrorString(e));
@@ -761,7 +870,7 @@ rpod_status create_plan(rpod_plan* plan, const rpod_desc* descs, int32_t count, 
 }
 
 rpod_status compute_impl(rpod_plan_s* P, const void* const* S, const uint64_t* seeds, void* const* Phi,
-                         double* const* sigma, void* const* A) {
+                         double* const* sigma, void* const* A, const float* mu = nullptr) {
     const int count = (int)P->items.size();
     for (int i = 0; i < count; ++i) {
         const Item& it = P->items[i];
@@ -777,13 +886,91 @@ rpod_status compute_impl(rpod_plan_s* P, const void* const* S, const uint64_t* s
         const size_t so = dt_size(it.L.tacc);
         if ((uintptr_t)Phi[i] % so || (uintptr_t)A[i] % so || (uintptr_t)sigma[i] % 8)
             return fail(RPOD_EINVAL, "matrix %d: Phi, A or sigma is not aligned to its element size", i);
-        P->host_calls[i] = CallDesc{S[i], Phi[i], sigma[i], A[i], seeds[i]};
+        P->host_calls[i] = CallDesc{S[i], Phi[i], sigma[i], A[i], seeds[i], {0.f, 0.f, 0.f, 0.f}};
+        if (mu != nullptr)
+            for (int k = 0; k < 4; ++k) P->host_calls[i].mu[k] = mu[k];
     }
     HIP_TRY(launch_set_calls(P->calls(), P->host_calls.data(), count, P->st));
     if (P->exec != nullptr && !P->timing)
         HIP_TRY(hipGraphLaunch(P->exec, P->st));
     else
-        HIP_TRY(replay(P, P->st));
+        HIP_TRY(replay(P, P->programs, P->st));
+    return RPOD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Warm plans
+// ---------------------------------------------------------------------------
+rpod_status warm_check(const rpod_desc* d, const rpod_warm_s* M) {
+    if (M == nullptr) return fail(RPOD_EINVAL, "model is NULL");
+    rpod_status s = validate(d);
+    if (s != RPOD_OK) return s;
+    if (d->dtype == RPOD_F64) return fail(RPOD_EUNSUPPORTED, "warm plans take FP32, BF16 or FP16 matrices");
+    if (d->m != M->d.m) return fail(RPOD_EINVAL, "desc.m (%lld) differs from the model's m (%lld)", (long long)d->m,
+                                    (long long)M->d.m);
+    if (d->r != M->d.r) return fail(RPOD_EINVAL, "desc.r (%d) differs from the model's r (%d)", d->r, M->d.r);
+    if (d->p < 1) return fail(RPOD_EINVAL, "warm plans need p >= 1 Gaussian columns");
+    return RPOD_OK;
+}
+
+// Warm region after the matrix region; returns its size.
+size_t warm_region(rpod_plan_s* P) {
+    const Item& it = P->items[0];
+    const Layout& L = it.L;
+    P->ldXw = roundup(P->model->Kr, 16);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    P->w_Xw = take((size_t)P->ldXw * L.lp * 4);
+    P->w_c = take(WARM_K * 8);
+    P->w_kstar = take(sizeof(int));
+    P->w_Xv = take((size_t)L.nP * L.rp * 8);
+    P->w_Yres = take((size_t)L.mP * L.rp * 8);
+    P->w_part = take((size_t)L.rp * L.nchunk * 8);
+    P->w_rho = take(8);
+    return off;
+}
+
+// Lay out and record a warm plan (host only); returns the workspace bytes.
+rpod_status warm_build(rpod_plan_s* P, const rpod_desc* desc, rpod_warm_s* M, int32_t q_fb, double tol,
+                       std::vector<char>* blob_out, size_t* bytes) {
+    rpod_status s = warm_check(desc, M);
+    if (s != RPOD_OK) return s;
+    if (q_fb < 0) return fail(RPOD_EINVAL, "q_fallback must be >= 0");
+    if (!(tol >= 0.0)) return fail(RPOD_EINVAL, "tol must be >= 0");
+    BatchLayout bl;
+    s = batch_layout(desc, 1, nullptr, bl);
+    if (s != RPOD_OK) return s;
+    P->items = bl.items;
+    P->o_flags = bl.o_flags;
+    P->o_calls = bl.o_calls;
+    P->model = M;
+    P->tol = tol;
+    P->q_fb = q_fb;
+    P->o_warm = bl.o_items_end;
+    const size_t wbytes = warm_region(P);
+    P->o_prog = P->o_warm + wbytes;
+    Builder B;
+    P->programs.assign(1, {});
+    {
+        std::vector<const Item*> cls{&P->items[0]};
+        Recorder R{P, B, cls, P->programs[0]};
+        R.record_warm();
+    }
+    // the fallback: plain rPOD with q_fb iterations on the same buffers
+    Item fb = P->items[0];
+    fb.d.q = q_fb;
+    P->fb_programs.assign(1, {});
+    {
+        std::vector<const Item*> cls{&fb};
+        Recorder R{P, B, cls, P->fb_programs[0]};
+        R.record();
+    }
+    *bytes = P->o_prog + (B.blob.size() + 255) / 256 * 256;
+    if (blob_out) *blob_out = B.blob;
     return RPOD_OK;
 }
 
@@ -1013,6 +1200,79 @@ rpod_status rpod_autotune(const rpod_desc* descs, int32_t count, const void* con
                     cache_path, best, best_ms);
 }
 
+rpod_status rpod_workspace_size_warm(const rpod_desc* desc, rpod_warm model, int32_t q_fallback, size_t* bytes) {
+    if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
+    rpod_plan_s tmp;
+    return warm_build(&tmp, desc, model, q_fallback, 0.0, nullptr, bytes);
+}
+
+rpod_status rpod_plan_create_warm(rpod_plan* plan, const rpod_desc* desc, rpod_warm model, int32_t q_fallback,
+                                  double tol, void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (workspace == nullptr || (uintptr_t)workspace % 256 != 0)
+        return fail(RPOD_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    rpod_plan_s* P = new (std::nothrow) rpod_plan_s;
+    if (P == nullptr) return fail(RPOD_ENOMEM, "host allocation of the plan failed");
+    P->ws = static_cast<char*>(workspace);  // recorded arguments point into the workspace
+    P->ws_bytes = workspace_bytes;
+    P->st = static_cast<hipStream_t>(hip_stream);
+    std::vector<char> blob;
+    size_t need = 0;
+    rpod_status s = warm_build(P, desc, model, q_fallback, tol, &blob, &need);
+    if (s != RPOD_OK) {
+        delete P;
+        return s;
+    }
+    if (workspace_bytes < need) {
+        delete P;
+        return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+    }
+    P->host_calls.resize(1);
+    hipError_t e = hipMemsetAsync(workspace, 0, need, P->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->ws + P->o_prog, blob.data(), blob.size(), hipMemcpyHostToDevice, P->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->st);
+    if (e != hipSuccess) {
+        destroy_plan(P);
+        return fail(RPOD_EHIP, "initialising the workspace failed: %s", hipGetErrorString(e));
+    }
+    const char* ng = std::getenv("RPOD_NO_GRAPH");
+    if (!(ng && ng[0] == '1')) {
+        e = capture(P, P->programs, &P->graph, &P->exec);
+        if (e == hipSuccess) e = capture(P, P->fb_programs, &P->fb_graph, &P->fb_exec);
+        if (e != hipSuccess) {
+            destroy_plan(P);
+            return fail(RPOD_EHIP, "capturing the launch graphs failed: %s", hipGetErrorString(e));
+        }
+    }
+    *plan = P;
+    return RPOD_OK;
+}
+
+rpod_status rpod_compute_warm(rpod_plan plan, const void* S, const float* mu, uint64_t seed, void* Phi,
+                              double* sigma, void* A, int32_t* fell_back, double* rho) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    if (plan->model == nullptr) return fail(RPOD_EINVAL, "not a warm plan: use rpod_compute");
+    if (mu == nullptr) return fail(RPOD_EINVAL, "mu is NULL");
+    rpod_status s = compute_impl(plan, &S, &seed, &Phi, &sigma, &A, mu);
+    if (s != RPOD_OK) return s;
+    double rh = 0.0;
+    int fl = 0;
+    HIP_TRY(hipMemcpyAsync(&rh, plan->wat<double>(plan->w_rho), sizeof(double), hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipMemcpyAsync(&fl, plan->flags(plan->items[0]), sizeof(int), hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipStreamSynchronize(plan->st));
+    const bool fb = !(rh <= plan->tol) || (fl & (RPOD_FLAG_BREAKDOWN | RPOD_FLAG_NONFINITE));
+    if (fb) {
+        if (plan->fb_exec != nullptr && !plan->timing)
+            HIP_TRY(hipGraphLaunch(plan->fb_exec, plan->st));
+        else
+            HIP_TRY(replay(plan, plan->fb_programs, plan->st));
+    }
+    if (fell_back) *fell_back = fb ? 1 : 0;
+    if (rho) *rho = rh;
+    return RPOD_OK;
+}
+
 rpod_status rpod_plan_destroy(rpod_plan plan) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     hipError_t e = hipStreamSynchronize(plan->st);
@@ -1024,6 +1284,7 @@ rpod_status rpod_plan_destroy(rpod_plan plan) {
 rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi, double* sigma, void* A) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     if (plan->items.size() != 1) return fail(RPOD_EINVAL, "plan holds a batch: use rpod_compute_batched");
+    if (plan->model != nullptr) return fail(RPOD_EINVAL, "warm plan: use rpod_compute_warm");
     return compute_impl(plan, &S, &seed, &Phi, &sigma, &A);
 }
 
@@ -1032,6 +1293,7 @@ rpod_status rpod_compute_batched(rpod_plan plan, const void* const* S, const uin
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     if (S == nullptr || seeds == nullptr || Phi == nullptr || sigma == nullptr || A == nullptr)
         return fail(RPOD_EINVAL, "pointer arrays must be non-NULL");
+    if (plan->model != nullptr) return fail(RPOD_EINVAL, "warm plan: use rpod_compute_warm");
     return compute_impl(plan, S, seeds, Phi, sigma, A);
 }
 

@@ -87,7 +87,8 @@ constexpr int SX16_LDX = SX16_BK + 8;   // X tile column stride (elements): conf
 template <typename T16, int NT, bool VEC>
 __device__ __forceinline__ void sx16_body(const GLOBAL unsigned short* __restrict__ S, int64_t ldS, int64_t m,
                                           int64_t n, const GLOBAL unsigned short* __restrict__ X, int64_t ldX,
-                                          GLOBAL float* __restrict__ Y, int64_t ldY, int64_t mstore, int64_t bx) {
+                                          GLOBAL float* __restrict__ Y, int64_t ldY, int64_t mstore, int cmax,
+                                          int64_t bx) {
     __shared__ unsigned short tile[SX16_BK * SX16_LDR];
     __shared__ __attribute__((aligned(16))) unsigned short xt[16 * NT * SX16_LDX];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -155,6 +156,7 @@ __device__ __forceinline__ void sx16_body(const GLOBAL unsigned short* __restric
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
+            if (16 * c + r16 >= cmax) continue;
             const int64_t row = i0 + wave * 64 + 16 * mt + 4 * kg;
             GLOBAL float* py = Y + (int64_t)(16 * c + r16) * ldY + row;
             if (row + 3 < mstore) {
@@ -173,7 +175,8 @@ __global__ __launch_bounds__(256, 2) void k_sx16(Group<SxArgs> g) {
     const SxArgs& a = g.args[it];
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
     sx16_body<T16, NT, VEC>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.X), a.ldX,
-                            gbl((float*)a.Y), a.ldY, a.mstore, blockIdx.x - g.tstart[it]);
+                            gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
+                            blockIdx.x - g.tstart[it]);
 }
 
 // ---------------------------------------------------------------------------

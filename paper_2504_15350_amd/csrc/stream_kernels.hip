@@ -50,29 +50,36 @@ __device__ __forceinline__ void store4(GLOBAL Tout* p, T a, T b, T c, T d) {
 //   A[mm][k] = S[iw + 4 mm + t][j0 + 4 k + s],  B[k][nn] = X[j0 + 4 k + s][16 c + nn]
 // so output row mm of MFMA t is global row iw + 4 mm + t.
 // ---------------------------------------------------------------------------
-template <typename Tin, typename Tout, int NT, bool VEC, bool UPPER>
+// Tc: matrix-core type (X's type). S of a narrower storage type Tin is
+// converted in registers (Tc = double: the FP64 residual products). Only
+// output columns below cmax are stored.
+template <typename Tin, typename Tc, typename Tout, int NT, bool VEC, bool UPPER>
 __device__ __forceinline__ void sx_body(const GLOBAL Tin* S, int64_t ldS, int64_t m, int64_t n,
-                                        const GLOBAL Tin* __restrict__ X, int64_t ldX, GLOBAL Tout* Y, int64_t ldY,
-                                        int64_t mstore, int64_t bx) {
+                                        const GLOBAL Tc* __restrict__ X, int64_t ldX, GLOBAL Tout* Y, int64_t ldY,
+                                        int64_t mstore, int cmax, int64_t bx) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
     const int64_t iw = bx * 256 + wave * 64;
     const int64_t irow = iw + 4 * r16;
 
-    V4<Tin> acc[4][NT];
+    V4<Tc> acc[4][NT];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int c = 0; c < NT; ++c) acc[t][c] = V4<Tin>{0, 0, 0, 0};
+        for (int c = 0; c < NT; ++c) acc[t][c] = V4<Tc>{0, 0, 0, 0};
 
     if (iw < m) {
         for (int64_t j0 = 0; j0 < n; j0 += 16) {
-            V4<Tin> a[4], b[NT];
+            V4<Tc> a[4], b[NT];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) a[s] = load_rows4<VEC>(S, ldS, m, n, irow, j0 + 4 * kg + s);
+            for (int s = 0; s < 4; ++s) {
+                const V4<Tin> raw = load_rows4<VEC>(S, ldS, m, n, irow, j0 + 4 * kg + s);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[s][t] = (Tc)raw[t];
+            }
 #pragma unroll
             for (int c = 0; c < NT; ++c)
-                b[c] = *reinterpret_cast<const GLOBAL V4<Tin>*>(X + (int64_t)(16 * c + r16) * ldX + j0 + 4 * kg);
+                b[c] = *reinterpret_cast<const GLOBAL V4<Tc>*>(X + (int64_t)(16 * c + r16) * ldX + j0 + 4 * kg);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -88,10 +95,11 @@ __device__ __forceinline__ void sx_body(const GLOBAL Tin* S, int64_t ldS, int64_
     // row iw + 4 mm + t: rows t = 0..3 are contiguous
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
+        if (16 * c + r16 >= cmax) continue;
         GLOBAL Tout* py = Y + (int64_t)(16 * c + r16) * ldY;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t row = iw + 4 * mfma_row<Tin>(kg, v);
+            const int64_t row = iw + 4 * mfma_row<Tc>(kg, v);
             if (row + 3 < mstore) {
                 store4<Tout>(py + row, acc[0][c][v], acc[1][c][v], acc[2][c][v], acc[3][c][v]);
             } else {
@@ -109,8 +117,21 @@ __global__ __launch_bounds__(256) void k_sx(Group<SxArgs> g) {
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
-    sx_body<Tin, Tout, NT, VEC, UPPER>(gbl((const Tin*)S), a.ldS, a.m, a.n, gbl((const Tin*)a.X), a.ldX,
-                                       gbl((Tout*)a.Y), a.ldY, a.mstore, blockIdx.x - g.tstart[it]);
+    sx_body<Tin, Tin, Tout, NT, VEC, UPPER>(gbl((const Tin*)S), a.ldS, a.m, a.n, gbl((const Tin*)a.X), a.ldX,
+                                            gbl((Tout*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
+                                            blockIdx.x - g.tstart[it]);
+}
+
+// Y (FP64) = S X with X in FP64 and S of any storage type, FP64 matrix cores.
+template <typename Tin, int NT, bool VEC>
+__global__ __launch_bounds__(256) void k_sx_wide(Group<SxArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const SxArgs& a = g.args[it];
+    if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    sx_body<Tin, double, double, NT, VEC, false>(gbl((const Tin*)S), a.ldS, a.m, a.n, gbl((const double*)a.X),
+                                                 a.ldX, gbl((double*)a.Y), a.ldY, a.mstore,
+                                                 a.cmax > 0 ? a.cmax : 16 * NT, blockIdx.x - g.tstart[it]);
 }
 
 // ---------------------------------------------------------------------------
@@ -224,6 +245,35 @@ static hipError_t sx_dispatch(int nt, const GroupLaunch<SxArgs>& L, bool vec, bo
 #undef RPOD_SX_CASE
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename Tin, int NT>
+static hipError_t sxw_nt(const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st) {
+    const Group<SxArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
+    if (vec)
+        hipLaunchKernelGGL((k_sx_wide<Tin, NT, true>), dim3(L.tiles), dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((k_sx_wide<Tin, NT, false>), dim3(L.tiles), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+template <typename Tin>
+static hipError_t sxw_dispatch(int nt, const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st) {
+    switch (nt) {
+#define RPOD_SXW_CASE(K) case K: return sxw_nt<Tin, K>(L, vec, st);
+        RPOD_SXW_CASE(1) RPOD_SXW_CASE(2) RPOD_SXW_CASE(3) RPOD_SXW_CASE(4)
+        RPOD_SXW_CASE(5) RPOD_SXW_CASE(6) RPOD_SXW_CASE(7) RPOD_SXW_CASE(8)
+#undef RPOD_SXW_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sx_wide(int tin, int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st) {
+    if (tin == DT_F32) return sxw_dispatch<float>(nt, L, vec, st);
+    if (tin == DT_BF16) return sxw_dispatch<__bf16>(nt, L, vec, st);
+    if (tin == DT_F16) return sxw_dispatch<_Float16>(nt, L, vec, st);
+    if (tin == DT_F64) return sxw_dispatch<double>(nt, L, vec, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const GroupLaunch<SxArgs>& L, hipStream_t st) {

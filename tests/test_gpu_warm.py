@@ -1,0 +1,282 @@
+"""GPU tests of the learned warm start against the CPU FP64 oracle.
+
+Network forward, loss, gradient and Adam step, the bank Grams and targets,
+the warm-started rPOD with its residual and fallback, and the gain of the
+trained network over an untrained (uniform-weight) one and over plain rPOD
+at the same number of passes. Inputs: the parametric family
+S(mu) = U(mu) diag(exp(-alpha k)) V^T + noise on a 64 x 128 grid.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_15350_amd as rp
+import synth
+from oracle import metrics, philox, pod
+from oracle import rpod as orpod
+from oracle import warm as ow
+
+from test_gpu_parity import DEV, say
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, N, R, P = 64, 128, 300, 20, 10
+COUNT, NTRAIN = 40, 30
+NOISE = 1e-7
+
+OFFS = {"W1": (0, (256, 4)), "b1": (1024, (256,)), "W2": (1280, (256, 256)), "b2": (66816, (256,)),
+        "W3": (67072, (8, 256)), "b3": (69120, (8,))}
+
+
+def unpack(flat):
+    flat = np.asarray(flat, dtype=np.float64)
+    return {k: flat[o:o + int(np.prod(sh))].reshape(sh) for k, (o, sh) in OFFS.items()}
+
+
+def pack(P):
+    out = np.zeros(rp.WARM_PARAMS, dtype=np.float32)
+    for k, (o, sh) in OFFS.items():
+        out[o:o + int(np.prod(sh))] = np.asarray(P[k], dtype=np.float32).reshape(-1)
+    return out
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def world():
+    """The family, 40 parameter draws, the matrices, and a bank of 8 GPU rPOD bases."""
+    fam = synth.ParamFamily(NX, NY)
+    mu, mu_hat = synth.draw_params(COUNT, seed=21)
+    g = np.random.default_rng(22)
+    perm = g.permutation(COUNT)
+    train, test = np.sort(perm[:NTRAIN]), np.sort(perm[NTRAIN:])
+    mats = [fam.matrix(mu[i], N, noise_std=NOISE, seed=100 + i, dtype=np.float32) for i in range(COUNT)]
+    Sd = [torch.from_numpy(d["St"]).to(DEV) for d in mats]
+    # plain GPU rPOD bases of every training matrix (the training targets and the bank)
+    bases = {}
+    plan = rp.Plan(fam.m, N, R, P, 2, dtype=torch.float32, device=DEV)
+    for i in train:
+        Phi_t, _, _ = plan.compute(Sd[i], 7 + int(i))
+        bases[int(i)] = Phi_t.clone()
+    plan.close()
+    bank_idx = [int(train[j]) for j in synth.farthest_points(mu_hat[train], 8)]
+    say(f"[warm] bank matrices {bank_idx}")
+    return dict(fam=fam, mu=mu, mu_hat=mu_hat, train=train, test=test, mats=mats, Sd=Sd, bases=bases,
+                bank_idx=bank_idx)
+
+
+def make_model(world, seed=3):
+    model = rp.WarmModel(world["fam"].m, R, max_train=64, seed=seed, device=DEV)
+    model.set_bank([world["bases"][i] for i in world["bank_idx"]])
+    return model
+
+
+def bank64(world):
+    return [world["bases"][i].double().cpu().numpy().T for i in world["bank_idx"]]
+
+
+def test_init_is_glorot_uniform_and_seeded(world):
+    a = make_model(world, seed=11).params().cpu().numpy()
+    b = make_model(world, seed=11).params().cpu().numpy()
+    c = make_model(world, seed=12).params().cpu().numpy()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    P = unpack(a)
+    for k, fan in (("W1", 260), ("W2", 512), ("W3", 264)):
+        lim = np.sqrt(6.0 / fan)
+        assert np.max(np.abs(P[k])) <= lim and np.max(np.abs(P[k])) > 0.9 * lim
+    for k in ("b1", "b2", "b3"):
+        assert np.all(P[k] == 0)
+
+
+def test_bank_grams_match_oracle(world):
+    model = make_model(world)
+    B = bank64(world)
+    GW = ow.bank_gram(B)
+    assert rel(model.gram().cpu().numpy(), GW) < 1e-5
+    assert rel(model.gram8().cpu().numpy(), ow.block_gram(GW, 8, R)) < 1e-5
+
+
+def test_targets_match_oracle(world):
+    model = make_model(world)
+    B = bank64(world)
+    for i in list(world["train"][:3]):
+        b = model.targets(world["bases"][int(i)]).cpu().numpy()
+        want = ow.targets(B, world["bases"][int(i)].double().cpu().numpy().T)
+        assert rel(b, want) < 1e-5, (i, b, want)
+
+
+def _pairs(world, model, idx):
+    mu = torch.tensor(world["mu_hat"][idx], dtype=torch.float32, device=DEV).contiguous()
+    b = torch.stack([model.targets(world["bases"][int(i)]) for i in idx]).contiguous()
+    return mu, b
+
+
+def test_loss_and_gradient_match_oracle(world):
+    model = make_model(world, seed=5)
+    idx = world["train"][:16]
+    mu, b = _pairs(world, model, idx)
+    loss = model.loss_grad(mu, b).item()
+    torch.cuda.synchronize()
+    Pm = unpack(model.params().cpu().numpy())
+    G8 = model.gram8().cpu().numpy()
+    Bh = b.cpu().numpy()
+    X = mu.double().cpu().numpy()
+    want_loss, _ = ow.loss(Pm, X, Bh, G8, R)
+    assert abs(loss - want_loss) <= 1e-5 * max(1.0, abs(want_loss))
+    want = ow.backward(Pm, X, Bh, G8)
+    got = unpack(model.grads().cpu().numpy())
+    for k in ow.PARAM_ORDER:
+        e = rel(got[k], want[k])
+        say(f"[grad] {k} rel {e:.2e}")
+        assert e < 1e-5, k
+
+
+def test_adam_step_matches_oracle(world):
+    model = make_model(world, seed=6)
+    idx = world["train"][:16]
+    mu, b = _pairs(world, model, idx)
+    P0 = unpack(model.params().cpu().numpy())
+    model.train(mu, b, 1, lr=1e-3, weight_decay=1e-5)
+    torch.cuda.synchronize()
+    P1 = unpack(model.params().cpu().numpy())
+    G8 = model.gram8().cpu().numpy()
+    g = ow.backward(P0, mu.double().cpu().numpy(), b.cpu().numpy(), G8)
+    Pw = {k: v.copy() for k, v in P0.items()}
+    ow.adam_step(Pw, g, {}, lr=1e-3, weight_decay=1e-5)
+    for k in ow.PARAM_ORDER:
+        gk = g[k] + 1e-5 * P0[k]
+        big = np.abs(gk) > 1e-3 * np.max(np.abs(gk))   # the first step is a sign step: skip near-zero gradients
+        d_gpu, d_ref = (P1[k] - P0[k])[big], (Pw[k] - P0[k])[big]
+        assert np.max(np.abs(d_gpu - d_ref)) <= 1e-4 * 1e-3, k
+
+
+def test_predict_matches_oracle_forward(world):
+    model = make_model(world, seed=7)
+    mu = torch.tensor(world["mu_hat"][:10], dtype=torch.float32, device=DEV).contiguous()
+    c = model.predict(mu).cpu().numpy()
+    want = ow.mlp_forward(unpack(model.params().cpu().numpy()), mu.double().cpu().numpy())["c"]
+    assert rel(c, want) < 1e-5
+
+
+def trained_model(world, epochs=400):
+    model = make_model(world, seed=9)
+    mu, b = _pairs(world, model, world["train"])
+    losses = model.train(mu, b, epochs, lr=1e-3, weight_decay=1e-5).cpu().numpy()
+    return model, losses
+
+
+def test_training_reduces_the_loss(world):
+    _, losses = trained_model(world)
+    say(f"[train] loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def _warm_ref(world, model, i, q, c, kstar):
+    S = world["mats"][i]["St"].astype(np.float64).T
+    om = philox.gaussian_sketch(1000 + i, N, P).astype(np.float32).astype(np.float64)
+    return ow.warm_rpod(S, bank64(world), c, kstar, R, om, q)
+
+
+def test_warm_plan_matches_oracle(world):
+    model, _ = trained_model(world, 200)
+    plan = rp.WarmPlan(model, N, P, 0, q_fallback=2, tol=1e9, device=DEV)
+    checked = 0
+    for i in world["test"][:6]:
+        i = int(i)
+        mu = world["mu_hat"][i].astype(np.float32)
+        c = model.predict(torch.tensor(mu[None], device=DEV)).double().cpu().numpy()[0]
+        top = np.sort(c)[::-1]
+        if top[0] - top[1] < 1e-4:
+            continue  # both sides must take the same argmax: skip near-ties
+        Phi_t, sig, A_t, fb, rho = plan.compute(world["Sd"][i], mu, 1000 + i)
+        assert not fb
+        Pr, sr, Ar, ex = _warm_ref(world, model, i, 0, c, ow.argmax_first(c))
+        Phi = Phi_t.double().cpu().numpy().T
+        A = A_t.double().cpu().numpy().T
+        s = sig.cpu().numpy()
+        res = dict(sigma=metrics.sigma_rel_err(s, sr), orth=metrics.orth_err(Phi))
+        if metrics.gap_ok(ex["ritz"], R):
+            res["sin"] = metrics.sin_theta_max(Phi, Pr)
+            res["A"] = metrics.lowrank_rel_diff(Phi, A, Pr, Ar)
+        say(f"[warm] matrix {i} rho {rho:.3e} (oracle {ex['rho']:.3e}) {res}")
+        assert res["sigma"] < 1e-5 and res["orth"] < 1e-5
+        assert res.get("sin", 0) < 1e-4 and res.get("A", 0) < 1e-4
+        assert abs(rho - ex["rho"]) <= 1e-3 * ex["rho"] + 1e-6
+        checked += 1
+    plan.close()
+    assert checked >= 3
+
+
+def test_forced_fallback_equals_plain_rpod(world):
+    model = make_model(world)
+    i = int(world["test"][0])
+    plan = rp.WarmPlan(model, N, P, 0, q_fallback=2, tol=0.0, device=DEV)
+    Phi_t, sig, A_t, fb, rho = plan.compute(world["Sd"][i], world["mu_hat"][i], 55)
+    assert fb and rho > 0
+    plain = rp.Plan(world["fam"].m, N, R, P, 2, dtype=torch.float32, device=DEV)
+    Pp, sp, Ap = plain.compute(world["Sd"][i], 55)
+    assert torch.equal(Phi_t, Pp) and torch.equal(sig, sp) and torch.equal(A_t, Ap)
+    plan.close()
+    plain.close()
+
+
+def test_one_hot_on_the_exact_basis_gives_exact_pod(world):
+    """Bank basis 0 = the exact leading basis of a noise-free matrix and a
+    network forced to weight it alone: q = 0 reproduces the exact POD."""
+    fam = world["fam"]
+    mu = world["mu"][int(world["test"][1])]
+    d = fam.matrix(mu, N, noise_std=0.0, seed=300, dtype=np.float32)
+    U = d["U"][:, :R]
+    bases = [torch.from_numpy(np.ascontiguousarray(U.T.astype(np.float32))).to(DEV)]
+    bases += [world["bases"][i] for i in world["bank_idx"][1:]]
+    model = rp.WarmModel(fam.m, R, max_train=8, seed=1, device=DEV)
+    model.set_bank(bases)
+    prm = model.params()
+    prm[67072:69120] = 0.0          # W3 = 0
+    prm[69120:69128] = 0.0
+    prm[69120] = 30.0               # b3: logit 30 on bank basis 0
+    plan = rp.WarmPlan(model, N, P, 0, q_fallback=2, tol=1e-3, device=DEV)
+    St = torch.from_numpy(d["St"]).to(DEV)
+    Phi_t, sig, A_t, fb, rho = plan.compute(St, world["mu_hat"][0], 5)
+    S = d["St"].astype(np.float64).T
+    P1, s1, A1, _ = pod.pod_svd(S, R)
+    e_sig = metrics.sigma_rel_err(sig.cpu().numpy(), s1)
+    e_sin = metrics.sin_theta_max(Phi_t.double().cpu().numpy().T, P1)
+    say(f"[one-hot] rho {rho:.2e} sigma {e_sig:.2e} sin {e_sin:.2e} fell_back {fb}")
+    assert not fb and rho < 1e-4 and e_sig < 1e-5 and e_sin < 1e-4
+    plan.close()
+
+
+def test_trained_network_gains_over_untrained_and_plain(world):
+    """At the same sketch (r predicted + p Gaussian columns, q = 0), the
+    trained network's subspace gives smaller errors against the exact POD
+    than an untrained network with uniform weights and than plain rPOD with
+    q = 0 on the full Gaussian sketch."""
+    model, _ = trained_model(world, 400)
+    flat = rp.WarmModel(world["fam"].m, R, max_train=8, seed=1, device=DEV)
+    flat.set_bank([world["bases"][i] for i in world["bank_idx"]])
+    flat.params()[67072:69128] = 0.0   # W3 = b3 = 0: uniform weights
+    pw = rp.WarmPlan(model, N, P, 0, q_fallback=2, tol=1e9, device=DEV)
+    pu = rp.WarmPlan(flat, N, P, 0, q_fallback=2, tol=1e9, device=DEV)
+    pp = rp.Plan(world["fam"].m, N, R, P, 0, dtype=torch.float32, device=DEV)
+    errs = {"trained": [], "uniform": [], "plain_q0": []}
+    for i in world["test"]:
+        i = int(i)
+        S = world["mats"][i]["St"].astype(np.float64).T
+        _, s1, _, _ = pod.pod_svd(S, R)
+        mu = world["mu_hat"][i]
+        for name, run in (("trained", lambda: pw.compute(world["Sd"][i], mu, 9)[1]),
+                          ("uniform", lambda: pu.compute(world["Sd"][i], mu, 9)[1]),
+                          ("plain_q0", lambda: pp.compute(world["Sd"][i], 9)[1])):
+            errs[name].append(metrics.sigma_rel_err(run().cpu().numpy(), s1))
+    med = {k: float(np.median(v)) for k, v in errs.items()}
+    say(f"[gain] median max-sigma error over {len(world['test'])} test matrices: {med}")
+    assert med["trained"] < med["uniform"]
+    assert med["trained"] < med["plain_q0"]
+    for p_ in (pw, pu, pp):
+        p_.close()
