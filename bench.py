@@ -20,6 +20,15 @@ q = 2, spectral decay in [0.05, 0.2], all drawn per matrix from the seed):
 one batched plan in BF16 and in FP32 against 64 single plain FP32 plans run
 one after another, reported under "batched_vs_plain".
 
+Also measured (unless --no-warm): the learned warm start on the parametric
+sweep S(mu) = U(mu) diag(exp(-alpha k)) V^T + noise (1e-9), m = 131072 (a
+256 x 512 grid), n = 2000, r = 50, 128 parameter vectors (96 train, 32
+test): the network is trained on plain-rPOD bases of the training matrices
+with a bank of 8 of them, then every test matrix is solved by plain FP32
+rPOD (q = 2) and by warm-started rPOD (q = 0 and 1, residual tolerance 1e-3,
+plain q = 2 as the fallback), in FP32 and BF16; errors are against the
+generator's exact singular values. Reported under "warm_vs_plain".
+
 Per-kernel times of the passes over S come from HIP events that the library
 records on its stream around every pass during the timed steps.
 """
@@ -305,6 +314,96 @@ def batch_block(dev, steps, warmup):
     }
 
 
+WARM = dict(nx=256, ny=512, n=2000, r=50, p=10, count=128, n_train=96, seed=5, noise=1e-9, epochs=2000)
+
+
+def warm_block(dev, reps):
+    """Train the warm-start network on the sweep and time plain vs warm rPOD on the test matrices."""
+    import torch
+    import synth
+    import paper_2504_15350_amd as rp
+    W = WARM
+    t0 = time.perf_counter()
+    fam = synth.ParamFamily(W["nx"], W["ny"])
+    F_dev = torch.from_numpy(fam.F.astype(np.float32)).to(dev)
+    mu, mu_hat = synth.draw_params(W["count"], seed=W["seed"])
+    train, test = synth.train_test_split(W["count"], W["n_train"], seed=W["seed"])
+    m, n, r, p = fam.m, W["n"], W["r"], W["p"]
+    plain = rp.Plan(m, n, r, p, 2, dtype=torch.float32, device=dev)
+    bases = {}
+    for i in train:
+        St = fam.matrix_device(mu[i], n, noise_std=W["noise"], seed=2000 + int(i), device=dev, F_dev=F_dev)
+        bases[int(i)] = plain.compute(St, 3000 + int(i))[0].clone()
+        del St
+    bank_idx = [int(train[j]) for j in synth.farthest_points(mu_hat[train], 8)]
+    model = rp.WarmModel(m, r, max_train=len(train), seed=W["seed"], device=dev)
+    model.set_bank([bases[i] for i in bank_idx])
+    mu_t = torch.tensor(mu_hat[train], dtype=torch.float32, device=dev).contiguous()
+    b_t = torch.stack([model.targets(bases[int(i)]) for i in train]).contiguous()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = model.train(mu_t, b_t, W["epochs"], lr=1e-3, weight_decay=1e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    losses = losses.cpu().numpy()
+    log(f"[bench] warm start: bank and targets in {t1 - t0:.1f} s, {W['epochs']} epochs in {t_train:.2f} s, "
+        f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    tests = [fam.matrix_device(mu[i], n, noise_std=W["noise"], seed=2000 + int(i), device=dev, F_dev=F_dev)
+             for i in test]
+    exact = [fam.spectrum(mu[i][3], fam.K)[:r] for i in test]
+    del F_dev
+
+    def run(kind, mats, q=None):
+        if kind == "plain":
+            pl = rp.Plan(m, n, r, p, 2, dtype=mats[0].dtype, device=dev)
+            call = lambda j: pl.compute(mats[j], 4000 + j, check=False)[1]
+        else:
+            pl = rp.WarmPlan(model, n, p, q, q_fallback=2, tol=1e-3, dtype=mats[0].dtype, device=dev)
+            state = {}
+
+            def call(j):
+                out = pl.compute(mats[j], mu_hat[test[j]], 4000 + j, check=False)
+                state[j] = out[3]
+                return out[1]
+        sig = [call(j) for j in range(len(mats))]   # warm-up pass, also the results
+        torch.cuda.synchronize()
+        errs = [float(np.max(np.abs(s_.cpu().numpy() - e) / e)) for s_, e in zip(sig, exact)]
+        t = time.perf_counter()
+        for _ in range(reps):
+            for j in range(len(mats)):
+                call(j)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / (reps * len(mats))
+        pl.status()
+        fb = sum(state.values()) if kind != "plain" else None
+        pl.close()
+        return dict(ms_per_matrix=round(ms, 4), sigma_err_median=float(np.median(errs)),
+                    sigma_err_max=float(np.max(errs)), frac_within_1e3=float(np.mean(np.array(errs) <= 1e-3)),
+                    fallbacks=fb)
+
+    out = {"plain_fp32_q2": run("plain", tests), "warm_fp32_q0": run("warm", tests, 0),
+           "warm_fp32_q1": run("warm", tests, 1)}
+    tests16 = [St.to(torch.bfloat16) for St in tests]
+    del tests
+    torch.cuda.empty_cache()
+    out["plain_bf16_q2"] = run("plain", tests16)
+    out["warm_bf16_q0"] = run("warm", tests16, 0)
+    out["warm_bf16_q1"] = run("warm", tests16, 1)
+    del tests16
+    model.close()
+    plain.close()
+    torch.cuda.empty_cache()
+    base = out["plain_fp32_q2"]["ms_per_matrix"]
+    for k, v in out.items():
+        v["speedup_vs_plain_fp32"] = round(base / v["ms_per_matrix"], 2)
+        log(f"[bench] warm sweep {k}: {v}")
+    return {"config": {"m": m, "n": n, "r": r, "p": p, "matrices": W["count"], "train": W["n_train"],
+                       "test": len(test), "bank": 8, "epochs": W["epochs"], "noise_std": W["noise"],
+                       "residual_tol": 1e-3, "fallback_q": 2, "reps": reps},
+            "train_seconds": round(t_train, 3), "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+            "results": out}
+
+
 def cpu_baseline(St, w, seed):
     """The oracle's FP64 rPOD (as it stands) on a row sample, scaled to the full matrix."""
     from oracle import philox
@@ -338,6 +437,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-vs-plain measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batch measurement")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the row-sharded multi-GPU "
@@ -387,6 +487,10 @@ def main():
     if not args.no_batch:
         batch = batch_block(dev, max(3, args.steps // 4), max(1, args.warmup // 2))
 
+    warm = None
+    if not args.no_warm:
+        warm = warm_block(dev, 3)
+
     res = {
         "metric": "rPOD time-to-r-modes",
         "value": round(main_res["ms"], 4),
@@ -410,6 +514,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed_vs_plain": extra,
         "batched_vs_plain": batch,
+        "warm_vs_plain": warm,
     }
     print(json.dumps(res), flush=True)
 
