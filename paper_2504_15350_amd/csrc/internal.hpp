@@ -88,11 +88,15 @@ hipError_t launch_gram(int tin, int nt, const GroupLaunch<GramArgs>& L, const Gr
 hipError_t launch_chol_inv(const GroupLaunch<CholArgs>& L, hipStream_t st);
 
 // Symmetric eigen-decomposition of the lp x lp FP64 Gram matrix G_B = B B^T
-// by one-sided Jacobi (Hestenes) on its columns, one workgroup of
-// jacobi_threads(lp) threads per matrix (all matrices of a launch share lp).
+// (lp a multiple of 16, <= 128): diagonally pivoted Cholesky G_B = P L L^T P^T,
+// then one-sided Jacobi (Hestenes) on the columns of L, preconditioned as
+// by Drmac and Veselic; one workgroup of jacobi_threads(lp) threads per
+// matrix (all matrices of a launch share lp).
 //   UB: lp x lp column-major, column k = k-th eigenvector (= left singular
-//   vector of B) by descending eigenvalue; sig[k] = sqrt(eigenvalue).
-//   A pair is rotated while |w_p . w_q| > tol |w_p| |w_q|.
+//   vector of B) by descending eigenvalue; sig[k] = sqrt(eigenvalue), the
+//   k-th singular value of B, computed as a column norm. Directions beyond
+//   the numerical rank of G_B (pivot below lp u max diag) get sig = 0 and a
+//   zero UB column. A pair is rotated while |w_p . w_q| > tol |w_p| |w_q|.
 int jacobi_threads(int lp);
 hipError_t launch_jacobi(int lp, const GroupLaunch<JacobiArgs>& L, hipStream_t st);
 
@@ -155,7 +159,7 @@ hipError_t launch_gather_cols(double* G, int Kr, int c0, int ncol, const double*
 hipError_t launch_block_sumsq(const double* src, int64_t sa, int64_t sb, int r, int KA, int KB, double* out,
                               hipStream_t st);
 // Plan steps (grouped): network forward of the call's parameter vector, the
-// predicted subspace's coordinates (tiles: lp per matrix), the scaled right
+// predicted subspace's coordinates (tiles: lp ceil(ldX / 64) per matrix, iters <= 2), the scaled right
 // vectors (tiles: ceil(nP rp / 256)), the residual partials (tiles: r x
 // nchunk) and the residual rho = max_k ||S v_k - sigma_k phi_k|| / sigma_k
 // (one workgroup per matrix; DEV_FLAG_RESIDUAL when rho > tol).

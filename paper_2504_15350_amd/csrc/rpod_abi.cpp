@@ -548,7 +548,7 @@ struct Recorder {
         Step z{K_WZ};
         B.add(z, std::vector<WarmZArgs>{{M->at<double>(M->L.gram), P->wat<double>(P->w_c), P->wat<int>(P->w_kstar),
                                          P->wat<float>(P->w_Xw), P->ldXw, r, M->Kr, L.lp, 2}},
-              std::vector<int>{L.lp});
+              std::vector<int>{L.lp * (int)((P->ldXw + 63) / 64)});
         out.push_back(z);
         Step o{K_OMEGA};
         o.tout = L.tin;

@@ -4,6 +4,7 @@
 //   k_gram         FP64 Gram matrix Y^T Y of a tall matrix on FP64 MFMA
 //   k_chol_inv     Cholesky + triangular inverse for CholeskyQR (step 4)
 //   k_jacobi       SVD of the small T of step 6 via the eigenvectors of T T^T
+//                  (pivoted Cholesky, then preconditioned one-sided Jacobi)
 //   k_lift_coef    the small factors of the lift (step 7) and the coefficients
 //   k_colmax/...   deterministic sign convention and output packing
 #include "device_common.hpp"
@@ -443,53 +444,156 @@ hipError_t launch_chol_inv(const GroupLaunch<CholArgs>& L, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// One-sided Jacobi on the columns of the symmetric PSD G_B (lp x lp, FP64,
-// in LDS, one workgroup). Rotations act on column pairs chosen by the
-// round-robin (circle) schedule, lp/2 disjoint pairs per round, TPP threads
-// per pair reducing with lane shuffles. At convergence the columns are
-// w_k = lambda_k u_k with G_B = U diag(lambda) U^T; sigma_k = sqrt(lambda_k).
+// Small SVD of step 6 (eigenvectors of G_B = T T^T), one workgroup per matrix.
 // ---------------------------------------------------------------------------
-constexpr int JLD = LPMAX + 1;
-
 __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
     return __shfl_xor(v, mask, 64);
 }
 
-__device__ __forceinline__ void jacobi_body(const double* __restrict__ G, int l, int lp, double* __restrict__ UB,
-                                            double* __restrict__ sig, int* flags, double tol) {
-    __shared__ double W[LPMAX * JLD];  // column c at W[c * JLD + row]
-    __shared__ double nrm[LPMAX];
-    __shared__ int s_rot;
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int npair = lp / 2;
-    const int tpp = nthr / npair;  // 16, 32 or 64 (power of two)
-
-    for (int e = tid; e < lp * lp; e += nthr) {
-        const int c = e / lp, row = e % lp;
-        W[c * JLD + row] = (c < l && row < l) ? G[row * lp + c] : 0.0;
+// Preconditioned one-sided Jacobi (Drmac and Veselic, SIMAX 2008): with the
+// diagonally pivoted Cholesky factorisation G = P L L^T P^T, the left
+// singular vectors of P L are the eigenvectors of G and its singular values
+// the square roots of G's eigenvalues. One-sided Jacobi on the columns of
+// L (a row permutation does not change the column inner products) then
+// needs few sweeps. Results: UB[:, k] = P (L V)[:, k] / sigma_k by
+// descending sigma_k = ||(L V)[:, k]||; factorisation stops at the first
+// pivot below lp u times the largest diagonal entry of G (the remaining
+// columns of L are zero, as are their sigma and UB columns).
+template <int LP, int NTHR>
+__device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, int l, double* __restrict__ UB,
+                                                 double* __restrict__ sig, int* flags, double tol, int* sweeps_out) {
+    constexpr int NPAIR = LP / 2;
+    constexpr int TPP = NTHR / NPAIR;
+    constexpr int RPT = LP / TPP;
+    static_assert(TPP >= 1 && TPP <= 64 && (TPP & (TPP - 1)) == 0 && RPT * TPP == LP, "pair layout");
+    constexpr int LDW = LP + 1;
+    __shared__ double W[LP * LDW];   // A[row][col] at W[col * LDW + row]
+    __shared__ double nrm[LP];
+    __shared__ int perm[LP];
+    __shared__ double s_val[NTHR / 64];
+    __shared__ int s_idx[NTHR / 64];
+    __shared__ int s_piv, s_rank, s_rot;
+    __shared__ double s_dmax;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < LP * LP; e += NTHR) {
+        const int c = e / LP, row = e % LP;
+        W[c * LDW + row] = (c < l && row < l) ? G[row * LP + c] : 0.0;
+    }
+    for (int c = tid; c < LP; c += NTHR) perm[c] = c;
+    if (tid == 0) {
+        double dm = 0.0;
+        for (int i = 0; i < l; ++i) dm = fmax(dm, G[i * LP + i]);
+        s_dmax = dm;
+        s_rank = l;
     }
     __syncthreads();
-
-    const int pr = tid / tpp;     // pair slot
-    const int sub = tid % tpp;    // lane within the pair group
+    const double thr = (double)LP * 0x1.0p-53 * s_dmax;
+    // ---- diagonally pivoted Cholesky (right-looking, full symmetric storage) ----
+    for (int j = 0; j < l; ++j) {
+        // pivot: largest remaining diagonal entry, lowest index on ties
+        double bv = -1.0;
+        int bi = LP;
+        for (int i = j + tid; i < l; i += NTHR) {
+            const double v = W[i * LDW + i];
+            if (v > bv) { bv = v; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = shfl_xor_d(bv, off);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) { s_val[wave] = bv; s_idx[wave] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double v = s_val[0];
+            int ix = s_idx[0];
+            for (int w = 1; w < NTHR / 64; ++w)
+                if (s_val[w] > v || (s_val[w] == v && s_idx[w] < ix)) { v = s_val[w]; ix = s_idx[w]; }
+            s_piv = ix;
+            if (!(v > thr)) s_rank = j;  // remaining Schur complement negligible (or not finite)
+        }
+        __syncthreads();
+        if (s_rank == j) break;
+        const int pv = s_piv;
+        if (pv != j) {  // symmetric swap of rows and columns j and pv
+            for (int k = tid; k < LP; k += NTHR) {
+                const double a = W[k * LDW + j];
+                W[k * LDW + j] = W[k * LDW + pv];
+                W[k * LDW + pv] = a;
+            }
+            __syncthreads();
+            for (int k = tid; k < LP; k += NTHR) {
+                const double a = W[j * LDW + k];
+                W[j * LDW + k] = W[pv * LDW + k];
+                W[pv * LDW + k] = a;
+            }
+            if (tid == 0) {
+                const int t = perm[j];
+                perm[j] = perm[pv];
+                perm[pv] = t;
+            }
+            __syncthreads();
+        }
+        const double ljj = sqrt(W[j * LDW + j]);
+        const double inv = 1.0 / ljj;
+        __syncthreads();
+        for (int i = j + 1 + tid; i < l; i += NTHR) W[j * LDW + i] *= inv;   // column j below the diagonal
+        if (tid == 0) W[j * LDW + j] = ljj;
+        __syncthreads();
+        // trailing update, both triangles (later symmetric swaps move whole
+        // rows and columns): A[i][k] -= L[i][j] L[k][j], j < i, k < l
+        const int nt = l - j - 1;
+        for (int e = tid; e < nt * nt; e += NTHR) {
+            const int k = j + 1 + e / nt, i = j + 1 + e % nt;
+            W[k * LDW + i] -= W[j * LDW + i] * W[j * LDW + k];
+        }
+        __syncthreads();
+    }
+    const int rank = s_rank;
+    // L: lower triangle of the first `rank` columns; everything else zero
+    for (int e = tid; e < LP * LP; e += NTHR) {
+        const int c = e / LP, row = e % LP;
+        if (c >= rank || row < c || row >= l) W[c * LDW + row] = 0.0;
+    }
+    __syncthreads();
+    // ---- one-sided Jacobi on the columns of L ----
+    const int pr = tid / TPP, sub = tid % TPP;
     int sweep = 0;
-    const int max_sweeps = 40;
+    constexpr int max_sweeps = 40;
     for (; sweep < max_sweeps; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
-        for (int rnd = 0; rnd < lp - 1; ++rnd) {
-            // circle method: element lp-1 fixed, others rotate
+        for (int rnd = 0; rnd < LP - 1; ++rnd) {
             int p, q;
-            if (pr == 0) { p = lp - 1; q = rnd; }
-            else { p = (rnd + pr) % (lp - 1); q = (rnd - pr + (lp - 1)) % (lp - 1); }
-            if (p > q) { const int t = p; p = q; q = t; }
-            double al = 0.0, be = 0.0, ga = 0.0;
-            for (int row = sub; row < lp; row += tpp) {
-                const double wp = W[p * JLD + row], wq = W[q * JLD + row];
-                al += wp * wp; be += wq * wq; ga += wp * wq;
+            if (pr == 0) {
+                p = LP - 1;
+                q = rnd;
+            } else {
+                p = rnd + pr;
+                if (p >= LP - 1) p -= LP - 1;
+                q = rnd - pr;
+                if (q < 0) q += LP - 1;
             }
-            for (int off = tpp / 2; off > 0; off >>= 1) {
+            if (p > q) {
+                const int t = p;
+                p = q;
+                q = t;
+            }
+            double wp[RPT], wq[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                wp[r] = W[p * LDW + sub + r * TPP];
+                wq[r] = W[q * LDW + sub + r * TPP];
+            }
+            double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                al += wp[r] * wp[r];
+                be += wq[r] * wq[r];
+                ga += wp[r] * wq[r];
+            }
+#pragma unroll
+            for (int off = TPP / 2; off > 0; off >>= 1) {
                 al += shfl_xor_d(al, off);
                 be += shfl_xor_d(be, off);
                 ga += shfl_xor_d(ga, off);
@@ -498,10 +602,10 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ G, int l,
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                for (int row = sub; row < lp; row += tpp) {
-                    const double wp = W[p * JLD + row], wq = W[q * JLD + row];
-                    W[p * JLD + row] = c * wp - s * wq;
-                    W[q * JLD + row] = s * wp + c * wq;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    W[p * LDW + sub + r * TPP] = c * wp[r] - s * wq[r];
+                    W[q * LDW + sub + r * TPP] = s * wp[r] + c * wq[r];
                 }
                 if (sub == 0) s_rot = 1;
             }
@@ -511,38 +615,41 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ G, int l,
         __syncthreads();
     }
     if (sweep == max_sweeps && tid == 0) atomicOr(flags, DEV_FLAG_JACOBI_SLOW);
-
-    for (int c = tid; c < lp; c += nthr) {
+    if (sweeps_out != nullptr && tid == 0) *sweeps_out = sweep;
+    for (int c = tid; c < LP; c += NTHR) {
         double s = 0.0;
-        for (int row = 0; row < lp; ++row) s += W[c * JLD + row] * W[c * JLD + row];
+        for (int row = 0; row < LP; ++row) s += W[c * LDW + row] * W[c * LDW + row];
         nrm[c] = sqrt(s);
     }
     __syncthreads();
-    for (int c = tid; c < lp; c += nthr) {
+    for (int c = tid; c < LP; c += NTHR) {
         const double v = nrm[c];
-        int rank = 0;
-        for (int k = 0; k < lp; ++k) rank += (nrm[k] > v) || (nrm[k] == v && k < c);
-        sig[rank] = sqrt(v);
+        int rank_c = 0;
+        for (int k = 0; k < LP; ++k) rank_c += (nrm[k] > v) || (nrm[k] == v && k < c);
+        sig[rank_c] = v;
         const double inv = v > 0.0 ? 1.0 / v : 0.0;
-        for (int row = 0; row < lp; ++row) UB[(int64_t)rank * lp + row] = W[c * JLD + row] * inv;
+        for (int row = 0; row < LP; ++row) UB[(int64_t)rank_c * LP + perm[row]] = W[c * LDW + row] * inv;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi(Group<JacobiArgs> g) {
+// eight lanes per column pair: 4 lp threads per workgroup
+template <int LP>
+__global__ __launch_bounds__(4 * LP) void k_jacobi(Group<JacobiArgs> g) {
     const JacobiArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
-    jacobi_body(a.G, a.l, a.lp, a.UB, a.sig, a.flags, a.tol);
+    jacobi_chol_body<LP, 4 * LP>(a.G, a.l, a.UB, a.sig, a.flags, a.tol, nullptr);
 }
 
-int jacobi_threads(int lp) {
-    const int npair = lp / 2;
-    int tpp = 64;  // threads per column pair: a power of two that divides the wave
-    while (tpp * npair > 1024) tpp /= 2;
-    return tpp * npair;
-}
+int jacobi_threads(int lp) { return 4 * lp; }
 
 hipError_t launch_jacobi(int lp, const GroupLaunch<JacobiArgs>& L, hipStream_t st) {
-    if (lp > LPMAX || lp % 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi, dim3(L.count), dim3(jacobi_threads(lp)), 0, st, mkg(L));
+    switch (lp) {
+#define RPOD_JAC_CASE(K) \
+    case K: hipLaunchKernelGGL(k_jacobi<K>, dim3(L.count), dim3(4 * K), 0, st, mkg(L)); break;
+        RPOD_JAC_CASE(16) RPOD_JAC_CASE(32) RPOD_JAC_CASE(48) RPOD_JAC_CASE(64)
+        RPOD_JAC_CASE(80) RPOD_JAC_CASE(96) RPOD_JAC_CASE(112) RPOD_JAC_CASE(128)
+#undef RPOD_JAC_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -301,40 +301,43 @@ hipError_t launch_warm_plan_forward(const GroupLaunch<WarmFwdArgs>& L, hipStream
     return hipGetLastError();
 }
 
-// column i of Z: iters products with C G_W starting from the unit vector of
-// bank column kstar r + i (G_W symmetric: read by columns for coalescing)
-constexpr int WARM_KR_MAX = 1024;
-
+// Z = (C G_W)^iters E_k* for iters <= 2, C = diag(c (x) 1_r), E_k* the
+// columns of bank block k*. Tile (column i, rows 64 t .. 64 t + 63); four
+// waves split the inner sum over the bank columns b and reduce in LDS:
+//   iters 2: Z[e][i] = c_e sum_b G_W[e][b] c_b G_W[b][k* r + i]
+// (G_W symmetric: read as G_W[b][e], coalesced over e).
 __global__ __launch_bounds__(256) void k_warm_z(Group<WarmZArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const WarmZArgs& a = g.args[it];
-    const int i = blockIdx.x - g.tstart[it];
+    const int t = blockIdx.x - g.tstart[it];
+    const int nrb = (int)((a.ldX + 63) / 64);
+    const int i = t / nrb, rb = t % nrb;
     const int Kr = a.Kr, r = a.r;
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int64_t e = (int64_t)rb * 64 + lane;
     GLOBAL float* X = gbl(a.X) + (int64_t)i * a.ldX;
-    if (i >= r) {
-        for (int64_t e = threadIdx.x; e < a.ldX; e += 256) X[e] = 0.f;
-        return;
-    }
-    __shared__ double z[WARM_KR_MAX], y[WARM_KR_MAX];
     const GLOBAL double* GW = gbl(a.GW);
     const int col = (*a.kstar) * r + i;
-    for (int e = threadIdx.x; e < Kr; e += 256) z[e] = (e == col) ? 1.0 : 0.0;
-    __syncthreads();
-    for (int t = 0; t < a.iters; ++t) {
-        for (int e = threadIdx.x; e < Kr; e += 256) {
+    __shared__ double red[256];
+    double z = 0.0;
+    if (i < r && e < Kr) {
+        if (a.iters == 0) {
+            z = (e == col) ? 1.0 : 0.0;
+        } else if (a.iters == 1) {
+            z = a.c[e / r] * GW[(int64_t)col * Kr + e];
+        } else {
             double s = 0.0;
-            if (t == 0) {
-                s = GW[(int64_t)col * Kr + e];
-            } else {
-                for (int b = 0; b < Kr; ++b) s += GW[(int64_t)b * Kr + e] * z[b];
-            }
-            y[e] = a.c[e / r] * s;
+            const int b0 = part * ((Kr + 3) / 4), b1 = min(Kr, b0 + (Kr + 3) / 4);
+            for (int b = b0; b < b1; ++b) s += GW[(int64_t)b * Kr + e] * (a.c[b / r] * GW[(int64_t)b * Kr + col]);
+            red[threadIdx.x] = s;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < Kr; e += 256) z[e] = y[e];
-        __syncthreads();
     }
-    for (int64_t e = threadIdx.x; e < a.ldX; e += 256) X[e] = e < Kr ? (float)z[e] : 0.f;
+    if (a.iters >= 2) {
+        __syncthreads();
+        if (part == 0 && i < r && e < Kr)
+            z = a.c[e / r] * ((red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]));
+    }
+    if (part == 0 && e < a.ldX) X[e] = (float)z;
 }
 
 hipError_t launch_warm_z(const GroupLaunch<WarmZArgs>& L, hipStream_t st) {
