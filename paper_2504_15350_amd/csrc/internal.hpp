@@ -41,9 +41,12 @@ hipError_t launch_sx_wide(int tin, int nt, bool vec, const GroupLaunch<SxArgs>& 
 
 // Split-K transposed product: slab s = S[rows of split s]^T Q[rows of split s]
 // (FP64 slabs nP x 16*nt, column-major). S: m x n (ldS); Q: m x 16*nt (ldQ,
-// zero rows up to roundup(m,16)). Split s covers rows [s*split_rows, ...).
-// Tiles: ncb = nP / 256 column blocks x nsplit.
+// zero rows up to roundup(m,64)). Tiles: ncb column blocks x nsplit.
+//   FP64 S: ncb = nP / 256, split s covers rows [s*split_rows, ...).
+//   FP32 S: ncb = nP / stq32_block_cols(), LDS-staged, splits interleaved in
+//   steps of 64 rows (step t of split s: rows 64 (t nsplit + s) ..).
 hipError_t launch_stq(int tin, int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st);
+int stq32_block_cols();
 
 // 16-bit (tin = DT_BF16 or DT_F16) versions on the 16x16x32 matrix cores:
 // Y (FP32) = S X with X in the same 16-bit type (ldX multiple of 8, zero rows

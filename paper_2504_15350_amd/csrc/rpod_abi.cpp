@@ -103,19 +103,20 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.nP = roundup(d->n, 256);
     L.tin = d->dtype;  // rpod_dtype and the internal codes coincide
     L.tacc = d->dtype == RPOD_F64 ? DT_F64 : DT_F32;
-    // split-K over rows for S^T Q. FP32/FP64: blocks of 256 columns and
-    // contiguous splits of >= 256 rows. 16-bit: blocks of 128 columns (256
+    // split-K over rows for S^T Q. FP64: blocks of 256 columns and
+    // contiguous splits of >= 256 rows. FP32: blocks of 128 columns, splits
+    // interleaved in steps of 64 rows. 16-bit: blocks of 128 columns (256
     // with the lo part), splits interleaved in steps of 128 rows.
-    const bool s16 = is16(L.tin);
-    const int64_t ncb = s16 ? L.nP / stq16_block_cols(false) : L.nP / 256;
-    const int64_t target = s16 ? wg_target : std::max<int64_t>(64, wg_target / 4);
+    const bool s16 = is16(L.tin), f32 = L.tin == DT_F32;
+    const int64_t ncb = s16 ? L.nP / stq16_block_cols(false) : f32 ? L.nP / stq32_block_cols() : L.nP / 256;
+    const int64_t target = (s16 || f32) ? wg_target : std::max<int64_t>(64, wg_target / 4);
     int64_t ns = (target + ncb - 1) / ncb;
     if (ns > 64) ns = 64;
-    const int64_t maxs = s16 ? (d->m + 127) / 128 : (d->m + 255) / 256;
+    const int64_t maxs = s16 ? (d->m + 127) / 128 : f32 ? (d->m + 63) / 64 : (d->m + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
     L.split_rows = roundup((d->m + ns - 1) / ns, 64);
-    L.nsplit = s16 ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
+    L.nsplit = (s16 || f32) ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
     L.ncb_lo = (int)(L.nP / stq16_block_cols(true));
     int64_t nc = d->m / 2048;
     L.nchunk = (int)(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
@@ -348,7 +349,8 @@ struct Recorder {
             a.Ql = s16 ? (const void*)P->at<char>(it, it.L.o_Ql) : nullptr;
             a.ldQ = it.L.mP; a.Zp = P->at<double>(it, it.L.o_Zp); a.nP = it.L.nP;
             a.split_rows = it.L.split_rows; a.nsplit = it.L.nsplit;
-            a.ncb = s16 ? (int)(it.L.nP / stq16_block_cols(s.lo)) : (int)(it.L.nP / 256);
+            a.ncb = s16 ? (int)(it.L.nP / stq16_block_cols(s.lo))
+                        : it.L.tin == DT_F32 ? (int)(it.L.nP / stq32_block_cols()) : (int)(it.L.nP / 256);
             a.call = it.idx;
             return a;
         });

@@ -199,6 +199,112 @@ __global__ __launch_bounds__(256) void k_stq(Group<StqArgs> g) {
                            a.split_rows, t % a.ncb, t / a.ncb);
 }
 
+// ---------------------------------------------------------------------------
+// Z_s = S^T Q for FP32 S, LDS-staged. Workgroup: 64 HBU columns of S (HBU
+// column tiles of 16 per wave, wave w owning columns 16 HBU w ..) over the
+// rows of split s, 64 rows per step.
+// Each step's S block (64 rows x 64 HBU columns) and Q block (64 rows x
+// 16 NT columns) are staged in LDS column-major with a 68-float column
+// stride (16-byte reads and writes without bank conflicts); the global
+// reads cover 4 columns x 256 bytes per wave instruction. The next step's
+// blocks are loaded into registers during the matrix-core work. MFMA
+// (u, c, s) of row group k takes, in lane (r, g), rows 16 k + 4 g + s:
+//   A[r][g] = S[i0 + 16 k + 4 g + s][j0 + 16 HBU w + 16 u + r],
+//   B[g][r] = Q[i0 + 16 k + 4 g + s][16 c + r].
+// Splits are interleaved: step t of split s covers rows 64 (t nsplit + s).
+// ---------------------------------------------------------------------------
+constexpr int STQ32_R = 64, STQ32_LDS = STQ32_R + 4;
+
+template <int NT, bool VEC, int HBU>
+__device__ __forceinline__ void stq32_body(const GLOBAL float* __restrict__ S, int64_t ldS, int64_t m, int64_t n,
+                                           const GLOBAL float* __restrict__ Q, int64_t ldQ,
+                                           GLOBAL double* __restrict__ Zp, int64_t nP, int nsplit, int ncb,
+                                           int tile) {
+    constexpr int R = STQ32_R, LD = STQ32_LDS, HB = 64 * HBU;
+    constexpr int CPC = R / 4;                 // 16-byte chunks per column of a block
+    constexpr int SPT = HB * CPC / 256;        // S chunks per thread
+    constexpr int QPT = 16 * NT * CPC / 256;   // Q chunks per thread
+    __shared__ __attribute__((aligned(16))) float ss[HB * LD];
+    __shared__ __attribute__((aligned(16))) float qs[16 * NT * LD];
+    const int cb = tile % ncb, sp = tile / ncb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int64_t j0 = (int64_t)cb * HB;
+    const int64_t ib = (int64_t)sp * R, stride = (int64_t)nsplit * R;
+
+    f32x4 acc[HBU][NT];
+#pragma unroll
+    for (int u = 0; u < HBU; ++u)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[u][c] = f32x4{0, 0, 0, 0};
+
+    f32x4 sr[SPT], qr[QPT];
+    auto fetch = [&](int64_t i0) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int ch = tid + 256 * q;
+            sr[q] = load_rows4<VEC>(S, ldS, m, n, i0 + 4 * (ch % CPC), j0 + ch / CPC);
+        }
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) {
+            const int ch = tid + 256 * q;
+            qr[q] = *reinterpret_cast<const GLOBAL f32x4*>(Q + (int64_t)(ch / CPC) * ldQ + i0 + 4 * (ch % CPC));
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int ch = tid + 256 * q;
+            *reinterpret_cast<f32x4*>(ss + (ch / CPC) * LD + 4 * (ch % CPC)) = sr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) {
+            const int ch = tid + 256 * q;
+            *reinterpret_cast<f32x4*>(qs + (ch / CPC) * LD + 4 * (ch % CPC)) = qr[q];
+        }
+    };
+    if (ib < m) fetch(ib);
+    for (int64_t i0 = ib; i0 < m; i0 += stride) {
+        __syncthreads();  // previous step consumed
+        put();
+        __syncthreads();
+        if (i0 + stride < m) fetch(i0 + stride);  // in flight during the matrix-core work
+#pragma unroll
+        for (int k = 0; k < R / 16; ++k) {
+            f32x4 a[HBU], b[NT];
+#pragma unroll
+            for (int u = 0; u < HBU; ++u)
+                a[u] = *reinterpret_cast<const f32x4*>(ss + (16 * HBU * wave + 16 * u + r16) * LD + 16 * k + 4 * kg);
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+                b[c] = *reinterpret_cast<const f32x4*>(qs + (16 * c + r16) * LD + 16 * k + 4 * kg);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int u = 0; u < HBU; ++u)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) acc[u][c] = mfma_16x16x4(a[u][s], b[c][s], acc[u][c]);
+        }
+    }
+    // D[4 g + v][r]: S column j0 + 16 HBU w + 16 u + 4 g + v, Q column 16 c + r
+    GLOBAL double* zp = Zp + (int64_t)sp * nP * (16 * NT);
+#pragma unroll
+    for (int u = 0; u < HBU; ++u)
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+            store4<double>(zp + (int64_t)(16 * c + r16) * nP + j0 + 16 * HBU * wave + 16 * u + 4 * kg, acc[u][c][0],
+                           acc[u][c][1], acc[u][c][2], acc[u][c][3]);
+}
+
+template <int NT, bool VEC, int HBU>
+__global__ __launch_bounds__(256) void k_stq32(Group<StqArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const StqArgs& a = g.args[it];
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    stq32_body<NT, VEC, HBU>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.Q), a.ldQ, gbl(a.Zp), a.nP,
+                             a.nsplit, a.ncb, blockIdx.x - g.tstart[it]);
+}
+
 // out[e] = sum of the nsplit slabs, fixed order; 256 elements per workgroup
 __global__ void k_reduce_slabs(Group<ReduceArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
@@ -288,12 +394,21 @@ hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const Grou
 template <typename Tin, int NT>
 static hipError_t stq_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
     const Group<StqArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
-    if (vec)
-        hipLaunchKernelGGL((k_stq<Tin, NT, true>), dim3(L.tiles), dim3(256), 0, st, g);
-    else
-        hipLaunchKernelGGL((k_stq<Tin, NT, false>), dim3(L.tiles), dim3(256), 0, st, g);
+    if constexpr (sizeof(Tin) == 4) {  // FP32: the LDS-staged kernel, two column tiles per wave
+        if (vec)
+            hipLaunchKernelGGL((k_stq32<NT, true, 2>), dim3(L.tiles), dim3(256), 0, st, g);
+        else
+            hipLaunchKernelGGL((k_stq32<NT, false, 2>), dim3(L.tiles), dim3(256), 0, st, g);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_stq<Tin, NT, true>), dim3(L.tiles), dim3(256), 0, st, g);
+        else
+            hipLaunchKernelGGL((k_stq<Tin, NT, false>), dim3(L.tiles), dim3(256), 0, st, g);
+    }
     return hipGetLastError();
 }
+
+int stq32_block_cols() { return 128; }
 
 template <typename Tin>
 static hipError_t stq_dispatch(int nt, const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {

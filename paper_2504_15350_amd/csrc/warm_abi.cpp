@@ -47,13 +47,15 @@ void geometry(rpod_warm_s& M) {
     M.bank_cols = (int)rup(M.Kr, 128);
     M.nPb = rup(M.Kr, 256);
     M.rpad = (int)rup(d.r, 16);
-    const int64_t ncb = M.nPb / 256;
-    int64_t ns = (256 + ncb - 1) / ncb;
+    // bank^T products use the FP32 split-K kernel: 128-column blocks, splits
+    // interleaved in steps of 64 rows
+    const int64_t ncb = M.nPb / stq32_block_cols();
+    int64_t ns = (2048 + ncb - 1) / ncb;
     ns = std::min<int64_t>(ns, 64);
-    ns = std::min<int64_t>(ns, (d.m + 255) / 256);
+    ns = std::min<int64_t>(ns, (d.m + 63) / 64);
     ns = std::max<int64_t>(ns, 1);
     M.split_rows = rup((d.m + ns - 1) / ns, 64);
-    M.nsplit = (int)((d.m + M.split_rows - 1) / M.split_rows);
+    M.nsplit = (int)ns;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -100,7 +102,7 @@ rpod_status bank_product(rpod_warm_s& M, const float* Q, int nt) {
     a.nP = M.nPb;
     a.split_rows = M.split_rows;
     a.nsplit = M.nsplit;
-    a.ncb = (int)(M.nPb / 256);
+    a.ncb = (int)(M.nPb / stq32_block_cols());
     a.call = -1;
     ReduceArgs ra{M.at<double>(M.o_Zp), M.nPb * 16 * nt, M.at<double>(M.o_Zt), M.nsplit};
     const int tiles = a.ncb * a.nsplit;
