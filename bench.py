@@ -438,7 +438,20 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-vs-plain measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batch measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start sweep")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES bytes (the reference kernel for scaling "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the row-sharded multi-GPU "
               f"design is not built in this version", file=sys.stderr)
