@@ -34,6 +34,12 @@ struct GroupLaunch {
 //   multiple of 4 (vector loads). upper: X is upper triangular (16 x 16 tiles
 //   below the diagonal skipped).
 hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const GroupLaunch<SxArgs>& L, hipStream_t st);
+// The pass Y = S X over an FP32 S with a long inner dimension (the passes
+// over the snapshot matrix): same contract as launch_sx with tin = tout =
+// FP32, not triangular; rows per workgroup = sx_pass_rows(nt, rows over
+// the launch's matrices) (256, or 512 with two row groups per wave).
+hipError_t launch_sx_pass(int nt, bool vec, int rows, const GroupLaunch<SxArgs>& L, hipStream_t st);
+int sx_pass_rows(int nt, int64_t rows_total);
 // The same product with X and Y in FP64 and S of any storage type tin,
 // converted to FP64 in registers (FP64 matrix cores; vec: 8-byte-or-wider
 // aligned vector loads as for launch_sx with that storage type).

@@ -161,12 +161,12 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // ---------------------------------------------------------------------------
 // Recorded program
 // ---------------------------------------------------------------------------
-enum Kind { K_ZERO, K_OMEGA, K_SX, K_SX16, K_STQ, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT, K_SIGNS,
+enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXP, K_SX16, K_STQ, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT, K_SIGNS,
             K_FIN, K_SPLIT, K_WFWD, K_WZ, K_VSCALE, K_SXW, K_RESID };
 
 struct Step {
     Kind kind;
-    int tin = 0, tout = 0, nt = 0, lp = 0;
+    int tin = 0, tout = 0, nt = 0, lp = 0;  // lp: padded size (small SVD) or rows per workgroup (FP32 pass)
     bool vec = true, upper = false, lo = false;
     int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S (timed)
     size_t a1 = 0, t1 = 0, a2 = 0, t2 = 0;  // program-blob offsets of the argument / tile tables
@@ -313,8 +313,8 @@ struct Recorder {
     }
     // pass over S: Y = S X
     void pass_sx() {
-        const bool s16 = is16(L0().tin);
-        Step s{s16 ? K_SX16 : K_SX};
+        const bool s16 = is16(L0().tin), f32 = L0().tin == DT_F32;
+        Step s{s16 ? K_SX16 : f32 ? K_SXP : K_SX};
         s.tin = L0().tin; s.tout = L0().tacc; s.nt = L0().nt; s.pass = 0;
         s.vec = true;
         for (const Item* it : C) {
@@ -327,7 +327,11 @@ struct Recorder {
             return SxArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, it.L.o_X), it.L.nP,
                           P->at<char>(it, it.L.o_Y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
         });
-        B.add(s, args, tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
+        int64_t rows_total = 0;
+        for (const Item* it : C) rows_total += it->L.mP;
+        const int rows = f32 ? sx_pass_rows(L0().nt, rows_total) : 256;
+        s.lp = rows;  // rows per workgroup of the pass kernel
+        B.add(s, args, tiles([rows](const Item& it) { return (int)((it.L.mP + rows - 1) / rows); }));
         out.push_back(s);
     }
     // pass over S: slabs of S^T Q1 (lo: Q1 carried as hi + lo on 16-bit paths), then their sum Zt
@@ -641,6 +645,7 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_ZERO: return launch_zero_ints(P->gl<ZeroArgs>(s, false), st);
         case K_OMEGA: return launch_omega(s.tout, P->gl<OmegaArgs>(s, false), st);
         case K_SX: return launch_sx(s.tin, s.tout, s.nt, s.vec, s.upper, P->gl<SxArgs>(s, false), st);
+        case K_SXP: return launch_sx_pass(s.nt, s.vec, s.lp, P->gl<SxArgs>(s, false), st);
         case K_SX16: return launch_sx16(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
         case K_STQ: return launch_stq(s.tin, s.nt, s.vec, P->gl<StqArgs>(s, false), st);
         case K_STQ16: return launch_stq16(s.tin, s.nt, s.lo, s.vec, P->gl<StqArgs>(s, false), st);
