@@ -34,12 +34,6 @@ struct GroupLaunch {
 //   multiple of 4 (vector loads). upper: X is upper triangular (16 x 16 tiles
 //   below the diagonal skipped).
 hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const GroupLaunch<SxArgs>& L, hipStream_t st);
-// The pass Y = S X over an FP32 S with a long inner dimension (the passes
-// over the snapshot matrix): same contract as launch_sx with tin = tout =
-// FP32, not triangular; rows per workgroup = sx_pass_rows(nt, rows over
-// the launch's matrices) (256, or 512 with two row groups per wave).
-hipError_t launch_sx_pass(int nt, bool vec, int rows, const GroupLaunch<SxArgs>& L, hipStream_t st);
-int sx_pass_rows(int nt, int64_t rows_total);
 // The same product with X and Y in FP64 and S of any storage type tin,
 // converted to FP64 in registers (FP64 matrix cores; vec: 8-byte-or-wider
 // aligned vector loads as for launch_sx with that storage type).
@@ -69,6 +63,23 @@ int stq16_rows_per_step(bool lo);
 // one workgroup per 1024 elements).
 hipError_t launch_split16(int tin, const GroupLaunch<SplitArgs>& L, hipStream_t st);
 
+// FP32 S on the BF16 matrix cores with every operand split exactly into three
+// BF16 parts (six products per term, FP32-accurate dot products):
+//   launch_sx_e6: Y = S X, X given as its three parts one after another
+//   (each ldX x 16 nt, zero rows up to roundup(n, 32)); 256 rows per workgroup.
+//   launch_stq_e6: slabs of S^T Q, Q given as three parts one after another
+//   (each ldQ x 16 nt, zero rows up to roundup(m, 32)); tiles ncb =
+//   nP / stq_e6_block_cols() x nsplit, splits interleaved in units of 64
+//   rows (split s: rows 64 (k nsplit + s) .., k = 0, 1, ..), nP a multiple
+//   of stq_e6_block_cols(); nsplit a multiple of 8 keeps each split's column
+//   blocks on one XCD.
+//   launch_split3: the parts of an FP32 array (count a multiple of 4) into
+//   hi, hi + count, hi + 2 count; one workgroup per 1024 elements.
+hipError_t launch_sx_e6(int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st);
+hipError_t launch_stq_e6(int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st);
+hipError_t launch_split3(const GroupLaunch<SplitArgs>& L, hipStream_t st);
+int stq_e6_block_cols();
+
 // out[e] = sum over the nsplit slabs, fixed order; one workgroup per 256 elements.
 hipError_t launch_reduce_slabs(const GroupLaunch<ReduceArgs>& L, hipStream_t st);
 
@@ -94,7 +105,9 @@ hipError_t launch_gram(int tin, int nt, const GroupLaunch<GramArgs>& L, const Gr
 //   R64 / R32: R^-1, lp x lp column-major.
 //   mode 0: first factorisation of an orthonormalisation (resets *local);
 //   mode 1: unconditional; mode 2: run only if *local has DEV_FLAG_SHIFTED.
-hipError_t launch_chol_inv(const GroupLaunch<CholArgs>& L, hipStream_t st);
+//   lp: the padded size shared by the launch's matrices (one wave per
+//   matrix for lp <= 64, a workgroup of 256 threads above).
+hipError_t launch_chol_inv(int lp, const GroupLaunch<CholArgs>& L, hipStream_t st);
 
 // Symmetric eigen-decomposition of the lp x lp FP64 Gram matrix G_B = B B^T
 // (lp a multiple of 16, <= 128): diagonally pivoted Cholesky G_B = P L L^T P^T,

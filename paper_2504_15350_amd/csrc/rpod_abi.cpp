@@ -67,7 +67,7 @@ struct Layout {
     int nchunk;
     int gram_cap;
     // byte offsets into the matrix's workspace region
-    size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
+    size_t o_X, o_X3, o_Y, o_Q1, o_Qh, o_Ql, o_Q3, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
     size_t total;
 };
@@ -104,16 +104,17 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.tin = d->dtype;  // rpod_dtype and the internal codes coincide
     L.tacc = d->dtype == RPOD_F64 ? DT_F64 : DT_F32;
     // split-K over rows for S^T Q. FP64: blocks of 256 columns and
-    // contiguous splits of >= 256 rows. FP32: blocks of 128 columns, splits
-    // interleaved in steps of 64 rows. 16-bit: blocks of 128 columns (256
+    // contiguous splits of >= 256 rows. FP32: blocks of 256 columns, splits
+    // interleaved in units of 64 rows. 16-bit: blocks of 128 columns (256
     // with the lo part), splits interleaved in steps of 128 rows.
     const bool s16 = is16(L.tin), f32 = L.tin == DT_F32;
-    const int64_t ncb = s16 ? L.nP / stq16_block_cols(false) : f32 ? L.nP / stq32_block_cols() : L.nP / 256;
+    const int64_t ncb = s16 ? L.nP / stq16_block_cols(false) : f32 ? L.nP / stq_e6_block_cols() : L.nP / 256;
     const int64_t target = (s16 || f32) ? wg_target : std::max<int64_t>(64, wg_target / 4);
     int64_t ns = (target + ncb - 1) / ncb;
     if (ns > 64) ns = 64;
     const int64_t maxs = s16 ? (d->m + 127) / 128 : f32 ? (d->m + 63) / 64 : (d->m + 255) / 256;
     if (ns > maxs) ns = maxs;
+    if (f32 && ns >= 8) ns -= ns % 8;  // whole XCD groups of splits
     if (ns < 1) ns = 1;
     L.split_rows = roundup((d->m + ns - 1) / ns, 64);
     L.nsplit = (s16 || f32) ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
@@ -130,10 +131,12 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     };
     const size_t lp2 = (size_t)L.lp * L.lp;
     L.o_X = take((size_t)L.nP * L.lp * si);
+    L.o_X3 = take(f32 ? (size_t)3 * L.nP * L.lp * 2 : 0);  // FP32: the three BF16 parts of X
     L.o_Y = take((size_t)L.mP * L.lp * sa);
     L.o_Q1 = take((size_t)L.mP * L.lp * sa);
     L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Ql = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
+    L.o_Q3 = take(f32 ? (size_t)3 * L.mP * L.lp * 2 : 0);  // FP32: the three BF16 parts of Q1
     L.o_Zp = take((size_t)L.nsplit * L.nP * L.lp * 8);
     L.o_Zt = take((size_t)L.nP * L.lp * 8);
     L.o_Zw = take((size_t)L.nP * L.lp * 8);
@@ -161,12 +164,12 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // ---------------------------------------------------------------------------
 // Recorded program
 // ---------------------------------------------------------------------------
-enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXP, K_SX16, K_STQ, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT, K_SIGNS,
-            K_FIN, K_SPLIT, K_WFWD, K_WZ, K_VSCALE, K_SXW, K_RESID };
+enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXE6, K_SX16, K_STQ, K_STQE6, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT,
+            K_SIGNS, K_FIN, K_SPLIT, K_SPLIT3, K_WFWD, K_WZ, K_VSCALE, K_SXW, K_RESID };
 
 struct Step {
     Kind kind;
-    int tin = 0, tout = 0, nt = 0, lp = 0;  // lp: padded size (small SVD) or rows per workgroup (FP32 pass)
+    int tin = 0, tout = 0, nt = 0, lp = 0;  // lp: padded size (small SVD, Cholesky)
     bool vec = true, upper = false, lo = false;
     int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S (timed)
     size_t a1 = 0, t1 = 0, a2 = 0, t2 = 0;  // program-blob offsets of the argument / tile tables
@@ -301,7 +304,24 @@ struct Recorder {
               }),
               tiles([](const Item& it) { return (int)((it.L.nP + 255) / 256) * ((it.L.lp + 1) / 2); }));
         out.push_back(s);
+        split3_x();
     }
+    // FP32: the three BF16 parts of an FP32 operand of the passes over S
+    void split3(size_t Layout::*src, size_t Layout::*dst, bool tall) {
+        if (L0().tin != DT_F32) return;
+        Step s{K_SPLIT3};
+        B.add(s, each([&](const Item& it) {
+                  const int64_t rows = tall ? it.L.mP : it.L.nP;
+                  return SplitArgs{P->at<float>(it, it.L.*src), rows * it.L.lp,
+                                   P->at<unsigned short>(it, it.L.*dst), nullptr};
+              }),
+              tiles([tall](const Item& it) {
+                  const int64_t rows = tall ? it.L.mP : it.L.nP;
+                  return (int)((rows * it.L.lp / 4 + 255) / 256);
+              }));
+        out.push_back(s);
+    }
+    void split3_x() { split3(&Layout::o_X, &Layout::o_X3, false); }
     // generic tall x small product (internal operands)
     void sx(int tin, int tout, int nt, bool upper, std::vector<SxArgs> args) {
         Step s{K_SX};
@@ -314,7 +334,7 @@ struct Recorder {
     // pass over S: Y = S X
     void pass_sx() {
         const bool s16 = is16(L0().tin), f32 = L0().tin == DT_F32;
-        Step s{s16 ? K_SX16 : f32 ? K_SXP : K_SX};
+        Step s{s16 ? K_SX16 : f32 ? K_SXE6 : K_SX};
         s.tin = L0().tin; s.tout = L0().tacc; s.nt = L0().nt; s.pass = 0;
         s.vec = true;
         for (const Item* it : C) {
@@ -324,20 +344,16 @@ struct Recorder {
             s.flops += 2.0 * it->d.m * it->d.n * it->L.l;
         }
         std::vector<SxArgs> args = each([&](const Item& it) {
-            return SxArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, it.L.o_X), it.L.nP,
+            return SxArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, f32 ? it.L.o_X3 : it.L.o_X), it.L.nP,
                           P->at<char>(it, it.L.o_Y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
         });
-        int64_t rows_total = 0;
-        for (const Item* it : C) rows_total += it->L.mP;
-        const int rows = f32 ? sx_pass_rows(L0().nt, rows_total) : 256;
-        s.lp = rows;  // rows per workgroup of the pass kernel
-        B.add(s, args, tiles([rows](const Item& it) { return (int)((it.L.mP + rows - 1) / rows); }));
+        B.add(s, args, tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
         out.push_back(s);
     }
     // pass over S: slabs of S^T Q1 (lo: Q1 carried as hi + lo on 16-bit paths), then their sum Zt
     void pass_stq(bool lo) {
-        const bool s16 = is16(L0().tin);
-        Step s{s16 ? K_STQ16 : K_STQ};
+        const bool s16 = is16(L0().tin), f32 = L0().tin == DT_F32;
+        Step s{s16 ? K_STQ16 : f32 ? K_STQE6 : K_STQ};
         s.tin = L0().tin; s.nt = L0().nt; s.pass = 1; s.lo = s16 && lo;
         s.vec = true;
         for (const Item* it : C) {
@@ -349,12 +365,12 @@ struct Recorder {
         std::vector<StqArgs> args = each([&](const Item& it) {
             StqArgs a{};
             a.S = nullptr; a.ldS = it.d.ld; a.m = it.d.m; a.n = it.d.n;
-            a.Q = s16 ? (const void*)P->at<char>(it, it.L.o_Qh) : (const void*)P->at<char>(it, it.L.o_Q1);
+            a.Q = P->at<char>(it, s16 ? it.L.o_Qh : f32 ? it.L.o_Q3 : it.L.o_Q1);
             a.Ql = s16 ? (const void*)P->at<char>(it, it.L.o_Ql) : nullptr;
             a.ldQ = it.L.mP; a.Zp = P->at<double>(it, it.L.o_Zp); a.nP = it.L.nP;
             a.split_rows = it.L.split_rows; a.nsplit = it.L.nsplit;
             a.ncb = s16 ? (int)(it.L.nP / stq16_block_cols(s.lo))
-                        : it.L.tin == DT_F32 ? (int)(it.L.nP / stq32_block_cols()) : (int)(it.L.nP / 256);
+                        : f32 ? (int)(it.L.nP / stq_e6_block_cols()) : (int)(it.L.nP / 256);
             a.call = it.idx;
             return a;
         });
@@ -384,6 +400,7 @@ struct Recorder {
     }
     void chol(std::vector<CholArgs> args) {
         Step s{K_CHOL};
+        s.lp = L0().lp;
         B.add(s, args, std::vector<int>(args.size(), 1));
         out.push_back(s);
     }
@@ -433,6 +450,7 @@ struct Recorder {
                   tiles([](const Item& it) { return (int)((it.L.mP * it.L.lp / 4 + 255) / 256); }));
             out.push_back(s);
         }
+        split3(&Layout::o_Q1, &Layout::o_Q3, true);
     }
     // Zw = Zt R^-1 (R from the last tall orthonormalisation): Zw = S^T Q
     void small_from_slabs() {
@@ -473,6 +491,7 @@ struct Recorder {
         gram(DT_F64, gargs(true, true));
         chol(cargs(2, 2));
         sx(DT_F64, tin, L0().nt, true, app(&Layout::o_Zw2, &Layout::o_X, 2, true));
+        split3_x();
     }
     void finish() {
         const Layout& L = L0();
@@ -645,18 +664,20 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_ZERO: return launch_zero_ints(P->gl<ZeroArgs>(s, false), st);
         case K_OMEGA: return launch_omega(s.tout, P->gl<OmegaArgs>(s, false), st);
         case K_SX: return launch_sx(s.tin, s.tout, s.nt, s.vec, s.upper, P->gl<SxArgs>(s, false), st);
-        case K_SXP: return launch_sx_pass(s.nt, s.vec, s.lp, P->gl<SxArgs>(s, false), st);
+        case K_SXE6: return launch_sx_e6(s.nt, s.vec, P->gl<SxArgs>(s, false), st);
         case K_SX16: return launch_sx16(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
         case K_STQ: return launch_stq(s.tin, s.nt, s.vec, P->gl<StqArgs>(s, false), st);
+        case K_STQE6: return launch_stq_e6(s.nt, s.vec, P->gl<StqArgs>(s, false), st);
         case K_STQ16: return launch_stq16(s.tin, s.nt, s.lo, s.vec, P->gl<StqArgs>(s, false), st);
         case K_REDUCE: return launch_reduce_slabs(P->gl<ReduceArgs>(s, false), st);
         case K_GRAM: return launch_gram(s.tin, s.nt, P->gl<GramArgs>(s, false), P->gl<GramArgs>(s, true), st);
-        case K_CHOL: return launch_chol_inv(P->gl<CholArgs>(s, false), st);
+        case K_CHOL: return launch_chol_inv(s.lp, P->gl<CholArgs>(s, false), st);
         case K_JACOBI: return launch_jacobi(s.lp, P->gl<JacobiArgs>(s, false), st);
         case K_LIFT: return launch_lift_coef(P->gl<LiftArgs>(s, false), st);
         case K_SIGNS: return launch_signs(s.tin, P->gl<ColmaxArgs>(s, false), P->gl<SignArgs>(s, true), st);
         case K_FIN: return launch_finalize(s.tin, P->gl<FinArgs>(s, false), P->gl<FinArgs>(s, true), st);
         case K_SPLIT: return launch_split16(s.tin, P->gl<SplitArgs>(s, false), st);
+        case K_SPLIT3: return launch_split3(P->gl<SplitArgs>(s, false), st);
         case K_WFWD: return launch_warm_plan_forward(P->gl<WarmFwdArgs>(s, false), st);
         case K_WZ: return launch_warm_z(P->gl<WarmZArgs>(s, false), st);
         case K_VSCALE: return launch_warm_vscale(P->gl<VscaleArgs>(s, false), st);

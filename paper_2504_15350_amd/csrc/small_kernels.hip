@@ -438,8 +438,127 @@ __global__ __launch_bounds__(256) void k_chol_inv(Group<CholArgs> g) {
     chol_body(a.G, a.l, a.lp, a.M, a.R64, a.R32, a.flags, a.local, a.mode);
 }
 
-hipError_t launch_chol_inv(const GroupLaunch<CholArgs>& L, hipStream_t st) {
-    hipLaunchKernelGGL(k_chol_inv, dim3(L.count), dim3(256), 0, st, mkg(L));
+// ---------------------------------------------------------------------------
+// The same factorisation and inverse for lp = LP <= 64 in one wave, without
+// LDS or barriers. Lane j keeps column j of the upper triangle in registers
+// (w[i] = A[i][j], i <= j; row i of G read coalesced) and its diagonal
+// G[j][j]. Step k: the pivot is read from lane k, lanes j >= k scale their
+// w[k] into R[k][j], and the trailing update w[i] -= R[k][i] R[k][j] takes
+// R[k][i] from lane i by v_readlane (the same operations, in the same
+// order, as the workgroup version). The inverse is formed by rows: lane t
+// solves x^T R = e_t^T by forward substitution,
+//   x[c] = (delta_tc - sum_{k<c} x[k] R[k][c]) / R[c][c],
+// R[k][c] read from lane c, and stores row t of R^-1 (coalesced
+// column-major stores).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int LP>
+__global__ __launch_bounds__(64) void k_chol_wave(Group<CholArgs> gr) {
+    const CholArgs& a = gr.args[blockIdx.x];  // one wave per matrix
+    const int j = threadIdx.x;
+    const int l = a.l, lp = a.lp;
+    const double* __restrict__ G = a.G;
+    if (a.mode == 2 && !(*a.local & DEV_FLAG_SHIFTED)) return;
+    if (a.mode == 0 && j == 0) *a.local = 0;
+
+    double w[LP];
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < LP; ++i) {
+        w[i] = (j < LP) ? G[i * lp + j] : 0.0;
+        fin = fin && isfinite(w[i]);
+    }
+    const double gd = (j < LP) ? G[j * lp + j] : 0.0;  // G[j][j]
+    bool ok = __all(fin);
+    if (!ok && j == 0) atomicOr(a.flags, DEV_FLAG_NONFINITE);
+    if (ok) {
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            if (attempt == 1) {
+                double tr = 0.0;
+                for (int k = 0; k < l; ++k) tr += read_lane(gd, k);
+                const double shift = 11.0 * ((double)a.M * l + (double)l * (l + 1)) * 0x1.0p-53 * tr;
+#pragma unroll
+                for (int i = 0; i < LP; ++i) w[i] = ((j < LP) ? G[i * lp + j] : 0.0) + (i == j ? shift : 0.0);
+            }
+            bool fail = false;
+#pragma unroll
+            for (int k = 0; k < LP; ++k) {
+                if (k < l && !fail) {
+                    const double d = read_lane(w[k], k);
+                    const double tol = (double)l * 0x1.0p-52 * read_lane(gd, k);
+                    if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot (uniform)
+                        fail = true;
+                    } else {
+                        const double rinv = 1.0 / sqrt(d);
+                        if (j >= k) w[k] *= rinv;  // row k of R
+                        // rows i >= l are padding: updated too, never read
+#pragma unroll
+                        for (int i = k + 1; i < LP; ++i) w[i] -= read_lane(w[k], i) * w[k];
+                    }
+                }
+            }
+            if (!fail) break;
+            if (attempt == 0) {
+                if (j == 0) {
+                    atomicOr(a.flags, DEV_FLAG_SHIFTED);
+                    *a.local |= DEV_FLAG_SHIFTED;
+                }
+            } else {
+                if (j == 0) atomicOr(a.flags, DEV_FLAG_BREAKDOWN);
+                ok = false;
+            }
+        }
+    }
+    if (ok) {
+        double x[LP];  // row j of R^-1
+#pragma unroll
+        for (int c = 0; c < LP; ++c) {
+            if (c < l) {
+                // two partial sums shorten the dependent chain
+                double s0 = (c == j) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < c; ++k) {
+                    const double rkc = read_lane(w[k], c);
+                    if (k & 1) s1 -= x[k] * rkc;
+                    else s0 -= x[k] * rkc;
+                }
+                x[c] = (s0 + s1) / read_lane(w[c], c);
+            } else {
+                x[c] = (c == j) ? 1.0 : 0.0;  // padding: identity
+            }
+        }
+        if (j < LP) {
+#pragma unroll
+            for (int c = 0; c < LP; ++c) {
+                const double v = (j >= l && c < l) ? 0.0 : x[c];
+                a.R64[c * lp + j] = v;
+                a.R32[c * lp + j] = (float)v;
+            }
+        }
+    } else if (j < LP) {
+#pragma unroll
+        for (int c = 0; c < LP; ++c) {
+            const double v = (c == j) ? 1.0 : 0.0;
+            a.R64[c * lp + j] = v;
+            a.R32[c * lp + j] = (float)v;
+        }
+    }
+}
+
+hipError_t launch_chol_inv(int lp, const GroupLaunch<CholArgs>& L, hipStream_t st) {
+    switch (lp) {
+        case 16: hipLaunchKernelGGL(k_chol_wave<16>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
+        case 32: hipLaunchKernelGGL(k_chol_wave<32>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
+        case 48: hipLaunchKernelGGL(k_chol_wave<48>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
+        case 64: hipLaunchKernelGGL(k_chol_wave<64>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
+        default: hipLaunchKernelGGL(k_chol_inv, dim3(L.count), dim3(256), 0, st, mkg(L)); break;
+    }
     return hipGetLastError();
 }
 

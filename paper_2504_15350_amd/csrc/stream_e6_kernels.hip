@@ -1,0 +1,414 @@
+// Passes over an FP32 snapshot matrix on the BF16 matrix cores.
+//
+// Every FP32 value x is split exactly into three bfloat16 parts
+//   x = h + m + l,  h = bf16(x), m = bf16(x - h), l = bf16(x - h - m)
+// (each difference is exact in FP32). A product of two split operands keeps
+// the six terms hh, hm, mh, hl, mm, lh, each an exact BF16 x BF16 product
+// accumulated in FP32 by the 16x16x32 MFMA. With |m| <= 2^-8 |x| and
+// |l| <= 2^-16 |x| the dropped terms ml, lm, ll weigh together about
+// 2^-23 |x| |y|, the size of one FP32 rounding of the product, so a dot
+// product is as accurate as one with FP32 products and FP32 accumulation.
+// The BF16 matrix cores run 16 times the FP32 rate: with six products per
+// term both passes stay bound by HBM, not by the FP32 matrix-core rate.
+//
+//   k_sx_e6   Y = S X   (X given split: three BF16 arrays of n x 16 NT)
+//   k_stq_e6  slabs of Z = S^T Q (Q given split), interleaved row splits
+//   k_split3  the three-way split of an FP32 array
+//
+// MFMA operand layout (16x16x32 bf16, gfx950): lane l supplies
+// A[l%16][8(l/16) + i] and B[8(l/16) + i][l%16], i = 0..7; the result holds
+// D[4(l/16) + v][l%16].
+#include <hip/hip_bf16.h>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace rpod {
+
+typedef __bf16 e6_bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short e6_u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mma_bf16(e6_u16x8 a, e6_u16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(e6_bf16x8, a), __builtin_bit_cast(e6_bf16x8, b),
+                                                   c, 0, 0, 0);
+}
+
+typedef float e6_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 e6_bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned e6_u32x4 __attribute__((ext_vector_type(4)));
+
+// Three-way split of two values; each result word packs the parts of a
+// (low half) and b (high half). Rounding to nearest at every level.
+__device__ __forceinline__ void split_pair(float a, float b, unsigned& h, unsigned& m, unsigned& l) {
+    const e6_f32x2 x{a, b};
+    h = __builtin_bit_cast(unsigned, __builtin_convertvector(x, e6_bf16x2));
+    const e6_f32x2 r = x - e6_f32x2{__builtin_bit_cast(float, h << 16), __builtin_bit_cast(float, h & 0xffff0000u)};
+    m = __builtin_bit_cast(unsigned, __builtin_convertvector(r, e6_bf16x2));
+    const e6_f32x2 t = r - e6_f32x2{__builtin_bit_cast(float, m << 16), __builtin_bit_cast(float, m & 0xffff0000u)};
+    l = __builtin_bit_cast(unsigned, __builtin_convertvector(t, e6_bf16x2));
+}
+
+// eight values (x0 then x1) -> the three BF16 operands
+__device__ __forceinline__ void split8(f32x4 x0, f32x4 x1, e6_u16x8& ah, e6_u16x8& am, e6_u16x8& al) {
+    e6_u32x4 h, m, l;
+    unsigned a, b, c;
+    split_pair(x0[0], x0[1], a, b, c); h[0] = a; m[0] = b; l[0] = c;
+    split_pair(x0[2], x0[3], a, b, c); h[1] = a; m[1] = b; l[1] = c;
+    split_pair(x1[0], x1[1], a, b, c); h[2] = a; m[2] = b; l[2] = c;
+    split_pair(x1[2], x1[3], a, b, c); h[3] = a; m[3] = b; l[3] = c;
+    ah = __builtin_bit_cast(e6_u16x8, h);
+    am = __builtin_bit_cast(e6_u16x8, m);
+    al = __builtin_bit_cast(e6_u16x8, l);
+}
+
+// acc += the six leading terms of (ah + am + al)(bh + bm + bl), small terms first
+__device__ __forceinline__ void mma6(const e6_u16x8& ah, const e6_u16x8& am, const e6_u16x8& al, const e6_u16x8& bh,
+                                     const e6_u16x8& bm, const e6_u16x8& bl, f32x4& acc) {
+    f32x4 s = acc;
+    s = mma_bf16(al, bh, s);
+    s = mma_bf16(am, bm, s);
+    s = mma_bf16(ah, bl, s);
+    s = mma_bf16(am, bh, s);
+    s = mma_bf16(ah, bm, s);
+    acc = mma_bf16(ah, bh, s);
+}
+
+// Four consecutive rows i..i+3 of column j (FP32), rows >= lim or columns >= n read 0.
+template <bool VEC>
+__device__ __forceinline__ f32x4 e6_rows4(const GLOBAL float* S, int64_t ld, int64_t lim, int64_t n, int64_t i,
+                                          int64_t j) {
+    f32x4 v = {0, 0, 0, 0};
+    if (j < n) {
+        const GLOBAL float* p = S + j * ld + i;
+        if (VEC && i + 3 < lim) {
+            v = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL f32x4*>(p));  // streamed once
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (i + t < lim) v[t] = p[t];
+        }
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Y = S X. Workgroup = 4 waves = 256 rows. Per 32-column step lane (r, g)
+// of a wave holds rows 4 r .. 4 r + 3 of columns j0 + 8 g + i, i = 0..7 (a
+// wave instruction covers 4 columns x 256 bytes); element t of these is the
+// A operand of row tile t (MFMA row r of tile t is row 4 r + t of the wave),
+// K index 8 g + i. The step's block of the three X parts (32 rows x 16 NT
+// columns each) is staged in LDS, double-buffered, and shared by the four
+// waves. All four tiles are split before the matrix-core work, and the next
+// step's S columns are loaded after it.
+// ---------------------------------------------------------------------------
+constexpr int E6_XLD = 40;  // halfwords per staged X column (32 rows + pad)
+
+template <int NT, bool VEC>
+__device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, int64_t m, int64_t n,
+                                           const GLOBAL unsigned short* __restrict__ X, int64_t ldX,
+                                           GLOBAL float* Y, int64_t ldY, int64_t mstore, int cmax, int64_t bx,
+                                           unsigned short* xs) {
+    constexpr int XB = 3 * 16 * NT * E6_XLD;    // one staged X block
+    constexpr int XCH = 3 * 16 * NT * 4;        // its 16-byte chunks
+    constexpr int XPT = (XCH + 255) / 256;
+    const int64_t part = ldX * (16 * NT);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int64_t iw = bx * 256 + wave * 64;
+    const int64_t irow = iw + 4 * r16;
+    const bool fast = VEC && iw + 64 <= m;  // whole wave in range: unguarded vector loads
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[t][c] = f32x4{0, 0, 0, 0};
+    f32x4 sv[8];
+    auto load_s = [&](int64_t j0) {
+        if (fast && j0 + 32 <= n) {
+            const GLOBAL float* p = S + (j0 + 8 * g) * ldS + irow;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                sv[i] = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL f32x4*>(p + i * ldS));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sv[i] = e6_rows4<VEC>(S, ldS, m, n, irow, j0 + 8 * g + i);
+        }
+    };
+    e6_u16x8 xr[XPT];
+    auto load_x = [&](int64_t j0) {
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+            const int ch = tid + 256 * q;
+            if (ch < XCH) {
+                const int col = ch >> 2, prt = col / (16 * NT), qc = col % (16 * NT);
+                xr[q] = *reinterpret_cast<const GLOBAL e6_u16x8*>(X + prt * part + (int64_t)qc * ldX + j0 +
+                                                                 8 * (ch & 3));
+            }
+        }
+    };
+    auto put_x = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+            const int ch = tid + 256 * q;
+            if (ch < XCH) *reinterpret_cast<e6_u16x8*>(xs + buf * XB + (ch >> 2) * E6_XLD + 8 * (ch & 3)) = xr[q];
+        }
+    };
+    load_s(0);  // rows >= m read as 0 (guarded path)
+    load_x(0);
+    put_x(0);
+    int buf = 0;
+    for (int64_t j0 = 0; j0 < n; j0 += 32) {  // uniform trip count: the barriers below are reached by all waves
+        const bool more = j0 + 32 < n;
+        e6_u16x8 ah[4], am[4], al[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            split8(f32x4{sv[0][t], sv[1][t], sv[2][t], sv[3][t]}, f32x4{sv[4][t], sv[5][t], sv[6][t], sv[7][t]}, ah[t],
+                   am[t], al[t]);
+        if (more) load_x(j0 + 32);
+        __syncthreads();  // block buf staged
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const unsigned short* xb = xs + buf * XB + (16 * c + r16) * E6_XLD + 8 * g;
+            const e6_u16x8 bh = *reinterpret_cast<const e6_u16x8*>(xb);
+            const e6_u16x8 bm = *reinterpret_cast<const e6_u16x8*>(xb + 16 * NT * E6_XLD);
+            const e6_u16x8 bl = *reinterpret_cast<const e6_u16x8*>(xb + 2 * 16 * NT * E6_XLD);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) mma6(ah[t], am[t], al[t], bh, bm, bl, acc[t][c]);
+        }
+        if (more) {
+            load_s(j0 + 32);
+            put_x(buf ^ 1);  // block buf ^ 1 was last read before this step's barrier
+            buf ^= 1;
+        }
+    }
+    // D[4 g + v][r] of tile t: row iw + 4 (4 g + v) + t, output column 16 c + r
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        if (16 * c + r16 >= cmax) continue;
+        GLOBAL float* py = Y + (int64_t)(16 * c + r16) * ldY;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = iw + 4 * (4 * g + v);
+            if (row + 3 < mstore) {
+                *reinterpret_cast<GLOBAL f32x4*>(py + row) =
+                    f32x4{acc[0][c][v], acc[1][c][v], acc[2][c][v], acc[3][c][v]};
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (row + t < mstore) py[row + t] = acc[t][c][v];
+            }
+        }
+    }
+}
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1, 2))) void k_sx_e6(
+    Group<SxArgs> g) {
+    __shared__ __attribute__((aligned(16))) unsigned short xs[2 * 3 * 16 * NT * E6_XLD];
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const SxArgs& a = g.args[it];
+    if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    sx_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.X), a.ldX,
+                        gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT, blockIdx.x - g.tstart[it],
+                        xs);
+}
+
+// ---------------------------------------------------------------------------
+// Z_s = S^T Q. Workgroup: 256 columns of S (four column tiles of 16 per
+// wave), 32 rows per step; the step's S block (32 x 256, FP32) and the three
+// BF16 parts of the Q block (32 x 16 NT) are staged in LDS column-major and
+// the next step's blocks are loaded into registers during the matrix-core
+// work. Lane (r, g) reads rows 8 g .. 8 g + 7 of its S column (the A
+// operand, split in registers) and of each Q column part (the B operand).
+// Splits interleaved in units of 64 rows (one 128-byte line of a Q part):
+// unit k of split s covers rows 64 (k nsplit + s) .. + 63, two steps.
+// Tiles go to the XCDs (workgroup b runs on XCD b mod 8) so that each XCD
+// holds every column block of its splits: the Q rows of a split are then
+// fetched into one L2 only.
+// ---------------------------------------------------------------------------
+constexpr int E6_R = 32, E6_LDS = E6_R + 4, E6_LDQ = E6_R + 8, E6_HB = 256;
+
+template <int NT, bool VEC>
+__device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, int64_t ldS, int64_t m, int64_t n,
+                                            const GLOBAL unsigned short* __restrict__ Q, int64_t ldQ,
+                                            GLOBAL double* __restrict__ Zp, int64_t nP, int nsplit, int ncb,
+                                            int tile, float* ss, unsigned short* qs) {
+    constexpr int R = E6_R, LD = E6_LDS, LDQ = E6_LDQ, HB = E6_HB, U = HB / 64;
+    constexpr int CPC = R / 4;                  // 16-byte S chunks per column
+    constexpr int SPT = HB * CPC / 256;         // S chunks per thread
+    constexpr int QCPC = R / 8;                 // 16-byte Q chunks per column part
+    constexpr int QCH = 3 * 16 * NT * QCPC;     // Q chunks per step (three parts)
+    constexpr int QPT = (QCH + 255) / 256;
+    const int64_t qpart = ldQ * (16 * NT);
+    const int cb = tile % ncb, sp = tile / ncb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int64_t j0 = (int64_t)cb * HB;
+    const int64_t ib = (int64_t)sp * (2 * R), jump = (int64_t)nsplit * (2 * R) - R;
+    // next step: the second half of the unit, or the first half of the next unit
+    auto next = [&](int64_t i) { return ((i / R) & 1) ? i + jump : i + R; };
+
+    f32x4 acc[U][NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[u][c] = f32x4{0, 0, 0, 0};
+
+    f32x4 sr[SPT];
+    e6_u16x8 qr[QPT];
+    auto fetch = [&](int64_t i0) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int ch = tid + 256 * q;
+            sr[q] = e6_rows4<VEC>(S, ldS, m, n, i0 + 4 * (ch % CPC), j0 + ch / CPC);
+        }
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) {
+            const int ch = tid + 256 * q;
+            if (ch < QCH) {
+                const int col = ch / QCPC, prt = col / (16 * NT), qc = col % (16 * NT);
+                qr[q] = *reinterpret_cast<const GLOBAL e6_u16x8*>(Q + prt * qpart + (int64_t)qc * ldQ + i0 +
+                                                                 8 * (ch % QCPC));
+            }
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int ch = tid + 256 * q;
+            *reinterpret_cast<f32x4*>(ss + (ch / CPC) * LD + 4 * (ch % CPC)) = sr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) {
+            const int ch = tid + 256 * q;
+            if (ch < QCH) *reinterpret_cast<e6_u16x8*>(qs + (ch / QCPC) * LDQ + 8 * (ch % QCPC)) = qr[q];
+        }
+    };
+    if (ib < m) fetch(ib);
+    for (int64_t i0 = ib; i0 < m; i0 = next(i0)) {
+        __syncthreads();  // previous step consumed
+        put();
+        __syncthreads();
+        if (next(i0) < m) fetch(next(i0));  // in flight during the matrix-core work
+        e6_u16x8 ah[U], am[U], al[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float* src = ss + (16 * U * wave + 16 * u + r16) * LD + 8 * g;
+            split8(*reinterpret_cast<const f32x4*>(src), *reinterpret_cast<const f32x4*>(src + 4), ah[u], am[u],
+                   al[u]);
+        }
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int o = (16 * c + r16) * LDQ + 8 * g;
+            const e6_u16x8 bh = *reinterpret_cast<const e6_u16x8*>(qs + o);
+            const e6_u16x8 bm = *reinterpret_cast<const e6_u16x8*>(qs + 16 * NT * LDQ + o);
+            const e6_u16x8 bl = *reinterpret_cast<const e6_u16x8*>(qs + 2 * 16 * NT * LDQ + o);
+#pragma unroll
+            for (int u = 0; u < U; ++u) mma6(ah[u], am[u], al[u], bh, bm, bl, acc[u][c]);
+        }
+    }
+    // D[4 g + v][r]: S column j0 + 16 U w + 16 u + 4 g + v, Q column 16 c + r
+    GLOBAL double* zp = Zp + (int64_t)sp * nP * (16 * NT);
+    typedef double d4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+            *reinterpret_cast<GLOBAL d4*>(zp + (int64_t)(16 * c + r16) * nP + j0 + 16 * U * wave + 16 * u + 4 * g) =
+                d4{acc[u][c][0], acc[u][c][1], acc[u][c][2], acc[u][c][3]};
+}
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1, 2))) void k_stq_e6(
+    Group<StqArgs> g) {
+    __shared__ __attribute__((aligned(16))) float ss[E6_HB * E6_LDS];
+    __shared__ __attribute__((aligned(16))) unsigned short qs[3 * 16 * NT * E6_LDQ];
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const StqArgs& a = g.args[it];
+    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    // XCD-aware order: local tile b (XCD b mod 8 when the item starts at a
+    // multiple of 8) takes tile (b mod 8) T / 8 + b / 8 of the item's T
+    const int local = blockIdx.x - g.tstart[it], ntl = a.ncb * a.nsplit;
+    const int tile = ((ntl & 7) == 0 && (g.tstart[it] & 7) == 0) ? (local & 7) * (ntl >> 3) + (local >> 3) : local;
+    // Q holds the three parts one after another, each ldQ x 16 NT
+    stq_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q), a.ldQ, gbl(a.Zp),
+                         a.nP, a.nsplit, a.ncb, tile, ss, qs);
+}
+
+// three-way split, 4 elements per thread; out: h, m, l parts one after another
+__global__ void k_split3(Group<SplitArgs> g) {
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const SplitArgs& sa = g.args[it];
+    const int64_t e = ((int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x) * 4;
+    if (e >= sa.count) return;
+    const f32x4 q = *reinterpret_cast<const GLOBAL f32x4*>(gbl(sa.Q) + e);
+    unsigned h0, m0, l0, h1, m1, l1;
+    split_pair(q[0], q[1], h0, m0, l0);
+    split_pair(q[2], q[3], h1, m1, l1);
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    GLOBAL unsigned short* out = gbl(sa.hi);
+    *reinterpret_cast<GLOBAL u32x2*>(out + e) = u32x2{h0, h1};
+    *reinterpret_cast<GLOBAL u32x2*>(out + sa.count + e) = u32x2{m0, m1};
+    *reinterpret_cast<GLOBAL u32x2*>(out + 2 * sa.count + e) = u32x2{l0, l1};
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename A>
+static Group<A> mke6(const GroupLaunch<A>& L) {
+    Group<A> g;
+    g.args = L.args;
+    g.tstart = L.tstart;
+    g.calls = L.calls;
+    g.count = L.count;
+    return g;
+}
+
+template <int NT>
+static hipError_t sxe6_nt(const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st) {
+    if (vec)
+        hipLaunchKernelGGL((k_sx_e6<NT, true>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+    else
+        hipLaunchKernelGGL((k_sx_e6<NT, false>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+    return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t stqe6_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
+    if (vec)
+        hipLaunchKernelGGL((k_stq_e6<NT, true>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+    else
+        hipLaunchKernelGGL((k_stq_e6<NT, false>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+    return hipGetLastError();
+}
+
+hipError_t launch_sx_e6(int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st) {
+    switch (nt) {
+#define RPOD_E6_CASE(K) case K: return sxe6_nt<K>(L, vec, st);
+        RPOD_E6_CASE(1) RPOD_E6_CASE(2) RPOD_E6_CASE(3) RPOD_E6_CASE(4)
+        RPOD_E6_CASE(5) RPOD_E6_CASE(6) RPOD_E6_CASE(7) RPOD_E6_CASE(8)
+#undef RPOD_E6_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stq_e6(int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st) {
+    switch (nt) {
+#define RPOD_E6_CASE(K) case K: return stqe6_nt<K>(L, vec, st);
+        RPOD_E6_CASE(1) RPOD_E6_CASE(2) RPOD_E6_CASE(3) RPOD_E6_CASE(4)
+        RPOD_E6_CASE(5) RPOD_E6_CASE(6) RPOD_E6_CASE(7) RPOD_E6_CASE(8)
+#undef RPOD_E6_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_split3(const GroupLaunch<SplitArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_split3, dim3(L.tiles), dim3(256), 0, st, mke6(L));
+    return hipGetLastError();
+}
+
+int stq_e6_block_cols() { return E6_HB; }
+
+}  // namespace rpod

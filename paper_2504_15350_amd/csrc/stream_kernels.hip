@@ -122,88 +122,6 @@ __global__ __launch_bounds__(256) void k_sx(Group<SxArgs> g) {
                                             blockIdx.x - g.tstart[it]);
 }
 
-// The pass Y = S X over an FP32 S (long K = n): H row groups of 64 per wave
-// (256 H rows per workgroup) and, with PF, the loads of the next 16 columns
-// issued before the matrix-core work of the current ones. Measured on the
-// 262144 x 5000 shape: H = 2 is fastest for 3..5 output tiles, PF for 6..8.
-template <int NT, bool VEC, int H, bool PF>
-__device__ __forceinline__ void sx_pass_body(const GLOBAL float* S, int64_t ldS, int64_t m, int64_t n,
-                                             const GLOBAL float* __restrict__ X, int64_t ldX, GLOBAL float* Y,
-                                             int64_t ldY, int64_t mstore, int cmax, int64_t bx) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r16 = lane & 15, kg = lane >> 4;
-    const int64_t iw = bx * (256 * H) + wave * (64 * H);
-    f32x4 acc[H][4][NT];
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int c = 0; c < NT; ++c) acc[h][t][c] = f32x4{0, 0, 0, 0};
-    if (iw < m) {
-        f32x4 an[H][4], bn[NT];
-        auto load = [&](int64_t j0) {
-#pragma unroll
-            for (int h = 0; h < H; ++h)
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    an[h][s] = load_rows4<VEC>(S, ldS, m, n, iw + 64 * h + 4 * r16, j0 + 4 * kg + s);
-#pragma unroll
-            for (int c = 0; c < NT; ++c)
-                bn[c] = *reinterpret_cast<const GLOBAL f32x4*>(X + (int64_t)(16 * c + r16) * ldX + j0 + 4 * kg);
-        };
-        if (PF) load(0);
-        for (int64_t j0 = 0; j0 < n; j0 += 16) {
-            if (!PF) load(j0);
-            f32x4 a[H][4], b[NT];
-#pragma unroll
-            for (int h = 0; h < H; ++h)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) a[h][s] = an[h][s];
-#pragma unroll
-            for (int c = 0; c < NT; ++c) b[c] = bn[c];
-            if (PF && j0 + 16 < n) load(j0 + 16);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int h = 0; h < H; ++h)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-#pragma unroll
-                        for (int c = 0; c < NT; ++c) acc[h][t][c] = mfma_16x16x4(a[h][s][t], b[c][s], acc[h][t][c]);
-        }
-    }
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            if (16 * c + r16 >= cmax) continue;
-            GLOBAL float* py = Y + (int64_t)(16 * c + r16) * ldY;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = iw + 64 * h + 4 * (4 * kg + v);
-                if (row + 3 < mstore) {
-                    store4<float>(py + row, acc[h][0][c][v], acc[h][1][c][v], acc[h][2][c][v], acc[h][3][c][v]);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (row + t < mstore) py[row + t] = acc[h][t][c][v];
-                }
-            }
-        }
-}
-
-template <int NT, bool VEC, int H>
-__global__ __launch_bounds__(256) void k_sx_pass(Group<SxArgs> g) {
-    const int it = group_item(g.tstart, g.count, blockIdx.x);
-    const SxArgs& a = g.args[it];
-    if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
-    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
-    sx_pass_body<NT, VEC, H, (NT >= 6)>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
-                                        gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
-                                        blockIdx.x - g.tstart[it]);
-}
-
 // Y (FP64) = S X with X in FP64 and S of any storage type, FP64 matrix cores.
 template <typename Tin, int NT, bool VEC>
 __global__ __launch_bounds__(256) void k_sx_wide(Group<SxArgs> g) {
@@ -462,41 +380,6 @@ hipError_t launch_sx_wide(int tin, int nt, bool vec, const GroupLaunch<SxArgs>& 
     if (tin == DT_F16) return sxw_dispatch<_Float16>(nt, L, vec, st);
     if (tin == DT_F64) return sxw_dispatch<double>(nt, L, vec, st);
     return hipErrorInvalidValue;
-}
-
-int sx_pass_rows(int nt, int64_t rows_total) {
-    // two row groups per wave for 3..5 output tiles when that still leaves
-    // at least 512 workgroups
-    return (nt >= 3 && nt <= 5 && rows_total >= 512 * 512) ? 512 : 256;
-}
-
-template <int NT>
-static hipError_t sxp_nt(const GroupLaunch<SxArgs>& L, bool vec, int rows, hipStream_t st) {
-    const Group<SxArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
-    if (rows == 512 && NT >= 3 && NT <= 5) {
-        if (vec)
-            hipLaunchKernelGGL((k_sx_pass<NT, true, 2>), dim3(L.tiles), dim3(256), 0, st, g);
-        else
-            hipLaunchKernelGGL((k_sx_pass<NT, false, 2>), dim3(L.tiles), dim3(256), 0, st, g);
-    } else if (rows == 256) {
-        if (vec)
-            hipLaunchKernelGGL((k_sx_pass<NT, true, 1>), dim3(L.tiles), dim3(256), 0, st, g);
-        else
-            hipLaunchKernelGGL((k_sx_pass<NT, false, 1>), dim3(L.tiles), dim3(256), 0, st, g);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_sx_pass(int nt, bool vec, int rows, const GroupLaunch<SxArgs>& L, hipStream_t st) {
-    switch (nt) {
-#define RPOD_SXP_CASE(K) case K: return sxp_nt<K>(L, vec, rows, st);
-        RPOD_SXP_CASE(1) RPOD_SXP_CASE(2) RPOD_SXP_CASE(3) RPOD_SXP_CASE(4)
-        RPOD_SXP_CASE(5) RPOD_SXP_CASE(6) RPOD_SXP_CASE(7) RPOD_SXP_CASE(8)
-#undef RPOD_SXP_CASE
-        default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const GroupLaunch<SxArgs>& L, hipStream_t st) {
