@@ -438,16 +438,32 @@ __global__ __launch_bounds__(256) void k_chol_inv(Group<CholArgs> g) {
     chol_body(a.G, a.l, a.lp, a.M, a.R64, a.R32, a.flags, a.local, a.mode);
 }
 
+// 1 / sqrt(x) and 1 / x for x > 0 (finite): the hardware estimates refined by
+// two Newton steps each (the error of the estimate squares at every step).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
 // ---------------------------------------------------------------------------
 // The same factorisation and inverse for lp = LP <= 64 in one wave, without
 // LDS or barriers. Lane j keeps column j of the upper triangle in registers
 // (w[i] = A[i][j], i <= j; row i of G read coalesced) and its diagonal
-// G[j][j]. Step k: the pivot is read from lane k, lanes j >= k scale their
-// w[k] into R[k][j], and the trailing update w[i] -= R[k][i] R[k][j] takes
-// R[k][i] from lane i by v_readlane (the same operations, in the same
-// order, as the workgroup version). The inverse is formed by rows: lane t
+// G[j][j]. Step k: the pivot d is read from lane k, lanes j >= k scale their
+// w[k] by 1 / sqrt(d) (refined hardware estimate) into R[k][j], and the
+// trailing update w[i] -= R[k][i] R[k][j] takes R[k][i] from lane i by
+// v_readlane (the update order of the workgroup version). The inverse is formed by rows: lane t
 // solves x^T R = e_t^T by forward substitution,
-//   x[c] = (delta_tc - sum_{k<c} x[k] R[k][c]) / R[c][c],
+//   x[c] = (delta_tc - sum_{k<c} x[k] R[k][c]) / R[c][c] (refined reciprocal),
 // R[k][c] read from lane c, and stores row t of R^-1 (coalesced
 // column-major stores).
 // ---------------------------------------------------------------------------
@@ -495,7 +511,7 @@ __global__ __launch_bounds__(64) void k_chol_wave(Group<CholArgs> gr) {
                     if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot (uniform)
                         fail = true;
                     } else {
-                        const double rinv = 1.0 / sqrt(d);
+                        const double rinv = rsqrt_nr(d);
                         if (j >= k) w[k] *= rinv;  // row k of R
                         // rows i >= l are padding: updated too, never read
 #pragma unroll
@@ -528,7 +544,7 @@ __global__ __launch_bounds__(64) void k_chol_wave(Group<CholArgs> gr) {
                     if (k & 1) s1 -= x[k] * rkc;
                     else s0 -= x[k] * rkc;
                 }
-                x[c] = (s0 + s1) / read_lane(w[c], c);
+                x[c] = (s0 + s1) * rcp_nr(read_lane(w[c], c));
             } else {
                 x[c] = (c == j) ? 1.0 : 0.0;  // padding: identity
             }
@@ -569,113 +585,197 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
     return __shfl_xor(v, mask, 64);
 }
 
+// Value of lane (l ^ pattern) within rows of 16 by a DPP move (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140, DPP_QUAD_1032 = 0xB1, DPP_QUAD_2301 = 0x4E;
+
+// Sum over each aligned group of 8 lanes, the same bits in all 8 lanes
+// (the three steps pair commuting operands).
+__device__ __forceinline__ double sum8(double x) {
+    x += dpp_d<DPP_HALF_MIRROR>(x);
+    x += dpp_d<DPP_QUAD_1032>(x);
+    x += dpp_d<DPP_QUAD_2301>(x);
+    return x;
+}
+
+// Maximum over the wave, returned uniformly.
+__device__ __forceinline__ double wave_max(double x) {
+    x = fmax(x, dpp_d<DPP_HALF_MIRROR>(x));
+    x = fmax(x, dpp_d<DPP_QUAD_1032>(x));
+    x = fmax(x, dpp_d<DPP_QUAD_2301>(x));
+    x = fmax(x, dpp_d<DPP_MIRROR>(x));
+    return fmax(fmax(read_lane(x, 0), read_lane(x, 16)), fmax(read_lane(x, 32), read_lane(x, 48)));
+}
+
 // Preconditioned one-sided Jacobi (Drmac and Veselic, SIMAX 2008): with the
 // diagonally pivoted Cholesky factorisation G = P L L^T P^T, the left
 // singular vectors of P L are the eigenvectors of G and its singular values
 // the square roots of G's eigenvalues. One-sided Jacobi on the columns of
-// L (a row permutation does not change the column inner products) then
-// needs few sweeps. Results: UB[:, k] = P (L V)[:, k] / sigma_k by
-// descending sigma_k = ||(L V)[:, k]||; factorisation stops at the first
+// P L (a row permutation does not change the column inner products) then
+// needs few sweeps. Results: UB[:, k] = (P L V)[:, k] / sigma_k by
+// descending sigma_k = ||(P L V)[:, k]||; factorisation stops at the first
 // pivot below lp u times the largest diagonal entry of G (the remaining
-// columns of L are zero, as are their sigma and UB columns).
+// columns are zero, as are their sigma and UB columns).
+// lp <= 64: the factorisation runs in one wave without moving data: lane i
+// keeps row i of the Schur complement (original order) in registers, the
+// pivot is the largest remaining diagonal entry (lowest index on ties), its
+// row is published through LDS, and column j of P L is stored in original
+// row order. lp > 64: the workgroup factorises with symmetric swaps in LDS.
+// Sweeps: round-robin pairs, eight lanes per pair (each lane two pairs of
+// adjacent rows per 16-row group, 16-byte LDS accesses), sums by DPP.
 template <int LP, int NTHR>
 __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, int l, double* __restrict__ UB,
                                                  double* __restrict__ sig, int* flags, double tol, int* sweeps_out) {
     constexpr int NPAIR = LP / 2;
     constexpr int TPP = NTHR / NPAIR;
     constexpr int RPT = LP / TPP;
-    static_assert(TPP >= 1 && TPP <= 64 && (TPP & (TPP - 1)) == 0 && RPT * TPP == LP, "pair layout");
-    constexpr int LDW = LP + 1;
-    __shared__ double W[LP * LDW];   // A[row][col] at W[col * LDW + row]
+    static_assert(TPP == 8 && RPT * TPP == LP, "pair layout: eight lanes per pair");
+    constexpr int LDW = LP + 2;      // 16-byte aligned columns
+    __shared__ __attribute__((aligned(16))) double W[LP * LDW];   // A[row][col] at W[col * LDW + row]
     __shared__ double nrm[LP];
     __shared__ int perm[LP];
-    __shared__ double s_val[NTHR / 64];
-    __shared__ int s_idx[NTHR / 64];
-    __shared__ int s_piv, s_rank, s_rot;
-    __shared__ double s_dmax;
+    __shared__ int s_rank, s_rot;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < LP * LP; e += NTHR) {
-        const int c = e / LP, row = e % LP;
-        W[c * LDW + row] = (c < l && row < l) ? G[row * LP + c] : 0.0;
-    }
-    for (int c = tid; c < LP; c += NTHR) perm[c] = c;
-    if (tid == 0) {
-        double dm = 0.0;
-        for (int i = 0; i < l; ++i) dm = fmax(dm, G[i * LP + i]);
-        s_dmax = dm;
-        s_rank = l;
-    }
-    __syncthreads();
-    const double thr = (double)LP * 0x1.0p-53 * s_dmax;
-    // ---- diagonally pivoted Cholesky (right-looking, full symmetric storage) ----
-    for (int j = 0; j < l; ++j) {
-        // pivot: largest remaining diagonal entry, lowest index on ties
-        double bv = -1.0;
-        int bi = LP;
-        for (int i = j + tid; i < l; i += NTHR) {
-            const double v = W[i * LDW + i];
-            if (v > bv) { bv = v; bi = i; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ov = shfl_xor_d(bv, off);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
-        if (lane == 0) { s_val[wave] = bv; s_idx[wave] = bi; }
+    if constexpr (LP <= 64) {
+        __shared__ __attribute__((aligned(16))) double rowbuf[64];
+        for (int e = tid; e < LP * LDW; e += NTHR) W[e] = 0.0;
+        for (int c = tid; c < LP; c += NTHR) perm[c] = c;
         __syncthreads();
+        if (wave == 0) {
+            const int i = lane;
+            const bool live = i < l;
+            double a[LP];  // row i of the Schur complement, original column order
+#pragma unroll
+            for (int k = 0; k < LP; ++k) a[k] = (live && k < l) ? G[i * LP + k] : 0.0;
+            double dg = live ? G[i * LP + i] : 0.0;
+            const double thr = (double)LP * 0x1.0p-53 * wave_max(live ? dg : 0.0);
+            bool done = !live;
+            int rank = l;
+            for (int j = 0; j < l; ++j) {
+                const double v = done ? -1.0 : dg;
+                const double vmax = wave_max(v);
+                if (!(vmax > thr)) {  // remaining Schur complement negligible (or not finite)
+                    rank = j;
+                    break;
+                }
+                const int pv = __ffsll((unsigned long long)__ballot(!done && v == vmax)) - 1;
+                if (i == pv) {
+#pragma unroll
+                    for (int k = 0; k < LP; ++k) rowbuf[k] = a[k];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                const double app = rowbuf[pv];
+                const double inv = rsqrt_nr(app), ljj = app * inv;
+                double lij = done ? 0.0 : rowbuf[i] * inv;
+                if (i == pv) {
+                    lij = ljj;
+                    done = true;
+                }
+                if (i < LP) W[j * LDW + i] = lij;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (!done) {
+#pragma unroll
+                    for (int k = 0; k < LP; ++k) a[k] -= lij * W[j * LDW + k];
+                    dg -= lij * lij;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            }
+            if (lane == 0) s_rank = rank;
+        }
+        __syncthreads();
+    } else {
+        __shared__ double s_val[NTHR / 64];
+        __shared__ int s_idx[NTHR / 64];
+        __shared__ int s_piv;
+        __shared__ double s_dmax;
+        for (int e = tid; e < LP * LP; e += NTHR) {
+            const int c = e / LP, row = e % LP;
+            W[c * LDW + row] = (c < l && row < l) ? G[row * LP + c] : 0.0;
+        }
+        for (int c = tid; c < LP; c += NTHR) perm[c] = c;
         if (tid == 0) {
-            double v = s_val[0];
-            int ix = s_idx[0];
-            for (int w = 1; w < NTHR / 64; ++w)
-                if (s_val[w] > v || (s_val[w] == v && s_idx[w] < ix)) { v = s_val[w]; ix = s_idx[w]; }
-            s_piv = ix;
-            if (!(v > thr)) s_rank = j;  // remaining Schur complement negligible (or not finite)
+            double dm = 0.0;
+            for (int i = 0; i < l; ++i) dm = fmax(dm, G[i * LP + i]);
+            s_dmax = dm;
+            s_rank = l;
         }
         __syncthreads();
-        if (s_rank == j) break;
-        const int pv = s_piv;
-        if (pv != j) {  // symmetric swap of rows and columns j and pv
-            for (int k = tid; k < LP; k += NTHR) {
-                const double a = W[k * LDW + j];
-                W[k * LDW + j] = W[k * LDW + pv];
-                W[k * LDW + pv] = a;
+        const double thr = (double)LP * 0x1.0p-53 * s_dmax;
+        // diagonally pivoted Cholesky (right-looking, full symmetric storage)
+        for (int j = 0; j < l; ++j) {
+            // pivot: largest remaining diagonal entry, lowest index on ties
+            double bv = -1.0;
+            int bi = LP;
+            for (int i = j + tid; i < l; i += NTHR) {
+                const double v = W[i * LDW + i];
+                if (v > bv) { bv = v; bi = i; }
             }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = shfl_xor_d(bv, off);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if (lane == 0) { s_val[wave] = bv; s_idx[wave] = bi; }
             __syncthreads();
-            for (int k = tid; k < LP; k += NTHR) {
-                const double a = W[j * LDW + k];
-                W[j * LDW + k] = W[pv * LDW + k];
-                W[pv * LDW + k] = a;
-            }
             if (tid == 0) {
-                const int t = perm[j];
-                perm[j] = perm[pv];
-                perm[pv] = t;
+                double v = s_val[0];
+                int ix = s_idx[0];
+                for (int w = 1; w < NTHR / 64; ++w)
+                    if (s_val[w] > v || (s_val[w] == v && s_idx[w] < ix)) { v = s_val[w]; ix = s_idx[w]; }
+                s_piv = ix;
+                if (!(v > thr)) s_rank = j;
+            }
+            __syncthreads();
+            if (s_rank == j) break;
+            const int pv = s_piv;
+            if (pv != j) {  // symmetric swap of rows and columns j and pv
+                for (int k = tid; k < LP; k += NTHR) {
+                    const double a = W[k * LDW + j];
+                    W[k * LDW + j] = W[k * LDW + pv];
+                    W[k * LDW + pv] = a;
+                }
+                __syncthreads();
+                for (int k = tid; k < LP; k += NTHR) {
+                    const double a = W[j * LDW + k];
+                    W[j * LDW + k] = W[pv * LDW + k];
+                    W[pv * LDW + k] = a;
+                }
+                if (tid == 0) {
+                    const int t = perm[j];
+                    perm[j] = perm[pv];
+                    perm[pv] = t;
+                }
+                __syncthreads();
+            }
+            const double ljj = sqrt(W[j * LDW + j]);
+            const double inv = 1.0 / ljj;
+            __syncthreads();
+            for (int i = j + 1 + tid; i < l; i += NTHR) W[j * LDW + i] *= inv;   // column j below the diagonal
+            if (tid == 0) W[j * LDW + j] = ljj;
+            __syncthreads();
+            // trailing update, both triangles: A[i][k] -= L[i][j] L[k][j]
+            const int nt = l - j - 1;
+            for (int e = tid; e < nt * nt; e += NTHR) {
+                const int k = j + 1 + e / nt, i = j + 1 + e % nt;
+                W[k * LDW + i] -= W[j * LDW + i] * W[j * LDW + k];
             }
             __syncthreads();
         }
-        const double ljj = sqrt(W[j * LDW + j]);
-        const double inv = 1.0 / ljj;
-        __syncthreads();
-        for (int i = j + 1 + tid; i < l; i += NTHR) W[j * LDW + i] *= inv;   // column j below the diagonal
-        if (tid == 0) W[j * LDW + j] = ljj;
-        __syncthreads();
-        // trailing update, both triangles (later symmetric swaps move whole
-        // rows and columns): A[i][k] -= L[i][j] L[k][j], j < i, k < l
-        const int nt = l - j - 1;
-        for (int e = tid; e < nt * nt; e += NTHR) {
-            const int k = j + 1 + e / nt, i = j + 1 + e % nt;
-            W[k * LDW + i] -= W[j * LDW + i] * W[j * LDW + k];
+        // L: lower triangle of the first `rank` columns; everything else zero
+        const int rank = s_rank;
+        for (int e = tid; e < LP * LP; e += NTHR) {
+            const int c = e / LP, row = e % LP;
+            if (c >= rank || row < c || row >= l) W[c * LDW + row] = 0.0;
         }
         __syncthreads();
     }
-    const int rank = s_rank;
-    // L: lower triangle of the first `rank` columns; everything else zero
-    for (int e = tid; e < LP * LP; e += NTHR) {
-        const int c = e / LP, row = e % LP;
-        if (c >= rank || row < c || row >= l) W[c * LDW + row] = 0.0;
-    }
-    __syncthreads();
-    // ---- one-sided Jacobi on the columns of L ----
+    // ---- one-sided Jacobi on the columns ----
     const int pr = tid / TPP, sub = tid % TPP;
     int sweep = 0;
     constexpr int max_sweeps = 40;
@@ -698,33 +798,38 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
                 p = q;
                 q = t;
             }
-            double wp[RPT], wq[RPT];
+            // lane sub: rows 16 k + 2 sub, 16 k + 2 sub + 1 (k < RPT / 2)
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            d2 wp[RPT / 2], wq[RPT / 2];
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                wp[r] = W[p * LDW + sub + r * TPP];
-                wq[r] = W[q * LDW + sub + r * TPP];
+            for (int k = 0; k < RPT / 2; ++k) {
+                wp[k] = *reinterpret_cast<const d2*>(W + p * LDW + 16 * k + 2 * sub);
+                wq[k] = *reinterpret_cast<const d2*>(W + q * LDW + 16 * k + 2 * sub);
             }
             double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                al += wp[r] * wp[r];
-                be += wq[r] * wq[r];
-                ga += wp[r] * wq[r];
-            }
+            for (int k = 0; k < RPT / 2; ++k)
 #pragma unroll
-            for (int off = TPP / 2; off > 0; off >>= 1) {
-                al += shfl_xor_d(al, off);
-                be += shfl_xor_d(be, off);
-                ga += shfl_xor_d(ga, off);
-            }
-            if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                const double zeta = (be - al) / (2.0 * ga);
-                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int h = 0; h < 2; ++h) {
+                    al += wp[k][h] * wp[k][h];
+                    be += wq[k][h] * wq[k][h];
+                    ga += wp[k][h] * wq[k][h];
+                }
+            al = sum8(al);
+            be = sum8(be);
+            ga = sum8(ga);
+            if (al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {  // |ga| > tol sqrt(al be)
+                // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga), written as
+                // t = sign(zeta) |2 ga| / (|be - al| + sqrt((be - al)^2 + (2 ga)^2)); c = 1 / sqrt(1 + t^2)
+                const double d = be - al, e2 = 2.0 * ga;
+                const double sg = (d == 0.0 || ((d > 0.0) == (e2 > 0.0))) ? 1.0 : -1.0;
+                const double h2 = fma(d, d, e2 * e2);
+                const double t = sg * fabs(e2) * rcp_nr(fabs(d) + h2 * rsqrt_nr(h2));
+                const double c = rsqrt_nr(fma(t, t, 1.0)), s = c * t;
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    W[p * LDW + sub + r * TPP] = c * wp[r] - s * wq[r];
-                    W[q * LDW + sub + r * TPP] = s * wp[r] + c * wq[r];
+                for (int k = 0; k < RPT / 2; ++k) {
+                    *reinterpret_cast<d2*>(W + p * LDW + 16 * k + 2 * sub) = c * wp[k] - s * wq[k];
+                    *reinterpret_cast<d2*>(W + q * LDW + 16 * k + 2 * sub) = s * wp[k] + c * wq[k];
                 }
                 if (sub == 0) s_rot = 1;
             }

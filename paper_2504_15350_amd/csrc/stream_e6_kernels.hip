@@ -221,13 +221,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
 // the next step's blocks are loaded into registers during the matrix-core
 // work. Lane (r, g) reads rows 8 g .. 8 g + 7 of its S column (the A
 // operand, split in registers) and of each Q column part (the B operand).
+// Columns are stored unpadded with their 16-byte chunks XOR-swizzled (S
+// column c: chunk k at k ^ ((c / 2) mod 8); Q column c: chunk k at
+// k ^ ((c / 4) mod 4)), which keeps both the staging writes and the operand
+// reads free of bank conflicts for every 16 lanes.
 // Splits interleaved in units of 64 rows (one 128-byte line of a Q part):
 // unit k of split s covers rows 64 (k nsplit + s) .. + 63, two steps.
 // Tiles go to the XCDs (workgroup b runs on XCD b mod 8) so that each XCD
 // holds every column block of its splits: the Q rows of a split are then
 // fetched into one L2 only.
 // ---------------------------------------------------------------------------
-constexpr int E6_R = 32, E6_LDS = E6_R + 4, E6_LDQ = E6_R + 8, E6_HB = 256;
+constexpr int E6_R = 32, E6_LDS = E6_R, E6_LDQ = E6_R, E6_HB = 256;
 
 template <int NT, bool VEC>
 __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, int64_t ldS, int64_t m, int64_t n,
@@ -273,16 +277,17 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
             }
         }
     };
+    static_assert(CPC == 8 && QCPC == 4, "swizzle patterns assume 32-row steps");
     auto put = [&]() {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
-            const int ch = tid + 256 * q;
-            *reinterpret_cast<f32x4*>(ss + (ch / CPC) * LD + 4 * (ch % CPC)) = sr[q];
+            const int ch = tid + 256 * q, col = ch / CPC;
+            *reinterpret_cast<f32x4*>(ss + col * LD + 4 * ((ch % CPC) ^ ((col >> 1) & 7))) = sr[q];
         }
 #pragma unroll
         for (int q = 0; q < QPT; ++q) {
-            const int ch = tid + 256 * q;
-            if (ch < QCH) *reinterpret_cast<e6_u16x8*>(qs + (ch / QCPC) * LDQ + 8 * (ch % QCPC)) = qr[q];
+            const int ch = tid + 256 * q, col = ch / QCPC;
+            if (ch < QCH) *reinterpret_cast<e6_u16x8*>(qs + col * LDQ + 8 * ((ch % QCPC) ^ ((col >> 2) & 3))) = qr[q];
         }
     };
     if (ib < m) fetch(ib);
@@ -294,13 +299,15 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
         e6_u16x8 ah[U], am[U], al[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const float* src = ss + (16 * U * wave + 16 * u + r16) * LD + 8 * g;
-            split8(*reinterpret_cast<const f32x4*>(src), *reinterpret_cast<const f32x4*>(src + 4), ah[u], am[u],
-                   al[u]);
+            const int col = 16 * U * wave + 16 * u + r16, sw = (col >> 1) & 7;
+            const float* src = ss + col * LD;
+            split8(*reinterpret_cast<const f32x4*>(src + 4 * ((2 * g) ^ sw)),
+                   *reinterpret_cast<const f32x4*>(src + 4 * ((2 * g + 1) ^ sw)), ah[u], am[u], al[u]);
         }
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            const int o = (16 * c + r16) * LDQ + 8 * g;
+            const int col = 16 * c + r16;
+            const int o = col * LDQ + 8 * (g ^ ((col >> 2) & 3));
             const e6_u16x8 bh = *reinterpret_cast<const e6_u16x8*>(qs + o);
             const e6_u16x8 bm = *reinterpret_cast<const e6_u16x8*>(qs + 16 * NT * LDQ + o);
             const e6_u16x8 bl = *reinterpret_cast<const e6_u16x8*>(qs + 2 * 16 * NT * LDQ + o);
