@@ -454,19 +454,7 @@ __device__ __forceinline__ double rcp_nr(double x) {
     return y;
 }
 
-// ---------------------------------------------------------------------------
-// The same factorisation and inverse for lp = LP <= 64 in one wave, without
-// LDS or barriers. Lane j keeps column j of the upper triangle in registers
-// (w[i] = A[i][j], i <= j; row i of G read coalesced) and its diagonal
-// G[j][j]. Step k: the pivot d is read from lane k, lanes j >= k scale their
-// w[k] by 1 / sqrt(d) (refined hardware estimate) into R[k][j], and the
-// trailing update w[i] -= R[k][i] R[k][j] takes R[k][i] from lane i by
-// v_readlane (the update order of the workgroup version). The inverse is formed by rows: lane t
-// solves x^T R = e_t^T by forward substitution,
-//   x[c] = (delta_tc - sum_{k<c} x[k] R[k][c]) / R[c][c] (refined reciprocal),
-// R[k][c] read from lane c, and stores row t of R^-1 (coalesced
-// column-major stores).
-// ---------------------------------------------------------------------------
+// v of lane `lane` (wave-uniform lane index), as a uniform value.
 __device__ __forceinline__ double read_lane(double v, int lane) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
@@ -474,105 +462,182 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-template <int LP>
-__global__ __launch_bounds__(64) void k_chol_wave(Group<CholArgs> gr) {
-    const CholArgs& a = gr.args[blockIdx.x];  // one wave per matrix
-    const int j = threadIdx.x;
+// ---------------------------------------------------------------------------
+// Blocked version for lp = 16 NB <= 64 with NB waves: lane j of wave p keeps
+// rows 16 p .. 16 p + 15 of column j in registers. Step k: wave k / 16 reads
+// the pivot from lane k, scales its row k into R[k][:] (1 / sqrt from the
+// refined estimate) and publishes it through LDS (two alternating buffers,
+// one barrier per step); every wave then updates its rows i > k,
+// A[i][j] -= R[k][i] R[k][j] (the update order of the workgroup version).
+// The inverse X = R^-1 is formed by 16 x 16 blocks: the diagonal blocks by
+// forward substitution on rows (lane t: x[c] = (delta_tc - sum_{k<c} x[k]
+// R[k][c]) / R[c][c]), then the blocks at distance d = 1, 2, .. above the
+// diagonal, X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj, one wave per block.
+// Padding rows and columns of R become identity, so X has identity padding.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
+    constexpr int LP = 16 * NB, LDR = LP + 2, NTHR = 64 * NB;
+    __shared__ __attribute__((aligned(16))) double rowb[2][LP];
+    __shared__ __attribute__((aligned(16))) double Rs[LP * LDR];  // R, column-major
+    __shared__ __attribute__((aligned(16))) double Xs[LP * LDR];  // R^-1, column-major
+    __shared__ __attribute__((aligned(16))) double Ts[NB * 256];  // per-wave 16 x 16 scratch
+    __shared__ int s_fail;
+    const CholArgs& a = gr.args[blockIdx.x];  // one workgroup per matrix
+    const int tid = threadIdx.x, j = tid & 63, wave = tid >> 6;
     const int l = a.l, lp = a.lp;
     const double* __restrict__ G = a.G;
     if (a.mode == 2 && !(*a.local & DEV_FLAG_SHIFTED)) return;
-    if (a.mode == 0 && j == 0) *a.local = 0;
+    if (a.mode == 0 && tid == 0) *a.local = 0;
 
-    double w[LP];
+    const bool colv = j < LP;
+    double w[16];  // A[16 wave + r][j]
     bool fin = true;
 #pragma unroll
-    for (int i = 0; i < LP; ++i) {
-        w[i] = (j < LP) ? G[i * lp + j] : 0.0;
-        fin = fin && isfinite(w[i]);
+    for (int r = 0; r < 16; ++r) {
+        w[r] = colv ? G[(16 * wave + r) * lp + j] : 0.0;
+        fin = fin && isfinite(w[r]);
     }
-    const double gd = (j < LP) ? G[j * lp + j] : 0.0;  // G[j][j]
-    bool ok = __all(fin);
-    if (!ok && j == 0) atomicOr(a.flags, DEV_FLAG_NONFINITE);
+    const double gd = colv ? G[j * lp + j] : 0.0;
+    bool ok = __syncthreads_and(fin) != 0;
+    if (!ok && tid == 0) atomicOr(a.flags, DEV_FLAG_NONFINITE);
     if (ok) {
+#pragma unroll 1
         for (int attempt = 0; attempt < 2; ++attempt) {
             if (attempt == 1) {
                 double tr = 0.0;
-                for (int k = 0; k < l; ++k) tr += read_lane(gd, k);
+                for (int k = 0; k < l; ++k) tr += G[k * lp + k];
                 const double shift = 11.0 * ((double)a.M * l + (double)l * (l + 1)) * 0x1.0p-53 * tr;
 #pragma unroll
-                for (int i = 0; i < LP; ++i) w[i] = ((j < LP) ? G[i * lp + j] : 0.0) + (i == j ? shift : 0.0);
+                for (int r = 0; r < 16; ++r)
+                    w[r] = (colv ? G[(16 * wave + r) * lp + j] : 0.0) + (16 * wave + r == j ? shift : 0.0);
             }
+            if (tid == 0) s_fail = 0;
+            __syncthreads();
             bool fail = false;
 #pragma unroll
             for (int k = 0; k < LP; ++k) {
-                if (k < l && !fail) {
-                    const double d = read_lane(w[k], k);
+                if (k >= l) break;
+                const int kk = k & 15, pw = k >> 4;
+                double* rb = rowb[k & 1];
+                if (wave == pw) {
+                    const double d = read_lane(w[kk], k);
                     const double tol = (double)l * 0x1.0p-52 * read_lane(gd, k);
-                    if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot (uniform)
-                        fail = true;
+                    if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot
+                        if (j == 0) s_fail = 1;
                     } else {
-                        const double rinv = rsqrt_nr(d);
-                        if (j >= k) w[k] *= rinv;  // row k of R
-                        // rows i >= l are padding: updated too, never read
-#pragma unroll
-                        for (int i = k + 1; i < LP; ++i) w[i] -= read_lane(w[k], i) * w[k];
+                        const double v = (j >= k) ? w[kk] * rsqrt_nr(d) : 0.0;  // R[k][j]
+                        w[kk] = v;
+                        if (colv) rb[j] = v;
                     }
                 }
+                __syncthreads();
+                if (s_fail) {
+                    fail = true;
+                    break;
+                }
+                const double rkj = colv ? rb[j] : 0.0;
+                if (wave == pw) {
+#pragma unroll
+                    for (int r = kk + 1; r < 16; ++r) w[r] -= rb[16 * pw + r] * rkj;
+                } else if (wave > pw) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) w[r] -= rb[16 * wave + r] * rkj;
+                }
             }
+            __syncthreads();  // every thread has read s_fail
             if (!fail) break;
             if (attempt == 0) {
-                if (j == 0) {
+                if (tid == 0) {
                     atomicOr(a.flags, DEV_FLAG_SHIFTED);
                     *a.local |= DEV_FLAG_SHIFTED;
                 }
             } else {
-                if (j == 0) atomicOr(a.flags, DEV_FLAG_BREAKDOWN);
+                if (tid == 0) atomicOr(a.flags, DEV_FLAG_BREAKDOWN);
                 ok = false;
             }
         }
     }
     if (ok) {
-        double x[LP];  // row j of R^-1
+        // R with identity padding and zero lower part
+        if (colv) {
 #pragma unroll
-        for (int c = 0; c < LP; ++c) {
-            if (c < l) {
-                // two partial sums shorten the dependent chain
+            for (int r = 0; r < 16; ++r) {
+                const int i = 16 * wave + r;
+                const double v = (i < l && j < l) ? ((i <= j) ? w[r] : 0.0) : (i == j ? 1.0 : 0.0);
+                Rs[j * LDR + i] = v;
+            }
+        }
+        __syncthreads();
+        if (j < 16) {  // diagonal block of wave p: lane t = row t
+            const int o = 16 * wave;
+            double x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
                 double s0 = (c == j) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
                 for (int k = 0; k < c; ++k) {
-                    const double rkc = read_lane(w[k], c);
+                    const double rkc = Rs[(o + c) * LDR + o + k];
                     if (k & 1) s1 -= x[k] * rkc;
                     else s0 -= x[k] * rkc;
                 }
-                x[c] = (s0 + s1) * rcp_nr(read_lane(w[c], c));
-            } else {
-                x[c] = (c == j) ? 1.0 : 0.0;  // padding: identity
+                x[c] = (s0 + s1) * rcp_nr(Rs[(o + c) * LDR + o + c]);
             }
-        }
-        if (j < LP) {
 #pragma unroll
-            for (int c = 0; c < LP; ++c) {
-                const double v = (j >= l && c < l) ? 0.0 : x[c];
-                a.R64[c * lp + j] = v;
-                a.R32[c * lp + j] = (float)v;
+            for (int c = 0; c < 16; ++c) Xs[(o + c) * LDR + o + j] = x[c];
+        }
+        __syncthreads();
+        const int r = j & 15, cq = j >> 4;  // lane: row r, columns 4 cq .. 4 cq + 3 of a block
+        for (int d = 1; d < NB; ++d) {
+            const int ib = wave, jb = wave + d;
+            if (jb < NB) {
+                double tv[4] = {0.0, 0.0, 0.0, 0.0};  // T = sum_{kb=ib+1..jb} R_{ib,kb} X_{kb,jb}
+                for (int kb = ib + 1; kb <= jb; ++kb) {
+#pragma unroll
+                    for (int m = 0; m < 16; ++m) {
+                        const double rv = Rs[(16 * kb + m) * LDR + 16 * ib + r];
+#pragma unroll
+                        for (int cc = 0; cc < 4; ++cc)
+                            tv[cc] = fma(rv, Xs[(16 * jb + 4 * cq + cc) * LDR + 16 * kb + m], tv[cc]);
+                    }
+                }
+                double* T = Ts + 256 * wave;
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) T[(4 * cq + cc) * 16 + r] = tv[cc];
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                double xv[4] = {0.0, 0.0, 0.0, 0.0};  // X_{ib,jb} = -X_{ib,ib} T
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    const double xim = Xs[(16 * ib + m) * LDR + 16 * ib + r];
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) xv[cc] = fma(-xim, T[(4 * cq + cc) * 16 + m], xv[cc]);
+                }
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) Xs[(16 * jb + 4 * cq + cc) * LDR + 16 * ib + r] = xv[cc];
             }
+            __syncthreads();
         }
-    } else if (j < LP) {
-#pragma unroll
-        for (int c = 0; c < LP; ++c) {
-            const double v = (c == j) ? 1.0 : 0.0;
-            a.R64[c * lp + j] = v;
-            a.R32[c * lp + j] = (float)v;
+        for (int e = tid; e < LP * LP; e += NTHR) {
+            const int t = e % LP, c = e / LP;
+            const double v = ((t >> 4) <= (c >> 4)) ? Xs[c * LDR + t] : 0.0;
+            a.R64[e] = v;
+            a.R32[e] = (float)v;
+        }
+    } else {
+        for (int e = tid; e < LP * LP; e += NTHR) {
+            const double v = (e % LP == e / LP) ? 1.0 : 0.0;
+            a.R64[e] = v;
+            a.R32[e] = (float)v;
         }
     }
 }
 
 hipError_t launch_chol_inv(int lp, const GroupLaunch<CholArgs>& L, hipStream_t st) {
     switch (lp) {
-        case 16: hipLaunchKernelGGL(k_chol_wave<16>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
-        case 32: hipLaunchKernelGGL(k_chol_wave<32>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
-        case 48: hipLaunchKernelGGL(k_chol_wave<48>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
-        case 64: hipLaunchKernelGGL(k_chol_wave<64>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
+        case 16: hipLaunchKernelGGL(k_chol_blk<1>, dim3(L.count), dim3(64), 0, st, mkg(L)); break;
+        case 32: hipLaunchKernelGGL(k_chol_blk<2>, dim3(L.count), dim3(128), 0, st, mkg(L)); break;
+        case 48: hipLaunchKernelGGL(k_chol_blk<3>, dim3(L.count), dim3(192), 0, st, mkg(L)); break;
+        case 64: hipLaunchKernelGGL(k_chol_blk<4>, dim3(L.count), dim3(256), 0, st, mkg(L)); break;
         default: hipLaunchKernelGGL(k_chol_inv, dim3(L.count), dim3(256), 0, st, mkg(L)); break;
     }
     return hipGetLastError();
