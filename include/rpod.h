@@ -308,9 +308,14 @@ rpod_status rpod_warm_predict(rpod_warm model, const float* mu, int32_t N, float
  * subspace (l = r + p <= 128), q >= 0 subspace iterations after it. A
  * compute call runs Y = [W, S Omega_p] (Omega_p: the first p columns of the
  * sketch of `seed`), CholeskyQR2, q iterations, T = Q^T S and steps 6-7 of
- * Alg. 1, then the residual of the returned modes
- *   rho = max_{k <= r} ||S v_k - sigma_k phi_k|| / sigma_k   (FP64 products);
- * if rho > tol (or the warm run broke down) the plain rPOD with q_fallback
+ * Alg. 1, then the a-posteriori residual of the range basis Q (l columns),
+ * the probabilistic bound of Halko, Martinsson and Tropp (SIAM Review 2011,
+ * Sec. 4.3, eq. 4.3) relative to the largest computed singular value:
+ *   rho = 10 sqrt(2/pi) max_{i <= 16} ||(I - Q Q^T) S w_i|| / sigma_1,
+ * w_i the columns of the sketch of `seed` drawn with counter word 3 = 1 (see
+ * rpod_generate_omega), S w_i with FP64 products; rho bounds
+ * ||S - Q Q^T S|| / sigma_1 from above with probability >= 1 - 10^-16.
+ * If rho > tol (or the warm run broke down) the plain rPOD with q_fallback
  * iterations and the full sketch of `seed` recomputes the outputs. The model
  * must outlive the plan; its weights and bank are read at every call. */
 rpod_status rpod_workspace_size_warm(const rpod_desc* desc, rpod_warm model, int32_t q_fallback, size_t* bytes);

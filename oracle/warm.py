@@ -25,8 +25,14 @@ Predicted subspace: W = P(c)^j Phi_k*, k* = argmax c (lowest index on ties):
 Warm rPOD: Y = [W, S Omega_p] (Omega_p the first p columns of the Gaussian
   sketch), Q = orth(Y), q subspace iterations as in Alg. 1 (stable form),
   then steps 5-7 of Alg. 1 and the coefficients.
-Residual of the returned modes: rho = max_k ||S v_k - sigma_k phi_k|| / sigma_k,
-  zero for an exact singular triplet.
+A-posteriori residual of the range basis Q (l orthonormal columns): the
+  probabilistic bound of Halko, Martinsson and Tropp (SIAM Review 2011,
+  Sec. 4.3, eq. 4.3), ||(I - Q Q^T) S|| <= 10 sqrt(2/pi) max_i ||(I - Q Q^T)
+  S w_i|| with probability at least 1 - 10^-d for d independent standard
+  Gaussian probes w_i, taken relative to sigma_1:
+  rho = 10 sqrt(2/pi) max_i ||(I - Q Q^T) S w_i|| / sigma_1.
+  The probes are the columns of the Philox sketch of the same seed drawn
+  with counter word 3 = 1 (stream 1), independent of the sketch itself.
 """
 
 import numpy as np
@@ -137,15 +143,20 @@ def assemble(GW, c, kstar, r, j=2):
     return Z
 
 
-def residual(S, Phi, sigma, Vt):
-    """max_k ||S v_k - sigma_k phi_k|| / sigma_k over the returned modes."""
-    SV = s_times(S, np.asarray(Vt).T)
-    R = SV - Phi * sigma[None, :]
-    return float(np.max(np.linalg.norm(R, axis=0) / sigma))
+PROBES = 16                        # d, the number of Gaussian probes
+HMT_FACTOR = 10.0 * np.sqrt(2.0 / np.pi)
 
 
-def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2):
-    """Warm-started rPOD; returns (Phi, sigma, A, extras) with extras['rho']."""
+def probe_residual(S, Q, sigma1, probes):
+    """rho = 10 sqrt(2/pi) max_i ||(I - Q Q^T) S w_i|| / sigma_1 (HMT 2011, eq. 4.3)."""
+    Y = s_times(S, np.asarray(probes, dtype=np.float64))
+    R = Y - Q @ (Q.T @ Y)
+    return float(HMT_FACTOR * np.max(np.linalg.norm(R, axis=0)) / sigma1)
+
+
+def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2, probes=None):
+    """Warm-started rPOD; returns (Phi, sigma, A, extras); extras['rho'] is the
+    probe residual of the final range basis when `probes` is given."""
     Phi_b = np.hstack([np.asarray(b, dtype=np.float64) for b in bases])
     Z = assemble(Phi_b.T @ Phi_b, c, kstar, r, j)
     W = Phi_b @ Z
@@ -155,6 +166,7 @@ def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2):
         Zs = _orth(st_times(S, Q))
         Q = _orth(s_times(S, Zs))
     Phi, s, A, ex = _finish(S, Q, r, 65536)
-    ex["rho"] = residual(S, Phi, s, ex["Vt_r"])
+    if probes is not None:
+        ex["rho"] = probe_residual(S, Q, s[0], probes)
     ex["W"] = W
     return Phi, s, A, ex

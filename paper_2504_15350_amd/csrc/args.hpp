@@ -122,6 +122,7 @@ struct OmegaArgs {  // Gaussian sketch; seed from call table entry `call` (or `s
     int64_t n, rows_pad, ldo;
     uint64_t seed;
     int l, lpad, call;
+    uint32_t stream;  // counter word 3 (0: the sketch, 1: the residual probes)
 };
 
 struct SplitArgs {  // 16-bit hi/lo split
@@ -153,31 +154,23 @@ struct WarmZArgs {  // coordinates Z of the predicted subspace in the bank, FP32
     int r, Kr, lp, iters;
 };
 
-struct VscaleArgs {  // Xv[:, k] = At[:, k] / sig[k] (k < r), zero elsewhere
-    const double* At;
-    int64_t ldA, n, nP;
-    const double* sig;
-    double* Xv;
-    int r, rp;
+struct ProbeResArgs {  // per row chunk: sums over rows of (Y[:, i] - (Q1 M)[:, i])^2, i < d
+    const double* Y;      // m x d (ldY)
+    int64_t ldY, m;
+    const float* Q1;      // m x lp (ldQ)
+    int64_t ldQ;
+    const double* M;      // lp x d (ld lp)
+    double* part;         // nchunk x d
+    int lp, d;
 };
 
-struct ResidArgs {  // per (mode, row chunk) partial sums of ||Yres_k - sig_k Phi_k||^2
-    const double* Yres;
-    int64_t ldY, m, chunk;
-    const void* Phi;    // FP32 or FP64 (tphi)
-    int64_t ldP;
-    const double* sig;
-    double* part;
-    int r, nchunk;
-};
-
-struct ResidFinalArgs {
+struct ProbeFinalArgs {  // rho = factor max_i sqrt(sum of part[:, i]) / sig[0]
     const double* part;
     const double* sig;
     double* rho;
     int* flags;
     double tol;
-    int r, nchunk;
+    int d, nchunk;
 };
 
 // Workgroup -> (item, local tile) for grouped launches.

@@ -181,15 +181,19 @@ hipError_t launch_gather_cols(double* G, int Kr, int c0, int ncol, const double*
 hipError_t launch_block_sumsq(const double* src, int64_t sa, int64_t sb, int r, int KA, int KB, double* out,
                               hipStream_t st);
 // Plan steps (grouped): network forward of the call's parameter vector, the
-// predicted subspace's coordinates (tiles: lp ceil(ldX / 64) per matrix, iters <= 2), the scaled right
-// vectors (tiles: ceil(nP rp / 256)), the residual partials (tiles: r x
-// nchunk) and the residual rho = max_k ||S v_k - sigma_k phi_k|| / sigma_k
-// (one workgroup per matrix; DEV_FLAG_RESIDUAL when rho > tol).
+// predicted subspace's coordinates (tiles: lp ceil(ldX / 64) per matrix,
+// iters <= 2), and the a-posteriori residual of the range basis: per 256-row
+// chunk the squared norms of Y - Q1 M for the d <= WARM_PROBES probe columns
+// (tiles: ceil(m / 256)), then rho = WARM_HMT_FACTOR max_i ||(Y - Q1 M)[:, i]||
+// / sig[0] (one workgroup per matrix; DEV_FLAG_RESIDUAL when rho > tol or
+// not finite). lp <= WARM_MAXLP.
+constexpr int WARM_PROBES = 16, WARM_MAXLP = 128;
+constexpr int WARM_PROJ_COLS = 256;  // column block of the FP64 S^T Q kernel (holds lp <= 128)
+constexpr double WARM_HMT_FACTOR = 7.978845608028654;  // 10 sqrt(2 / pi)
 hipError_t launch_warm_plan_forward(const GroupLaunch<WarmFwdArgs>& L, hipStream_t st);
 hipError_t launch_warm_z(const GroupLaunch<WarmZArgs>& L, hipStream_t st);
-hipError_t launch_warm_vscale(const GroupLaunch<VscaleArgs>& L, hipStream_t st);
-hipError_t launch_warm_resid(int tphi, const GroupLaunch<ResidArgs>& P, const GroupLaunch<ResidFinalArgs>& F,
-                             hipStream_t st);
+hipError_t launch_warm_probe_res(const GroupLaunch<ProbeResArgs>& P, const GroupLaunch<ProbeFinalArgs>& F,
+                                 hipStream_t st);
 
 // Write count call-table entries from host values (through kernel arguments).
 hipError_t launch_set_calls(CallDesc* table, const CallDesc* host, int count, hipStream_t st);

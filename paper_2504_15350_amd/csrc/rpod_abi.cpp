@@ -165,7 +165,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // Recorded program
 // ---------------------------------------------------------------------------
 enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXE6, K_SX16, K_STQ, K_STQE6, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT,
-            K_SIGNS, K_FIN, K_SPLIT, K_SPLIT3, K_WFWD, K_WZ, K_VSCALE, K_SXW, K_RESID };
+            K_SIGNS, K_FIN, K_SPLIT, K_SPLIT3, K_WFWD, K_WZ, K_SXW, K_PROBE };
 
 struct Step {
     Kind kind;
@@ -233,6 +233,9 @@ struct rpod_plan_s {
     hipGraph_t fb_graph = nullptr;
     hipGraphExec_t fb_exec = nullptr;
     size_t o_warm = 0, w_Xw = 0, w_c = 0, w_kstar = 0, w_Xv = 0, w_Yres = 0, w_part = 0, w_rho = 0;
+    size_t w_pZp = 0, w_pC = 0, w_pM = 0;  // residual probes: split-K slabs, Zw^T W, R^-1 Zw^T W
+    int probe_nsplit = 1;
+    int64_t probe_split_rows = 0;
     int64_t ldXw = 0;
     double tol = 0.0;
     int q_fb = 0;
@@ -608,27 +611,49 @@ struct Recorder {
         pass_stq(true);
         small_from_slabs();
         finish();
-        // residual: Yres = S V_r (FP64 products), then rho
-        Step v{K_VSCALE};
-        B.add(v, std::vector<VscaleArgs>{{P->at<double>(it, L.o_At), L.nP, it.d.n, L.nP, P->at<double>(it, L.o_sig),
-                                          P->wat<double>(P->w_Xv), r, L.rp}},
-              std::vector<int>{(int)((L.nP * L.rp + 255) / 256)});
-        out.push_back(v);
+        // a-posteriori residual of the range basis Q = Q1 R^-1 (Halko, Martinsson
+        // and Tropp 2011, eq. 4.3): d Gaussian probes W (stream 1 of the call's
+        // seed), Y = S W with FP64 products, Q^T Y = Zw^T W (Zw = S^T Q from the
+        // last pass), M = R^-1 Q^T Y, and the norms of Y - Q1 M
+        constexpr int d = WARM_PROBES;
+        double* Xp = P->wat<double>(P->w_Xv);
+        double* Yp = P->wat<double>(P->w_Yres);
+        Step o2{K_OMEGA};
+        o2.tout = DT_F64;
+        OmegaArgs pa{};
+        pa.out = Xp; pa.n = it.d.n; pa.rows_pad = L.nP; pa.ldo = L.nP; pa.seed = 0;
+        pa.l = d; pa.lpad = d; pa.call = it.idx; pa.stream = 1;
+        B.add(o2, std::vector<OmegaArgs>{pa}, std::vector<int>{(int)((L.nP + 255) / 256) * (d / 2)});
+        out.push_back(o2);
         Step w{K_SXW};
-        w.tin = L.tin; w.nt = L.ntr;
+        w.tin = L.tin; w.nt = d / 16;
         w.vec = it.d.ld % (s16 ? 8 : 4) == 0;
-        B.add(w, std::vector<SxArgs>{{nullptr, it.d.ld, it.d.m, it.d.n, P->wat<double>(P->w_Xv), L.nP,
-                                      P->wat<double>(P->w_Yres), L.mP, L.mP, nullptr, 0, it.idx, 0}},
+        B.add(w, std::vector<SxArgs>{{nullptr, it.d.ld, it.d.m, it.d.n, Xp, L.nP, Yp, L.mP, L.mP, nullptr, 0, it.idx, 0}},
               std::vector<int>{(int)(L.mP / 256)});
         out.push_back(w);
-        Step rs{K_RESID};
-        rs.tin = L.tacc;
-        const int64_t chunk = (it.d.m + L.nchunk - 1) / L.nchunk;
-        B.add(rs, std::vector<ResidArgs>{{P->wat<double>(P->w_Yres), L.mP, it.d.m, chunk, P->at<char>(it, L.o_Phi), L.mP,
-                                          P->at<double>(it, L.o_sig), P->wat<double>(P->w_part), r, L.nchunk}},
-              std::vector<int>{r * L.nchunk});
-        B.add(rs, std::vector<ResidFinalArgs>{{P->wat<double>(P->w_part), P->at<double>(it, L.o_sig),
-                                               P->wat<double>(P->w_rho), P->flags(it), P->tol, r, L.nchunk}},
+        Step k{K_STQ};  // C = Zw^T W: FP64 split-K over the n rows, one 256-column block
+        k.tin = DT_F64; k.nt = d / 16; k.vec = true;
+        StqArgs ka{};
+        ka.S = P->at<double>(it, L.o_Zw); ka.ldS = L.nP; ka.m = it.d.n; ka.n = L.lp;
+        ka.Q = Xp; ka.Ql = nullptr; ka.ldQ = L.nP; ka.Zp = P->wat<double>(P->w_pZp); ka.nP = WARM_PROJ_COLS;
+        ka.split_rows = P->probe_split_rows; ka.nsplit = P->probe_nsplit; ka.ncb = 1; ka.call = -1;
+        B.add(k, std::vector<StqArgs>{ka}, std::vector<int>{ka.nsplit});
+        out.push_back(k);
+        Step rd{K_REDUCE};
+        B.add(rd, std::vector<ReduceArgs>{{P->wat<double>(P->w_pZp), (int64_t)WARM_PROJ_COLS * d,
+                                           P->wat<double>(P->w_pC), P->probe_nsplit}},
+              std::vector<int>{(WARM_PROJ_COLS * d + 255) / 256});
+        out.push_back(rd);
+        sx(DT_F64, DT_F64, d / 16, false,
+           std::vector<SxArgs>{{P->at<char>(it, L.o_R64[1]), L.lp, L.lp, L.lp, P->wat<double>(P->w_pC), WARM_PROJ_COLS,
+                                P->wat<double>(P->w_pM), L.lp, L.lp, nullptr, 0, -1}});
+        Step rs{K_PROBE};
+        const int nchunk = (int)((it.d.m + 255) / 256);
+        B.add(rs, std::vector<ProbeResArgs>{{Yp, L.mP, it.d.m, P->at<float>(it, L.o_Q1), L.mP, P->wat<double>(P->w_pM),
+                                             P->wat<double>(P->w_part), L.lp, d}},
+              std::vector<int>{nchunk});
+        B.add(rs, std::vector<ProbeFinalArgs>{{P->wat<double>(P->w_part), P->at<double>(it, L.o_sig),
+                                               P->wat<double>(P->w_rho), P->flags(it), P->tol, d, nchunk}},
               std::vector<int>{1}, true);
         out.push_back(rs);
     }
@@ -680,9 +705,8 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_SPLIT3: return launch_split3(P->gl<SplitArgs>(s, false), st);
         case K_WFWD: return launch_warm_plan_forward(P->gl<WarmFwdArgs>(s, false), st);
         case K_WZ: return launch_warm_z(P->gl<WarmZArgs>(s, false), st);
-        case K_VSCALE: return launch_warm_vscale(P->gl<VscaleArgs>(s, false), st);
         case K_SXW: return launch_sx_wide(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
-        case K_RESID: return launch_warm_resid(s.tin, P->gl<ResidArgs>(s, false), P->gl<ResidFinalArgs>(s, true), st);
+        case K_PROBE: return launch_warm_probe_res(P->gl<ProbeResArgs>(s, false), P->gl<ProbeFinalArgs>(s, true), st);
     }
     return hipErrorInvalidValue;
 }
@@ -955,10 +979,18 @@ size_t warm_region(rpod_plan_s* P) {
     P->w_Xw = take((size_t)P->ldXw * L.lp * 4);
     P->w_c = take(WARM_K * 8);
     P->w_kstar = take(sizeof(int));
-    P->w_Xv = take((size_t)L.nP * L.rp * 8);
-    P->w_Yres = take((size_t)L.mP * L.rp * 8);
-    P->w_part = take((size_t)L.rp * L.nchunk * 8);
+    P->w_Xv = take((size_t)L.nP * WARM_PROBES * 8);
+    P->w_Yres = take((size_t)L.mP * WARM_PROBES * 8);
+    P->w_part = take((size_t)((it.d.m + 255) / 256) * WARM_PROBES * 8);
     P->w_rho = take(8);
+    // split-K of Zw^T W over the n rows: splits of >= 256 rows, at most 64
+    int64_t ns = (it.d.n + 255) / 256;
+    if (ns > 64) ns = 64;
+    P->probe_split_rows = roundup((it.d.n + ns - 1) / ns, 64);
+    P->probe_nsplit = (int)((it.d.n + P->probe_split_rows - 1) / P->probe_split_rows);
+    P->w_pZp = take((size_t)P->probe_nsplit * WARM_PROJ_COLS * WARM_PROBES * 8);
+    P->w_pC = take((size_t)WARM_PROJ_COLS * WARM_PROBES * 8);
+    P->w_pM = take((size_t)L.lp * WARM_PROBES * 8);
     return off;
 }
 

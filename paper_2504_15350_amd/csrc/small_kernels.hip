@@ -68,13 +68,13 @@ hipError_t launch_set_calls(CallDesc* table, const CallDesc* host, int count, hi
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void omega_body(uint64_t seed, int64_t n, int l, int lpad, int64_t rows_pad, GLOBAL T* out,
-                                           int64_t ldo, int64_t bx, int t /* column pair */) {
+                                           int64_t ldo, int64_t bx, int t /* column pair */, uint32_t stream) {
     const int64_t j = bx * blockDim.x + threadIdx.x;
     if (j >= rows_pad) return;
     const int c0 = 2 * t, c1 = 2 * t + 1;
     double g0 = 0.0, g1 = 0.0;
     if (j < n && c0 < l) {
-        const philox_out o = philox4x32_10((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, 0u,
+        const philox_out o = philox4x32_10((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, stream,
                                            (uint32_t)seed, (uint32_t)(seed >> 32));
         const uint64_t a = ((uint64_t)(o.x[0] >> 5) << 26) + (o.x[1] >> 6);
         const uint64_t b = ((uint64_t)(o.x[2] >> 5) << 26) + (o.x[3] >> 6);
@@ -97,12 +97,12 @@ __global__ void k_omega(Group<OmegaArgs> g) {
     const int t = blockIdx.x - g.tstart[it];
     const int nb = (int)((a.rows_pad + 255) / 256);
     const uint64_t seed = a.call >= 0 ? g.calls[a.call].seed : a.seed;
-    omega_body<T>(seed, a.n, a.l, a.lpad, a.rows_pad, gbl((T*)a.out), a.ldo, t % nb, t / nb);
+    omega_body<T>(seed, a.n, a.l, a.lpad, a.rows_pad, gbl((T*)a.out), a.ldo, t % nb, t / nb, a.stream);
 }
 
 template <typename T>
 __global__ void k_omega_direct(uint64_t seed, int64_t n, int l, int64_t ldo, T* out) {
-    omega_body<T>(seed, n, l, l, n, gbl(out), ldo, blockIdx.x, blockIdx.y);
+    omega_body<T>(seed, n, l, l, n, gbl(out), ldo, blockIdx.x, blockIdx.y, 0u);
 }
 
 hipError_t launch_omega(int tout, const GroupLaunch<OmegaArgs>& L, hipStream_t st) {

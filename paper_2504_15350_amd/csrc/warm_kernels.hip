@@ -345,73 +345,71 @@ hipError_t launch_warm_z(const GroupLaunch<WarmZArgs>& L, hipStream_t st) {
     return hipGetLastError();
 }
 
-__global__ void k_warm_vscale(Group<VscaleArgs> g) {
+// A-posteriori residual of the range basis Q = Q1 R^-1 (Halko, Martinsson and
+// Tropp 2011, eq. 4.3): with Y = S W for d Gaussian probes and M = R^-1 Q^T Y,
+// (I - Q Q^T) S W = Y - Q1 M. One thread per row: the d residual entries of
+// the row from its Q1 row and M (staged in LDS), squares summed over the
+// workgroup's 256 rows in a fixed order.
+__global__ __launch_bounds__(256) void k_warm_probe_res(Group<ProbeResArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
-    const VscaleArgs& a = g.args[it];
-    const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
-    if (e >= a.nP * a.rp) return;
-    const int k = (int)(e / a.nP);
-    const int64_t j = e % a.nP;
-    gbl(a.Xv)[e] = (k < a.r && j < a.n) ? gbl(a.At)[(int64_t)k * a.ldA + j] / a.sig[k] : 0.0;
-}
-
-hipError_t launch_warm_vscale(const GroupLaunch<VscaleArgs>& L, hipStream_t st) {
-    hipLaunchKernelGGL(k_warm_vscale, dim3(L.tiles), dim3(256), 0, st, mkw(L));
-    return hipGetLastError();
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_warm_resid(Group<ResidArgs> g) {
-    const int it = group_item(g.tstart, g.count, blockIdx.x);
-    const ResidArgs& a = g.args[it];
-    const int t = blockIdx.x - g.tstart[it];
-    const int k = t / a.nchunk, ch = t % a.nchunk;
-    const int64_t i0 = (int64_t)ch * a.chunk;
-    const int64_t i1 = (i0 + a.chunk < a.m) ? i0 + a.chunk : a.m;
-    const GLOBAL double* Y = gbl(a.Yres) + (int64_t)k * a.ldY;
-    const GLOBAL T* Phi = gbl((const T*)a.Phi) + (int64_t)k * a.ldP;
-    const double s = a.sig[k];
-    double acc = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-        const double d = Y[i] - s * (double)Phi[i];
-        acc += d * d;
+    const ProbeResArgs& a = g.args[it];
+    const int ch = blockIdx.x - g.tstart[it];
+    __shared__ double Ms[WARM_MAXLP * WARM_PROBES];
+    __shared__ double red[WARM_PROBES][256];
+    for (int e = threadIdx.x; e < a.lp * a.d; e += 256) Ms[e] = a.M[e];
+    __syncthreads();
+    const int64_t i = (int64_t)ch * 256 + threadIdx.x;
+    double acc[WARM_PROBES];
+#pragma unroll
+    for (int c = 0; c < WARM_PROBES; ++c) acc[c] = 0.0;
+    if (i < a.m) {
+        const GLOBAL double* Y = gbl(a.Y);
+#pragma unroll
+        for (int c = 0; c < WARM_PROBES; ++c) acc[c] = c < a.d ? Y[(int64_t)c * a.ldY + i] : 0.0;
+        const GLOBAL float* Q = gbl(a.Q1);
+        for (int k = 0; k < a.lp; ++k) {
+            const double q = (double)Q[(int64_t)k * a.ldQ + i];
+#pragma unroll
+            for (int c = 0; c < WARM_PROBES; ++c) acc[c] = fma(-q, Ms[c * a.lp + k], acc[c]);
+        }
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = acc;
+#pragma unroll
+    for (int c = 0; c < WARM_PROBES; ++c) red[c][threadIdx.x] = acc[c] * acc[c];
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        if ((int)threadIdx.x < off) {
+#pragma unroll
+            for (int c = 0; c < WARM_PROBES; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) a.part[(int64_t)k * a.nchunk + ch] = red[0];
+    if ((int)threadIdx.x < a.d) a.part[(int64_t)ch * a.d + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_warm_resid_final(Group<ResidFinalArgs> g) {
-    const ResidFinalArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
-    __shared__ double rk[128];
-    for (int k = threadIdx.x; k < a.r; k += blockDim.x) {
+__global__ void k_warm_probe_final(Group<ProbeFinalArgs> g) {
+    const ProbeFinalArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
+    __shared__ double nr[WARM_PROBES];
+    if ((int)threadIdx.x < a.d) {
         double s = 0.0;
-        for (int ch = 0; ch < a.nchunk; ++ch) s += a.part[(int64_t)k * a.nchunk + ch];
-        rk[k] = sqrt(s) / a.sig[k];
+        for (int ch = 0; ch < a.nchunk; ++ch) s += a.part[(int64_t)ch * a.d + threadIdx.x];
+        nr[threadIdx.x] = sqrt(s);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double rho = 0.0;
-        for (int k = 0; k < a.r; ++k) rho = (rk[k] > rho || rk[k] != rk[k]) ? rk[k] : rho;
+        double mx = 0.0;
+        for (int c = 0; c < a.d; ++c) mx = (nr[c] > mx || nr[c] != nr[c]) ? nr[c] : mx;
+        const double rho = WARM_HMT_FACTOR * mx / a.sig[0];
         *a.rho = rho;
         if (!(rho <= a.tol)) atomicOr(a.flags, DEV_FLAG_RESIDUAL);
     }
 }
 
-hipError_t launch_warm_resid(int tphi, const GroupLaunch<ResidArgs>& P, const GroupLaunch<ResidFinalArgs>& F,
-                             hipStream_t st) {
-    if (tphi == DT_F64)
-        hipLaunchKernelGGL(k_warm_resid<double>, dim3(P.tiles), dim3(256), 0, st, mkw(P));
-    else
-        hipLaunchKernelGGL(k_warm_resid<float>, dim3(P.tiles), dim3(256), 0, st, mkw(P));
+hipError_t launch_warm_probe_res(const GroupLaunch<ProbeResArgs>& P, const GroupLaunch<ProbeFinalArgs>& F,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_warm_probe_res, dim3(P.tiles), dim3(256), 0, st, mkw(P));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_warm_resid_final, dim3(F.count), dim3(128), 0, st, mkw(F));
+    hipLaunchKernelGGL(k_warm_probe_final, dim3(F.count), dim3(64), 0, st, mkw(F));
     return hipGetLastError();
 }
 

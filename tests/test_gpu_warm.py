@@ -179,7 +179,8 @@ def test_training_reduces_the_loss(world):
 def _warm_ref(world, model, i, q, c, kstar):
     S = world["mats"][i]["St"].astype(np.float64).T
     om = philox.gaussian_sketch(1000 + i, N, P).astype(np.float32).astype(np.float64)
-    return ow.warm_rpod(S, bank64(world), c, kstar, R, om, q)
+    probes = philox.gaussian_sketch(1000 + i, N, ow.PROBES, stream=1)
+    return ow.warm_rpod(S, bank64(world), c, kstar, R, om, q, probes=probes)
 
 
 def test_warm_plan_matches_oracle(world):
@@ -206,7 +207,8 @@ def test_warm_plan_matches_oracle(world):
         say(f"[warm] matrix {i} rho {rho:.3e} (oracle {ex['rho']:.3e}) {res}")
         assert res["sigma"] < 1e-5 and res["orth"] < 1e-5
         assert res.get("sin", 0) < 1e-4 and res.get("A", 0) < 1e-4
-        assert abs(rho - ex["rho"]) <= 1e-3 * ex["rho"] + 1e-6
+        # rho from an FP32-accurate basis: absolute error ~ 10 sqrt(2/pi) u_fp32 ||S w|| / sigma_1
+        assert abs(rho - ex["rho"]) <= 1e-3 * ex["rho"] + 1e-5
         checked += 1
     plan.close()
     assert checked >= 3
@@ -226,12 +228,14 @@ def test_forced_fallback_equals_plain_rpod(world):
 
 
 def test_one_hot_on_the_exact_basis_gives_exact_pod(world):
-    """Bank basis 0 = the exact leading basis of a noise-free matrix and a
-    network forced to weight it alone: q = 0 reproduces the exact POD."""
+    """Bank basis 0 = the exact basis of a noise-free rank-r matrix and a
+    network forced to weight it alone: q = 0 reproduces the exact POD, and
+    the range basis spans S, so the residual stays far below the tolerance."""
     fam = world["fam"]
     mu = world["mu"][int(world["test"][1])]
-    d = fam.matrix(mu, N, noise_std=0.0, seed=300, dtype=np.float32)
+    d = fam.matrix(mu, N, noise_std=0.0, seed=300)
     U = d["U"][:, :R]
+    d["St"] = np.ascontiguousarray(((d["V"][:, :R] * d["sigma"][None, :R]) @ U.T).astype(np.float32))
     bases = [torch.from_numpy(np.ascontiguousarray(U.T.astype(np.float32))).to(DEV)]
     bases += [world["bases"][i] for i in world["bank_idx"][1:]]
     model = rp.WarmModel(fam.m, R, max_train=8, seed=1, device=DEV)
