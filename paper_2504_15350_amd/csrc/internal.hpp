@@ -105,8 +105,8 @@ hipError_t launch_gram(int tin, int nt, const GroupLaunch<GramArgs>& L, const Gr
 //   R64 / R32: R^-1, lp x lp column-major.
 //   mode 0: first factorisation of an orthonormalisation (resets *local);
 //   mode 1: unconditional; mode 2: run only if *local has DEV_FLAG_SHIFTED.
-//   lp: the padded size shared by the launch's matrices (lp / 16 waves per
-//   matrix, blocked, for lp <= 64; a workgroup of 256 threads above).
+//   lp: the padded size shared by the launch's matrices (a multiple of 16;
+//   lp / 16 waves per matrix, blocked).
 hipError_t launch_chol_inv(int lp, const GroupLaunch<CholArgs>& L, hipStream_t st);
 
 // Symmetric eigen-decomposition of the lp x lp FP64 Gram matrix G_B = B B^T

@@ -2,11 +2,13 @@
 //
 //   k_omega        Gaussian sketch (Alg. 1 step 1) from Philox4x32-10
 //   k_gram         FP64 Gram matrix Y^T Y of a tall matrix on FP64 MFMA
-//   k_chol_inv     Cholesky + triangular inverse for CholeskyQR (step 4)
+//   k_chol_blk     Cholesky + triangular inverse for CholeskyQR (step 4)
 //   k_jacobi       SVD of the small T of step 6 via the eigenvectors of T T^T
 //                  (pivoted Cholesky, then preconditioned one-sided Jacobi)
 //   k_lift_coef    the small factors of the lift (step 7) and the coefficients
 //   k_colmax/...   deterministic sign convention and output packing
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -310,134 +312,6 @@ hipError_t launch_gram(int tin, int nt, const GroupLaunch<GramArgs>& L, const Gr
     return hipErrorInvalidValue;
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky and triangular inverse, one workgroup of 256 threads, FP64 in LDS.
-// A holds G; the factorisation overwrites its upper triangle with R
-// (G = R^T R). The inverse X = R^-1 is built by Gauss-Jordan elimination
-// from the last column backwards, storing X[i][j] (i < j) transposed in the
-// strict lower triangle of A and its diagonal in xd.
-// ---------------------------------------------------------------------------
-constexpr int LPMAX = 128;
-constexpr int LDA = LPMAX + 1;
-
-__device__ __forceinline__ void chol_body(const double* __restrict__ G, int l, int lp, int64_t M,
-                                          double* __restrict__ Rinv64, float* __restrict__ Rinv32, int* flags,
-                                          int* local, int mode) {
-    __shared__ double A[LPMAX * LDA];
-    __shared__ double xd[LPMAX];
-    __shared__ double gdiag[LPMAX];
-    __shared__ int s_fail, s_nonfinite;
-    __shared__ double s_trace;
-    const int tid = threadIdx.x;
-    const int ti = tid & 15, tj = tid >> 4;  // 16 x 16 thread grid for the 2-D updates
-
-    if (mode == 2 && !(*local & DEV_FLAG_SHIFTED)) return;
-    if (tid == 0) {
-        s_fail = 0;
-        s_nonfinite = 0;
-        if (mode == 0) *local = 0;
-    }
-    __syncthreads();
-    for (int e = tid; e < lp * lp; e += 256) {
-        const double g = G[e];
-        if (!isfinite(g)) s_nonfinite = 1;
-    }
-    __syncthreads();
-    bool ok = (s_nonfinite == 0);
-    if (!ok && tid == 0) atomicOr(flags, DEV_FLAG_NONFINITE);
-
-    if (ok) {
-        if (tid == 0) {
-            double tr = 0.0;
-            for (int k = 0; k < l; ++k) tr += G[k * lp + k];
-            s_trace = tr;
-        }
-        for (int k = tid; k < l; k += 256) gdiag[k] = G[k * lp + k];
-        __syncthreads();
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            const double shift =
-                attempt == 0 ? 0.0 : 11.0 * ((double)M * l + (double)l * (l + 1)) * 0x1.0p-53 * s_trace;
-            for (int i = tj; i < l; i += 16)
-                for (int j = ti; j < l; j += 16) A[i * LDA + j] = G[i * lp + j] + (i == j ? shift : 0.0);
-            if (tid == 0) s_fail = 0;
-            __syncthreads();
-            for (int k = 0; k < l; ++k) {
-                const double d = A[k * LDA + k];
-                const double tol = (double)l * 0x1.0p-52 * gdiag[k];
-                if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot (uniform)
-                    if (tid == 0) s_fail = 1;
-                    break;
-                }
-                const double rinv = 1.0 / sqrt(d);
-                __syncthreads();  // everyone has read the pivot
-                for (int j = k + tid; j < l; j += 256) A[k * LDA + j] *= rinv;  // row k of R
-                __syncthreads();
-                // trailing update of the upper triangle, rows/columns k+1..l-1
-                for (int i = k + 1 + tj; i < l; i += 16) {
-                    const double rki = A[k * LDA + i];
-                    for (int j = i + ((ti - (i - k - 1)) % 16 + 16) % 16; j < l; j += 16)
-                        A[i * LDA + j] -= rki * A[k * LDA + j];
-                }
-                __syncthreads();
-            }
-            __syncthreads();
-            if (!s_fail) break;
-            if (attempt == 0) {
-                if (tid == 0) {
-                    atomicOr(flags, DEV_FLAG_SHIFTED);
-                    *local |= DEV_FLAG_SHIFTED;
-                }
-            } else {
-                if (tid == 0) atomicOr(flags, DEV_FLAG_BREAKDOWN);
-                ok = false;
-            }
-            __syncthreads();
-        }
-    }
-
-    if (ok) {
-        // X = R^-1 by Gauss-Jordan from the last column; X[i][j] (i < j) is
-        // kept transposed in the strict lower triangle of A, X[k][k] in xd
-        for (int i = tj; i < l; i += 16)
-            for (int j = ti; j < i; j += 16) A[i * LDA + j] = 0.0;
-        for (int k = tid; k < l; k += 256) xd[k] = 1.0;
-        __syncthreads();
-        for (int k = l - 1; k >= 0; --k) {
-            const double inv = 1.0 / A[k * LDA + k];
-            if (tid == 0) xd[k] *= inv;
-            for (int j = k + 1 + tid; j < l; j += 256) A[j * LDA + k] *= inv;
-            __syncthreads();
-            // rows i < k, columns j >= k: X[i][j] -= R[i][k] X[k][j]
-            for (int j = k + tj; j < l; j += 16) {
-                const double xkj = (j == k) ? xd[k] : A[j * LDA + k];
-                for (int i = ti; i < k; i += 16) A[j * LDA + i] -= A[i * LDA + k] * xkj;
-            }
-            __syncthreads();
-        }
-        for (int e = tid; e < lp * lp; e += 256) {
-            const int k = e % lp, c = e / lp;  // element (k, c), column-major
-            double v;
-            if (k >= l || c >= l) v = (k == c) ? 1.0 : 0.0;
-            else if (k == c) v = xd[k];
-            else if (k < c) v = A[c * LDA + k];
-            else v = 0.0;
-            Rinv64[e] = v;
-            Rinv32[e] = (float)v;
-        }
-    } else {
-        for (int e = tid; e < lp * lp; e += 256) {
-            const double v = (e % lp == e / lp) ? 1.0 : 0.0;
-            Rinv64[e] = v;
-            Rinv32[e] = (float)v;
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void k_chol_inv(Group<CholArgs> g) {
-    const CholArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
-    chol_body(a.G, a.l, a.lp, a.M, a.R64, a.R32, a.flags, a.local, a.mode);
-}
-
 // 1 / sqrt(x) and 1 / x for x > 0 (finite): the hardware estimates refined by
 // two Newton steps each (the error of the estimate squares at every step).
 __device__ __forceinline__ double rsqrt_nr(double x) {
@@ -463,25 +337,29 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Blocked version for lp = 16 NB <= 64 with NB waves: lane j of wave p keeps
-// rows 16 p .. 16 p + 15 of column j in registers. Step k: wave k / 16 reads
-// the pivot from lane k, scales its row k into R[k][:] (1 / sqrt from the
-// refined estimate) and publishes it through LDS (two alternating buffers,
-// one barrier per step); every wave then updates its rows i > k,
-// A[i][j] -= R[k][i] R[k][j] (the update order of the workgroup version).
+// Blocked version for lp = 16 NB <= 128 with NB waves: lane j of wave p
+// keeps rows 16 p .. 16 p + 15 of columns j and j + 64 (lp > 64) in
+// registers. Step k: wave k / 16 reads the pivot from the lane holding
+// column k, scales its row k into R[k][:] (1 / sqrt from the refined
+// estimate) and publishes it through LDS (two alternating buffers, one
+// barrier per step); every wave then updates its rows i > k,
+// A[i][j] -= R[k][i] R[k][j] (right-looking).
 // The inverse X = R^-1 is formed by 16 x 16 blocks: the diagonal blocks by
 // forward substitution on rows (lane t: x[c] = (delta_tc - sum_{k<c} x[k]
 // R[k][c]) / R[c][c]), then the blocks at distance d = 1, 2, .. above the
-// diagonal, X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj, one wave per block.
+// diagonal, X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj, one wave per block. R and
+// X are kept in LDS as their upper-triangular 16 x 16 blocks only (block
+// (ib, jb), ib <= jb, at jb (jb + 1) / 2 + ib, column-major inside).
 // Padding rows and columns of R become identity, so X has identity padding.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int blk(int ib, int jb) { return (jb * (jb + 1) / 2 + ib) * 256; }  // ib <= jb
+
 template <int NB>
 __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
-    constexpr int LP = 16 * NB, LDR = LP + 2, NTHR = 64 * NB;
+    constexpr int LP = 16 * NB, NTHR = 64 * NB, CPL = (LP + 63) / 64, NTRI = NB * (NB + 1) / 2 * 256;
     __shared__ __attribute__((aligned(16))) double rowb[2][LP];
-    __shared__ __attribute__((aligned(16))) double Rs[LP * LDR];  // R, column-major
-    __shared__ __attribute__((aligned(16))) double Xs[LP * LDR];  // R^-1, column-major
-    __shared__ __attribute__((aligned(16))) double Ts[NB * 256];  // per-wave 16 x 16 scratch
+    __shared__ __attribute__((aligned(16))) double Rs[NTRI];  // R, upper blocks
+    __shared__ __attribute__((aligned(16))) double Xs[NTRI];  // R^-1, upper blocks
     __shared__ int s_fail;
     const CholArgs& a = gr.args[blockIdx.x];  // one workgroup per matrix
     const int tid = threadIdx.x, j = tid & 63, wave = tid >> 6;
@@ -490,15 +368,19 @@ __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
     if (a.mode == 2 && !(*a.local & DEV_FLAG_SHIFTED)) return;
     if (a.mode == 0 && tid == 0) *a.local = 0;
 
-    const bool colv = j < LP;
-    double w[16];  // A[16 wave + r][j]
+    double w[CPL][16];  // A[16 wave + r][j + 64 cc]
+    double gd[CPL];
     bool fin = true;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        w[r] = colv ? G[(16 * wave + r) * lp + j] : 0.0;
-        fin = fin && isfinite(w[r]);
+    for (int cc = 0; cc < CPL; ++cc) {
+        const int col = j + 64 * cc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            w[cc][r] = col < LP ? G[(16 * wave + r) * lp + col] : 0.0;
+            fin = fin && isfinite(w[cc][r]);
+        }
+        gd[cc] = col < LP ? G[col * lp + col] : 0.0;
     }
-    const double gd = colv ? G[j * lp + j] : 0.0;
     bool ok = __syncthreads_and(fin) != 0;
     if (!ok && tid == 0) atomicOr(a.flags, DEV_FLAG_NONFINITE);
     if (ok) {
@@ -509,42 +391,67 @@ __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
                 for (int k = 0; k < l; ++k) tr += G[k * lp + k];
                 const double shift = 11.0 * ((double)a.M * l + (double)l * (l + 1)) * 0x1.0p-53 * tr;
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    w[r] = (colv ? G[(16 * wave + r) * lp + j] : 0.0) + (16 * wave + r == j ? shift : 0.0);
+                for (int cc = 0; cc < CPL; ++cc) {
+                    const int col = j + 64 * cc;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        w[cc][r] = (col < LP ? G[(16 * wave + r) * lp + col] : 0.0) +
+                                   (16 * wave + r == col ? shift : 0.0);
+                }
             }
             if (tid == 0) s_fail = 0;
             __syncthreads();
             bool fail = false;
+            // steps k = 64 kc + 16 pb + kk: kc and kk compile-time (register indices), pb a runtime loop
+            auto steps = [&](auto KC) {
+                constexpr int kc = decltype(KC)::value;
+                for (int pb = 0; pb < 4 && !fail; ++pb) {
+                    const int pw = 4 * kc + pb;  // wave holding rows 16 pw ..
+                    if (pw >= NB || 16 * pw >= l) break;
 #pragma unroll
-            for (int k = 0; k < LP; ++k) {
-                if (k >= l) break;
-                const int kk = k & 15, pw = k >> 4;
-                double* rb = rowb[k & 1];
-                if (wave == pw) {
-                    const double d = read_lane(w[kk], k);
-                    const double tol = (double)l * 0x1.0p-52 * read_lane(gd, k);
-                    if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot
-                        if (j == 0) s_fail = 1;
-                    } else {
-                        const double v = (j >= k) ? w[kk] * rsqrt_nr(d) : 0.0;  // R[k][j]
-                        w[kk] = v;
-                        if (colv) rb[j] = v;
+                    for (int kk = 0; kk < 16; ++kk) {
+                        const int k = 16 * pw + kk, kl = 16 * pb + kk;
+                        if (k >= l || fail) continue;  // uniform; no break, so the loop unrolls
+                        double* rb = rowb[k & 1];
+                        if (wave == pw) {
+                            const double d = read_lane(w[kc][kk], kl);
+                            const double tol = (double)l * 0x1.0p-52 * read_lane(gd[kc], kl);
+                            if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot
+                                if (j == 0) s_fail = 1;
+                            } else {
+                                const double rinv = rsqrt_nr(d);
+#pragma unroll
+                                for (int cc = 0; cc < CPL; ++cc) {
+                                    const int col = j + 64 * cc;
+                                    const double v = (col >= k) ? w[cc][kk] * rinv : 0.0;  // R[k][col]
+                                    w[cc][kk] = v;
+                                    if (col < LP) rb[col] = v;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        if (s_fail) {
+                            fail = true;
+                            continue;
+                        }
+#pragma unroll
+                        for (int cc = 0; cc < CPL; ++cc) {
+                            const int col = j + 64 * cc;
+                            const double rkj = col < LP ? rb[col] : 0.0;
+                            if (wave == pw) {
+#pragma unroll
+                                for (int r = 0; r < 16; ++r)  // fixed trip count: unrolls with static r
+                                    if (r > kk) w[cc][r] -= rb[16 * pw + r] * rkj;
+                            } else if (wave > pw) {
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) w[cc][r] -= rb[16 * wave + r] * rkj;
+                            }
+                        }
                     }
                 }
-                __syncthreads();
-                if (s_fail) {
-                    fail = true;
-                    break;
-                }
-                const double rkj = colv ? rb[j] : 0.0;
-                if (wave == pw) {
-#pragma unroll
-                    for (int r = kk + 1; r < 16; ++r) w[r] -= rb[16 * pw + r] * rkj;
-                } else if (wave > pw) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) w[r] -= rb[16 * wave + r] * rkj;
-                }
-            }
+            };
+            steps(std::integral_constant<int, 0>{});
+            if constexpr (CPL > 1) steps(std::integral_constant<int, 1>{});
             __syncthreads();  // every thread has read s_fail
             if (!fail) break;
             if (attempt == 0) {
@@ -559,32 +466,39 @@ __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
         }
     }
     if (ok) {
-        // R with identity padding and zero lower part
-        if (colv) {
+        // R (upper blocks; lower part of the diagonal blocks zero) with identity padding
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = 16 * wave + r;
-                const double v = (i < l && j < l) ? ((i <= j) ? w[r] : 0.0) : (i == j ? 1.0 : 0.0);
-                Rs[j * LDR + i] = v;
+        for (int cc = 0; cc < CPL; ++cc) {
+            const int col = j + 64 * cc, cb = col >> 4;
+            if (col < LP && wave <= cb) {
+                double* dst = Rs + blk(wave, cb) + (col & 15) * 16;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = 16 * wave + r;
+                    dst[r] = (i <= col) ? ((i < l && col < l) ? w[cc][r] : (i == col ? 1.0 : 0.0)) : 0.0;
+                }
             }
         }
         __syncthreads();
         if (j < 16) {  // diagonal block of wave p: lane t = row t
-            const int o = 16 * wave;
+            const double* Rd = Rs + blk(wave, wave);
             double x[16];
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 double s0 = (c == j) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-                for (int k = 0; k < c; ++k) {
-                    const double rkc = Rs[(o + c) * LDR + o + k];
-                    if (k & 1) s1 -= x[k] * rkc;
-                    else s0 -= x[k] * rkc;
+                for (int k = 0; k < 16; ++k) {
+                    if (k < c) {
+                        const double rkc = Rd[c * 16 + k];
+                        if (k & 1) s1 -= x[k] * rkc;
+                        else s0 -= x[k] * rkc;
+                    }
                 }
-                x[c] = (s0 + s1) * rcp_nr(Rs[(o + c) * LDR + o + c]);
+                x[c] = (s0 + s1) * rcp_nr(Rd[c * 16 + c]);
             }
+            double* Xd = Xs + blk(wave, wave);
 #pragma unroll
-            for (int c = 0; c < 16; ++c) Xs[(o + c) * LDR + o + j] = x[c];
+            for (int c = 0; c < 16; ++c) Xd[c * 16 + j] = x[c];  // zero below the diagonal
         }
         __syncthreads();
         const int r = j & 15, cq = j >> 4;  // lane: row r, columns 4 cq .. 4 cq + 3 of a block
@@ -593,33 +507,37 @@ __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
             if (jb < NB) {
                 double tv[4] = {0.0, 0.0, 0.0, 0.0};  // T = sum_{kb=ib+1..jb} R_{ib,kb} X_{kb,jb}
                 for (int kb = ib + 1; kb <= jb; ++kb) {
+                    const double* Rb = Rs + blk(ib, kb);
+                    const double* Xb = Xs + blk(kb, jb);
 #pragma unroll
                     for (int m = 0; m < 16; ++m) {
-                        const double rv = Rs[(16 * kb + m) * LDR + 16 * ib + r];
+                        const double rv = Rb[m * 16 + r];
 #pragma unroll
-                        for (int cc = 0; cc < 4; ++cc)
-                            tv[cc] = fma(rv, Xs[(16 * jb + 4 * cq + cc) * LDR + 16 * kb + m], tv[cc]);
+                        for (int cc = 0; cc < 4; ++cc) tv[cc] = fma(rv, Xb[(4 * cq + cc) * 16 + m], tv[cc]);
                     }
                 }
-                double* T = Ts + 256 * wave;
+                // T goes through the (still unused) slot of X_{ib,jb}: written, read, then overwritten
+                double* T = Xs + blk(ib, jb);
 #pragma unroll
                 for (int cc = 0; cc < 4; ++cc) T[(4 * cq + cc) * 16 + r] = tv[cc];
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                const double* Xd = Xs + blk(ib, ib);
                 double xv[4] = {0.0, 0.0, 0.0, 0.0};  // X_{ib,jb} = -X_{ib,ib} T
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
-                    const double xim = Xs[(16 * ib + m) * LDR + 16 * ib + r];
+                    const double xim = Xd[m * 16 + r];
 #pragma unroll
                     for (int cc = 0; cc < 4; ++cc) xv[cc] = fma(-xim, T[(4 * cq + cc) * 16 + m], xv[cc]);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) Xs[(16 * jb + 4 * cq + cc) * LDR + 16 * ib + r] = xv[cc];
+                for (int cc = 0; cc < 4; ++cc) T[(4 * cq + cc) * 16 + r] = xv[cc];
             }
             __syncthreads();
         }
         for (int e = tid; e < LP * LP; e += NTHR) {
             const int t = e % LP, c = e / LP;
-            const double v = ((t >> 4) <= (c >> 4)) ? Xs[c * LDR + t] : 0.0;
+            const double v = ((t >> 4) <= (c >> 4)) ? Xs[blk(t >> 4, c >> 4) + (c & 15) * 16 + (t & 15)] : 0.0;
             a.R64[e] = v;
             a.R32[e] = (float)v;
         }
@@ -638,7 +556,11 @@ hipError_t launch_chol_inv(int lp, const GroupLaunch<CholArgs>& L, hipStream_t s
         case 32: hipLaunchKernelGGL(k_chol_blk<2>, dim3(L.count), dim3(128), 0, st, mkg(L)); break;
         case 48: hipLaunchKernelGGL(k_chol_blk<3>, dim3(L.count), dim3(192), 0, st, mkg(L)); break;
         case 64: hipLaunchKernelGGL(k_chol_blk<4>, dim3(L.count), dim3(256), 0, st, mkg(L)); break;
-        default: hipLaunchKernelGGL(k_chol_inv, dim3(L.count), dim3(256), 0, st, mkg(L)); break;
+        case 80: hipLaunchKernelGGL(k_chol_blk<5>, dim3(L.count), dim3(320), 0, st, mkg(L)); break;
+        case 96: hipLaunchKernelGGL(k_chol_blk<6>, dim3(L.count), dim3(384), 0, st, mkg(L)); break;
+        case 112: hipLaunchKernelGGL(k_chol_blk<7>, dim3(L.count), dim3(448), 0, st, mkg(L)); break;
+        case 128: hipLaunchKernelGGL(k_chol_blk<8>, dim3(L.count), dim3(512), 0, st, mkg(L)); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
