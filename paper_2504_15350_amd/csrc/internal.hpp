@@ -86,11 +86,12 @@ hipError_t launch_reduce_slabs(const GroupLaunch<ReduceArgs>& L, hipStream_t st)
 // Gram matrix G = Y^T Y in FP64 of a tall M x 16*nt column-major matrix
 // (ld multiple of 4, zero rows up to roundup(M,16)), type tin (F64/F32).
 // Gpart holds gram_partial_count(nt) doubles; G is lp x lp row-major.
-// L: gram_tiles(nt, nwg) workgroups per matrix (nwg = gram_nwg(M, cap), at
-// most one per 64 rows and at most min(cap, 256)); R: the reduction,
-// gram_reduce_tiles(nt) workgroups per matrix.
+// L: gram_tiles(nt, nwg) workgroups per matrix (nwg = gram_nwg(M, cap, nt),
+// at most one per 64 rows and at most cap; cap 0: about 512 workgroups over
+// the pair groups); R: the reduction, gram_reduce_tiles(nt) workgroups per
+// matrix.
 int64_t gram_partial_count(int nt);
-int gram_nwg(int64_t M, int cap);
+int gram_nwg(int64_t M, int cap, int nt);
 int gram_tiles(int nt, int nwg);
 int gram_reduce_tiles(int nt);
 hipError_t launch_gram(int tin, int nt, const GroupLaunch<GramArgs>& L, const GroupLaunch<GramArgs>& R,

@@ -420,7 +420,7 @@ struct Recorder {
         auto gargs = [&](auto buf, bool cond) {
             return each([&](const Item& it) {
                 return GramArgs{buf(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap)};
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
             });
         };
         auto cargs = [&](int k, int mode) {
@@ -471,7 +471,7 @@ struct Recorder {
             return each([&](const Item& it) {
                 return GramArgs{P->at<char>(it, second ? it.L.o_Zw2 : it.L.o_Zw), it.L.nP, it.d.n,
                                 P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.n, it.L.gram_cap)};
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
             });
         };
         auto app = [&](size_t Layout::*src, size_t Layout::*dst, int k, bool cond) {
@@ -501,7 +501,7 @@ struct Recorder {
         // step 6: SVD of T through the eigenvectors of T T^T
         gram(DT_F64, each([&](const Item& it) {
                  return GramArgs{P->at<char>(it, it.L.o_Zw), it.L.nP, it.d.n, P->at<double>(it, it.L.o_Gpart),
-                                 P->at<double>(it, it.L.o_G), nullptr, 0, gram_nwg(it.d.n, it.L.gram_cap)};
+                                 P->at<double>(it, it.L.o_G), nullptr, 0, gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
              }));
         Step j{K_JACOBI};
         j.lp = L.lp;
@@ -820,7 +820,7 @@ rpod_status batch_layout(const rpod_desc* descs, int32_t count, const rpod_tunin
     if (ts != RPOD_OK) return ts;
     int64_t wg = count == 1 ? 4096 : std::max<int64_t>(256, 8192 / count);
     if (tune && tune->stq_workgroups > 0) wg = tune->stq_workgroups;
-    const int gcap = (tune && tune->gram_workgroups > 0) ? tune->gram_workgroups : 256;
+    const int gcap = (tune && tune->gram_workgroups > 0) ? tune->gram_workgroups : 0;  // 0: automatic
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;

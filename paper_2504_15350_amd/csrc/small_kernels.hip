@@ -162,7 +162,7 @@ hipError_t launch_sketch_bits(uint64_t seed, int64_t n, int l, uint32_t* out, hi
 // pair group of the launch; partials are reduced over the 4 waves in LDS in a
 // fixed order and written per workgroup.
 // ---------------------------------------------------------------------------
-constexpr int GRAM_WGS = 256;
+constexpr int GRAM_WGS = 512;
 
 __host__ __device__ constexpr int npairs_of(int nt) { return nt * (nt + 1) / 2; }
 __host__ __device__ constexpr int gram_groups(int nt) { return nt <= 4 ? 1 : 3; }
@@ -192,17 +192,18 @@ __device__ __forceinline__ void gram_body(const GLOBAL Tin* __restrict__ Y, int6
 #pragma unroll
             for (int s = 0; s < 4; ++s) x[a][s] = (double)v[s];
         }
-        int p = 0;
+        // row slot outermost: consecutive matrix-core instructions are independent
 #pragma unroll
-        for (int a = 0; a < NT; ++a)
+        for (int s = 0; s < 4; ++s) {
+            int p = 0;
 #pragma unroll
-            for (int b = a; b < NT; ++b) {
-                if (p >= PLO && p < PHI) {
+            for (int a = 0; a < NT; ++a)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) acc[p - PLO] = mfma_16x16x4(x[a][s], x[b][s], acc[p - PLO]);
+                for (int b = a; b < NT; ++b) {
+                    if (p >= PLO && p < PHI) acc[p - PLO] = mfma_16x16x4(x[a][s], x[b][s], acc[p - PLO]);
+                    ++p;
                 }
-                ++p;
-            }
+        }
     }
     // fixed-order reduction over the 4 waves
     for (int w = 0; w < 4; ++w) {
@@ -224,14 +225,22 @@ __device__ __forceinline__ void gram_body(const GLOBAL Tin* __restrict__ Y, int6
     }
 }
 
-// grouped: local tile t is partial workgroup t % nwg of pair group t / nwg
+// grouped: local tile t is partial workgroup bx of pair group grp. With
+// several pair groups, the groups of one row block sit 8 tiles apart (the
+// same XCD when the item starts at a multiple of 8, at about the same time),
+// so the second and third reads of the rows come from that XCD's L2.
 template <typename Tin, int NT>
 __global__ __launch_bounds__(256) void k_gram(Group<GramArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const GramArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
     const int t = blockIdx.x - g.tstart[it];
-    const int bx = t % a.nwg, grp = t / a.nwg;
+    constexpr int NG = gram_groups(NT);
+    int bx = t % a.nwg, grp = t / a.nwg;
+    if (NG > 1 && (a.nwg & 7) == 0 && (g.tstart[it] & 7) == 0) {
+        grp = (t >> 3) % NG;
+        bx = (t / (8 * NG)) * 8 + (t & 7);
+    }
     constexpr int NP = npairs_of(NT), PG = gram_pg(NT);
     __shared__ double red[PG * 256];
     const GLOBAL Tin* Y = gbl((const Tin*)a.Y);
@@ -272,10 +281,14 @@ __global__ void k_gram_reduce(Group<GramArgs> g, int nt) {
     G[(16 * b + nn) * lp + 16 * a + mm] = s;
 }
 
-int gram_nwg(int64_t M, int cap) {
+// Partial workgroups per pair group: one per 4 row blocks, at most `cap`;
+// by default (cap 0) 256 for a single pair group (measured: more partials
+// cost more in the reduction than they save) and about 512 workgroups over
+// several pair groups (two waves per SIMD), rounded down to a multiple of 8.
+int gram_nwg(int64_t M, int cap, int nt) {
     const int64_t nrb = (M + 15) / 16;
     int64_t nwg = (nrb + 3) / 4;
-    if (cap < 1 || cap > GRAM_WGS) cap = GRAM_WGS;
+    if (cap < 1 || cap > GRAM_WGS) cap = gram_groups(nt) == 1 ? 256 : (GRAM_WGS / gram_groups(nt)) & ~7;
     if (nwg > cap) nwg = cap;
     if (nwg < 1) nwg = 1;
     return (int)nwg;
