@@ -418,19 +418,25 @@ __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
             // steps k = 64 kc + 16 pb + kk: kc and kk compile-time (register indices), pb a runtime loop
             auto steps = [&](auto KC) {
                 constexpr int kc = decltype(KC)::value;
-                for (int pb = 0; pb < 4 && !fail; ++pb) {
+                for (int pb = 0; pb < 4; ++pb) {
                     const int pw = 4 * kc + pb;  // wave holding rows 16 pw ..
                     if (pw >= NB || 16 * pw >= l) break;
 #pragma unroll
                     for (int kk = 0; kk < 16; ++kk) {
                         const int k = 16 * pw + kk, kl = 16 * pb + kk;
-                        if (k >= l || fail) continue;  // uniform; no break, so the loop unrolls
+                        if (k >= l) continue;  // uniform; no break, so the loop unrolls
                         double* rb = rowb[k & 1];
                         if (wave == pw) {
                             const double d = read_lane(w[kc][kk], kl);
                             const double tol = (double)l * 0x1.0p-52 * read_lane(gd[kc], kl);
                             if (!(d > tol) || !(d > 0.0)) {  // non-positive, tiny or NaN pivot
+                                // recorded once; the row becomes NaN, so every later pivot fails too
                                 if (j == 0) s_fail = 1;
+#pragma unroll
+                                for (int cc = 0; cc < CPL; ++cc) {
+                                    const int col = j + 64 * cc;
+                                    if (col < LP) rb[col] = __builtin_nan("");
+                                }
                             } else {
                                 const double rinv = rsqrt_nr(d);
 #pragma unroll
@@ -443,10 +449,6 @@ __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
                             }
                         }
                         __syncthreads();
-                        if (s_fail) {
-                            fail = true;
-                            continue;
-                        }
 #pragma unroll
                         for (int cc = 0; cc < CPL; ++cc) {
                             const int col = j + 64 * cc;
@@ -465,6 +467,8 @@ __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
             };
             steps(std::integral_constant<int, 0>{});
             if constexpr (CPL > 1) steps(std::integral_constant<int, 1>{});
+            __syncthreads();
+            fail = s_fail != 0;
             __syncthreads();  // every thread has read s_fail
             if (!fail) break;
             if (attempt == 0) {
