@@ -261,11 +261,24 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
 
     f32x4 sr[SPT];
     e6_u16x8 qr[QPT];
+    // chunk q of a thread: column j0 + tid / CPC + q (256 / CPC), rows 4 (tid mod CPC) .. +3 of the step
+    constexpr int CSTEP = 256 / CPC;
+    const int64_t jt = j0 + tid / CPC;
+    const GLOBAL float* sbase = S + jt * ldS + 4 * (tid % CPC);
     auto fetch = [&](int64_t i0) {
+        if (VEC && i0 + R <= m) {  // whole step in range: one unguarded vector load per chunk
+            const GLOBAL float* p = sbase + i0;
 #pragma unroll
-        for (int q = 0; q < SPT; ++q) {
-            const int ch = tid + 256 * q;
-            sr[q] = e6_rows4<VEC>(S, ldS, m, n, i0 + 4 * (ch % CPC), j0 + ch / CPC);
+            for (int q = 0; q < SPT; ++q)
+                sr[q] = (jt + CSTEP * q < n)
+                            ? __builtin_nontemporal_load(reinterpret_cast<const GLOBAL f32x4*>(p + CSTEP * q * ldS))
+                            : f32x4{0, 0, 0, 0};
+        } else {
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) {
+                const int ch = tid + 256 * q;
+                sr[q] = e6_rows4<VEC>(S, ldS, m, n, i0 + 4 * (ch % CPC), j0 + ch / CPC);
+            }
         }
 #pragma unroll
         for (int q = 0; q < QPT; ++q) {
