@@ -182,16 +182,23 @@ __device__ __forceinline__ void gram_body(const GLOBAL Tin* __restrict__ Y, int6
 #pragma unroll
     for (int p = 0; p < PG; ++p) acc[p] = f64x4{0, 0, 0, 0};
 
-    const int64_t nrb = (M + 15) / 16;
-    for (int64_t rb = (int64_t)bx * 4 + wave; rb < nrb; rb += (int64_t)nwg * 4) {
-        const int64_t i0 = rb * 16 + 4 * kg;
+    const int64_t nrb = (M + 15) / 16, rstride = (int64_t)nwg * 4;
+    // the next row block is loaded while the matrix cores work on this one
+    V4<Tin> vn[NT];
+    auto load = [&](int64_t rb) {
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+            vn[a] = *reinterpret_cast<const GLOBAL V4<Tin>*>(Y + (int64_t)(16 * a + r16) * ld + rb * 16 + 4 * kg);
+    };
+    int64_t rb = (int64_t)bx * 4 + wave;
+    if (rb < nrb) load(rb);
+    for (; rb < nrb; rb += rstride) {
         double x[NT][4];
 #pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            const V4<Tin> v = *reinterpret_cast<const GLOBAL V4<Tin>*>(Y + (int64_t)(16 * a + r16) * ld + i0);
+        for (int a = 0; a < NT; ++a)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) x[a][s] = (double)v[s];
-        }
+            for (int s = 0; s < 4; ++s) x[a][s] = (double)vn[a][s];
+        if (rb + rstride < nrb) load(rb + rstride);
         // row slot outermost: consecutive matrix-core instructions are independent
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -253,28 +260,40 @@ __global__ __launch_bounds__(256) void k_gram(Group<GramArgs> g) {
 }
 
 // grouped: npairs(nt) tiles of 256 elements per matrix
-__global__ void k_gram_reduce(Group<GramArgs> g, int nt) {
+__global__ __launch_bounds__(256) void k_gram_reduce(Group<GramArgs> g, int nt) {
+    __shared__ double part[8][32];
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const GramArgs& ga = g.args[it];
     if (ga.cond != nullptr && !(*ga.cond & ga.cond_mask)) return;
     const int np = nt * (nt + 1) / 2;
-    const int e = (blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
-    if (e >= np * 256) return;
+    // 32 entries per workgroup, eight threads per entry: thread t sums the
+    // partials w = t, t + 8, .. (independent loads in flight), and the eight
+    // sums are combined in a fixed order
+    const int el = threadIdx.x & 31, t = threadIdx.x >> 5;
+    const int e = (blockIdx.x - g.tstart[it]) * 32 + el;
+    const bool live = e < np * 256;
+    double acc = 0.0;
+    if (live) {
+        const GLOBAL double* src = gbl(ga.Gpart) + e;  // entry e = pair e / 256, element e mod 256
+        const int64_t wstride = (int64_t)np * 256;
+        const int nwg = ga.nwg;
+        double a4[4] = {0, 0, 0, 0};
+        int w = t;
+        for (; w + 24 < nwg; w += 32)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a4[u] += src[(int64_t)(w + 8 * u) * wstride];
+        for (; w < nwg; w += 8) a4[0] += src[(int64_t)w * wstride];
+        acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    }
+    part[t][el] = acc;
+    __syncthreads();
+    if (t != 0 || !live) return;
+    const double s = ((part[0][el] + part[1][el]) + (part[2][el] + part[3][el])) +
+                     ((part[4][el] + part[5][el]) + (part[6][el] + part[7][el]));
     const int p = e / 256, mm = (e % 256) / 16, nn = e % 16;
     int a = 0, q = p;
     while (q >= nt - a) { q -= nt - a; ++a; }
     const int b = a + q;
-    // eight independent partial sums (loads in flight together), combined in a fixed order
-    double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const GLOBAL double* src = gbl(ga.Gpart) + (int64_t)p * 256 + (e % 256);
-    const int64_t wstride = (int64_t)np * 256;
-    const int nwg = ga.nwg;
-    int w = 0;
-    for (; w + 8 <= nwg; w += 8)
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc8[u] += src[(w + u) * wstride];
-    for (; w < nwg; ++w) acc8[0] += src[w * wstride];
-    const double s = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
     const int lp = 16 * nt;
     GLOBAL double* G = gbl(ga.G);
     G[(16 * a + mm) * lp + 16 * b + nn] = s;
@@ -295,7 +314,7 @@ int gram_nwg(int64_t M, int cap, int nt) {
 }
 
 int gram_tiles(int nt, int nwg) { return nwg * gram_groups(nt); }
-int gram_reduce_tiles(int nt) { return npairs_of(nt); }
+int gram_reduce_tiles(int nt) { return npairs_of(nt) * 8; }  // 32 entries per workgroup
 
 template <typename Tin, int NT>
 static hipError_t gram_nt(const GroupLaunch<GramArgs>& L, const GroupLaunch<GramArgs>& R, hipStream_t st) {
