@@ -48,10 +48,11 @@ struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)
 };
 
 struct ReduceArgs {  // out = sum of nsplit slabs
-    const double* Zp;
+    const void* Zp;  // FP64 slabs, or FP32 ones when f32 is set
     int64_t count;
     double* out;
     int nsplit;
+    int f32;
 };
 
 struct GramArgs {  // G = Y^T Y, FP64

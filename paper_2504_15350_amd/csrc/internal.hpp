@@ -52,7 +52,8 @@ int stq32_block_cols();
 // Y (FP32) = S X with X in the same 16-bit type (ldX multiple of 8, zero rows
 // up to roundup(n, 32)), one workgroup per 256 rows; slabs of S^T Q with Q
 // given as 16-bit hi and lo parts (zero rows up to roundup(m, 128)), the lo
-// product added when lo is set. Splits are interleaved in steps of
+// product added when lo is set, written as FP32 slabs (the FP32
+// accumulators). Splits are interleaved in steps of
 // stq16_rows_per_step(lo) rows; tiles: ncb = nP / stq16_block_cols(lo) x
 // nsplit. vec: S 16-byte aligned with ldS a multiple of 8.
 hipError_t launch_sx16(int tin, int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st);
@@ -67,7 +68,7 @@ hipError_t launch_split16(int tin, const GroupLaunch<SplitArgs>& L, hipStream_t 
 // BF16 parts (six products per term, FP32-accurate dot products):
 //   launch_sx_e6: Y = S X, X given as its three parts one after another
 //   (each ldX x 16 nt, zero rows up to roundup(n, 32)); 256 rows per workgroup.
-//   launch_stq_e6: slabs of S^T Q, Q given as three parts one after another
+//   launch_stq_e6: FP32 slabs of S^T Q, Q given as three parts one after another
 //   (each ldQ x 16 nt, zero rows up to roundup(m, 32)); tiles ncb =
 //   nP / stq_e6_block_cols() x nsplit, splits interleaved in units of 64
 //   rows (split s: rows 64 (k nsplit + s) .., k = 0, 1, ..), nP a multiple
@@ -80,7 +81,8 @@ hipError_t launch_stq_e6(int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStr
 hipError_t launch_split3(const GroupLaunch<SplitArgs>& L, hipStream_t st);
 int stq_e6_block_cols();
 
-// out[e] = sum over the nsplit slabs, fixed order; one workgroup per 256 elements.
+// out[e] = sum over the nsplit slabs in FP64, fixed order (FP32 slabs when
+// f32 is set, else FP64); one workgroup per 256 elements.
 hipError_t launch_reduce_slabs(const GroupLaunch<ReduceArgs>& L, hipStream_t st);
 
 // Gram matrix G = Y^T Y in FP64 of a tall M x 16*nt column-major matrix

@@ -383,8 +383,9 @@ struct Recorder {
         out.push_back(s);
         Step r{K_REDUCE};
         B.add(r, each([&](const Item& it) {
+                  // the FP32 and 16-bit passes accumulate in FP32 and write FP32 slabs
                   return ReduceArgs{P->at<double>(it, it.L.o_Zp), it.L.nP * it.L.lp, P->at<double>(it, it.L.o_Zt),
-                                    it.L.nsplit};
+                                    it.L.nsplit, it.L.tin != DT_F64 ? 1 : 0};
               }),
               tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
         out.push_back(r);
@@ -641,7 +642,7 @@ struct Recorder {
         out.push_back(k);
         Step rd{K_REDUCE};
         B.add(rd, std::vector<ReduceArgs>{{P->wat<double>(P->w_pZp), (int64_t)WARM_PROJ_COLS * d,
-                                           P->wat<double>(P->w_pC), P->probe_nsplit}},
+                                           P->wat<double>(P->w_pC), P->probe_nsplit, 0}},
               std::vector<int>{(WARM_PROJ_COLS * d + 255) / 256});
         out.push_back(rd);
         sx(DT_F64, DT_F64, d / 16, false,

@@ -201,7 +201,7 @@ template <typename T16, int NT, bool VEC, bool LO, int G>
 __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restrict__ S, int64_t ldS, int64_t m,
                                            int64_t n, const GLOBAL unsigned short* __restrict__ Qh,
                                            const GLOBAL unsigned short* __restrict__ Ql, int64_t ldQ,
-                                           GLOBAL double* __restrict__ Zp, int64_t nP, int nsplit, int ncb, int tile) {
+                                           GLOBAL float* __restrict__ Zp, int64_t nP, int nsplit, int ncb, int tile) {
     constexpr int R = LO ? 64 : 128;
     constexpr int LDS_ = R + 8;   // column stride (elements) of the LDS blocks
     constexpr int LPC = R / 8;    // 16-byte chunks per column of a block
@@ -300,17 +300,15 @@ __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restri
         }
         compute(G - 1);
     }
-    GLOBAL double* zp = Zp + (int64_t)sp * nP * (16 * NT);
+    GLOBAL float* zp = Zp + (int64_t)sp * nP * (16 * NT);  // FP32 slabs (summed in FP64 afterwards)
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                GLOBAL double* pz = zp + (int64_t)(16 * c + r16) * nP + j0 + HB * g + 32 * wave + 16 * u + 4 * kg;
-                typedef double d4 __attribute__((ext_vector_type(4)));
-                *reinterpret_cast<GLOBAL d4*>(pz) = d4{acc[g][u][c][0], acc[g][u][c][1], acc[g][u][c][2], acc[g][u][c][3]};
-            }
+            for (int c = 0; c < NT; ++c)
+                *reinterpret_cast<GLOBAL f32x4*>(zp + (int64_t)(16 * c + r16) * nP + j0 + HB * g + 32 * wave + 16 * u +
+                                                 4 * kg) = acc[g][u][c];
 }
 
 // grouped launch: local tile t covers column block t % ncb of split t / ncb
@@ -320,7 +318,7 @@ __global__ __launch_bounds__(256, 2) void k_stq16(Group<StqArgs> g) {
     const StqArgs& a = g.args[it];
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
     stq16_body<T16, NT, VEC, LO, G>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q),
-                                    gbl((const unsigned short*)a.Ql), a.ldQ, gbl(a.Zp), a.nP, a.nsplit, a.ncb,
+                                    gbl((const unsigned short*)a.Ql), a.ldQ, gbl((float*)a.Zp), a.nP, a.nsplit, a.ncb,
                                     blockIdx.x - g.tstart[it]);
 }
 

@@ -236,7 +236,7 @@ constexpr int E6_R = 32, E6_LDS = E6_R, E6_LDQ = E6_R, E6_HB = 256;
 template <int NT, bool VEC>
 __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, int64_t ldS, int64_t m, int64_t n,
                                             const GLOBAL unsigned short* __restrict__ Q, int64_t ldQ,
-                                            GLOBAL double* __restrict__ Zp, int64_t nP, int nsplit, int ncb,
+                                            GLOBAL float* __restrict__ Zp, int64_t nP, int nsplit, int ncb,
                                             int tile, float* ss, unsigned short* qs) {
     constexpr int R = E6_R, LD = E6_LDS, LDQ = E6_LDQ, HB = E6_HB, U = HB / 64;
     constexpr int CPC = R / 4;                  // 16-byte S chunks per column
@@ -328,15 +328,15 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
             for (int u = 0; u < U; ++u) mma6(ah[u], am[u], al[u], bh, bm, bl, acc[u][c]);
         }
     }
-    // D[4 g + v][r]: S column j0 + 16 U w + 16 u + 4 g + v, Q column 16 c + r
-    GLOBAL double* zp = Zp + (int64_t)sp * nP * (16 * NT);
-    typedef double d4 __attribute__((ext_vector_type(4)));
+    // D[4 g + v][r]: S column j0 + 16 U w + 16 u + 4 g + v, Q column 16 c + r; the
+    // slab keeps the FP32 accumulators as they are (summed in FP64 afterwards)
+    GLOBAL float* zp = Zp + (int64_t)sp * nP * (16 * NT);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int c = 0; c < NT; ++c)
-            *reinterpret_cast<GLOBAL d4*>(zp + (int64_t)(16 * c + r16) * nP + j0 + 16 * U * wave + 16 * u + 4 * g) =
-                d4{acc[u][c][0], acc[u][c][1], acc[u][c][2], acc[u][c][3]};
+            *reinterpret_cast<GLOBAL f32x4*>(zp + (int64_t)(16 * c + r16) * nP + j0 + 16 * U * wave + 16 * u + 4 * g) =
+                acc[u][c];
 }
 
 template <int NT, bool VEC>
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
     const int local = blockIdx.x - g.tstart[it], ntl = a.ncb * a.nsplit;
     const int tile = ((ntl & 7) == 0 && (g.tstart[it] & 7) == 0) ? (local & 7) * (ntl >> 3) + (local >> 3) : local;
     // Q holds the three parts one after another, each ldQ x 16 NT
-    stq_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q), a.ldQ, gbl(a.Zp),
+    stq_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q), a.ldQ, gbl((float*)a.Zp),
                          a.nP, a.nsplit, a.ncb, tile, ss, qs);
 }
 

@@ -305,15 +305,20 @@ __global__ __launch_bounds__(256) void k_stq32(Group<StqArgs> g) {
                              a.nsplit, a.ncb, blockIdx.x - g.tstart[it]);
 }
 
-// out[e] = sum of the nsplit slabs, fixed order; 256 elements per workgroup
+// out[e] = sum of the nsplit slabs in FP64, fixed order; 256 elements per workgroup
 __global__ void k_reduce_slabs(Group<ReduceArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const ReduceArgs& a = g.args[it];
     const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
     if (e >= a.count) return;
-    const GLOBAL double* Zp = gbl(a.Zp);
     double s = 0.0;
-    for (int k = 0; k < a.nsplit; ++k) s += Zp[(int64_t)k * a.count + e];
+    if (a.f32) {
+        const GLOBAL float* Zp = gbl((const float*)a.Zp);
+        for (int k = 0; k < a.nsplit; ++k) s += (double)Zp[(int64_t)k * a.count + e];
+    } else {
+        const GLOBAL double* Zp = gbl((const double*)a.Zp);
+        for (int k = 0; k < a.nsplit; ++k) s += Zp[(int64_t)k * a.count + e];
+    }
     *gbl(a.out + e) = s;
 }
 

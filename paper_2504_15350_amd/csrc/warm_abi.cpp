@@ -104,7 +104,7 @@ rpod_status bank_product(rpod_warm_s& M, const float* Q, int nt) {
     a.nsplit = M.nsplit;
     a.ncb = (int)(M.nPb / stq32_block_cols());
     a.call = -1;
-    ReduceArgs ra{M.at<double>(M.o_Zp), M.nPb * 16 * nt, M.at<double>(M.o_Zt), M.nsplit};
+    ReduceArgs ra{M.at<double>(M.o_Zp), M.nPb * 16 * nt, M.at<double>(M.o_Zt), M.nsplit, 0};
     const int tiles = a.ncb * a.nsplit;
     const int rtiles = (int)((ra.count + 255) / 256);
     struct Blob {
