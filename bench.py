@@ -186,6 +186,8 @@ def measure(name, St, steps, warmup):
 
 
 BATCH = dict(count=64, shape_seed=4, p=10, q=2, seed0=1000)
+# (stq_workgroups, gram_workgroups) per storage type, 0 = the library's default
+BATCH_TUNING = {"fp32": (128, 64), "bf16": (0, 64)}
 
 
 def make_batch(dev):
@@ -276,19 +278,16 @@ def batch_block(dev, steps, warmup):
     elems = sum(m * n for (m, n, _r, _a) in shapes)
     log(f"[bench] generated the 64-matrix batch ({elems / 1e9:.2f} G elements) in {time.perf_counter() - t0:.1f} s")
     import paper_2504_15350_amd as rp
-    bshapes = [(m, n, r, BATCH["p"]) for (m, n, r, _a) in shapes]
     plain = measure_batch(mats, shapes, steps, warmup, batched=False)
-    t0 = time.perf_counter()
-    tune32, tms32 = rp.autotune(bshapes, BATCH["q"], mats, repeats=2)
-    log(f"[bench] autotuned the FP32 batch in {time.perf_counter() - t0:.1f} s: {tune32} ({tms32:.2f} ms per call)")
+    # Launch shapes: the values rpod_autotune chose for this batch when it last ran here. The
+    # autotuner itself is not called: one of its runs aborted without a message and the cause
+    # has not been found.
+    tune32, tune16 = rp.Tuning(*BATCH_TUNING["fp32"]), rp.Tuning(*BATCH_TUNING["bf16"])
     b32 = measure_batch(mats, shapes, steps, warmup, batched=True, tuning=tune32)
     mats16 = [St.to(torch.bfloat16) for St in mats]
     del mats
     torch.cuda.empty_cache()
     b16d = measure_batch(mats16, shapes, steps, warmup, batched=True)
-    t0 = time.perf_counter()
-    tune16, tms16 = rp.autotune(bshapes, BATCH["q"], mats16, repeats=2)
-    log(f"[bench] autotuned the BF16 batch in {time.perf_counter() - t0:.1f} s: {tune16} ({tms16:.2f} ms per call)")
     b16 = measure_batch(mats16, shapes, steps, warmup, batched=True, tuning=tune16)
     del mats16
     torch.cuda.empty_cache()
@@ -305,7 +304,8 @@ def batch_block(dev, steps, warmup):
         "batched_bf16_ms": round(b16["ms"], 3),
         "batched_bf16_default_tuning_ms": round(b16d["ms"], 3),
         "tuning": {"fp32": {"stq_workgroups": tune32.stq_workgroups, "gram_workgroups": tune32.gram_workgroups},
-                   "bf16": {"stq_workgroups": tune16.stq_workgroups, "gram_workgroups": tune16.gram_workgroups}},
+                   "bf16": {"stq_workgroups": tune16.stq_workgroups, "gram_workgroups": tune16.gram_workgroups},
+                   "source": "fixed: the autotuner's earlier choice for this batch"},
         "kernel_by_kernel_ms": {"plain_fp32": round(plain["ms_timed"], 3), "batched_fp32": round(b32["ms_timed"], 3),
                                 "batched_bf16": round(b16["ms_timed"], 3)},
         "speedup_batched_fp32": round(plain["ms"] / b32["ms"], 2),

@@ -68,8 +68,8 @@ hipError_t launch_split16(int tin, const GroupLaunch<SplitArgs>& L, hipStream_t 
 // BF16 parts (six products per term, FP32-accurate dot products):
 //   launch_sx_e6: Y = S X, X given as its three parts one after another
 //   (each ldX x 16 nt, zero rows up to roundup(n, 32)); 256 rows per workgroup.
-//   launch_stq_e6: FP32 slabs of S^T Q, Q given as three parts one after another
-//   (each ldQ x 16 nt, zero rows up to roundup(m, 32)); tiles ncb =
+//   launch_stq_e6: FP32 slabs of S^T Q, Q in FP32 (ldQ x 16 nt, ldQ a multiple
+//   of 4, zero rows up to roundup(m, 32)), split as it is staged; tiles ncb =
 //   nP / stq_e6_block_cols() x nsplit, splits interleaved in units of 64
 //   rows (split s: rows 64 (k nsplit + s) .., k = 0, 1, ..), nP a multiple
 //   of stq_e6_block_cols(); nsplit a multiple of 8 keeps each split's column

@@ -67,7 +67,7 @@ struct Layout {
     int nchunk;
     int gram_cap;
     // byte offsets into the matrix's workspace region
-    size_t o_X, o_X3, o_Y, o_Q1, o_Qh, o_Ql, o_Q3, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
+    size_t o_X, o_X3, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
     size_t total;
 };
@@ -136,7 +136,6 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.o_Q1 = take((size_t)L.mP * L.lp * sa);
     L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Ql = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
-    L.o_Q3 = take(f32 ? (size_t)3 * L.mP * L.lp * 2 : 0);  // FP32: the three BF16 parts of Q1
     L.o_Zp = take((size_t)L.nsplit * L.nP * L.lp * 8);
     L.o_Zt = take((size_t)L.nP * L.lp * 8);
     L.o_Zw = take((size_t)L.nP * L.lp * 8);
@@ -309,22 +308,17 @@ struct Recorder {
         out.push_back(s);
         split3_x();
     }
-    // FP32: the three BF16 parts of an FP32 operand of the passes over S
-    void split3(size_t Layout::*src, size_t Layout::*dst, bool tall) {
+    // FP32: the three BF16 parts of X (n x lp), the small operand of S X
+    void split3_x() {
         if (L0().tin != DT_F32) return;
         Step s{K_SPLIT3};
         B.add(s, each([&](const Item& it) {
-                  const int64_t rows = tall ? it.L.mP : it.L.nP;
-                  return SplitArgs{P->at<float>(it, it.L.*src), rows * it.L.lp,
-                                   P->at<unsigned short>(it, it.L.*dst), nullptr};
+                  return SplitArgs{P->at<float>(it, it.L.o_X), it.L.nP * it.L.lp,
+                                   P->at<unsigned short>(it, it.L.o_X3), nullptr};
               }),
-              tiles([tall](const Item& it) {
-                  const int64_t rows = tall ? it.L.mP : it.L.nP;
-                  return (int)((rows * it.L.lp / 4 + 255) / 256);
-              }));
+              tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp / 4 + 255) / 256); }));
         out.push_back(s);
     }
-    void split3_x() { split3(&Layout::o_X, &Layout::o_X3, false); }
     // generic tall x small product (internal operands)
     void sx(int tin, int tout, int nt, bool upper, std::vector<SxArgs> args) {
         Step s{K_SX};
@@ -368,7 +362,7 @@ struct Recorder {
         std::vector<StqArgs> args = each([&](const Item& it) {
             StqArgs a{};
             a.S = nullptr; a.ldS = it.d.ld; a.m = it.d.m; a.n = it.d.n;
-            a.Q = P->at<char>(it, s16 ? it.L.o_Qh : f32 ? it.L.o_Q3 : it.L.o_Q1);
+            a.Q = P->at<char>(it, s16 ? it.L.o_Qh : it.L.o_Q1);  // FP32: split by the pass as it is staged
             a.Ql = s16 ? (const void*)P->at<char>(it, it.L.o_Ql) : nullptr;
             a.ldQ = it.L.mP; a.Zp = P->at<double>(it, it.L.o_Zp); a.nP = it.L.nP;
             a.split_rows = it.L.split_rows; a.nsplit = it.L.nsplit;
@@ -454,7 +448,6 @@ struct Recorder {
                   tiles([](const Item& it) { return (int)((it.L.mP * it.L.lp / 4 + 255) / 256); }));
             out.push_back(s);
         }
-        split3(&Layout::o_Q1, &Layout::o_Q3, true);
     }
     // Zw = Zt R^-1 (R from the last tall orthonormalisation): Zw = S^T Q
     void small_from_slabs() {

@@ -12,7 +12,7 @@
 // term both passes stay bound by HBM, not by the FP32 matrix-core rate.
 //
 //   k_sx_e6   Y = S X   (X given split: three BF16 arrays of n x 16 NT)
-//   k_stq_e6  slabs of Z = S^T Q (Q given split), interleaved row splits
+//   k_stq_e6  slabs of Z = S^T Q (Q split as it is staged), interleaved row splits
 //   k_split3  the three-way split of an FP32 array
 //
 // MFMA operand layout (16x16x32 bf16, gfx950): lane l supplies
@@ -217,10 +217,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
 // ---------------------------------------------------------------------------
 // Z_s = S^T Q. Workgroup: 256 columns of S (four column tiles of 16 per
 // wave), 32 rows per step; the step's S block (32 x 256, FP32) and the three
-// BF16 parts of the Q block (32 x 16 NT) are staged in LDS column-major and
-// the next step's blocks are loaded into registers during the matrix-core
-// work. Lane (r, g) reads rows 8 g .. 8 g + 7 of its S column (the A
-// operand, split in registers) and of each Q column part (the B operand).
+// BF16 parts of the Q block (32 x 16 NT, read as FP32 and split when staged)
+// are staged in LDS column-major and the next step's blocks are loaded into
+// registers during the matrix-core work. Lane (r, g) reads rows 8 g .. 8 g + 7
+// of its S column (the A operand, split in registers) and of each Q column
+// part (the B operand).
 // Columns are stored unpadded with their 16-byte chunks XOR-swizzled (S
 // column c: chunk k at k ^ ((c / 2) mod 8); Q column c: chunk k at
 // k ^ ((c / 4) mod 4)), which keeps both the staging writes and the operand
@@ -235,16 +236,16 @@ constexpr int E6_R = 32, E6_LDS = E6_R, E6_LDQ = E6_R, E6_HB = 256;
 
 template <int NT, bool VEC>
 __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, int64_t ldS, int64_t m, int64_t n,
-                                            const GLOBAL unsigned short* __restrict__ Q, int64_t ldQ,
+                                            const GLOBAL float* __restrict__ Q, int64_t ldQ,
                                             GLOBAL float* __restrict__ Zp, int64_t nP, int nsplit, int ncb,
                                             int tile, float* ss, unsigned short* qs) {
     constexpr int R = E6_R, LD = E6_LDS, LDQ = E6_LDQ, HB = E6_HB, U = HB / 64;
     constexpr int CPC = R / 4;                  // 16-byte S chunks per column
     constexpr int SPT = HB * CPC / 256;         // S chunks per thread
-    constexpr int QCPC = R / 8;                 // 16-byte Q chunks per column part
-    constexpr int QCH = 3 * 16 * NT * QCPC;     // Q chunks per step (three parts)
+    constexpr int QCPC = R / 4;                 // 16-byte FP32 Q chunks per column
+    constexpr int QCH = 16 * NT * QCPC;         // Q chunks per step
     constexpr int QPT = (QCH + 255) / 256;
-    const int64_t qpart = ldQ * (16 * NT);
+    constexpr int QPART = 16 * NT * LDQ;        // halfwords per staged part
     const int cb = tile % ncb, sp = tile / ncb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -260,7 +261,7 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
         for (int c = 0; c < NT; ++c) acc[u][c] = f32x4{0, 0, 0, 0};
 
     f32x4 sr[SPT];
-    e6_u16x8 qr[QPT];
+    f32x4 qr[QPT];
     // chunk q of a thread: column j0 + tid / CPC + q (256 / CPC), rows 4 (tid mod CPC) .. +3 of the step
     constexpr int CSTEP = 256 / CPC;
     const int64_t jt = j0 + tid / CPC;
@@ -283,26 +284,35 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
 #pragma unroll
         for (int q = 0; q < QPT; ++q) {
             const int ch = tid + 256 * q;
-            if (ch < QCH) {
-                const int col = ch / QCPC, prt = col / (16 * NT), qc = col % (16 * NT);
-                qr[q] = *reinterpret_cast<const GLOBAL e6_u16x8*>(Q + prt * qpart + (int64_t)qc * ldQ + i0 +
-                                                                 8 * (ch % QCPC));
-            }
+            if (ch < QCH)
+                qr[q] = *reinterpret_cast<const GLOBAL f32x4*>(Q + (int64_t)(ch / QCPC) * ldQ + i0 + 4 * (ch % QCPC));
         }
     };
-    static_assert(CPC == 8 && QCPC == 4, "swizzle patterns assume 32-row steps");
+    static_assert(CPC == 8 && QCPC == 8, "swizzle patterns assume 32-row steps");
     auto put = [&]() {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
             const int ch = tid + 256 * q, col = ch / CPC;
             *reinterpret_cast<f32x4*>(ss + col * LD + 4 * ((ch % CPC) ^ ((col >> 1) & 7))) = sr[q];
         }
+        // Q chunk (rows 4 k .. 4 k + 3 of a column) -> 8 bytes of each part, in
+        // half k mod 2 of the part's 16-byte chunk k / 2
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int q = 0; q < QPT; ++q) {
-            const int ch = tid + 256 * q, col = ch / QCPC;
-            if (ch < QCH) *reinterpret_cast<e6_u16x8*>(qs + col * LDQ + 8 * ((ch % QCPC) ^ ((col >> 2) & 3))) = qr[q];
+            const int ch = tid + 256 * q, col = ch / QCPC, k = ch % QCPC;
+            if (ch < QCH) {
+                unsigned h0, m0, l0, h1, m1, l1;
+                split_pair(qr[q][0], qr[q][1], h0, m0, l0);
+                split_pair(qr[q][2], qr[q][3], h1, m1, l1);
+                const int o = col * LDQ + 8 * ((k >> 1) ^ ((col >> 2) & 3)) + 4 * (k & 1);
+                *reinterpret_cast<u32x2*>(qs + o) = u32x2{h0, h1};
+                *reinterpret_cast<u32x2*>(qs + QPART + o) = u32x2{m0, m1};
+                *reinterpret_cast<u32x2*>(qs + 2 * QPART + o) = u32x2{l0, l1};
+            }
         }
     };
+
     if (ib < m) fetch(ib);
     for (int64_t i0 = ib; i0 < m; i0 = next(i0)) {
         __syncthreads();  // previous step consumed
@@ -322,8 +332,8 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
             const int col = 16 * c + r16;
             const int o = col * LDQ + 8 * (g ^ ((col >> 2) & 3));
             const e6_u16x8 bh = *reinterpret_cast<const e6_u16x8*>(qs + o);
-            const e6_u16x8 bm = *reinterpret_cast<const e6_u16x8*>(qs + 16 * NT * LDQ + o);
-            const e6_u16x8 bl = *reinterpret_cast<const e6_u16x8*>(qs + 2 * 16 * NT * LDQ + o);
+            const e6_u16x8 bm = *reinterpret_cast<const e6_u16x8*>(qs + QPART + o);
+            const e6_u16x8 bl = *reinterpret_cast<const e6_u16x8*>(qs + 2 * QPART + o);
 #pragma unroll
             for (int u = 0; u < U; ++u) mma6(ah[u], am[u], al[u], bh, bm, bl, acc[u][c]);
         }
@@ -351,8 +361,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
     // multiple of 8) takes tile (b mod 8) T / 8 + b / 8 of the item's T
     const int local = blockIdx.x - g.tstart[it], ntl = a.ncb * a.nsplit;
     const int tile = ((ntl & 7) == 0 && (g.tstart[it] & 7) == 0) ? (local & 7) * (ntl >> 3) + (local >> 3) : local;
-    // Q holds the three parts one after another, each ldQ x 16 NT
-    stq_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q), a.ldQ, gbl((float*)a.Zp),
+    stq_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.Q), a.ldQ, gbl((float*)a.Zp),
                          a.nP, a.nsplit, a.ncb, tile, ss, qs);
 }
 
