@@ -66,19 +66,16 @@ hipError_t launch_split16(int tin, const GroupLaunch<SplitArgs>& L, hipStream_t 
 
 // FP32 S on the BF16 matrix cores with every operand split exactly into three
 // BF16 parts (six products per term, FP32-accurate dot products):
-//   launch_sx_e6: Y = S X, X given as its three parts one after another
-//   (each ldX x 16 nt, zero rows up to roundup(n, 32)); 256 rows per workgroup.
+//   launch_sx_e6: Y = S X, X in FP32 (ldX x 16 nt, ldX a multiple of 4, zero
+//   rows up to roundup(n, 32)), split as it is staged; 256 rows per workgroup.
 //   launch_stq_e6: FP32 slabs of S^T Q, Q in FP32 (ldQ x 16 nt, ldQ a multiple
 //   of 4, zero rows up to roundup(m, 32)), split as it is staged; tiles ncb =
 //   nP / stq_e6_block_cols() x nsplit, splits interleaved in units of 64
 //   rows (split s: rows 64 (k nsplit + s) .., k = 0, 1, ..), nP a multiple
 //   of stq_e6_block_cols(); nsplit a multiple of 8 keeps each split's column
 //   blocks on one XCD.
-//   launch_split3: the parts of an FP32 array (count a multiple of 4) into
-//   hi, hi + count, hi + 2 count; one workgroup per 1024 elements.
 hipError_t launch_sx_e6(int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st);
 hipError_t launch_stq_e6(int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st);
-hipError_t launch_split3(const GroupLaunch<SplitArgs>& L, hipStream_t st);
 int stq_e6_block_cols();
 
 // out[e] = sum over the nsplit slabs in FP64, fixed order (FP32 slabs when

@@ -67,7 +67,7 @@ struct Layout {
     int nchunk;
     int gram_cap;
     // byte offsets into the matrix's workspace region
-    size_t o_X, o_X3, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
+    size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
     size_t total;
 };
@@ -131,7 +131,6 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     };
     const size_t lp2 = (size_t)L.lp * L.lp;
     L.o_X = take((size_t)L.nP * L.lp * si);
-    L.o_X3 = take(f32 ? (size_t)3 * L.nP * L.lp * 2 : 0);  // FP32: the three BF16 parts of X
     L.o_Y = take((size_t)L.mP * L.lp * sa);
     L.o_Q1 = take((size_t)L.mP * L.lp * sa);
     L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
@@ -164,7 +163,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // Recorded program
 // ---------------------------------------------------------------------------
 enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXE6, K_SX16, K_STQ, K_STQE6, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT,
-            K_SIGNS, K_FIN, K_SPLIT, K_SPLIT3, K_WFWD, K_WZ, K_SXW, K_PROBE };
+            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE };
 
 struct Step {
     Kind kind;
@@ -306,18 +305,6 @@ struct Recorder {
               }),
               tiles([](const Item& it) { return (int)((it.L.nP + 255) / 256) * ((it.L.lp + 1) / 2); }));
         out.push_back(s);
-        split3_x();
-    }
-    // FP32: the three BF16 parts of X (n x lp), the small operand of S X
-    void split3_x() {
-        if (L0().tin != DT_F32) return;
-        Step s{K_SPLIT3};
-        B.add(s, each([&](const Item& it) {
-                  return SplitArgs{P->at<float>(it, it.L.o_X), it.L.nP * it.L.lp,
-                                   P->at<unsigned short>(it, it.L.o_X3), nullptr};
-              }),
-              tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp / 4 + 255) / 256); }));
-        out.push_back(s);
     }
     // generic tall x small product (internal operands)
     void sx(int tin, int tout, int nt, bool upper, std::vector<SxArgs> args) {
@@ -341,7 +328,7 @@ struct Recorder {
             s.flops += 2.0 * it->d.m * it->d.n * it->L.l;
         }
         std::vector<SxArgs> args = each([&](const Item& it) {
-            return SxArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, f32 ? it.L.o_X3 : it.L.o_X), it.L.nP,
+            return SxArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, it.L.o_X), it.L.nP,
                           P->at<char>(it, it.L.o_Y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
         });
         B.add(s, args, tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
@@ -488,7 +475,6 @@ struct Recorder {
         gram(DT_F64, gargs(true, true));
         chol(cargs(2, 2));
         sx(DT_F64, tin, L0().nt, true, app(&Layout::o_Zw2, &Layout::o_X, 2, true));
-        split3_x();
     }
     void finish() {
         const Layout& L = L0();
@@ -696,7 +682,6 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_SIGNS: return launch_signs(s.tin, P->gl<ColmaxArgs>(s, false), P->gl<SignArgs>(s, true), st);
         case K_FIN: return launch_finalize(s.tin, P->gl<FinArgs>(s, false), P->gl<FinArgs>(s, true), st);
         case K_SPLIT: return launch_split16(s.tin, P->gl<SplitArgs>(s, false), st);
-        case K_SPLIT3: return launch_split3(P->gl<SplitArgs>(s, false), st);
         case K_WFWD: return launch_warm_plan_forward(P->gl<WarmFwdArgs>(s, false), st);
         case K_WZ: return launch_warm_z(P->gl<WarmZArgs>(s, false), st);
         case K_SXW: return launch_sx_wide(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);

@@ -11,9 +11,8 @@
 // The BF16 matrix cores run 16 times the FP32 rate: with six products per
 // term both passes stay bound by HBM, not by the FP32 matrix-core rate.
 //
-//   k_sx_e6   Y = S X   (X given split: three BF16 arrays of n x 16 NT)
+//   k_sx_e6   Y = S X   (X in FP32, split as it is staged)
 //   k_stq_e6  slabs of Z = S^T Q (Q split as it is staged), interleaved row splits
-//   k_split3  the three-way split of an FP32 array
 //
 // MFMA operand layout (16x16x32 bf16, gfx950): lane l supplies
 // A[l%16][8(l/16) + i] and B[8(l/16) + i][l%16], i = 0..7; the result holds
@@ -96,22 +95,22 @@ __device__ __forceinline__ f32x4 e6_rows4(const GLOBAL float* S, int64_t ld, int
 // of a wave holds rows 4 r .. 4 r + 3 of columns j0 + 8 g + i, i = 0..7 (a
 // wave instruction covers 4 columns x 256 bytes); element t of these is the
 // A operand of row tile t (MFMA row r of tile t is row 4 r + t of the wave),
-// K index 8 g + i. The step's block of the three X parts (32 rows x 16 NT
-// columns each) is staged in LDS, double-buffered, and shared by the four
-// waves. All four tiles are split before the matrix-core work, and the next
+// K index 8 g + i. The step's block of X (32 rows x 16 NT columns, read in
+// FP32 and split into its three BF16 parts as it is staged) is kept in LDS,
+// double-buffered, and shared by the four waves. All four tiles are split before the matrix-core work, and the next
 // step's S columns are loaded after it.
 // ---------------------------------------------------------------------------
 constexpr int E6_XLD = 40;  // halfwords per staged X column (32 rows + pad)
 
 template <int NT, bool VEC>
 __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, int64_t m, int64_t n,
-                                           const GLOBAL unsigned short* __restrict__ X, int64_t ldX,
+                                           const GLOBAL float* __restrict__ X, int64_t ldX,
                                            GLOBAL float* Y, int64_t ldY, int64_t mstore, int cmax, int64_t bx,
                                            unsigned short* xs) {
-    constexpr int XB = 3 * 16 * NT * E6_XLD;    // one staged X block
-    constexpr int XCH = 3 * 16 * NT * 4;        // its 16-byte chunks
+    constexpr int XPART = 16 * NT * E6_XLD;     // one staged part
+    constexpr int XB = 3 * XPART;               // one staged X block (three parts)
+    constexpr int XCH = 16 * NT * 8;            // 16-byte FP32 chunks of a block (4 rows each)
     constexpr int XPT = (XCH + 255) / 256;
-    const int64_t part = ldX * (16 * NT);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
     const int64_t iw = bx * 256 + wave * 64;
@@ -134,23 +133,29 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
             for (int i = 0; i < 8; ++i) sv[i] = e6_rows4<VEC>(S, ldS, m, n, irow, j0 + 8 * g + i);
         }
     };
-    e6_u16x8 xr[XPT];
+    f32x4 xr[XPT];
     auto load_x = [&](int64_t j0) {
 #pragma unroll
         for (int q = 0; q < XPT; ++q) {
             const int ch = tid + 256 * q;
-            if (ch < XCH) {
-                const int col = ch >> 2, prt = col / (16 * NT), qc = col % (16 * NT);
-                xr[q] = *reinterpret_cast<const GLOBAL e6_u16x8*>(X + prt * part + (int64_t)qc * ldX + j0 +
-                                                                 8 * (ch & 3));
-            }
+            if (ch < XCH) xr[q] = *reinterpret_cast<const GLOBAL f32x4*>(X + (int64_t)(ch >> 3) * ldX + j0 + 4 * (ch & 7));
         }
     };
+    // chunk (rows 4 k .. 4 k + 3 of a column) -> 8 bytes of each part
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
     auto put_x = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < XPT; ++q) {
             const int ch = tid + 256 * q;
-            if (ch < XCH) *reinterpret_cast<e6_u16x8*>(xs + buf * XB + (ch >> 2) * E6_XLD + 8 * (ch & 3)) = xr[q];
+            if (ch < XCH) {
+                unsigned h0, m0, l0, h1, m1, l1;
+                split_pair(xr[q][0], xr[q][1], h0, m0, l0);
+                split_pair(xr[q][2], xr[q][3], h1, m1, l1);
+                unsigned short* d = xs + buf * XB + (ch >> 3) * E6_XLD + 4 * (ch & 7);
+                *reinterpret_cast<u32x2*>(d) = u32x2{h0, h1};
+                *reinterpret_cast<u32x2*>(d + XPART) = u32x2{m0, m1};
+                *reinterpret_cast<u32x2*>(d + 2 * XPART) = u32x2{l0, l1};
+            }
         }
     };
     load_s(0);  // rows >= m read as 0 (guarded path)
@@ -170,8 +175,8 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
         for (int c = 0; c < NT; ++c) {
             const unsigned short* xb = xs + buf * XB + (16 * c + r16) * E6_XLD + 8 * g;
             const e6_u16x8 bh = *reinterpret_cast<const e6_u16x8*>(xb);
-            const e6_u16x8 bm = *reinterpret_cast<const e6_u16x8*>(xb + 16 * NT * E6_XLD);
-            const e6_u16x8 bl = *reinterpret_cast<const e6_u16x8*>(xb + 2 * 16 * NT * E6_XLD);
+            const e6_u16x8 bm = *reinterpret_cast<const e6_u16x8*>(xb + XPART);
+            const e6_u16x8 bl = *reinterpret_cast<const e6_u16x8*>(xb + 2 * XPART);
 #pragma unroll
             for (int t = 0; t < 4; ++t) mma6(ah[t], am[t], al[t], bh, bm, bl, acc[t][c]);
         }
@@ -209,7 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
-    sx_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.X), a.ldX,
+    sx_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
                         gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT, blockIdx.x - g.tstart[it],
                         xs);
 }
@@ -365,23 +370,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
                          a.nP, a.nsplit, a.ncb, tile, ss, qs);
 }
 
-// three-way split, 4 elements per thread; out: h, m, l parts one after another
-__global__ void k_split3(Group<SplitArgs> g) {
-    const int it = group_item(g.tstart, g.count, blockIdx.x);
-    const SplitArgs& sa = g.args[it];
-    const int64_t e = ((int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x) * 4;
-    if (e >= sa.count) return;
-    const f32x4 q = *reinterpret_cast<const GLOBAL f32x4*>(gbl(sa.Q) + e);
-    unsigned h0, m0, l0, h1, m1, l1;
-    split_pair(q[0], q[1], h0, m0, l0);
-    split_pair(q[2], q[3], h1, m1, l1);
-    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    GLOBAL unsigned short* out = gbl(sa.hi);
-    *reinterpret_cast<GLOBAL u32x2*>(out + e) = u32x2{h0, h1};
-    *reinterpret_cast<GLOBAL u32x2*>(out + sa.count + e) = u32x2{m0, m1};
-    *reinterpret_cast<GLOBAL u32x2*>(out + 2 * sa.count + e) = u32x2{l0, l1};
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -431,11 +419,6 @@ hipError_t launch_stq_e6(int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStr
 #undef RPOD_E6_CASE
         default: return hipErrorInvalidValue;
     }
-}
-
-hipError_t launch_split3(const GroupLaunch<SplitArgs>& L, hipStream_t st) {
-    hipLaunchKernelGGL(k_split3, dim3(L.tiles), dim3(256), 0, st, mke6(L));
-    return hipGetLastError();
 }
 
 int stq_e6_block_cols() { return E6_HB; }
