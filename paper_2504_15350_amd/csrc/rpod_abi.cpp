@@ -318,6 +318,18 @@ struct Recorder {
         B.add(s, args, t);
         out.push_back(s);
     }
+    // tall FP32 x small product on the BF16 matrix cores with split operands
+    // (FP32-accurate), used when the small side's rows lp are a multiple of 32
+    // (the kernel reads X rows up to a multiple of 32); FP64 or other lp: sx()
+    void sx_tall(int tacc, int nt, bool upper, std::vector<SxArgs> args) {
+        if (tacc != DT_F32 || L0().lp % 32 != 0) return sx(tacc, tacc, nt, upper, std::move(args));
+        Step s{K_SXE6};
+        s.tin = DT_F32; s.tout = DT_F32; s.nt = nt; s.vec = true;
+        std::vector<int> t;
+        for (const SxArgs& a : args) t.push_back((int)((std::max(a.mstore, a.m) + 255) / 256));
+        B.add(s, args, t);
+        out.push_back(s);
+    }
     // pass over S: Y = S X
     void pass_sx() {
         const bool s16 = is16(L0().tin), f32 = L0().tin == DT_F32;
@@ -422,10 +434,10 @@ struct Recorder {
         };
         gram(dt, gargs(In, false));
         chol(cargs(0, 0));
-        sx(dt, dt, L0().nt, true, apply(In, Out, 0, false));
+        sx_tall(dt, L0().nt, true, apply(In, Out, 0, false));
         gram(dt, gargs(Out, false));
         chol(cargs(kfin, 1));
-        sx(dt, dt, L0().nt, true, apply(Out, Out, kfin, true));  // shifted retry, in place (no-op otherwise)
+        sx_tall(dt, L0().nt, true, apply(Out, Out, kfin, true));  // shifted retry, in place (no-op otherwise)
         gram(dt, gargs(Out, true));
         chol(cargs(kfin, 2));
         if (is16(L0().tin)) {
@@ -506,7 +518,7 @@ struct Recorder {
               }),
               tiles([](const Item& it) { return (it.L.lp * it.L.rp + 255) / 256; }));
         out.push_back(lf);
-        sx(L.tacc, L.tacc, L.ntr, false, each([&](const Item& it) {
+        sx_tall(L.tacc, L.ntr, false, each([&](const Item& it) {
                const void* Mx = it.L.tacc == DT_F64 ? (const void*)P->at<char>(it, it.L.o_M64)
                                                     : (const void*)P->at<char>(it, it.L.o_M32);
                return SxArgs{P->at<char>(it, it.L.o_Q1), it.L.mP, it.d.m, it.L.lp, Mx, it.L.lp,
@@ -800,7 +812,9 @@ rpod_status batch_layout(const rpod_desc* descs, int32_t count, const rpod_tunin
     }
     rpod_status ts = check_tuning(tune);
     if (ts != RPOD_OK) return ts;
-    int64_t wg = count == 1 ? 4096 : std::max<int64_t>(256, 8192 / count);
+    // single matrix: 5120 = ten rounds of two workgroups on 256 CUs (16-bit: 80 column blocks x
+    // 64 splits; the hi + lo pass, 40 x 64, five rounds)
+    int64_t wg = count == 1 ? 5120 : std::max<int64_t>(256, 8192 / count);
     if (tune && tune->stq_workgroups > 0) wg = tune->stq_workgroups;
     const int gcap = (tune && tune->gram_workgroups > 0) ? tune->gram_workgroups : 0;  // 0: automatic
     size_t off = 0;
