@@ -311,15 +311,24 @@ __global__ void k_reduce_slabs(Group<ReduceArgs> g) {
     const ReduceArgs& a = g.args[it];
     const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
     if (e >= a.count) return;
-    double s = 0.0;
+    // eight partial sums (slabs k = u mod 8: independent loads in flight), combined in a fixed order
+    double p8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int ns = a.nsplit;
+    int k = 0;
     if (a.f32) {
-        const GLOBAL float* Zp = gbl((const float*)a.Zp);
-        for (int k = 0; k < a.nsplit; ++k) s += (double)Zp[(int64_t)k * a.count + e];
+        const GLOBAL float* Zp = gbl((const float*)a.Zp) + e;
+        for (; k + 8 <= ns; k += 8)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p8[u] += (double)Zp[(int64_t)(k + u) * a.count];
+        for (; k < ns; ++k) p8[k & 7] += (double)Zp[(int64_t)k * a.count];
     } else {
-        const GLOBAL double* Zp = gbl((const double*)a.Zp);
-        for (int k = 0; k < a.nsplit; ++k) s += Zp[(int64_t)k * a.count + e];
+        const GLOBAL double* Zp = gbl((const double*)a.Zp) + e;
+        for (; k + 8 <= ns; k += 8)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p8[u] += Zp[(int64_t)(k + u) * a.count];
+        for (; k < ns; ++k) p8[k & 7] += Zp[(int64_t)k * a.count];
     }
-    *gbl(a.out + e) = s;
+    *gbl(a.out + e) = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
 }
 
 // ---------------------------------------------------------------------------
