@@ -138,7 +138,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.o_Q1 = take((size_t)L.mP * L.lp * sa);
     L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Ql = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
-    L.o_Zp = take((size_t)L.nsplit * L.nP * L.lp * 8);
+    L.o_Zp = take((size_t)L.nsplit * L.nP * L.lp * (L.tin == DT_F64 ? 8 : 4));  // FP32 slabs off the FP64 path
     L.o_Zt = take((size_t)L.nP * L.lp * 8);
     L.o_Zw = take((size_t)L.nP * L.lp * 8);
     L.o_Zw2 = take((size_t)L.nP * L.lp * 8);
