@@ -160,6 +160,7 @@ def test_fp64_fourier_field_l128():
     (40, 30, 20, 10, 0, torch.float64, 0),       # l == n == min(m, n)
     (300, 40, 1, 0, 3, torch.float64, 0),        # r = 1, p = 0
     (70000, 150, 33, 15, 2, torch.float32, 0),   # several row tiles and K splits
+    (20011, 600, 100, 28, 1, torch.float32, 0),  # l = 128: eight column tiles on every FP32 kernel
 ])
 def test_ragged_shapes(m, n, r, p, q, dtype, ldpad):
     g = synth.lowrank_exp(m, n, decay=0.08, noise_std=1e-5, seed=m + n)
