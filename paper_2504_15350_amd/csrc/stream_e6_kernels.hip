@@ -231,8 +231,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
 // column c: chunk k at k ^ ((c / 2) mod 8); Q column c: chunk k at
 // k ^ ((c / 4) mod 4)), which keeps both the staging writes and the operand
 // reads free of bank conflicts for every 16 lanes.
-// Splits interleaved in units of 64 rows (one 128-byte line of a Q part):
-// unit k of split s covers rows 64 (k nsplit + s) .. + 63, two steps.
+// Splits interleaved in units of 64 rows (256 bytes of an FP32 Q column):
+// unit k of split s covers rows 64 (k nsplit + s) .. + 63, two steps. Each
+// workgroup writes its FP32 accumulators as its split's slab (summed in FP64
+// afterwards).
 // Tiles go to the XCDs (workgroup b runs on XCD b mod 8) so that each XCD
 // holds every column block of its splits: the Q rows of a split are then
 // fetched into one L2 only.
