@@ -127,7 +127,7 @@ hipError_t launch_jacobi(int lp, const GroupLaunch<JacobiArgs>& L, hipStream_t s
 hipError_t launch_lift_coef(const GroupLaunch<LiftArgs>& L, hipStream_t st);
 
 // Per-column argmax |Phi| partials over row chunks (tiles nchunk x r), then
-// per-column signs (tiles ceil(r / 64), 64 threads).
+// per-column signs (one 64-lane wave per column, tiles r).
 hipError_t launch_signs(int tphi, const GroupLaunch<ColmaxArgs>& C, const GroupLaunch<SignArgs>& S, hipStream_t st);
 
 // Phi_out (m x r, ld m) = Phi_int * sign; A_out (r x n, ld r) = sign * At^T;

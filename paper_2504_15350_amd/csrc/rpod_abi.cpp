@@ -541,7 +541,7 @@ struct Recorder {
                   return SignArgs{P->at<double>(it, it.L.o_pval), P->at<int64_t>(it, it.L.o_pidx),
                                   P->at<double>(it, it.L.o_signs), it.d.r, it.L.nchunk};
               }),
-              tiles([](const Item& it) { return (it.d.r + 63) / 64; }), true);
+              tiles([](const Item& it) { return it.d.r; }), true);  // one wave per column
         out.push_back(sg);
         Step fn{K_FIN};
         fn.tin = L.tacc;

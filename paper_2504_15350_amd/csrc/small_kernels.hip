@@ -970,20 +970,32 @@ __global__ __launch_bounds__(256) void k_colmax(Group<ColmaxArgs> g) {
     }
 }
 
-__global__ void k_signs(Group<SignArgs> g) {
+// One wave per column: lane k takes chunks k, k + 64, .., then a butterfly
+// keeps the largest magnitude, lowest row on ties (the same entry whatever
+// the order of the comparisons).
+__global__ __launch_bounds__(64) void k_signs(Group<SignArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SignArgs& a = g.args[it];
-    const int c = (blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
-    if (c >= a.r) return;
+    const int c = blockIdx.x - g.tstart[it];
+    if (c >= a.r) return;  // uniform
+    const int lane = threadIdx.x;
     double best = -1.0, bval = 0.0;
     int64_t bidx = INT64_MAX;
-    for (int k = 0; k < a.nchunk; ++k) {
+    for (int k = lane; k < a.nchunk; k += 64) {
         const double v = a.pval[(int64_t)c * a.nchunk + k];
         const int64_t ix = a.pidx[(int64_t)c * a.nchunk + k];
         const double av = fabs(v);
         if (av > best || (av == best && ix < bidx)) { best = av; bval = v; bidx = ix; }
     }
-    a.signs[c] = (bval < 0.0) ? -1.0 : 1.0;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = shfl_xor_d(best, off), ov = shfl_xor_d(bval, off);
+        const unsigned long long ub = (unsigned long long)bidx;
+        const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)ub, off, 64);
+        const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(ub >> 32), off, 64);
+        const int64_t oi = (int64_t)(((unsigned long long)hi << 32) | lo);
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bval = ov; bidx = oi; }
+    }
+    if (lane == 0) a.signs[c] = (bval < 0.0) ? -1.0 : 1.0;
 }
 
 hipError_t launch_signs(int tphi, const GroupLaunch<ColmaxArgs>& C, const GroupLaunch<SignArgs>& S, hipStream_t st) {
