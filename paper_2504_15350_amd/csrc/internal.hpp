@@ -132,7 +132,7 @@ hipError_t launch_signs(int tphi, const GroupLaunch<ColmaxArgs>& C, const GroupL
 
 // Phi_out (m x r, ld m) = Phi_int * sign; A_out (r x n, ld r) = sign * At^T;
 // sigma_out = sig[:r]; the outputs come from the call table.
-int fin_phi_tiles(int64_t m, int r);
+int fin_phi_tiles(int64_t m, int r, int tphi);  // tphi: type of Phi_int
 int fin_a_tiles(int64_t n, int r);
 hipError_t launch_finalize(int tphi, const GroupLaunch<FinArgs>& P, const GroupLaunch<FinArgs>& A, hipStream_t st);
 

@@ -549,7 +549,7 @@ struct Recorder {
             return FinArgs{P->at<char>(it, it.L.o_Phi), it.L.mP, it.d.m, P->at<double>(it, it.L.o_At), it.L.nP,
                            it.d.n, P->at<double>(it, it.L.o_signs), P->at<double>(it, it.L.o_sig), it.d.r, it.idx};
         });
-        B.add(fn, fargs, tiles([](const Item& it) { return fin_phi_tiles(it.d.m, it.d.r); }));
+        B.add(fn, fargs, tiles([](const Item& it) { return fin_phi_tiles(it.d.m, it.d.r, it.L.tacc); }));
         B.add(fn, fargs, tiles([](const Item& it) { return fin_a_tiles(it.d.n, it.d.r); }), true);
         out.push_back(fn);
     }

@@ -805,6 +805,7 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
     for (; sweep < max_sweeps; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
+        bool rot = false;  // this lane's pair rotated during the sweep
         for (int rnd = 0; rnd < LP - 1; ++rnd) {
             int p, q;
             if (pr == 0) {
@@ -854,10 +855,13 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
                     *reinterpret_cast<d2*>(W + p * LDW + 16 * k + 2 * sub) = c * wp[k] - s * wq[k];
                     *reinterpret_cast<d2*>(W + q * LDW + 16 * k + 2 * sub) = s * wp[k] + c * wq[k];
                 }
-                if (sub == 0) s_rot = 1;
+                rot = true;
             }
             __syncthreads();
         }
+        // one flag write per wave and sweep (a shared write every round costs 7 %)
+        if (__ballot(rot) != 0 && lane == 0) s_rot = 1;
+        __syncthreads();
         if (s_rot == 0) break;
         __syncthreads();
     }
@@ -945,10 +949,25 @@ __global__ __launch_bounds__(256) void k_colmax(Group<ColmaxArgs> g) {
     const int64_t i1 = (i0 + a.chunk < a.m) ? i0 + a.chunk : a.m;
     double best = -1.0, bval = 0.0;
     int64_t bidx = INT64_MAX;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-        const double v = (double)Phi[(int64_t)c * a.ld + i];
+    const GLOBAL T* col = Phi + (int64_t)c * a.ld;
+    auto visit = [&](double v, int64_t i) {  // increasing i per thread: strict > keeps the first
         const double av = fabs(v);
-        if (av > best) { best = av; bidx = i; bval = v; }  // increasing i: strict > keeps first
+        if (av > best) { best = av; bidx = i; bval = v; }
+    };
+    constexpr int V = 16 / sizeof(T);  // 16-byte loads when the chunk starts on one
+    if ((a.ld % V) == 0 && (i0 % V) == 0) {
+        typedef T TV __attribute__((ext_vector_type(V)));
+        for (int64_t i = i0 + (int64_t)threadIdx.x * V; i < i1; i += 256 * V) {
+            if (i + V <= i1) {
+                const TV v = *reinterpret_cast<const GLOBAL TV*>(col + i);
+#pragma unroll
+                for (int k = 0; k < V; ++k) visit((double)v[k], i + k);
+            } else {
+                for (int64_t k = i; k < i1; ++k) visit((double)col[k], k);
+            }
+        }
+    } else {
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) visit((double)col[i], i);
     }
     __shared__ double sb[256], sv[256];
     __shared__ int64_t si[256];
@@ -1009,19 +1028,31 @@ hipError_t launch_signs(int tphi, const GroupLaunch<ColmaxArgs>& C, const GroupL
     return hipGetLastError();
 }
 
-// grouped: Phi tiles (rows 256 (t % nb).., column t / nb); outputs from the call table
+// grouped: Phi tiles (rows 256 V (t % nb).., column t / nb, V elements of 16 bytes per
+// thread); outputs from the call table
 template <typename T>
 __global__ void k_fin_phi(Group<FinArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const FinArgs& a = g.args[it];
     const int t = blockIdx.x - g.tstart[it];
-    const int nb = (int)((a.m + 255) / 256);
+    constexpr int V = 16 / sizeof(T);  // elements per thread
+    const int nb = (int)((a.m + 256 * V - 1) / (256 * V));
     const int c = t / nb;
-    const int64_t i = (int64_t)(t % nb) * blockDim.x + threadIdx.x;
+    const int64_t i = ((int64_t)(t % nb) * 256 + threadIdx.x) * V;
     if (i >= a.m) return;
-    GLOBAL T* Pout = gbl((T*)g.calls[a.call].Phi);
-    const GLOBAL T* Pin = gbl((const T*)a.Phi_int);
-    Pout[(int64_t)c * a.m + i] = (T)(a.signs[c] * (double)Pin[(int64_t)c * a.ldP + i]);
+    GLOBAL T* Pout = gbl((T*)g.calls[a.call].Phi) + (int64_t)c * a.m;
+    const GLOBAL T* Pin = gbl((const T*)a.Phi_int) + (int64_t)c * a.ldP;
+    const double sg = a.signs[c];  // +1 or -1: the products are exact
+    if (i + V <= a.m && (a.m % V) == 0 && (a.ldP % V) == 0 && ((uintptr_t)Pout % 16) == 0) {
+        typedef T TV __attribute__((ext_vector_type(V)));
+        const TV v = *reinterpret_cast<const GLOBAL TV*>(Pin + i);
+        TV o;
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = (T)(sg * (double)v[k]);
+        *reinterpret_cast<GLOBAL TV*>(Pout + i) = o;
+    } else {
+        for (int64_t k = i; k < i + V && k < a.m; ++k) Pout[k] = (T)(sg * (double)Pin[k]);
+    }
 }
 
 template <typename T>
@@ -1037,7 +1068,10 @@ __global__ void k_fin_a(Group<FinArgs> g) {
     gbl((T*)cd.A)[e] = (T)(a.signs[k] * gbl(a.At)[(int64_t)k * a.ldA + j]);
 }
 
-int fin_phi_tiles(int64_t m, int r) { return (int)((m + 255) / 256) * r; }
+int fin_phi_tiles(int64_t m, int r, int tphi) {
+    const int64_t span = 256 * (tphi == DT_F64 ? 2 : 4);
+    return (int)((m + span - 1) / span) * r;
+}
 int fin_a_tiles(int64_t n, int r) { return (int)(((n * r > r ? n * r : r) + 255) / 256); }
 
 hipError_t launch_finalize(int tphi, const GroupLaunch<FinArgs>& P, const GroupLaunch<FinArgs>& A, hipStream_t st) {
