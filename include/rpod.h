@@ -81,12 +81,28 @@ typedef enum {
  *   dtype  an rpod_dtype value: storage type of S.
  *   r      target rank, >= 1;  p oversampling, >= 0;  q subspace iterations, >= 0.
  *          The sketch width l = r + p must satisfy l <= min(m, n) and l <= 128.
- *   flags  reserved, must be 0. */
+ *   flags  reserved, must be 0.
+ *   block_cols  fluctuation snapshots (Sec. 4.1): 0 decomposes S as given;
+ *          N^t >= 1 decomposes S' = S - [mean_1 1^T ... mean_M 1^T], where
+ *          the columns form M = n / N^t consecutive blocks of N^t snapshots
+ *          (one block per parameter, its N^t time instants) and mean_k is the
+ *          mean of block k's columns (the time average of that parameter).
+ *          Phi, sigma and A are then those of S' (A = Phi^T S'). S itself is
+ *          read as given and never modified: the block sums come out of the
+ *          first pass over S as M extra sketch columns and every product with
+ *          S is corrected algebraically, so no pass is added. n must be a
+ *          multiple of N^t and l <= n - M (every block of S' sums to zero, so
+ *          rank(S') <= n - M; else RPOD_EINVAL); M <= 64 and roundup(l, 16) +
+ *          roundup(M, 16) <= 128 (else RPOD_EUNSUPPORTED); not with warm plans.
+ *          Accuracy: the correction subtracts terms of the size of the means,
+ *          so with FP32 or 16-bit S the error relative to S' grows with the
+ *          ratio of the means to the fluctuations. */
 typedef struct {
     int64_t m, n, ld;
     int32_t dtype;
     int32_t r, p, q;
     uint32_t flags;
+    int64_t block_cols;
 } rpod_desc;
 
 typedef struct rpod_plan_s* rpod_plan;

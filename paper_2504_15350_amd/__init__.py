@@ -38,7 +38,7 @@ class RpodError(RuntimeError):
 class _Desc(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("dtype", ctypes.c_int32), ("r", ctypes.c_int32), ("p", ctypes.c_int32),
-                ("q", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("q", ctypes.c_int32), ("flags", ctypes.c_uint32), ("block_cols", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -137,14 +137,15 @@ def _dev_ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_desc(m, n, r, p, q, dtype, ld=None, flags=0):
+def make_desc(m, n, r, p, q, dtype, ld=None, flags=0, block_cols=0):
     if dtype not in _DTYPES:
         raise TypeError(f"unsupported dtype {dtype}")
-    return _Desc(int(m), int(n), int(m if ld is None else ld), _DTYPES[dtype], int(r), int(p), int(q), int(flags))
+    return _Desc(int(m), int(n), int(m if ld is None else ld), _DTYPES[dtype], int(r), int(p), int(q), int(flags),
+                 int(block_cols))
 
 
-def workspace_size(m, n, r, p, q, dtype, ld=None):
-    d = make_desc(m, n, r, p, q, dtype, ld)
+def workspace_size(m, n, r, p, q, dtype, ld=None, block_cols=0):
+    d = make_desc(m, n, r, p, q, dtype, ld, block_cols=block_cols)
     out = ctypes.c_size_t(0)
     _check(lib().rpod_workspace_size(ctypes.byref(d), ctypes.byref(out)))
     return out.value
@@ -165,7 +166,8 @@ def _shape_descs(shapes, q, dtype):
     for sh in shapes:
         m, n, r, p = (int(x) for x in sh[:4])
         ld = int(sh[4]) if len(sh) > 4 else m
-        out.append(((m, n, r, p, ld), make_desc(m, n, r, p, q, dtype, ld)))
+        bc = int(sh[5]) if len(sh) > 5 else 0  # block_cols: fluctuations about block time averages
+        out.append(((m, n, r, p, ld), make_desc(m, n, r, p, q, dtype, ld, block_cols=bc)))
     return out
 
 
@@ -237,14 +239,15 @@ def _norm_device(device):
 class Plan(_PlanBase):
     """A plan for one matrix shape: rpod_plan_create / rpod_compute / rpod_status_query."""
 
-    def __init__(self, m, n, r, p, q, dtype=torch.float32, ld=None, device="cuda", stream=None):
+    def __init__(self, m, n, r, p, q, dtype=torch.float32, ld=None, device="cuda", stream=None, block_cols=0):
         self.device = _norm_device(device)
         self.m, self.n, self.r, self.p, self.q = int(m), int(n), int(r), int(p), int(q)
         self.ld = self.m if ld is None else int(ld)
         self.dtype = dtype
+        self.block_cols = int(block_cols)  # > 0: decompose the fluctuations about block time averages
         self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
-        self._desc = make_desc(m, n, r, p, q, dtype, ld)
-        nbytes = workspace_size(m, n, r, p, q, dtype, ld)
+        self._desc = make_desc(m, n, r, p, q, dtype, ld, block_cols=block_cols)
+        nbytes = workspace_size(m, n, r, p, q, dtype, ld, block_cols=block_cols)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         sptr, self.stream = _stream_ptr(stream, self.device)
         h = ctypes.c_void_p()
@@ -284,7 +287,8 @@ class Plan(_PlanBase):
 class BatchPlan(_PlanBase):
     """A plan for a batch of matrices: rpod_plan_create_batched / rpod_compute_batched.
 
-    shapes: list of (m, n, r, p) or (m, n, r, p, ld); all share dtype and q.
+    shapes: list of (m, n, r, p), (m, n, r, p, ld) or (m, n, r, p, ld, block_cols);
+    all share dtype and q.
     """
 
     def __init__(self, shapes, q, dtype=torch.float32, device="cuda", stream=None, tuning=None):

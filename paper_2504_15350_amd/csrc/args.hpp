@@ -55,6 +55,39 @@ struct ReduceArgs {  // out = sum of nsplit slabs
     int f32;
 };
 
+// Fluctuation snapshots (Sec. 4.1): S' = S - M E^T / N with M the block sums
+// (m x K, columns lp .. lp + K - 1 of the first pass's output), E the n x K
+// block indicator and N the block length. Column-major small matrices:
+// C[k + c K].
+struct CprepArgs {  // C = E^T X / N for the sketch-side operand X; optionally E itself
+    void* X;        // storage type, ld rows, columns 0 .. lp - 1 read, lp .. lp + K - 1 written when ind
+    int64_t ld, n, N;
+    double* C;      // K x lp
+    int lp, K, ind;
+};
+
+struct CenterYArgs {  // Y[:, c] -= sum_k M[:, k] C[k + c K], rows < m, c < lp
+    void* Y;          // FP32/FP64, ld rows, lp + K columns (M after the first lp)
+    int64_t ld, m;
+    const double* C;
+    int lp, K;
+};
+
+struct CrossArgs {  // slabs of P = M^T Q over row chunks of `chunk` rows
+    const void* M;  // FP32/FP64, ld rows, K columns
+    const void* Q;  // FP32/FP64, ld rows, lp columns
+    int64_t ld, m, chunk;
+    double* Pp;     // one K x lp slab per chunk
+    int lp, K;
+};
+
+struct CenterZArgs {  // Z[j, c] -= P[j / N + c K] / N, j < n, c < lp
+    double* Z;        // FP64, ld rows
+    int64_t ld, n, N;
+    const double* P;
+    int lp, K;
+};
+
 struct GramArgs {  // G = Y^T Y, FP64
     const void* Y;
     int64_t ld, M;

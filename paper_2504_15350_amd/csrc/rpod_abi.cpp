@@ -66,9 +66,14 @@ struct Layout {
     int64_t split_rows;
     int nchunk;
     int gram_cap;
+    // fluctuation centring (Sec. 4.1): K blocks of N columns; K = 0: none.
+    // The first pass runs nta = lpa / 16 column tiles (lpa = lp + roundup(K, 16)).
+    int K, lpa, nta, ncc;
+    int64_t N, cchunk;
     // byte offsets into the matrix's workspace region
     size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
+    size_t o_Cb, o_Cp, o_Pc;  // centring: E^T X / N, slabs of Msum^T Q1 and their sum
     size_t total;
 };
 
@@ -86,6 +91,19 @@ rpod_status validate(const rpod_desc* d) {
     const int64_t mn = d->m < d->n ? d->m : d->n;
     if (l > mn) return fail(RPOD_EINVAL, "l = r + p = %lld exceeds min(m, n) = %lld", (long long)l, (long long)mn);
     if (l > 128) return fail(RPOD_EUNSUPPORTED, "l = r + p = %lld exceeds 128", (long long)l);
+    if (d->block_cols < 0) return fail(RPOD_EINVAL, "block_cols must be >= 0 (got %lld)", (long long)d->block_cols);
+    if (d->block_cols > 0) {
+        if (d->n % d->block_cols != 0)
+            return fail(RPOD_EINVAL, "n (%lld) must be a multiple of block_cols (%lld)", (long long)d->n,
+                        (long long)d->block_cols);
+        const int64_t K = d->n / d->block_cols;
+        if (l > d->n - K)  // each block of S' sums to zero: rank(S') <= n - K
+            return fail(RPOD_EINVAL, "l = r + p = %lld exceeds n - blocks = %lld, the rank bound of the fluctuations",
+                        (long long)l, (long long)(d->n - K));
+        if (K > 64 || roundup(l, 16) + roundup(K, 16) > 128)
+            return fail(RPOD_EUNSUPPORTED, "%lld blocks with l = %lld: needs at most 64 blocks and "
+                        "roundup(l, 16) + roundup(blocks, 16) <= 128", (long long)K, (long long)l);
+    }
     return RPOD_OK;
 }
 
@@ -124,6 +142,12 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.ncb_lo = (int)(L.nP / stq16_block_cols(true));
     int64_t nc = d->m / 2048;
     L.nchunk = (int)(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
+    L.N = d->block_cols;
+    L.K = d->block_cols > 0 ? (int)(d->n / d->block_cols) : 0;
+    L.lpa = L.lp + (int)roundup(L.K, 16);
+    L.nta = L.lpa / 16;
+    L.cchunk = roundup((d->m + 255) / 256, 32);  // rows per slab of Msum^T Q1
+    L.ncc = L.K > 0 ? (int)((d->m + L.cchunk - 1) / L.cchunk) : 0;
 
     const size_t sa = dt_size(L.tacc), si = dt_size(L.tin);
     size_t off = 0;
@@ -133,8 +157,8 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
         return o;
     };
     const size_t lp2 = (size_t)L.lp * L.lp;
-    L.o_X = take((size_t)L.nP * L.lp * si);
-    L.o_Y = take((size_t)L.mP * L.lp * sa);
+    L.o_X = take((size_t)L.nP * L.lpa * si);  // centring: indicator columns after the first lp
+    L.o_Y = take((size_t)L.mP * L.lpa * sa);  // centring: block sums after the first lp
     L.o_Q1 = take((size_t)L.mP * L.lp * sa);
     L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Ql = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
@@ -158,6 +182,9 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.o_pval = take((size_t)L.rp * L.nchunk * 8);
     L.o_pidx = take((size_t)L.rp * L.nchunk * 8);
     L.o_signs = take((size_t)L.rp * 8);
+    L.o_Cb = take((size_t)L.K * L.lp * 8);
+    L.o_Cp = take((size_t)L.ncc * L.K * L.lp * 8);
+    L.o_Pc = take((size_t)L.K * L.lp * 8);
     L.total = off;
     return L;
 }
@@ -166,7 +193,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // Recorded program
 // ---------------------------------------------------------------------------
 enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXE6, K_SX16, K_STQ, K_STQE6, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT,
-            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE };
+            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE, K_CPREP, K_CY, K_CCROSS, K_CZ };
 
 struct Step {
     Kind kind;
@@ -330,11 +357,11 @@ struct Recorder {
         B.add(s, args, t);
         out.push_back(s);
     }
-    // pass over S: Y = S X
-    void pass_sx() {
+    // pass over S: Y = S X (first: with the centring indicator columns, if any)
+    void pass_sx(bool first = false) {
         const bool s16 = is16(L0().tin), f32 = L0().tin == DT_F32;
         Step s{s16 ? K_SX16 : f32 ? K_SXE6 : K_SX};
-        s.tin = L0().tin; s.tout = L0().tacc; s.nt = L0().nt; s.pass = 0;
+        s.tin = L0().tin; s.tout = L0().tacc; s.nt = first ? L0().nta : L0().nt; s.pass = 0;
         s.vec = true;
         for (const Item* it : C) {
             s.vec = s.vec && (it->d.ld % (s16 ? 8 : 4) == 0);
@@ -385,6 +412,60 @@ struct Recorder {
               }),
               tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
         out.push_back(r);
+    }
+    // Fluctuation centring (Sec. 4.1) of the products with S; no-ops without blocks.
+    bool centred() const { return L0().K > 0; }
+    // C = E^T X / N for the operand of the next S X pass (ind: also write E)
+    void center_prep(bool ind) {
+        if (!centred()) return;
+        Step s{K_CPREP};
+        s.tin = L0().tin;
+        B.add(s, each([&](const Item& it) {
+                  return CprepArgs{P->at<char>(it, it.L.o_X), it.L.nP, it.d.n, it.L.N, P->at<double>(it, it.L.o_Cb),
+                                   it.L.lp, it.L.K, ind ? 1 : 0};
+              }),
+              tiles([](const Item& it) { return it.L.K; }));
+        out.push_back(s);
+    }
+    // Y -= Msum C after an S X pass
+    void center_y() {
+        if (!centred()) return;
+        Step s{K_CY};
+        s.tin = L0().tacc;
+        B.add(s, each([&](const Item& it) {
+                  return CenterYArgs{P->at<char>(it, it.L.o_Y), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Cb),
+                                     it.L.lp, it.L.K};
+              }),
+              tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
+        out.push_back(s);
+    }
+    // Zt -= E (Msum^T Q1) / N after an S^T Q pass
+    void center_z() {
+        if (!centred()) return;
+        Step s{K_CCROSS};
+        s.tin = L0().tacc;
+        B.add(s, each([&](const Item& it) {
+                  const size_t so = dt_size(it.L.tacc);
+                  return CrossArgs{P->at<char>(it, it.L.o_Y) + (size_t)it.L.lp * it.L.mP * so,
+                                   P->at<char>(it, it.L.o_Q1), it.L.mP, it.d.m, it.L.cchunk,
+                                   P->at<double>(it, it.L.o_Cp), it.L.lp, it.L.K};
+              }),
+              tiles([](const Item& it) { return it.L.ncc; }));
+        out.push_back(s);
+        Step r{K_REDUCE};
+        B.add(r, each([&](const Item& it) {
+                  return ReduceArgs{P->at<double>(it, it.L.o_Cp), (int64_t)it.L.K * it.L.lp,
+                                    P->at<double>(it, it.L.o_Pc), it.L.ncc, 0};
+              }),
+              tiles([](const Item& it) { return (it.L.K * it.L.lp + 255) / 256; }));
+        out.push_back(r);
+        Step z{K_CZ};
+        B.add(z, each([&](const Item& it) {
+                  return CenterZArgs{P->at<double>(it, it.L.o_Zt), it.L.nP, it.d.n, it.L.N,
+                                     P->at<double>(it, it.L.o_Pc), it.L.lp, it.L.K};
+              }),
+              tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
+        out.push_back(z);
     }
     void gram(int dt, std::vector<GramArgs> args) {
         Step s{K_GRAM};
@@ -654,26 +735,32 @@ struct Recorder {
     }
     void record() {
         zero();
-        omega();         // Alg. 1 step 1
-        pass_sx();       // step 2
-        orth_tall(1);    // step 4 (Q of the sketch)
+        omega();            // Alg. 1 step 1
+        center_prep(true);  // (fluctuations: the indicator columns and E^T Omega / N)
+        pass_sx(true);      // step 2 (and the block sums of S)
+        center_y();
+        orth_tall(1);       // step 4 (Q of the sketch)
         for (int it = 0; it < C[0]->d.q; ++it) {  // step 3, re-orthonormalised after every product
             pass_stq(false);
+            center_z();
             small_from_slabs();
             basis_small();
+            center_prep(false);
             pass_sx();
+            center_y();
             orth_tall(1);
         }
-        pass_stq(true);  // step 5 (refinement on 16-bit paths)
+        pass_stq(true);     // step 5 (refinement on 16-bit paths)
+        center_z();
         small_from_slabs();
-        finish();        // steps 6, 7 and the coefficients
+        finish();           // steps 6, 7 and the coefficients
     }
 };
 
 // Classes: matrices sharing the kernel template parameters of every step.
 std::vector<std::vector<const Item*>> classes_of(const std::vector<Item>& items) {
     std::map<std::pair<int, int>, std::vector<const Item*>> m;
-    for (const Item& it : items) m[{it.L.nt, it.L.ntr}].push_back(&it);
+    for (const Item& it : items) m[{it.L.nt * 256 + it.L.nta, it.L.ntr}].push_back(&it);
     std::vector<std::vector<const Item*>> out;
     for (auto& kv : m) out.push_back(kv.second);
     return out;
@@ -701,6 +788,10 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_WZ: return launch_warm_z(P->gl<WarmZArgs>(s, false), st);
         case K_SXW: return launch_sx_wide(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
         case K_PROBE: return launch_warm_probe_res(P->gl<ProbeResArgs>(s, false), P->gl<ProbeFinalArgs>(s, true), st);
+        case K_CPREP: return launch_center_prep(s.tin, P->gl<CprepArgs>(s, false), st);
+        case K_CY: return launch_center_y(s.tin, P->gl<CenterYArgs>(s, false), st);
+        case K_CCROSS: return launch_center_cross(s.tin, P->gl<CrossArgs>(s, false), st);
+        case K_CZ: return launch_center_z(P->gl<CenterZArgs>(s, false), st);
     }
     return hipErrorInvalidValue;
 }
@@ -995,6 +1086,7 @@ rpod_status warm_build(rpod_plan_s* P, const rpod_desc* desc, rpod_warm_s* M, in
                        std::vector<char>* blob_out, size_t* bytes) {
     rpod_status s = warm_check(desc, M);
     if (s != RPOD_OK) return s;
+    if (desc->block_cols != 0) return fail(RPOD_EUNSUPPORTED, "warm plans take block_cols = 0");
     if (q_fb < 0) return fail(RPOD_EINVAL, "q_fallback must be >= 0");
     if (!(tol >= 0.0)) return fail(RPOD_EINVAL, "tol must be >= 0");
     BatchLayout bl;

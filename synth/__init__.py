@@ -20,6 +20,11 @@ fourier_field   a QG-like field on a cell-centred nx x ny grid of
                 lowest Dirichlet modes sin(kx x) sin(ky y),
                 kx = pi a, ky = pi b / 2, with amplitude |k|^-beta times a
                 stationary unit-variance AR(1) series, plus white noise.
+add_block_means adds a time average per parameter block (Sec. 4.1: the
+                columns form blocks of N^t consecutive snapshots, one block
+                per parameter): a random combination of the 12 lowest
+                Fourier modes per block, scaled to a given RMS, added to
+                every column of that block.
 batch_shapes    the shapes of an uneven batch: m in {2^16, 2^17, 2^18},
                 n in [500, 4000], r in {10, 25, 50, 100}, decay in
                 [0.05, 0.2], all drawn per matrix from the seed.
@@ -253,7 +258,7 @@ def lowrank_exp_device(m, n, decay, noise_std=1e-4, seed=1, K=256, dtype=None, d
 # parametric family for the learned warm start
 # ---------------------------------------------------------------------------
 # stream ids: 6 = skew generators, 7 = parameter draws, 8 = train/test split
-_S_SKEW, _S_MU, _S_SPLIT = 6, 7, 8
+_S_SKEW, _S_MU, _S_SPLIT, _S_MEAN = 6, 7, 8, 9
 
 # physical box of the parameter vector (delta, sigma, Fr, alpha), mapped to [-1, 1]^4
 PARAM_BOX = np.array([[0.2, 0.6], [0.006, 0.01], [0.07, 0.11], [0.05, 0.2]])
@@ -364,3 +369,22 @@ class ParamFamily:
                 blk += noise_std * torch.randn((t1 - t0, self.m), generator=gen, device=dev, dtype=torch.float32)
             St[t0:t1] = blk.to(dtype)
         return St
+
+
+def add_block_means(St, nx, ny, block_cols, rms, seed):
+    """St (n, m) plus a smooth field per block of block_cols rows of St (in place).
+
+    Block k's field is sum_i c_ki F_i over the 12 lowest Fourier modes F_i,
+    c_ki ~ N(0, 1) from (seed, stream _S_MEAN), scaled to element RMS `rms`.
+    Returns the (m, K) fields that were added, in FP64.
+    """
+    n, m = St.shape
+    K = n // block_cols
+    modes, _ = fourier_modes(nx, ny, 12)
+    F = fourier_basis(nx, ny, modes)                        # (m, 12)
+    c = rng(seed, _S_MEAN).standard_normal((12, K))
+    means = F @ c
+    means *= rms / np.sqrt(np.mean(means * means))
+    for k in range(K):
+        St[k * block_cols:(k + 1) * block_cols] += means[:, k].astype(St.dtype)[None, :]
+    return means

@@ -43,6 +43,12 @@ def test_library_exports_every_declared_symbol():
     (dict(m=10, n=10, r=8, p=3, q=0), 1),            # l > min(m, n)
     (dict(m=1000, n=1000, r=100, p=29, q=0), 5),      # l > 128
     (dict(m=100, n=100, r=4, p=2, q=1, ld=99), 1),     # ld < m
+    (dict(m=100, n=100, r=4, p=2, q=1, block_cols=-1), 1),   # negative block length
+    (dict(m=100, n=100, r=4, p=2, q=1, block_cols=30), 1),   # n not a multiple of the block length
+    (dict(m=100, n=64, r=4, p=2, q=1, block_cols=1), 1),     # one-column blocks: S' = 0
+    (dict(m=100, n=20, r=15, p=2, q=1, block_cols=5), 1),    # l = 17 > n - blocks = 16
+    (dict(m=1000, n=650, r=4, p=2, q=1, block_cols=10), 5),  # 65 blocks
+    (dict(m=1000, n=400, r=100, p=10, q=1, block_cols=20), 5),  # roundup(l) + roundup(blocks) > 128
 ])
 def test_workspace_size_rejects(kw, status):
     ld = kw.pop("ld", None)
@@ -59,6 +65,11 @@ def test_workspace_size_accepts_edges():
     c = rp.workspace_size(4096, 200, 100, 28, 1, torch.float32)     # l == 128
     assert 0 < a < b and c > 0
     assert b % 256 == 0
+    # fluctuation centring: the indicator and block-sum columns and the small buffers
+    bc = rp.workspace_size(262144, 5000, 50, 10, 2, torch.float32, block_cols=500)
+    assert bc > b and bc - b < 40 * 2 ** 20
+    assert rp.workspace_size(1000, 640, 50, 14, 1, torch.float32, block_cols=10) > 0   # 64 blocks, l = 64
+    assert rp.workspace_size(1000, 300, 100, 12, 1, torch.bfloat16, block_cols=300) > 0  # one block, l = 112
 
 
 @needs_lib
