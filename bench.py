@@ -29,6 +29,11 @@ rPOD (q = 2) and by warm-started rPOD (q = 0 and 1, residual tolerance 1e-3,
 plain q = 2 as the fallback), in FP32 and BF16; errors are against the
 generator's exact singular values. Reported under "warm_vs_plain".
 
+Also measured (unless --no-center): fluctuation centring (Sec. 4.1) on the
+main workload with ten parameter blocks of 500 snapshots, each block given a
+smooth time average of the field's RMS: the plain plan against the centred
+plan (block_cols = 500) on that matrix, reported under "centred_vs_plain".
+
 Per-kernel times of the passes over S come from HIP events that the library
 records on its stream around every pass during the timed steps.
 """
@@ -123,14 +128,14 @@ def load_traffic(workload, kernel):
     return rec.get("bytes_per_launch")
 
 
-def measure(name, St, steps, warmup):
+def measure(name, St, steps, warmup, block_cols=0):
     """Time `steps` rPOD calls; per-pass kernel times from the library's HIP events."""
     import torch
     import paper_2504_15350_amd as rp
     w = WORKLOADS[name]
     n, m = St.shape
     dev = St.device
-    plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=St.dtype, device=dev)
+    plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=St.dtype, device=dev, block_cols=block_cols)
     out = (torch.empty((w["r"], m), dtype=plan.out_dtype, device=dev),
            torch.empty((w["r"],), dtype=torch.float64, device=dev),
            torch.empty((n, w["r"]), dtype=plan.out_dtype, device=dev))
@@ -408,6 +413,36 @@ def warm_block(dev, reps):
             "results": out}
 
 
+CENTER = dict(block_cols=500, mean_rms=1.0, seed=2)
+
+
+def center_block(St, steps, warmup):
+    """Fluctuation centring on the main workload: ten parameter blocks of 500
+    snapshots, each given a smooth time average of the fluctuations' RMS (added
+    to St in place); the plain and the centred plan timed on that matrix."""
+    import torch
+    import synth
+    w = WORKLOADS[DEFAULT]
+    n, m = St.shape
+    N = CENTER["block_cols"]
+    K = n // N
+    rms = float(St[:64].double().pow(2).mean().sqrt())
+    means = synth.add_block_means(np.zeros((K, m), np.float32), w["nx"], w["ny"], 1, CENTER["mean_rms"] * rms,
+                                  CENTER["seed"])
+    St.view(K, N, m).add_(torch.from_numpy(means.T.astype(np.float32)).to(St.device)[:, None, :])
+    torch.cuda.synchronize()
+    plain = measure(DEFAULT, St, steps, warmup)
+    cen = measure(DEFAULT, St, steps, warmup, block_cols=N)
+    return {
+        "config": {"workload": DEFAULT, "block_cols": N, "blocks": K, "mean_rms_over_field_rms": CENTER["mean_rms"],
+                   "steps": steps},
+        "plain_ms": round(plain["ms"], 4), "centred_ms": round(cen["ms"], 4),
+        "overhead": round(cen["ms"] / plain["ms"] - 1.0, 4),
+        "sigma1_plain": float(plain["sigma"][0]), "sigma1_centred": float(cen["sigma"][0]),
+        "centred_kernels": cen["kernels"], "centred_roofline": cen["roofline"],
+    }
+
+
 def cpu_baseline(St, w, seed):
     """The oracle's FP64 rPOD (as it stands) on a row sample, scaled to the full matrix."""
     from oracle import philox
@@ -442,6 +477,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-vs-plain measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batch measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start sweep")
+    ap.add_argument("--no-center", action="store_true", help="skip the fluctuation-centring measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES bytes (the reference kernel for scaling "
                          "HBM byte counters) and exit")
@@ -475,6 +511,10 @@ def main():
         log("[bench] timing the CPU oracle on a row sample ...")
         cpu = cpu_baseline(St, w, w["seed"])
         log(f"[bench] cpu baseline {cpu['value']:.0f} ms ({cpu['sample']})")
+    center = None
+    if not args.no_center and args.workload == DEFAULT:
+        center = center_block(St, max(3, args.steps // 2), max(1, args.warmup // 2))
+        log(f"[bench] centring: plain {center['plain_ms']:.3f} ms, centred {center['centred_ms']:.3f} ms")
     del St
     torch.cuda.empty_cache()
 
@@ -532,6 +572,7 @@ def main():
         "mixed_vs_plain": extra,
         "batched_vs_plain": batch,
         "warm_vs_plain": warm,
+        "centred_vs_plain": center,
     }
     print(json.dumps(res), flush=True)
 

@@ -73,12 +73,18 @@ struct CenterYArgs {  // Y[:, c] -= sum_k M[:, k] C[k + c K], rows < m, c < lp
     int lp, K;
 };
 
-struct CrossArgs {  // slabs of P = M^T Q over row chunks of `chunk` rows
+struct CrossArgs {  // partial sums of P = M^T Q over row chunks of `chunk` rows
     const void* M;  // FP32/FP64, ld rows, K columns
     const void* Q;  // FP32/FP64, ld rows, lp columns
     int64_t ld, m, chunk;
-    double* Pp;     // one K x lp slab per chunk
-    int lp, K;
+    double* Pp;     // entry-major: Pp[o * nchunk + chunk index], o = k + c K
+    int lp, K, nchunk;
+};
+
+struct CrossSumArgs {  // P[o] = sum over the nchunk partial sums of entry o
+    const double* Pp;
+    double* P;
+    int count, nchunk;
 };
 
 struct CenterZArgs {  // Z[j, c] -= P[j / N + c K] / N, j < n, c < lp

@@ -82,12 +82,13 @@ int stq_e6_block_cols();
 // f32 is set, else FP64); one workgroup per 256 elements.
 hipError_t launch_reduce_slabs(const GroupLaunch<ReduceArgs>& L, hipStream_t st);
 
-// Fluctuation centring (one workgroup per block for cprep, 256 rows per tile
-// for center_y, one tile per row chunk for cross, 256 entries per tile for
-// center_z). tx: storage type of X; tacc: type of Y, M and Q.
+// Fluctuation centring (K lp / 4 tiles for cprep: block k = t mod K, columns
+// 4 (t / K) ..; 256 rows per tile for center_y; one tile per row chunk for
+// cross; 256 entries per tile for center_z). tx: storage type of X; tacc: type of Y, M and Q.
 hipError_t launch_center_prep(int tx, const GroupLaunch<CprepArgs>& L, hipStream_t st);
 hipError_t launch_center_y(int tacc, const GroupLaunch<CenterYArgs>& L, hipStream_t st);
 hipError_t launch_center_cross(int tacc, const GroupLaunch<CrossArgs>& L, hipStream_t st);
+hipError_t launch_center_sum(const GroupLaunch<CrossSumArgs>& L, hipStream_t st);  // one tile per entry
 hipError_t launch_center_z(const GroupLaunch<CenterZArgs>& L, hipStream_t st);
 
 // Gram matrix G = Y^T Y in FP64 of a tall M x 16*nt column-major matrix

@@ -146,7 +146,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.K = d->block_cols > 0 ? (int)(d->n / d->block_cols) : 0;
     L.lpa = L.lp + (int)roundup(L.K, 16);
     L.nta = L.lpa / 16;
-    L.cchunk = roundup((d->m + 255) / 256, 32);  // rows per slab of Msum^T Q1
+    L.cchunk = roundup((d->m + 1023) / 1024, 32);  // rows per partial sum of Msum^T Q1 (up to 1024)
     L.ncc = L.K > 0 ? (int)((d->m + L.cchunk - 1) / L.cchunk) : 0;
 
     const size_t sa = dt_size(L.tacc), si = dt_size(L.tin);
@@ -193,7 +193,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // Recorded program
 // ---------------------------------------------------------------------------
 enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXE6, K_SX16, K_STQ, K_STQE6, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT,
-            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE, K_CPREP, K_CY, K_CCROSS, K_CZ };
+            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE, K_CPREP, K_CY, K_CCROSS, K_CSUM, K_CZ };
 
 struct Step {
     Kind kind;
@@ -424,7 +424,7 @@ struct Recorder {
                   return CprepArgs{P->at<char>(it, it.L.o_X), it.L.nP, it.d.n, it.L.N, P->at<double>(it, it.L.o_Cb),
                                    it.L.lp, it.L.K, ind ? 1 : 0};
               }),
-              tiles([](const Item& it) { return it.L.K; }));
+              tiles([](const Item& it) { return it.L.K * (it.L.lp / 4); }));
         out.push_back(s);
     }
     // Y -= Msum C after an S X pass
@@ -436,7 +436,7 @@ struct Recorder {
                   return CenterYArgs{P->at<char>(it, it.L.o_Y), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Cb),
                                      it.L.lp, it.L.K};
               }),
-              tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
+              tiles([](const Item& it) { return (int)((it.d.m + 255) / 256); }));
         out.push_back(s);
     }
     // Zt -= E (Msum^T Q1) / N after an S^T Q pass
@@ -448,16 +448,16 @@ struct Recorder {
                   const size_t so = dt_size(it.L.tacc);
                   return CrossArgs{P->at<char>(it, it.L.o_Y) + (size_t)it.L.lp * it.L.mP * so,
                                    P->at<char>(it, it.L.o_Q1), it.L.mP, it.d.m, it.L.cchunk,
-                                   P->at<double>(it, it.L.o_Cp), it.L.lp, it.L.K};
+                                   P->at<double>(it, it.L.o_Cp), it.L.lp, it.L.K, it.L.ncc};
               }),
               tiles([](const Item& it) { return it.L.ncc; }));
         out.push_back(s);
-        Step r{K_REDUCE};
+        Step r{K_CSUM};
         B.add(r, each([&](const Item& it) {
-                  return ReduceArgs{P->at<double>(it, it.L.o_Cp), (int64_t)it.L.K * it.L.lp,
-                                    P->at<double>(it, it.L.o_Pc), it.L.ncc, 0};
+                  return CrossSumArgs{P->at<double>(it, it.L.o_Cp), P->at<double>(it, it.L.o_Pc), it.L.K * it.L.lp,
+                                      it.L.ncc};
               }),
-              tiles([](const Item& it) { return (it.L.K * it.L.lp + 255) / 256; }));
+              tiles([](const Item& it) { return it.L.K * it.L.lp; }));
         out.push_back(r);
         Step z{K_CZ};
         B.add(z, each([&](const Item& it) {
@@ -791,6 +791,7 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_CPREP: return launch_center_prep(s.tin, P->gl<CprepArgs>(s, false), st);
         case K_CY: return launch_center_y(s.tin, P->gl<CenterYArgs>(s, false), st);
         case K_CCROSS: return launch_center_cross(s.tin, P->gl<CrossArgs>(s, false), st);
+        case K_CSUM: return launch_center_sum(P->gl<CrossSumArgs>(s, false), st);
         case K_CZ: return launch_center_z(P->gl<CenterZArgs>(s, false), st);
     }
     return hipErrorInvalidValue;
