@@ -81,7 +81,9 @@ typedef enum {
  *   dtype  an rpod_dtype value: storage type of S.
  *   r      target rank, >= 1;  p oversampling, >= 0;  q subspace iterations, >= 0.
  *          The sketch width l = r + p must satisfy l <= min(m, n) and l <= 128.
- *   flags  reserved, must be 0.
+ *   flags  0, or RPOD_DESC_ENERGY: the plan also computes ||S||_F^2 (one
+ *          more read of S per compute call, before the sketch) so that
+ *          rpod_energy() can report the energy of the computed modes.
  *   block_cols  fluctuation snapshots (Sec. 4.1): 0 decomposes S as given;
  *          N^t >= 1 decomposes S' = S - [mean_1 1^T ... mean_M 1^T], where
  *          the columns form M = n / N^t consecutive blocks of N^t snapshots
@@ -104,6 +106,9 @@ typedef struct {
     uint32_t flags;
     int64_t block_cols;
 } rpod_desc;
+
+/* rpod_desc.flags bits. */
+#define RPOD_DESC_ENERGY 0x1u  /* compute ||S||_F^2 for rpod_energy() */
 
 typedef struct rpod_plan_s* rpod_plan;
 
@@ -222,6 +227,20 @@ rpod_status rpod_compute_batched(rpod_plan plan, const void* const* S, const uin
  * entries, may be NULL) receives each matrix's status word; the return
  * value reflects the OR of all of them. */
 rpod_status rpod_status_query_batched(rpod_plan plan, int32_t* per_matrix_flags);
+
+/* Energy of the computed modes (Sec. 4.1, the energy criterion that picks the
+ * number of modes from a threshold 0 < delta < 1), read with squared singular
+ * values (the eigenvalue energy of the paper's tables): after a compute call
+ * on a plan made with RPOD_DESC_ENERGY, energy (host, l = r + p values)
+ * receives e_k = (sigma_1^2 + .. + sigma_k^2) / ||S||_F^2, k = 1..l, from the
+ * l singular values of the sketched problem (each at most the true sigma_k, so
+ * e_k never overstates the energy) and ||S||_F^2 computed on the GPU in FP64
+ * (not with block_cols: RPOD_EUNSUPPORTED at plan creation). *rank (host, may be NULL) receives the
+ * smallest k with e_k >= delta, or -1 when e_l < delta (a larger r + p is
+ * needed). item selects the matrix of a batched plan (0 otherwise).
+ * Synchronises the plan's stream. RPOD_EINVAL: NULL plan or energy, item out
+ * of range, delta outside (0, 1), or a plan made without RPOD_DESC_ENERGY. */
+rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* energy, int32_t* rank);
 
 /* The Gaussian sketch of Alg. 1 step 1 (entries N(0,1), Sec. 4.2), drawn on
  * the GPU: out (device) receives the n x l matrix column-major with leading

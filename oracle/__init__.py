@@ -15,6 +15,7 @@ pod      O1: deterministic POD by the thin SVD of the snapshot matrix
 rpod     O2: randomized POD, Alg. 1 of Sec. 4.2 (stable form with
          re-orthonormalisation after every product), and the literal form.
 metrics  sign-invariant comparison metrics (principal angles, sigma errors).
+energy   the energy of the leading modes and the rank rule (Sec. 4.1).
 center   fluctuation snapshots (Sec. 4.1): each snapshot minus the time
          average of its parameter's block of columns.
 warm     the learned warm start (an extension of Alg. 1, not in the paper):

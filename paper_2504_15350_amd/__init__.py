@@ -81,6 +81,7 @@ def lib():
             "rpod_plan_destroy": [vp],
             "rpod_compute": [vp, vp, u64, vp, vp, vp],
             "rpod_status_query": [vp, ctypes.POINTER(i32)],
+            "rpod_energy": [vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
             "rpod_generate_omega": [u64, i64, i32, i32, vp, i64, vp],
             "rpod_sketch_bits": [u64, i64, i32, vp, vp],
             "rpod_plan_set_timing": [vp, i32],
@@ -144,8 +145,11 @@ def make_desc(m, n, r, p, q, dtype, ld=None, flags=0, block_cols=0):
                  int(block_cols))
 
 
-def workspace_size(m, n, r, p, q, dtype, ld=None, block_cols=0):
-    d = make_desc(m, n, r, p, q, dtype, ld, block_cols=block_cols)
+DESC_ENERGY = 0x1  # rpod_desc.flags: compute ||S||_F^2 for rpod_energy
+
+
+def workspace_size(m, n, r, p, q, dtype, ld=None, block_cols=0, flags=0):
+    d = make_desc(m, n, r, p, q, dtype, ld, flags=flags, block_cols=block_cols)
     out = ctypes.c_size_t(0)
     _check(lib().rpod_workspace_size(ctypes.byref(d), ctypes.byref(out)))
     return out.value
@@ -239,15 +243,17 @@ def _norm_device(device):
 class Plan(_PlanBase):
     """A plan for one matrix shape: rpod_plan_create / rpod_compute / rpod_status_query."""
 
-    def __init__(self, m, n, r, p, q, dtype=torch.float32, ld=None, device="cuda", stream=None, block_cols=0):
+    def __init__(self, m, n, r, p, q, dtype=torch.float32, ld=None, device="cuda", stream=None, block_cols=0,
+                 energy=False):
         self.device = _norm_device(device)
         self.m, self.n, self.r, self.p, self.q = int(m), int(n), int(r), int(p), int(q)
         self.ld = self.m if ld is None else int(ld)
         self.dtype = dtype
         self.block_cols = int(block_cols)  # > 0: decompose the fluctuations about block time averages
         self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
-        self._desc = make_desc(m, n, r, p, q, dtype, ld, block_cols=block_cols)
-        nbytes = workspace_size(m, n, r, p, q, dtype, ld, block_cols=block_cols)
+        flags = DESC_ENERGY if energy else 0
+        self._desc = make_desc(m, n, r, p, q, dtype, ld, flags=flags, block_cols=block_cols)
+        nbytes = workspace_size(m, n, r, p, q, dtype, ld, block_cols=block_cols, flags=flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         sptr, self.stream = _stream_ptr(stream, self.device)
         h = ctypes.c_void_p()
@@ -273,6 +279,16 @@ class Plan(_PlanBase):
         if check:
             self.status()
         return Phi, sigma, A
+
+    def energy(self, delta):
+        """rpod_energy after a compute call (plans made with energy=True):
+        (e_k = sum_{i<=k} sigma_i^2 / ||S||_F^2 for k = 1..r+p as a numpy array,
+        the smallest k with e_k >= delta or -1)."""
+        import numpy as np
+        e = (ctypes.c_double * (self.r + self.p))()
+        rk = ctypes.c_int32(0)
+        _check(lib().rpod_energy(self._h, 0, ctypes.c_double(float(delta)), e, ctypes.byref(rk)))
+        return np.array(e[:], dtype=np.float64), rk.value
 
     def status(self):
         """Synchronise and return the device flags; raise on an error status."""

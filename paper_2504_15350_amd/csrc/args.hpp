@@ -94,6 +94,14 @@ struct CenterZArgs {  // Z[j, c] -= P[j / N + c K] / N, j < n, c < lp
     int lp, K;
 };
 
+struct FrobArgs {  // ||S||_F^2: per-workgroup partial sums, then their sum
+    const void* S;    // storage type; from call table entry `call` when call >= 0
+    int64_t ld, m, n;
+    double* part;     // nwg partial sums
+    double* out;      // the sum
+    int nwg, call;
+};
+
 struct GramArgs {  // G = Y^T Y, FP64
     const void* Y;
     int64_t ld, M;

@@ -89,6 +89,11 @@ hipError_t launch_center_prep(int tx, const GroupLaunch<CprepArgs>& L, hipStream
 hipError_t launch_center_y(int tacc, const GroupLaunch<CenterYArgs>& L, hipStream_t st);
 hipError_t launch_center_cross(int tacc, const GroupLaunch<CrossArgs>& L, hipStream_t st);
 hipError_t launch_center_sum(const GroupLaunch<CrossSumArgs>& L, hipStream_t st);  // one tile per entry
+
+// ||S||_F^2 in FP64 (tin: storage type): nwg tiles of partial sums (columns
+// strided over the tiles), then one tile adding them in order.
+hipError_t launch_frob(int tin, bool vec, const GroupLaunch<FrobArgs>& P, const GroupLaunch<FrobArgs>& F,
+                       hipStream_t st);
 hipError_t launch_center_z(const GroupLaunch<CenterZArgs>& L, hipStream_t st);
 
 // Gram matrix G = Y^T Y in FP64 of a tall M x 16*nt column-major matrix

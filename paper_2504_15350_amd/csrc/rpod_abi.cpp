@@ -74,6 +74,8 @@ struct Layout {
     size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
     size_t o_Cb, o_Cp, o_Pc;  // centring: E^T X / N, slabs of Msum^T Q1 and their sum
+    size_t o_Fp, o_Fro;       // energy: partial sums of ||S||_F^2 and the sum
+    int nfro;                 // their count (0 without RPOD_DESC_ENERGY)
     size_t total;
 };
 
@@ -85,7 +87,7 @@ rpod_status validate(const rpod_desc* d) {
     if (d->r < 1) return fail(RPOD_EINVAL, "r must be >= 1 (r=%d)", d->r);
     if (d->p < 0) return fail(RPOD_EINVAL, "p must be >= 0 (p=%d)", d->p);
     if (d->q < 0) return fail(RPOD_EINVAL, "q must be >= 0 (q=%d)", d->q);
-    if (d->flags != 0) return fail(RPOD_EINVAL, "flags must be 0");
+    if ((d->flags & ~RPOD_DESC_ENERGY) != 0) return fail(RPOD_EINVAL, "unknown flags 0x%x", d->flags);
     if (d->dtype < RPOD_F64 || d->dtype > RPOD_F16) return fail(RPOD_EINVAL, "unknown dtype %d", d->dtype);
     const int64_t l = (int64_t)d->r + d->p;
     const int64_t mn = d->m < d->n ? d->m : d->n;
@@ -93,6 +95,8 @@ rpod_status validate(const rpod_desc* d) {
     if (l > 128) return fail(RPOD_EUNSUPPORTED, "l = r + p = %lld exceeds 128", (long long)l);
     if (d->block_cols < 0) return fail(RPOD_EINVAL, "block_cols must be >= 0 (got %lld)", (long long)d->block_cols);
     if (d->block_cols > 0) {
+        if (d->flags & RPOD_DESC_ENERGY)
+            return fail(RPOD_EUNSUPPORTED, "RPOD_DESC_ENERGY is not available with block_cols");
         if (d->n % d->block_cols != 0)
             return fail(RPOD_EINVAL, "n (%lld) must be a multiple of block_cols (%lld)", (long long)d->n,
                         (long long)d->block_cols);
@@ -185,6 +189,9 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.o_Cb = take((size_t)L.K * L.lp * 8);
     L.o_Cp = take((size_t)L.ncc * L.K * L.lp * 8);
     L.o_Pc = take((size_t)L.K * L.lp * 8);
+    L.nfro = (d->flags & RPOD_DESC_ENERGY) ? 1024 : 0;
+    L.o_Fp = take((size_t)L.nfro * 8);
+    L.o_Fro = take(8);
     L.total = off;
     return L;
 }
@@ -193,7 +200,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // Recorded program
 // ---------------------------------------------------------------------------
 enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXE6, K_SX16, K_STQ, K_STQE6, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT,
-            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE, K_CPREP, K_CY, K_CCROSS, K_CSUM, K_CZ };
+            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE, K_CPREP, K_CY, K_CCROSS, K_CSUM, K_CZ, K_FROB };
 
 struct Step {
     Kind kind;
@@ -412,6 +419,22 @@ struct Recorder {
               }),
               tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
         out.push_back(r);
+    }
+    // ||S||_F^2 for the energy of the modes (plans with RPOD_DESC_ENERGY; a no-op otherwise)
+    void frob() {
+        if (L0().nfro == 0) return;
+        Step s{K_FROB};
+        s.tin = L0().tin;
+        s.vec = true;
+        // 16-byte loads where rpod_compute requires S to be 16-byte aligned (ld a multiple of 4, or 8 for 16-bit)
+        for (const Item* it : C) s.vec = s.vec && (it->d.ld % (is16(it->L.tin) ? 8 : 4) == 0);
+        auto args = each([&](const Item& it) {
+            return FrobArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<double>(it, it.L.o_Fp), P->at<double>(it, it.L.o_Fro),
+                            it.L.nfro, it.idx};
+        });
+        B.add(s, args, tiles([](const Item& it) { return it.L.nfro; }));
+        B.add(s, args, tiles([](const Item&) { return 1; }), true);
+        out.push_back(s);
     }
     // Fluctuation centring (Sec. 4.1) of the products with S; no-ops without blocks.
     bool centred() const { return L0().K > 0; }
@@ -735,6 +758,7 @@ struct Recorder {
     }
     void record() {
         zero();
+        frob();             // (energy: ||S||_F^2)
         omega();            // Alg. 1 step 1
         center_prep(true);  // (fluctuations: the indicator columns and E^T Omega / N)
         pass_sx(true);      // step 2 (and the block sums of S)
@@ -760,7 +784,7 @@ struct Recorder {
 // Classes: matrices sharing the kernel template parameters of every step.
 std::vector<std::vector<const Item*>> classes_of(const std::vector<Item>& items) {
     std::map<std::pair<int, int>, std::vector<const Item*>> m;
-    for (const Item& it : items) m[{it.L.nt * 256 + it.L.nta, it.L.ntr}].push_back(&it);
+    for (const Item& it : items) m[{(it.L.nt * 256 + it.L.nta) * 2 + (it.L.nfro > 0), it.L.ntr}].push_back(&it);
     std::vector<std::vector<const Item*>> out;
     for (auto& kv : m) out.push_back(kv.second);
     return out;
@@ -793,6 +817,7 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_CCROSS: return launch_center_cross(s.tin, P->gl<CrossArgs>(s, false), st);
         case K_CSUM: return launch_center_sum(P->gl<CrossSumArgs>(s, false), st);
         case K_CZ: return launch_center_z(P->gl<CenterZArgs>(s, false), st);
+        case K_FROB: return launch_frob(s.tin, s.vec, P->gl<FrobArgs>(s, false), P->gl<FrobArgs>(s, true), st);
     }
     return hipErrorInvalidValue;
 }
@@ -1088,6 +1113,7 @@ rpod_status warm_build(rpod_plan_s* P, const rpod_desc* desc, rpod_warm_s* M, in
     rpod_status s = warm_check(desc, M);
     if (s != RPOD_OK) return s;
     if (desc->block_cols != 0) return fail(RPOD_EUNSUPPORTED, "warm plans take block_cols = 0");
+    if (desc->flags != 0) return fail(RPOD_EUNSUPPORTED, "warm plans take flags = 0");
     if (q_fb < 0) return fail(RPOD_EINVAL, "q_fallback must be >= 0");
     if (!(tol >= 0.0)) return fail(RPOD_EINVAL, "tol must be >= 0");
     BatchLayout bl;
@@ -1461,6 +1487,30 @@ rpod_status rpod_status_query_batched(rpod_plan plan, int32_t* per_matrix_flags)
     }
     if (all & RPOD_FLAG_NONFINITE) return fail(RPOD_EINVAL_DATA, "non-finite values in S");
     if (all & RPOD_FLAG_BREAKDOWN) return fail(RPOD_EBREAKDOWN, "sketch rank-deficient after the shifted CholeskyQR retry");
+    return RPOD_OK;
+}
+
+rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* energy, int32_t* rank) {
+    if (plan == nullptr || energy == nullptr) return fail(RPOD_EINVAL, "plan and energy must be non-NULL");
+    if (item < 0 || item >= (int32_t)plan->items.size())
+        return fail(RPOD_EINVAL, "item %d out of range (the plan has %zu matrices)", item, plan->items.size());
+    if (!(delta > 0.0 && delta < 1.0)) return fail(RPOD_EINVAL, "delta must lie in (0, 1)");
+    const Item& it = plan->items[item];
+    if (it.L.nfro == 0) return fail(RPOD_EINVAL, "the plan was made without RPOD_DESC_ENERGY");
+    std::vector<double> sig(it.L.lp, 0.0);
+    double fro = 0.0;
+    HIP_TRY(hipMemcpyAsync(sig.data(), plan->at<double>(it, it.L.o_sig), sizeof(double) * it.L.lp,
+                           hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipMemcpyAsync(&fro, plan->at<double>(it, it.L.o_Fro), sizeof(double), hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipStreamSynchronize(plan->st));
+    int32_t rk = -1;
+    double acc = 0.0;
+    for (int k = 0; k < it.L.l; ++k) {
+        acc += sig[k] * sig[k];
+        energy[k] = fro > 0.0 ? acc / fro : 0.0;
+        if (rk < 0 && energy[k] >= delta) rk = k + 1;
+    }
+    if (rank) *rank = rk;
     return RPOD_OK;
 }
 

@@ -49,6 +49,8 @@ def test_library_exports_every_declared_symbol():
     (dict(m=100, n=20, r=15, p=2, q=1, block_cols=5), 1),    # l = 17 > n - blocks = 16
     (dict(m=1000, n=650, r=4, p=2, q=1, block_cols=10), 5),  # 65 blocks
     (dict(m=1000, n=400, r=100, p=10, q=1, block_cols=20), 5),  # roundup(l) + roundup(blocks) > 128
+    (dict(m=100, n=100, r=4, p=2, q=1, flags=2), 1),           # unknown flag
+    (dict(m=100, n=100, r=4, p=2, q=1, flags=1, block_cols=10), 5),  # energy with centring
 ])
 def test_workspace_size_rejects(kw, status):
     ld = kw.pop("ld", None)
@@ -70,6 +72,8 @@ def test_workspace_size_accepts_edges():
     assert bc > b and bc - b < 40 * 2 ** 20
     assert rp.workspace_size(1000, 640, 50, 14, 1, torch.float32, block_cols=10) > 0   # 64 blocks, l = 64
     assert rp.workspace_size(1000, 300, 100, 12, 1, torch.bfloat16, block_cols=300) > 0  # one block, l = 112
+    # energy: the partial sums of ||S||_F^2
+    assert rp.workspace_size(262144, 5000, 50, 10, 2, torch.float32, flags=rp.DESC_ENERGY) > b
 
 
 @needs_lib
