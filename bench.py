@@ -34,6 +34,10 @@ main workload with ten parameter blocks of 500 snapshots, each block given a
 smooth time average of the field's RMS: the plain plan against the centred
 plan (block_cols = 500) on that matrix, reported under "centred_vs_plain".
 
+Also measured with the centring (same switch): a plan with the energy report
+(RPOD_DESC_ENERGY: ||S||_F^2 on the GPU, one more read of S) on the main
+workload, reported under "energy_report" with the energies of the modes.
+
 Per-kernel times of the passes over S come from HIP events that the library
 records on its stream around every pass during the timed steps.
 """
@@ -128,14 +132,14 @@ def load_traffic(workload, kernel):
     return rec.get("bytes_per_launch")
 
 
-def measure(name, St, steps, warmup, block_cols=0):
+def measure(name, St, steps, warmup, block_cols=0, energy=False):
     """Time `steps` rPOD calls; per-pass kernel times from the library's HIP events."""
     import torch
     import paper_2504_15350_amd as rp
     w = WORKLOADS[name]
     n, m = St.shape
     dev = St.device
-    plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=St.dtype, device=dev, block_cols=block_cols)
+    plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=St.dtype, device=dev, block_cols=block_cols, energy=energy)
     out = (torch.empty((w["r"], m), dtype=plan.out_dtype, device=dev),
            torch.empty((w["r"],), dtype=torch.float64, device=dev),
            torch.empty((n, w["r"]), dtype=plan.out_dtype, device=dev))
@@ -165,6 +169,7 @@ def measure(name, St, steps, warmup, block_cols=0):
         kern[kname] = dict(launches=nl, avg_ms=tot / max(nl, 1), bytes=bpl, flops=fpl, total_ms=tot)
     plan.set_timing(False)
     sigma = out[1].cpu().numpy()
+    en = plan.energy(0.9) if energy else None
     plan.close()
     log(f"[bench] {name}: {ms:.3f} ms per rPOD over {steps} steps (flags {flags}); "
         + ", ".join(f"{k} {v['avg_ms']:.3f} ms x{v['launches'] // steps}" for k, v in kern.items()))
@@ -184,7 +189,7 @@ def measure(name, St, steps, warmup, block_cols=0):
                 hbm_gbs_algorithmic=round(gbs, 1))
     passes = sum(v["launches"] for v in kern.values()) / steps
     s_bytes = passes * m * n * St.element_size()
-    return dict(ms=ms, ms_graph=ms_graph, roofline=roof, sigma=sigma, flags=flags,
+    return dict(ms=ms, ms_graph=ms_graph, roofline=roof, sigma=sigma, flags=flags, energy=en,
                 hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
                 kernels={k: {"launches_per_step": v["launches"] // steps, "avg_ms": round(v["avg_ms"], 4)}
                          for k, v in kern.items()})
@@ -511,6 +516,15 @@ def main():
         log("[bench] timing the CPU oracle on a row sample ...")
         cpu = cpu_baseline(St, w, w["seed"])
         log(f"[bench] cpu baseline {cpu['value']:.0f} ms ({cpu['sample']})")
+    energy = None
+    if not args.no_center and args.workload == DEFAULT:
+        e_res = measure(DEFAULT, St, max(3, args.steps // 2), max(1, args.warmup // 2), energy=True)
+        e, rk = e_res["energy"]
+        energy = {"with_energy_ms": round(e_res["ms"], 4), "plain_ms": round(main_res["ms"], 4),
+                  "overhead": round(e_res["ms"] / main_res["ms"] - 1.0, 4),
+                  "energy_first_10": [round(float(x), 6) for x in e[:10]], "energy_at_l": round(float(e[-1]), 6),
+                  "rank_for_0.9": rk}
+        log(f"[bench] energy: {energy}")
     center = None
     if not args.no_center and args.workload == DEFAULT:
         center = center_block(St, max(3, args.steps // 2), max(1, args.warmup // 2))
@@ -573,6 +587,7 @@ def main():
         "batched_vs_plain": batch,
         "warm_vs_plain": warm,
         "centred_vs_plain": center,
+        "energy_report": energy,
     }
     print(json.dumps(res), flush=True)
 
