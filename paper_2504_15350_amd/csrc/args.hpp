@@ -33,6 +33,7 @@ struct SxArgs {  // Y = S X
     int cond_mask;
     int call;  // >= 0: S comes from call table entry `call`
     int cmax;  // > 0: only output columns < cmax are stored
+    double* fpart;  // FP32 first pass with the energy report: per-tile sums of S's squares
 };
 
 struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)

@@ -81,8 +81,12 @@ static void frob_t(bool vec, const GroupLaunch<FrobArgs>& P, hipStream_t st) {
         hipLaunchKernelGGL((k_frob_part<T, false>), dim3(P.tiles), dim3(256), 0, st, mkge(P));
 }
 
-hipError_t launch_frob(int tin, bool vec, const GroupLaunch<FrobArgs>& P, const GroupLaunch<FrobArgs>& F,
-                       hipStream_t st) {
+hipError_t launch_frob(int tin, bool vec, bool sum_only, const GroupLaunch<FrobArgs>& P,
+                       const GroupLaunch<FrobArgs>& F, hipStream_t st) {
+    if (sum_only) {
+        hipLaunchKernelGGL(k_frob_sum, dim3(F.tiles), dim3(256), 0, st, mkge(F));
+        return hipGetLastError();
+    }
     switch (tin) {
         case DT_F64: frob_t<double>(vec, P, st); break;
         case DT_F32: frob_t<float>(vec, P, st); break;

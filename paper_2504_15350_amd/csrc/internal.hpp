@@ -74,7 +74,8 @@ hipError_t launch_split16(int tin, const GroupLaunch<SplitArgs>& L, hipStream_t 
 //   rows (split s: rows 64 (k nsplit + s) .., k = 0, 1, ..), nP a multiple
 //   of stq_e6_block_cols(); nsplit a multiple of 8 keeps each split's column
 //   blocks on one XCD.
-hipError_t launch_sx_e6(int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st);
+// en: also write each tile's sum of the squares of the S entries it read to fpart[tile]
+hipError_t launch_sx_e6(int nt, bool vec, bool en, const GroupLaunch<SxArgs>& L, hipStream_t st);
 hipError_t launch_stq_e6(int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st);
 int stq_e6_block_cols();
 
@@ -92,8 +93,9 @@ hipError_t launch_center_sum(const GroupLaunch<CrossSumArgs>& L, hipStream_t st)
 
 // ||S||_F^2 in FP64 (tin: storage type): nwg tiles of partial sums (columns
 // strided over the tiles), then one tile adding them in order.
-hipError_t launch_frob(int tin, bool vec, const GroupLaunch<FrobArgs>& P, const GroupLaunch<FrobArgs>& F,
-                       hipStream_t st);
+// sum_only: only the final sum (the partial sums came from the FP32 first pass).
+hipError_t launch_frob(int tin, bool vec, bool sum_only, const GroupLaunch<FrobArgs>& P,
+                       const GroupLaunch<FrobArgs>& F, hipStream_t st);
 hipError_t launch_center_z(const GroupLaunch<CenterZArgs>& L, hipStream_t st);
 
 // Gram matrix G = Y^T Y in FP64 of a tall M x 16*nt column-major matrix

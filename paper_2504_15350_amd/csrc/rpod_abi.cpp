@@ -189,7 +189,8 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.o_Cb = take((size_t)L.K * L.lp * 8);
     L.o_Cp = take((size_t)L.ncc * L.K * L.lp * 8);
     L.o_Pc = take((size_t)L.K * L.lp * 8);
-    L.nfro = (d->flags & RPOD_DESC_ENERGY) ? 1024 : 0;
+    // FP32: the first pass's tiles (mP / 256) write the partial sums; otherwise a pass of 1024 tiles
+    L.nfro = (d->flags & RPOD_DESC_ENERGY) ? (L.tin == DT_F32 ? (int)(L.mP / 256) : 1024) : 0;
     L.o_Fp = take((size_t)L.nfro * 8);
     L.o_Fro = take(8);
     L.total = off;
@@ -206,6 +207,7 @@ struct Step {
     Kind kind;
     int tin = 0, tout = 0, nt = 0, lp = 0;  // lp: padded size (small SVD, Cholesky)
     bool vec = true, upper = false, lo = false;
+    bool energy = false;  // K_SXE6: also the per-tile sums of squares; K_FROB: only the final sum
     int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S (timed)
     size_t a1 = 0, t1 = 0, a2 = 0, t2 = 0;  // program-blob offsets of the argument / tile tables
     int count = 0, tiles1 = 0, tiles2 = 0;
@@ -376,9 +378,12 @@ struct Recorder {
             s.bytes += (double)it->d.m * it->d.n * sz + (double)it->d.n * it->L.l * sz + (double)it->d.m * it->L.l * 4.0;
             s.flops += 2.0 * it->d.m * it->d.n * it->L.l;
         }
+        s.energy = first && f32 && L0().nfro > 0;  // FP32 energy report: sums of squares from this pass
         std::vector<SxArgs> args = each([&](const Item& it) {
-            return SxArgs{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, it.L.o_X), it.L.nP,
-                          P->at<char>(it, it.L.o_Y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
+            SxArgs a{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, it.L.o_X), it.L.nP,
+                     P->at<char>(it, it.L.o_Y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
+            if (s.energy) a.fpart = P->at<double>(it, it.L.o_Fp);
+            return a;
         });
         B.add(s, args, tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
         out.push_back(s);
@@ -421,10 +426,13 @@ struct Recorder {
         out.push_back(r);
     }
     // ||S||_F^2 for the energy of the modes (plans with RPOD_DESC_ENERGY; a no-op otherwise)
-    void frob() {
-        if (L0().nfro == 0) return;
+    // after_first: FP32 plans add up the partial sums their first pass wrote (called after it);
+    // the other types read S in a pass of their own (called before the sketch)
+    void frob(bool after_first) {
+        if (L0().nfro == 0 || after_first != (L0().tin == DT_F32)) return;
         Step s{K_FROB};
         s.tin = L0().tin;
+        s.energy = after_first;
         s.vec = true;
         // 16-byte loads where rpod_compute requires S to be 16-byte aligned (ld a multiple of 4, or 8 for 16-bit)
         for (const Item* it : C) s.vec = s.vec && (it->d.ld % (is16(it->L.tin) ? 8 : 4) == 0);
@@ -758,10 +766,11 @@ struct Recorder {
     }
     void record() {
         zero();
-        frob();             // (energy: ||S||_F^2)
+        frob(false);        // (energy: ||S||_F^2 in a pass of its own, non-FP32 types)
         omega();            // Alg. 1 step 1
         center_prep(true);  // (fluctuations: the indicator columns and E^T Omega / N)
-        pass_sx(true);      // step 2 (and the block sums of S)
+        pass_sx(true);      // step 2 (and the block sums of S; FP32 energy: the partial sums of squares)
+        frob(true);
         center_y();
         orth_tall(1);       // step 4 (Q of the sketch)
         for (int it = 0; it < C[0]->d.q; ++it) {  // step 3, re-orthonormalised after every product
@@ -795,7 +804,7 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_ZERO: return launch_zero_ints(P->gl<ZeroArgs>(s, false), st);
         case K_OMEGA: return launch_omega(s.tout, P->gl<OmegaArgs>(s, false), st);
         case K_SX: return launch_sx(s.tin, s.tout, s.nt, s.vec, s.upper, P->gl<SxArgs>(s, false), st);
-        case K_SXE6: return launch_sx_e6(s.nt, s.vec, P->gl<SxArgs>(s, false), st);
+        case K_SXE6: return launch_sx_e6(s.nt, s.vec, s.energy, P->gl<SxArgs>(s, false), st);
         case K_SX16: return launch_sx16(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
         case K_STQ: return launch_stq(s.tin, s.nt, s.vec, P->gl<StqArgs>(s, false), st);
         case K_STQE6: return launch_stq_e6(s.nt, s.vec, P->gl<StqArgs>(s, false), st);
@@ -817,7 +826,8 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_CCROSS: return launch_center_cross(s.tin, P->gl<CrossArgs>(s, false), st);
         case K_CSUM: return launch_center_sum(P->gl<CrossSumArgs>(s, false), st);
         case K_CZ: return launch_center_z(P->gl<CenterZArgs>(s, false), st);
-        case K_FROB: return launch_frob(s.tin, s.vec, P->gl<FrobArgs>(s, false), P->gl<FrobArgs>(s, true), st);
+        case K_FROB:
+            return launch_frob(s.tin, s.vec, s.energy, P->gl<FrobArgs>(s, false), P->gl<FrobArgs>(s, true), st);
     }
     return hipErrorInvalidValue;
 }

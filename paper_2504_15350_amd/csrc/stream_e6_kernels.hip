@@ -102,11 +102,11 @@ __device__ __forceinline__ f32x4 e6_rows4(const GLOBAL float* S, int64_t ld, int
 // ---------------------------------------------------------------------------
 constexpr int E6_XLD = 40;  // halfwords per staged X column (32 rows + pad)
 
-template <int NT, bool VEC>
+template <int NT, bool VEC, bool EN = false>
 __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, int64_t m, int64_t n,
                                            const GLOBAL float* __restrict__ X, int64_t ldX,
                                            GLOBAL float* Y, int64_t ldY, int64_t mstore, int cmax, int64_t bx,
-                                           unsigned short* xs) {
+                                           unsigned short* xs, double* ssq = nullptr) {
     constexpr int XPART = 16 * NT * E6_XLD;     // one staged part
     constexpr int XB = 3 * XPART;               // one staged X block (three parts)
     constexpr int XCH = 16 * NT * 8;            // 16-byte FP32 chunks of a block (4 rows each)
@@ -162,8 +162,17 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
     load_x(0);
     put_x(0);
     int buf = 0;
+    double sq = 0.0;  // EN: sum of the squares of this lane's S entries (FP32 per step, FP64 across steps)
     for (int64_t j0 = 0; j0 < n; j0 += 32) {  // uniform trip count: the barriers below are reached by all waves
         const bool more = j0 + 32 < n;
+        if constexpr (EN) {
+            float p = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) p = fmaf(sv[i][t], sv[i][t], p);
+            sq += (double)p;
+        }
         e6_u16x8 ah[4], am[4], al[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -186,6 +195,7 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
             buf ^= 1;
         }
     }
+    if constexpr (EN) *ssq = sq;
     // D[4 g + v][r] of tile t: row iw + 4 (4 g + v) + t, output column 16 c + r
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
@@ -206,7 +216,9 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
     }
 }
 
-template <int NT, bool VEC>
+// EN: the energy report's variant (also each tile's sum of squares of S, in
+// a fixed order: per lane, then a tree over the workgroup)
+template <int NT, bool VEC, bool EN = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1, 2))) void k_sx_e6(
     Group<SxArgs> g) {
     __shared__ __attribute__((aligned(16))) unsigned short xs[2 * 3 * 16 * NT * E6_XLD];
@@ -214,9 +226,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
-    sx_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
-                        gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT, blockIdx.x - g.tstart[it],
-                        xs);
+    if constexpr (EN) {
+        __shared__ double red[256];
+        double sq = 0.0;
+        sx_e6_body<NT, VEC, true>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
+                                  gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
+                                  blockIdx.x - g.tstart[it], xs, &sq);
+        red[threadIdx.x] = sq;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && a.fpart != nullptr) a.fpart[blockIdx.x - g.tstart[it]] = red[0];
+    } else {
+        sx_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
+                            gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
+                            blockIdx.x - g.tstart[it], xs);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -386,11 +413,17 @@ static Group<A> mke6(const GroupLaunch<A>& L) {
 }
 
 template <int NT>
-static hipError_t sxe6_nt(const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st) {
-    if (vec)
+static hipError_t sxe6_nt(const GroupLaunch<SxArgs>& L, bool vec, bool en, hipStream_t st) {
+    if (en) {
+        if (vec)
+            hipLaunchKernelGGL((k_sx_e6<NT, true, true>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+        else
+            hipLaunchKernelGGL((k_sx_e6<NT, false, true>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+    } else if (vec) {
         hipLaunchKernelGGL((k_sx_e6<NT, true>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
-    else
+    } else {
         hipLaunchKernelGGL((k_sx_e6<NT, false>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+    }
     return hipGetLastError();
 }
 
@@ -403,9 +436,9 @@ static hipError_t stqe6_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sx_e6(int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st) {
+hipError_t launch_sx_e6(int nt, bool vec, bool en, const GroupLaunch<SxArgs>& L, hipStream_t st) {
     switch (nt) {
-#define RPOD_E6_CASE(K) case K: return sxe6_nt<K>(L, vec, st);
+#define RPOD_E6_CASE(K) case K: return sxe6_nt<K>(L, vec, en, st);
         RPOD_E6_CASE(1) RPOD_E6_CASE(2) RPOD_E6_CASE(3) RPOD_E6_CASE(4)
         RPOD_E6_CASE(5) RPOD_E6_CASE(6) RPOD_E6_CASE(7) RPOD_E6_CASE(8)
 #undef RPOD_E6_CASE
