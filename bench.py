@@ -438,7 +438,9 @@ def center_block(St, steps, warmup):
     torch.cuda.synchronize()
     plain = measure(DEFAULT, St, steps, warmup)
     cen = measure(DEFAULT, St, steps, warmup, block_cols=N)
+    recon = reconstruct_block(St, N)
     return {
+        "reconstruct_block0": recon,
         "config": {"workload": DEFAULT, "block_cols": N, "blocks": K, "mean_rms_over_field_rms": CENTER["mean_rms"],
                    "steps": steps},
         "plain_ms": round(plain["ms"], 4), "centred_ms": round(cen["ms"], 4),
@@ -446,6 +448,31 @@ def center_block(St, steps, warmup):
         "sigma1_plain": float(plain["sigma"][0]), "sigma1_centred": float(cen["sigma"][0]),
         "centred_kernels": cen["kernels"], "centred_roofline": cen["roofline"],
     }
+
+
+def reconstruct_block(St, N, reps=5):
+    """The reduced-order fields of the first parameter block (its time average
+    plus the 50 modes of the fluctuations weighted by their coefficients) and the
+    relative L2 error of their time average against the block's snapshots."""
+    import torch
+    import paper_2504_15350_amd as rp
+    w = WORKLOADS[DEFAULT]
+    n, m = St.shape
+    plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=St.dtype, device=St.device, block_cols=N)
+    Phi_t, _, A_t = plan.compute(St, w["seed"])
+    plan.close()
+    q0 = St[:N].double().mean(0).float().contiguous()
+    alpha_t = A_t[:N].contiguous()
+    ref_t = St[:N]
+    F, eps = rp.reconstruct(Phi_t, alpha_t, q0, ref_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rp.reconstruct(Phi_t, alpha_t, q0, ref_t, want_fields=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    gb = (N * m * 4 * 2 + m * w["r"] * 4) / 1e9  # fields written, reference read, modes read
+    return {"time_steps": N, "ms": round(ms, 4), "gbs": round(gb / (ms * 1e-3), 1), "eps_time_average": eps}
 
 
 def cpu_baseline(St, w, seed):

@@ -242,6 +242,29 @@ rpod_status rpod_status_query_batched(rpod_plan plan, int32_t* per_matrix_flags)
  * of range, delta outside (0, 1), or a plan made without RPOD_DESC_ENERGY. */
 rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* energy, int32_t* rank);
 
+/* Reconstruction of the reduced-order fields (Sec. 4, the ROM approximation:
+ * a field equals its zeroth-order time average plus the modes weighted by
+ * their coefficients) and the relative L2 error of time-averaged fields
+ * (Sec. 5, the error measure against the full-order solution).
+ *   dtype  RPOD_F64 or RPOD_F32: element type of Phi, mean, alpha, out, ref.
+ *   Phi    (device) m x r modes, leading dimension m; r in 1..128.
+ *   mean   (device, may be NULL = zero) the zeroth-order field, m values.
+ *   alpha  (device) r x T coefficients, leading dimension r (column t: time t).
+ *   out    (device, may be NULL) receives the m x T fields mean + Phi alpha,
+ *          leading dimension m.
+ *   ref    (device, may be NULL) m x T full-order fields, leading dimension
+ *          ld_ref >= m; with ref and eps non-NULL, *eps (host) receives
+ *          ||avg_t ref - avg_t(mean + Phi alpha)|| / ||avg_t ref|| (Euclidean
+ *          norms over the m cells: the L2 norm on a uniform grid up to the
+ *          cell area, which cancels) and the call synchronises the stream;
+ *          otherwise it only enqueues.
+ * Sums in FP64, fixed order. workspace (device, 256-byte aligned) of at
+ * least rpod_reconstruct_workspace_size(m, r) bytes, used only during the call. */
+rpod_status rpod_reconstruct_workspace_size(int64_t m, int32_t r, size_t* bytes);
+rpod_status rpod_reconstruct(int32_t dtype, int64_t m, int32_t r, int64_t T, const void* Phi, const void* mean,
+                             const void* alpha, void* out, const void* ref, int64_t ld_ref, void* workspace,
+                             size_t workspace_bytes, void* hip_stream, double* eps);
+
 /* The Gaussian sketch of Alg. 1 step 1 (entries N(0,1), Sec. 4.2), drawn on
  * the GPU: out (device) receives the n x l matrix column-major with leading
  * dimension ldo >= n, as double (dtype RPOD_F64) or float (RPOD_F32, the

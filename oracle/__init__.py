@@ -16,6 +16,8 @@ rpod     O2: randomized POD, Alg. 1 of Sec. 4.2 (stable form with
          re-orthonormalisation after every product), and the literal form.
 metrics  sign-invariant comparison metrics (principal angles, sigma errors).
 energy   the energy of the leading modes and the rank rule (Sec. 4.1).
+reconstruct  reduced-order fields (Sec. 4) and the relative L2 error of
+         time-averaged fields (Sec. 5).
 center   fluctuation snapshots (Sec. 4.1): each snapshot minus the time
          average of its parameter's block of columns.
 warm     the learned warm start (an extension of Alg. 1, not in the paper):

@@ -82,6 +82,9 @@ def lib():
             "rpod_compute": [vp, vp, u64, vp, vp, vp],
             "rpod_status_query": [vp, ctypes.POINTER(i32)],
             "rpod_energy": [vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
+            "rpod_reconstruct_workspace_size": [i64, i32, ctypes.POINTER(ctypes.c_size_t)],
+            "rpod_reconstruct": [i32, i64, i32, i64, vp, vp, vp, vp, vp, i64, vp, ctypes.c_size_t, vp,
+                                 ctypes.POINTER(ctypes.c_double)],
             "rpod_generate_omega": [u64, i64, i32, i32, vp, i64, vp],
             "rpod_sketch_bits": [u64, i64, i32, vp, vp],
             "rpod_plan_set_timing": [vp, i32],
@@ -231,6 +234,42 @@ def _check_St(St, dtype, device, m, n, ld):
         raise ValueError(f"St must have shape ({n}, >= {m})")
     if St.stride(1) != 1 or St.stride(0) != ld:
         raise ValueError("St must be row-major with row stride equal to the plan's ld")
+
+
+def reconstruct(Phi_t, alpha_t, mean=None, ref_t=None, want_fields=True, stream=None):
+    """rpod_reconstruct: fields mean + Phi alpha and the relative L2 error of the time averages.
+
+    Phi_t (r, m), alpha_t (T, r), mean (m,) or None, ref_t (T, ld_ref) or None, all on
+    one device in float32 or float64 (the column-major layouts of the C ABI).
+    Returns (fields_t (T, m) or None, eps or None).
+    """
+    dt = Phi_t.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise TypeError("Phi must be float32 or float64")
+    r, m = Phi_t.shape
+    T = alpha_t.shape[0]
+    for t in (alpha_t, mean, ref_t):
+        if t is not None and (t.dtype != dt or t.device != Phi_t.device or not t.is_contiguous()):
+            raise ValueError("alpha, mean and ref must be contiguous tensors of Phi's dtype and device")
+    if not Phi_t.is_contiguous() or alpha_t.shape[1] != r:
+        raise ValueError("Phi_t must be contiguous (r, m) and alpha_t (T, r)")
+    dev = Phi_t.device
+    nb = ctypes.c_size_t(0)
+    _check(lib().rpod_reconstruct_workspace_size(m, r, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    out = torch.empty((T, m), dtype=dt, device=dev) if want_fields else None
+    eps = ctypes.c_double(0.0)
+    ld_ref = ref_t.shape[1] if ref_t is not None else m
+    sptr, _s = _stream_ptr(stream, dev)
+    vp = ctypes.c_void_p
+    _check(lib().rpod_reconstruct(_DTYPES[dt], m, r, T, _dev_ptr(Phi_t),
+                                  _dev_ptr(mean) if mean is not None else vp(None), _dev_ptr(alpha_t),
+                                  _dev_ptr(out) if out is not None else vp(None),
+                                  _dev_ptr(ref_t) if ref_t is not None else vp(None), ld_ref, _dev_ptr(ws), nb.value,
+                                  sptr, ctypes.byref(eps)))
+    if ref_t is None:
+        torch.cuda.synchronize(dev)
+    return out, (eps.value if ref_t is not None else None)
 
 
 def _norm_device(device):

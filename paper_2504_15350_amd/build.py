@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librpod.so")
-SOURCES = ["stream_kernels.hip", "stream16_kernels.hip", "stream_e6_kernels.hip", "small_kernels.hip", "center_kernels.hip", "energy_kernels.hip",
+SOURCES = ["stream_kernels.hip", "stream16_kernels.hip", "stream_e6_kernels.hip", "small_kernels.hip", "center_kernels.hip", "energy_kernels.hip", "recon_kernels.hip",
            "warm_kernels.hip", "rpod_abi.cpp", "warm_abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -91,6 +91,13 @@ hipError_t launch_center_y(int tacc, const GroupLaunch<CenterYArgs>& L, hipStrea
 hipError_t launch_center_cross(int tacc, const GroupLaunch<CrossArgs>& L, hipStream_t st);
 hipError_t launch_center_sum(const GroupLaunch<CrossSumArgs>& L, hipStream_t st);  // one tile per entry
 
+// Reconstruction mean + Phi alpha (out may be NULL) and, with ref, the sums
+// ||avg ref - avg recon||^2 and ||avg ref||^2 into out2[0], out2[1] (abar: r
+// doubles, part: 2 ceil(m / 256) doubles of scratch). dt: DT_F64 or DT_F32.
+hipError_t launch_reconstruct(int dt, int64_t m, int r, int64_t T, const void* Phi, const void* mean,
+                              const void* alpha, void* out, const void* ref, int64_t ld_ref, double* abar,
+                              double* part, double* out2, hipStream_t st);
+
 // ||S||_F^2 in FP64 (tin: storage type): nwg tiles of partial sums (columns
 // strided over the tiles), then one tile adding them in order.
 // sum_only: only the final sum (the partial sums came from the FP32 first pass).

@@ -1,0 +1,136 @@
+// Reduced-order reconstruction (Sec. 4: a field is its zeroth-order time
+// average plus the modes weighted by their time-dependent coefficients) and
+// the relative L2 error of time-averaged fields against full-order ones
+// (Sec. 5). Plain launches (no grouping): the caller's pointers are kernel
+// arguments.
+//   k_recon_abar  abar_k = (1/T) sum_t alpha[k, t], one wave per mode
+//   k_recon_out   out[i, t] = mean[i] + sum_k Phi[i, k] alpha[k, t]
+//                 (256 rows x 16 times per tile; alpha block in LDS)
+//   k_recon_err   per tile of 256 rows: sums of (f - g)^2 and f^2 with
+//                 f = avg_t ref[i, t], g = mean[i] + sum_k Phi[i, k] abar_k
+//   k_recon_sum   the tiles' sums, in order
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace rpod {
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_recon_abar(const T* __restrict__ alpha, int r, int64_t T_, double* abar) {
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < T_; t += 64) s += (double)alpha[t * r + k];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) abar[k] = s / (double)T_;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_recon_out(const T* __restrict__ Phi, const T* __restrict__ mean,
+                                                   const T* __restrict__ alpha, T* __restrict__ out, int64_t m, int r,
+                                                   int64_t T_) {
+    __shared__ double as[128 * 16];  // alpha[k, t0 .. t0 + 15]
+    const int64_t t0 = (int64_t)blockIdx.y * 16;
+    for (int e = threadIdx.x; e < r * 16; e += 256) {
+        const int k = e % r, tt = e / r;
+        as[k + 128 * tt] = t0 + tt < T_ ? (double)alpha[(t0 + tt) * r + k] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const double base = mean != nullptr ? (double)mean[i] : 0.0;
+    double acc[16];
+#pragma unroll
+    for (int tt = 0; tt < 16; ++tt) acc[tt] = base;
+    for (int k = 0; k < r; ++k) {
+        const double ph = (double)Phi[(int64_t)k * m + i];
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) acc[tt] += ph * as[k + 128 * tt];
+    }
+#pragma unroll
+    for (int tt = 0; tt < 16; ++tt)
+        if (t0 + tt < T_) out[(t0 + tt) * m + i] = (T)acc[tt];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_recon_err(const T* __restrict__ Phi, const T* __restrict__ mean,
+                                                   const double* __restrict__ abar, const T* __restrict__ ref,
+                                                   int64_t ld_ref, int64_t m, int r, int64_t T_, double* part) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double d2 = 0.0, f2 = 0.0;
+    if (i < m) {
+        double f = 0.0;
+        for (int64_t t = 0; t < T_; ++t) f += (double)ref[t * ld_ref + i];
+        f /= (double)T_;
+        double g = mean != nullptr ? (double)mean[i] : 0.0;
+        for (int k = 0; k < r; ++k) g += (double)Phi[(int64_t)k * m + i] * abar[k];
+        d2 = (f - g) * (f - g);
+        f2 = f * f;
+    }
+    __shared__ double rd[256], rf[256];
+    rd[threadIdx.x] = d2;
+    rf[threadIdx.x] = f2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            rd[threadIdx.x] += rd[threadIdx.x + h];
+            rf[threadIdx.x] += rf[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = rd[0];
+        part[2 * blockIdx.x + 1] = rf[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recon_sum(const double* part, int nt, double* out2) {
+    double d = 0.0, f = 0.0;
+    for (int w = threadIdx.x; w < nt; w += 256) {
+        d += part[2 * w];
+        f += part[2 * w + 1];
+    }
+    __shared__ double rd[256], rf[256];
+    rd[threadIdx.x] = d;
+    rf[threadIdx.x] = f;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            rd[threadIdx.x] += rd[threadIdx.x + h];
+            rf[threadIdx.x] += rf[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out2[0] = rd[0];
+        out2[1] = rf[0];
+    }
+}
+
+template <typename T>
+static hipError_t recon_t(int64_t m, int r, int64_t T_, const void* Phi, const void* mean, const void* alpha,
+                          void* out, const void* ref, int64_t ld_ref, double* abar, double* part, double* out2,
+                          hipStream_t st) {
+    const unsigned rows = (unsigned)((m + 255) / 256);
+    if (out != nullptr) {
+        hipLaunchKernelGGL(k_recon_out<T>, dim3(rows, (unsigned)((T_ + 15) / 16)), dim3(256), 0, st, (const T*)Phi,
+                           (const T*)mean, (const T*)alpha, (T*)out, m, r, T_);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (ref != nullptr) {
+        hipLaunchKernelGGL(k_recon_abar<T>, dim3(r), dim3(64), 0, st, (const T*)alpha, r, T_, abar);
+        hipLaunchKernelGGL(k_recon_err<T>, dim3(rows), dim3(256), 0, st, (const T*)Phi, (const T*)mean,
+                           (const double*)abar, (const T*)ref, ld_ref, m, r, T_, part);
+        hipLaunchKernelGGL(k_recon_sum, dim3(1), dim3(256), 0, st, (const double*)part, (int)rows, out2);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(int dt, int64_t m, int r, int64_t T_, const void* Phi, const void* mean,
+                              const void* alpha, void* out, const void* ref, int64_t ld_ref, double* abar,
+                              double* part, double* out2, hipStream_t st) {
+    if (dt == DT_F64) return recon_t<double>(m, r, T_, Phi, mean, alpha, out, ref, ld_ref, abar, part, out2, st);
+    if (dt == DT_F32) return recon_t<float>(m, r, T_, Phi, mean, alpha, out, ref, ld_ref, abar, part, out2, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace rpod

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <cmath>
 #include <map>
 #include <new>
 #include <vector>
@@ -1521,6 +1522,42 @@ rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* ener
         if (rk < 0 && energy[k] >= delta) rk = k + 1;
     }
     if (rank) *rank = rk;
+    return RPOD_OK;
+}
+
+rpod_status rpod_reconstruct_workspace_size(int64_t m, int32_t r, size_t* bytes) {
+    if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
+    if (m < 1 || r < 1 || r > 128) return fail(RPOD_EINVAL, "need m >= 1 and 1 <= r <= 128");
+    *bytes = (size_t)roundup(r, 32) * 8 + 256 + (size_t)roundup(2 * ((m + 255) / 256), 32) * 8;
+    return RPOD_OK;
+}
+
+rpod_status rpod_reconstruct(int32_t dtype, int64_t m, int32_t r, int64_t T, const void* Phi, const void* mean,
+                             const void* alpha, void* out, const void* ref, int64_t ld_ref, void* workspace,
+                             size_t workspace_bytes, void* hip_stream, double* eps) {
+    if (dtype != RPOD_F64 && dtype != RPOD_F32) return fail(RPOD_EINVAL, "dtype must be RPOD_F64 or RPOD_F32");
+    if (T < 1) return fail(RPOD_EINVAL, "T must be >= 1");
+    size_t need = 0;
+    rpod_status s = rpod_reconstruct_workspace_size(m, r, &need);
+    if (s != RPOD_OK) return s;
+    if (Phi == nullptr || alpha == nullptr) return fail(RPOD_EINVAL, "Phi and alpha must be non-NULL");
+    if (ref != nullptr && ld_ref < m) return fail(RPOD_EINVAL, "ld_ref (%lld) must be >= m", (long long)ld_ref);
+    if (workspace == nullptr || (uintptr_t)workspace % 256 != 0)
+        return fail(RPOD_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < need) return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+    char* ws = static_cast<char*>(workspace);
+    double* abar = reinterpret_cast<double*>(ws);
+    double* out2 = reinterpret_cast<double*>(ws + (size_t)roundup(r, 32) * 8);
+    double* part = reinterpret_cast<double*>(ws + (size_t)roundup(r, 32) * 8 + 256);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(launch_reconstruct(dtype == RPOD_F64 ? DT_F64 : DT_F32, m, r, T, Phi, mean, alpha, out, ref, ld_ref, abar,
+                               part, out2, st));
+    if (ref != nullptr && eps != nullptr) {
+        double h[2] = {0.0, 0.0};
+        HIP_TRY(hipMemcpyAsync(h, out2, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        *eps = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+    }
     return RPOD_OK;
 }
 
