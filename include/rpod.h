@@ -258,7 +258,8 @@ rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* ener
  *          norms over the m cells: the L2 norm on a uniform grid up to the
  *          cell area, which cancels) and the call synchronises the stream;
  *          otherwise it only enqueues.
- * Sums in FP64, fixed order. workspace (device, 256-byte aligned) of at
+ * The fields are formed in dtype (fused multiply-adds); the error's sums in
+ * FP64, fixed order. workspace (device, 256-byte aligned) of at
  * least rpod_reconstruct_workspace_size(m, r) bytes, used only during the call. */
 rpod_status rpod_reconstruct_workspace_size(int64_t m, int32_t r, size_t* bytes);
 rpod_status rpod_reconstruct(int32_t dtype, int64_t m, int32_t r, int64_t T, const void* Phi, const void* mean,

@@ -5,9 +5,11 @@
 // arguments.
 //   k_recon_abar  abar_k = (1/T) sum_t alpha[k, t], one wave per mode
 //   k_recon_out   out[i, t] = mean[i] + sum_k Phi[i, k] alpha[k, t]
-//                 (256 rows x 16 times per tile; alpha block in LDS)
+//                 (256 rows x 256 times per tile, 16 at a time, alpha block in
+//                 LDS; arithmetic in the storage type)
 //   k_recon_err   per tile of 256 rows: sums of (f - g)^2 and f^2 with
-//                 f = avg_t ref[i, t], g = mean[i] + sum_k Phi[i, k] abar_k
+//                 f = avg_t ref[i, t] (eight interleaved sums, fixed order),
+//                 g = mean[i] + sum_k Phi[i, k] abar_k
 //   k_recon_sum   the tiles' sums, in order
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -27,27 +29,33 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_recon_out(const T* __restrict__ Phi, const T* __restrict__ mean,
                                                    const T* __restrict__ alpha, T* __restrict__ out, int64_t m, int r,
                                                    int64_t T_) {
-    __shared__ double as[128 * 16];  // alpha[k, t0 .. t0 + 15]
-    const int64_t t0 = (int64_t)blockIdx.y * 16;
-    for (int e = threadIdx.x; e < r * 16; e += 256) {
-        const int k = e % r, tt = e / r;
-        as[k + 128 * tt] = t0 + tt < T_ ? (double)alpha[(t0 + tt) * r + k] : 0.0;
-    }
-    __syncthreads();
+    __shared__ T as[128 * 16];  // alpha[k, t0 .. t0 + 15], in the storage type
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m) return;
-    const double base = mean != nullptr ? (double)mean[i] : 0.0;
-    double acc[16];
+    const T base = (mean != nullptr && i < m) ? mean[i] : (T)0;
+    const int64_t t1 = ((int64_t)blockIdx.y + 1) * 256 < T_ ? ((int64_t)blockIdx.y + 1) * 256 : T_;
+    // 256 time steps per tile in chunks of 16; products and sums in the
+    // storage type (the fields are stored in it), fused multiply-adds
+    for (int64_t t0 = (int64_t)blockIdx.y * 256; t0 < t1; t0 += 16) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < r * 16; e += 256) {
+            const int k = e % r, tt = e / r;
+            as[k + 128 * tt] = t0 + tt < T_ ? alpha[(t0 + tt) * r + k] : (T)0;
+        }
+        __syncthreads();
+        if (i < m) {
+            T acc[16];
 #pragma unroll
-    for (int tt = 0; tt < 16; ++tt) acc[tt] = base;
-    for (int k = 0; k < r; ++k) {
-        const double ph = (double)Phi[(int64_t)k * m + i];
+            for (int tt = 0; tt < 16; ++tt) acc[tt] = base;
+            for (int k = 0; k < r; ++k) {
+                const T ph = Phi[(int64_t)k * m + i];
 #pragma unroll
-        for (int tt = 0; tt < 16; ++tt) acc[tt] += ph * as[k + 128 * tt];
+                for (int tt = 0; tt < 16; ++tt) acc[tt] = fma(ph, as[k + 128 * tt], acc[tt]);
+            }
+#pragma unroll
+            for (int tt = 0; tt < 16; ++tt)
+                if (t0 + tt < T_) out[(t0 + tt) * m + i] = acc[tt];
+        }
     }
-#pragma unroll
-    for (int tt = 0; tt < 16; ++tt)
-        if (t0 + tt < T_) out[(t0 + tt) * m + i] = (T)acc[tt];
 }
 
 template <typename T>
@@ -57,9 +65,14 @@ __global__ __launch_bounds__(256) void k_recon_err(const T* __restrict__ Phi, co
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double d2 = 0.0, f2 = 0.0;
     if (i < m) {
-        double f = 0.0;
-        for (int64_t t = 0; t < T_; ++t) f += (double)ref[t * ld_ref + i];
-        f /= (double)T_;
+        double fs[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // eight independent sums keep loads in flight
+        int64_t t = 0;
+        for (; t + 8 <= T_; t += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) fs[u] += (double)ref[(t + u) * ld_ref + i];
+        }
+        for (; t < T_; ++t) fs[0] += (double)ref[t * ld_ref + i];
+        const double f = (((fs[0] + fs[1]) + (fs[2] + fs[3])) + ((fs[4] + fs[5]) + (fs[6] + fs[7]))) / (double)T_;
         double g = mean != nullptr ? (double)mean[i] : 0.0;
         for (int k = 0; k < r; ++k) g += (double)Phi[(int64_t)k * m + i] * abar[k];
         d2 = (f - g) * (f - g);
@@ -111,7 +124,7 @@ static hipError_t recon_t(int64_t m, int r, int64_t T_, const void* Phi, const v
                           hipStream_t st) {
     const unsigned rows = (unsigned)((m + 255) / 256);
     if (out != nullptr) {
-        hipLaunchKernelGGL(k_recon_out<T>, dim3(rows, (unsigned)((T_ + 15) / 16)), dim3(256), 0, st, (const T*)Phi,
+        hipLaunchKernelGGL(k_recon_out<T>, dim3(rows, (unsigned)((T_ + 255) / 256)), dim3(256), 0, st, (const T*)Phi,
                            (const T*)mean, (const T*)alpha, (T*)out, m, r, T_);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
