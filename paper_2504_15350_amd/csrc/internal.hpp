@@ -97,6 +97,12 @@ hipError_t launch_center_sum(const GroupLaunch<CrossSumArgs>& L, hipStream_t st)
 hipError_t launch_reconstruct(int dt, int64_t m, int r, int64_t T, const void* Phi, const void* mean,
                               const void* alpha, void* out, const void* ref, int64_t ld_ref, double* abar,
                               double* part, double* out2, hipStream_t st);
+// FP32 fields on the matrix cores (m a multiple of 4, out 16-byte aligned):
+// aug (lda x (r + 1), lda = roundup(m, 4)), x (ldx x 128, ldx = roundup(r + 1,
+// 32)), one SxArgs record and two ints of tile table, all device scratch.
+hipError_t launch_reconstruct_mfma(int64_t m, int r, int64_t T, const float* Phi, const float* mean,
+                                   const float* alpha, float* out, float* aug, int64_t lda, float* x, int ldx,
+                                   SxArgs* rec, int* tstart, hipStream_t st);
 
 // ||S||_F^2 in FP64 (tin: storage type): nwg tiles of partial sums (columns
 // strided over the tiles), then one tile adding them in order.

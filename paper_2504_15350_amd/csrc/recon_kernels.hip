@@ -118,6 +118,68 @@ __global__ __launch_bounds__(256) void k_recon_sum(const double* part, int nt, d
     }
 }
 
+// FP32 fields on the matrix cores: [Phi, mean] (m x (r + 1)) times the chunk's
+// [alpha; 1] ((r + 1) x 128) by the split-operand S X kernel. k_recon_aug
+// copies Phi and mean into the augmented matrix (leading dimension lda);
+// k_recon_xchunk writes the chunk's operand (ldx rows, zero below r + 1 and
+// past T) and the launch record of the chunk's S X product.
+__global__ __launch_bounds__(256) void k_recon_aug(const float* __restrict__ Phi, const float* __restrict__ mean,
+                                                   int64_t m, int r, float* __restrict__ aug, int64_t lda) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;  // 0 .. r
+    if (i >= m) return;
+    aug[(int64_t)k * lda + i] = k < r ? Phi[(int64_t)k * m + i] : (mean != nullptr ? mean[i] : 0.0f);
+}
+
+__global__ __launch_bounds__(256) void k_recon_xchunk(const float* __restrict__ alpha, int r, int64_t T_, int64_t t0,
+                                                      float* __restrict__ x, int ldx, const float* aug, int64_t lda,
+                                                      int64_t m, float* out, SxArgs* rec, int* tstart) {
+    const int e = blockIdx.x * 256 + threadIdx.x;  // ldx x 128 entries
+    if (e < ldx * 128) {
+        const int k = e % ldx, c = e / ldx;
+        const int64_t t = t0 + c;
+        float v = 0.0f;
+        if (t < T_) v = k < r ? alpha[t * r + k] : (k == r ? 1.0f : 0.0f);
+        x[e] = v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        SxArgs a{};
+        a.S = aug; a.ldS = lda; a.m = m; a.n = r + 1;
+        a.X = x; a.ldX = ldx;
+        a.Y = out + t0 * m; a.ldY = m; a.mstore = m;
+        a.cond = nullptr; a.cond_mask = 0; a.call = -1;
+        a.cmax = (int)(T_ - t0 < 128 ? T_ - t0 : 128);
+        a.fpart = nullptr;
+        *rec = a;
+        tstart[0] = 0;
+        tstart[1] = (int)((m + 255) / 256);
+    }
+}
+
+hipError_t launch_reconstruct_mfma(int64_t m, int r, int64_t T_, const float* Phi, const float* mean,
+                                   const float* alpha, float* out, float* aug, int64_t lda, float* x, int ldx,
+                                   SxArgs* rec, int* tstart, hipStream_t st) {
+    hipLaunchKernelGGL(k_recon_aug, dim3((unsigned)((m + 255) / 256), (unsigned)(r + 1)), dim3(256), 0, st, Phi, mean,
+                       m, r, aug, lda);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int64_t t0 = 0; t0 < T_; t0 += 128) {
+        hipLaunchKernelGGL(k_recon_xchunk, dim3((unsigned)((ldx * 128 + 255) / 256)), dim3(256), 0, st, alpha, r, T_,
+                           t0, x, ldx, (const float*)aug, lda, m, out, rec, tstart);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        GroupLaunch<SxArgs> L;
+        L.args = rec;
+        L.tstart = tstart;
+        L.calls = nullptr;
+        L.count = 1;
+        L.tiles = (int)((m + 255) / 256);
+        e = launch_sx_e6(8, true, false, L, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 static hipError_t recon_t(int64_t m, int r, int64_t T_, const void* Phi, const void* mean, const void* alpha,
                           void* out, const void* ref, int64_t ld_ref, double* abar, double* part, double* out2,

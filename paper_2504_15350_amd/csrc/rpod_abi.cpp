@@ -1525,10 +1525,39 @@ rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* ener
     return RPOD_OK;
 }
 
+// scratch of rpod_reconstruct: abar, the two sums, the error's partial sums,
+// and for FP32 fields on the matrix cores the augmented modes, one chunk's
+// operand and its launch record
+struct ReconLayout {
+    size_t abar, out2, part, aug, x, rec, tstart, total;
+    int64_t lda;
+    int ldx;
+};
+ReconLayout recon_layout(int64_t m, int r) {
+    ReconLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    L.lda = roundup(m, 4);
+    L.ldx = (int)roundup(r + 1, 32);
+    L.abar = take((size_t)r * 8);
+    L.out2 = take(16);
+    L.part = take((size_t)2 * ((m + 255) / 256) * 8);
+    L.aug = take((size_t)L.lda * (r + 1) * 4);
+    L.x = take((size_t)L.ldx * 128 * 4);
+    L.rec = take(sizeof(SxArgs));
+    L.tstart = take(2 * sizeof(int));
+    L.total = off;
+    return L;
+}
+
 rpod_status rpod_reconstruct_workspace_size(int64_t m, int32_t r, size_t* bytes) {
     if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
     if (m < 1 || r < 1 || r > 128) return fail(RPOD_EINVAL, "need m >= 1 and 1 <= r <= 128");
-    *bytes = (size_t)roundup(r, 32) * 8 + 256 + (size_t)roundup(2 * ((m + 255) / 256), 32) * 8;
+    *bytes = recon_layout(m, r).total;
     return RPOD_OK;
 }
 
@@ -1546,12 +1575,22 @@ rpod_status rpod_reconstruct(int32_t dtype, int64_t m, int32_t r, int64_t T, con
         return fail(RPOD_EINVAL, "workspace must be non-NULL and 256-byte aligned");
     if (workspace_bytes < need) return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
     char* ws = static_cast<char*>(workspace);
-    double* abar = reinterpret_cast<double*>(ws);
-    double* out2 = reinterpret_cast<double*>(ws + (size_t)roundup(r, 32) * 8);
-    double* part = reinterpret_cast<double*>(ws + (size_t)roundup(r, 32) * 8 + 256);
+    const ReconLayout RL = recon_layout(m, r);
+    double* abar = reinterpret_cast<double*>(ws + RL.abar);
+    double* out2 = reinterpret_cast<double*>(ws + RL.out2);
+    double* part = reinterpret_cast<double*>(ws + RL.part);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    HIP_TRY(launch_reconstruct(dtype == RPOD_F64 ? DT_F64 : DT_F32, m, r, T, Phi, mean, alpha, out, ref, ld_ref, abar,
-                               part, out2, st));
+    // FP32 fields on the matrix cores when the output allows 16-byte stores
+    const bool mfma = dtype == RPOD_F32 && out != nullptr && m % 4 == 0 && (uintptr_t)out % 16 == 0;
+    if (mfma)
+        HIP_TRY(launch_reconstruct_mfma(m, r, T, static_cast<const float*>(Phi), static_cast<const float*>(mean),
+                                        static_cast<const float*>(alpha), static_cast<float*>(out),
+                                        reinterpret_cast<float*>(ws + RL.aug), RL.lda,
+                                        reinterpret_cast<float*>(ws + RL.x), RL.ldx,
+                                        reinterpret_cast<SxArgs*>(ws + RL.rec), reinterpret_cast<int*>(ws + RL.tstart),
+                                        st));
+    HIP_TRY(launch_reconstruct(dtype == RPOD_F64 ? DT_F64 : DT_F32, m, r, T, Phi, mean, alpha, mfma ? nullptr : out,
+                               ref, ld_ref, abar, part, out2, st));
     if (ref != nullptr && eps != nullptr) {
         double h[2] = {0.0, 0.0};
         HIP_TRY(hipMemcpyAsync(h, out2, sizeof(h), hipMemcpyDeviceToHost, st));
