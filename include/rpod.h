@@ -258,8 +258,10 @@ rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* ener
  *          norms over the m cells: the L2 norm on a uniform grid up to the
  *          cell area, which cancels) and the call synchronises the stream;
  *          otherwise it only enqueues.
- * The fields are formed in dtype (fused multiply-adds); the error's sums in
- * FP64, fixed order. workspace (device, 256-byte aligned) of at
+ * FP32 fields with m a multiple of 4 and out 16-byte aligned are formed on
+ * the matrix cores with operands split exactly into BF16 parts (FP32-accurate
+ * products, FP32 sums); other fields by fused multiply-adds in dtype. The
+ * error's sums run in FP64, fixed order. workspace (device, 256-byte aligned) of at
  * least rpod_reconstruct_workspace_size(m, r) bytes, used only during the call. */
 rpod_status rpod_reconstruct_workspace_size(int64_t m, int32_t r, size_t* bytes);
 rpod_status rpod_reconstruct(int32_t dtype, int64_t m, int32_t r, int64_t T, const void* Phi, const void* mean,
