@@ -613,9 +613,10 @@ struct Recorder {
              }));
         Step j{K_JACOBI};
         j.lp = L.lp;
-        // rotation threshold: FP64 rounding level on the FP64 path; elsewhere far
-        // below the FP32 storage error of Q, which bounds the result anyway
-        const double jtol = L.tacc == DT_F64 ? (double)L.lp * 0x1.0p-53 : 1e-10;
+        // rotation threshold: FP64 rounding level on the FP64 path; elsewhere below
+        // the FP32 storage error of Q (6e-8), which bounds the result anyway (1e-8
+        // ends the iteration one sweep earlier than 1e-10 on the Fourier fields)
+        const double jtol = L.tacc == DT_F64 ? (double)L.lp * 0x1.0p-53 : 1e-8;
         B.add(j, each([&](const Item& it) {
                   return JacobiArgs{P->at<double>(it, it.L.o_G), P->at<double>(it, it.L.o_UB),
                                     P->at<double>(it, it.L.o_sig), P->flags(it), jtol, it.L.l, it.L.lp};
