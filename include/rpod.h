@@ -74,6 +74,11 @@ typedef enum {
 #define RPOD_FLAG_BREAKDOWN   0x2  /* -> RPOD_EBREAKDOWN */
 #define RPOD_FLAG_NONFINITE   0x4  /* -> RPOD_EINVAL_DATA */
 #define RPOD_FLAG_JACOBI_SLOW 0x8  /* small SVD hit its sweep limit (informational) */
+#define RPOD_FLAG_RANK_CUT    0x20 /* FP32/16-bit paths: the Gram matrix T T^T of step 6 was numerically
+                                      rank-deficient (a pivot below l u times its largest diagonal entry,
+                                      i.e. sigma_k below about sqrt(l u) sigma_1 = 1e-7 sigma_1); those
+                                      singular values and their mode columns are returned as 0
+                                      (informational; the FP64 path factors T^T itself and never cuts) */
 
 /* Problem description.
  *   m, n   rows (grid cells) and columns (snapshots) of S, both >= 1.

@@ -17,14 +17,14 @@ import os
 import torch
 
 __all__ = ["RpodError", "Plan", "BatchPlan", "Tuning", "autotune", "WarmModel", "WarmPlan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
-           "STATUS", "FLAG_SHIFTED", "FLAG_BREAKDOWN", "FLAG_NONFINITE", "FLAG_JACOBI_SLOW"]
+           "STATUS", "FLAG_SHIFTED", "FLAG_BREAKDOWN", "FLAG_NONFINITE", "FLAG_JACOBI_SLOW", "FLAG_RANK_CUT"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpod.so")
 
 STATUS = {0: "RPOD_OK", 1: "RPOD_EINVAL", 2: "RPOD_EINVAL_DATA", 3: "RPOD_ENOMEM", 4: "RPOD_EHIP",
           5: "RPOD_EUNSUPPORTED", 6: "RPOD_EBREAKDOWN"}
-FLAG_SHIFTED, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_JACOBI_SLOW = 0x1, 0x2, 0x4, 0x8
+FLAG_SHIFTED, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_JACOBI_SLOW, FLAG_RANK_CUT = 0x1, 0x2, 0x4, 0x8, 0x20
 
 _DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}
 

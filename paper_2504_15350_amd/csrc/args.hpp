@@ -123,13 +123,15 @@ struct CholArgs {  // Cholesky + inverse
     int l, lp, mode;
 };
 
-struct JacobiArgs {  // eigenvectors of the small Gram matrix
-    const double* G;
+struct JacobiArgs {  // left singular vectors of the small T: from its Gram matrix, or from a factor C
+    const double* G;   // Gram route: G = T T^T (lp x lp, row-major)
     double* UB;
     double* sig;
     int* flags;
     double tol;
     int l, lp;
+    const double* C;   // non-NULL: factor route, C (l x l, column-major, leading dimension ldc) with
+    int64_t ldc;       // C C^T = T T^T; one-sided Jacobi runs on the columns of C itself
 };
 
 struct LiftArgs {  // M = Rinv UB[:, :r], Ur = UB[:, :r]

@@ -47,6 +47,7 @@ template <> __device__ __forceinline__ int mfma_row<double>(int kg, int v) { ret
 #define DEV_FLAG_BREAKDOWN   0x2
 #define DEV_FLAG_NONFINITE   0x4
 #define DEV_FLAG_JACOBI_SLOW 0x8
+#define DEV_FLAG_RANK_CUT    0x20
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter c, key k.
 struct philox_out { uint32_t x[4]; };

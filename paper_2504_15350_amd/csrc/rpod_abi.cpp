@@ -65,6 +65,9 @@ struct Layout {
     int tin, tacc;
     int nsplit, ncb_lo;
     int64_t split_rows;
+    // FP64 small SVD: C = Zw^T Q2 by split-K over the n rows (contiguous splits)
+    int nsplit_c;
+    int64_t split_rows_c;
     int nchunk;
     int gram_cap;
     // fluctuation centring (Sec. 4.1): K blocks of N columns; K = 0: none.
@@ -145,6 +148,12 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.split_rows = roundup((d->m + ns - 1) / ns, 64);
     L.nsplit = (s16 || f32) ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
     L.ncb_lo = (int)(L.nP / stq16_block_cols(true));
+    {   // at most as many splits as the main product (its slab buffer holds these), >= 256 rows each
+        int64_t nsc = std::min<int64_t>(L.nsplit, (d->n + 255) / 256);
+        if (nsc < 1) nsc = 1;
+        L.split_rows_c = roundup((d->n + nsc - 1) / nsc, 64);
+        L.nsplit_c = (int)((d->n + L.split_rows_c - 1) / L.split_rows_c);
+    }
     int64_t nc = d->m / 2048;
     L.nchunk = (int)(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
     L.N = d->block_cols;
@@ -604,24 +613,92 @@ struct Recorder {
         chol(cargs(2, 2));
         sx(DT_F64, tin, L0().nt, true, app(&Layout::o_Zw2, &Layout::o_X, 2, true));
     }
+    // Orthonormal Q2 of the n x l iterate Zw = T^T by CholeskyQR2 (shifted
+    // CholeskyQR3 after a breakdown), written explicitly into Zw2; factors in
+    // R64[0] and R64[2] (R64[1] still holds the tall orthonormalisation's).
+    void orth_small_explicit() {
+        auto gargs = [&](size_t Layout::*src, bool cond) {
+            return each([&](const Item& it) {
+                return GramArgs{P->at<char>(it, it.L.*src), it.L.nP, it.d.n, P->at<double>(it, it.L.o_Gpart),
+                                P->at<double>(it, it.L.o_G), cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0,
+                                gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
+            });
+        };
+        auto app = [&](size_t Layout::*src, int k, bool cond) {
+            return each([&](const Item& it) {
+                return SxArgs{P->at<char>(it, it.L.*src), it.L.nP, it.d.n, it.L.lp, P->at<char>(it, it.L.o_R64[k]),
+                              it.L.lp, P->at<char>(it, it.L.o_Zw2), it.L.nP, it.L.nP,
+                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+            });
+        };
+        auto cargs = [&](int k, int mode) {
+            return each([&](const Item& it) {
+                return CholArgs{P->at<double>(it, it.L.o_G), it.d.n, P->at<double>(it, it.L.o_R64[k]),
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+            });
+        };
+        gram(DT_F64, gargs(&Layout::o_Zw, false));
+        chol(cargs(0, 0));
+        sx(DT_F64, DT_F64, L0().nt, true, app(&Layout::o_Zw, 0, false));
+        gram(DT_F64, gargs(&Layout::o_Zw2, false));
+        chol(cargs(2, 1));
+        sx(DT_F64, DT_F64, L0().nt, true, app(&Layout::o_Zw2, 2, true));  // shifted retry, in place
+        gram(DT_F64, gargs(&Layout::o_Zw2, true));
+        chol(cargs(2, 2));
+        sx(DT_F64, DT_F64, L0().nt, true, app(&Layout::o_Zw2, 2, false));  // Q2, in place
+    }
     void finish() {
         const Layout& L = L0();
-        // step 6: SVD of T through the eigenvectors of T T^T
-        gram(DT_F64, each([&](const Item& it) {
-                 return GramArgs{P->at<char>(it, it.L.o_Zw), it.L.nP, it.d.n, P->at<double>(it, it.L.o_Gpart),
-                                 P->at<double>(it, it.L.o_G), nullptr, 0, gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
-             }));
         Step j{K_JACOBI};
         j.lp = L.lp;
         // rotation threshold: FP64 rounding level on the FP64 path; elsewhere below
         // the FP32 storage error of Q (6e-8), which bounds the result anyway (1e-8
         // ends the iteration one sweep earlier than 1e-10 on the Fourier fields)
         const double jtol = L.tacc == DT_F64 ? (double)L.lp * 0x1.0p-53 : 1e-8;
-        B.add(j, each([&](const Item& it) {
-                  return JacobiArgs{P->at<double>(it, it.L.o_G), P->at<double>(it, it.L.o_UB),
-                                    P->at<double>(it, it.L.o_sig), P->flags(it), jtol, it.L.l, it.L.lp};
-              }),
-              tiles([](const Item&) { return 1; }));
+        if (L.tacc == DT_F64) {
+            // step 6 on the FP64 path, without squaring the condition number: T^T = Zw = Q2 R
+            // (CholeskyQR2 on the n side), C = Zw^T Q2 = R^T, and one-sided Jacobi on the
+            // columns of C gives the left singular vectors of T with errors of order
+            // u sigma_1 / sigma_k (the Gram route below has u (sigma_1 / sigma_k)^2)
+            orth_small_explicit();
+            Step k{K_STQ};
+            k.tin = DT_F64; k.nt = L.nt; k.vec = true;
+            auto kargs = each([&](const Item& it) {
+                StqArgs a{};
+                a.S = P->at<double>(it, it.L.o_Zw); a.ldS = it.L.nP; a.m = it.d.n; a.n = it.L.lp;
+                a.Q = P->at<double>(it, it.L.o_Zw2); a.Ql = nullptr; a.ldQ = it.L.nP;
+                a.Zp = P->at<double>(it, it.L.o_Zp); a.nP = WARM_PROJ_COLS;
+                a.split_rows = it.L.split_rows_c; a.nsplit = it.L.nsplit_c; a.ncb = 1; a.call = -1;
+                return a;
+            });
+            B.add(k, kargs, tiles([](const Item& it) { return it.L.nsplit_c; }));
+            out.push_back(k);
+            Step rd{K_REDUCE};
+            B.add(rd, each([&](const Item& it) {
+                      return ReduceArgs{P->at<double>(it, it.L.o_Zp), (int64_t)WARM_PROJ_COLS * it.L.lp,
+                                        P->at<double>(it, it.L.o_Zt), it.L.nsplit_c, 0};
+                  }),
+                  tiles([](const Item& it) { return (WARM_PROJ_COLS * it.L.lp + 255) / 256; }));
+            out.push_back(rd);
+            B.add(j, each([&](const Item& it) {
+                      return JacobiArgs{nullptr, P->at<double>(it, it.L.o_UB), P->at<double>(it, it.L.o_sig),
+                                        P->flags(it), jtol, it.L.l, it.L.lp, P->at<double>(it, it.L.o_Zt),
+                                        (int64_t)WARM_PROJ_COLS};
+                  }),
+                  tiles([](const Item&) { return 1; }));
+        } else {
+            // step 6: SVD of T through the eigenvectors of T T^T
+            gram(DT_F64, each([&](const Item& it) {
+                     return GramArgs{P->at<char>(it, it.L.o_Zw), it.L.nP, it.d.n, P->at<double>(it, it.L.o_Gpart),
+                                     P->at<double>(it, it.L.o_G), nullptr, 0, gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
+                 }));
+            B.add(j, each([&](const Item& it) {
+                      return JacobiArgs{P->at<double>(it, it.L.o_G), P->at<double>(it, it.L.o_UB),
+                                        P->at<double>(it, it.L.o_sig), P->flags(it), jtol, it.L.l, it.L.lp,
+                                        nullptr, 0};
+                  }),
+                  tiles([](const Item&) { return 1; }));
+        }
         out.push_back(j);
         // step 7: Phi = Q U_hat[:, :r] = Q1 (R^-1 U_hat[:, :r]); A = U_hat_r^T T
         Step lf{K_LIFT};

@@ -652,9 +652,13 @@ __device__ __forceinline__ double wave_max(double x) {
 // row order. lp > 64: the workgroup factorises with symmetric swaps in LDS.
 // Sweeps: round-robin pairs, eight lanes per pair (each lane two pairs of
 // adjacent rows per 16-row group, 16-byte LDS accesses), sums by DPP.
+// Factor route (C non-NULL): the columns of C (C C^T = T T^T, from an
+// orthonormal basis of T^T rather than from the Gram matrix) are loaded as
+// they are, with no permutation, and the sweeps start at once.
 template <int LP, int NTHR>
 __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, int l, double* __restrict__ UB,
-                                                 double* __restrict__ sig, int* flags, double tol, int* sweeps_out) {
+                                                 double* __restrict__ sig, int* flags, double tol, int* sweeps_out,
+                                                 const double* __restrict__ C = nullptr, int64_t ldc = 0) {
     constexpr int NPAIR = LP / 2;
     constexpr int TPP = NTHR / NPAIR;
     constexpr int RPT = LP / TPP;
@@ -665,7 +669,14 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
     __shared__ int perm[LP];
     __shared__ int s_rank, s_rot;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if constexpr (LP <= 64) {
+    if (C != nullptr) {
+        for (int e = tid; e < LP * LDW; e += NTHR) {
+            const int c = e / LDW, row = e % LDW;
+            W[e] = (c < l && row < l) ? C[(int64_t)c * ldc + row] : 0.0;
+        }
+        for (int c = tid; c < LP; c += NTHR) perm[c] = c;
+        __syncthreads();
+    } else if constexpr (LP <= 64) {
         __shared__ __attribute__((aligned(16))) double rowbuf[64];
         for (int e = tid; e < LP * LDW; e += NTHR) W[e] = 0.0;
         for (int c = tid; c < LP; c += NTHR) perm[c] = c;
@@ -712,6 +723,7 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
             if (lane == 0) s_rank = rank;
         }
         __syncthreads();
+        if (tid == 0 && s_rank < l) atomicOr(flags, DEV_FLAG_RANK_CUT);
     } else {
         __shared__ double s_val[NTHR / 64];
         __shared__ int s_idx[NTHR / 64];
@@ -792,6 +804,7 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
         }
         // L: lower triangle of the first `rank` columns; everything else zero
         const int rank = s_rank;
+        if (tid == 0 && rank < l) atomicOr(flags, DEV_FLAG_RANK_CUT);
         for (int e = tid; e < LP * LP; e += NTHR) {
             const int c = e / LP, row = e % LP;
             if (c >= rank || row < c || row >= l) W[c * LDW + row] = 0.0;
@@ -887,7 +900,7 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
 template <int LP>
 __global__ __launch_bounds__(4 * LP) void k_jacobi(Group<JacobiArgs> g) {
     const JacobiArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
-    jacobi_chol_body<LP, 4 * LP>(a.G, a.l, a.UB, a.sig, a.flags, a.tol, nullptr);
+    jacobi_chol_body<LP, 4 * LP>(a.G, a.l, a.UB, a.sig, a.flags, a.tol, nullptr, a.C, a.ldc);
 }
 
 int jacobi_threads(int lp) { return 4 * lp; }

@@ -177,6 +177,65 @@ def test_sketch_covers_rank_matches_exact_pod():
     assert metrics.sin_theta_max(gpu[0], P1) < 1e-10
 
 
+def _graded(m, n, decades_over_r, r, seed):
+    """Noise-free S = U diag(sigma) V^T with sigma_k = 10^(-d (k - 1) / (r - 1)), k = 1..n: sigma_1 / sigma_r
+    = 10^d exactly (U, V the seeded orthonormal factors of the 4096 x 200 generator). Returns St (n, m)."""
+    s = 10.0 ** (-decades_over_r * np.arange(n) / (r - 1))
+    U = synth._orthonormal(m, n, seed, 1)
+    V = synth._orthonormal(n, n, seed, 2)
+    return np.ascontiguousarray(((U * s) @ V.T).T)
+
+
+def test_fp64_graded_spectrum_kappa_1e3():
+    """sigma_1 / sigma_r = 1e3 at the flat FP64 tolerances. Through the Gram matrix T T^T the small SVD
+    would lose about u (sigma_1 / sigma_k)^2 ~ 1e-10 on sigma_20; the FP64 path factors T^T itself."""
+    St = _graded(4096, 200, 3.0, 20, 31)
+    res, *_ = case(St, 20, 10, 1, 7, torch.float64, name="graded 1e3")
+    assert res["sigma"] <= 1e-12
+
+
+def test_fp64_graded_spectrum_kappa_1e6():
+    """sigma_1 / sigma_r = 1e6 (sigma_l / sigma_1 ~ 6e-10: every orthonormalisation takes the shifted
+    retry). Both the device and the oracle resolve sigma_k to about u sigma_1 absolute (backward-stable
+    factorisations), so the bound is 1e-12 sigma_k + 1e3 u sigma_1, and the subspace bound is that
+    absolute error over the gap after mode r; the squared route would leave ~u (sigma_1/sigma_k)^2 = 1e-4."""
+    m, n, r, p, q, seed = 4096, 200, 20, 10, 1, 8
+    St = _graded(m, n, 6.0, r, 32)
+    say(f"[case] graded 1e6 m={m} n={n} r={r} p={p} q={q} seed={seed} float64")
+    Sd, S64 = upload(St, torch.float64)
+    Phi, sig, A = run_gpu(Sd, m, n, r, p, q, seed, torch.float64)
+    om = sketch_for(seed, n, r + p, torch.float64)
+    P2, s2, A2, ex = orpod.rpod_stable(S64, r, om, q)
+    u = 2.0 ** -53
+    bound = 1e-12 * s2 + 1e3 * u * s2[0]
+    err = np.abs(sig - s2)
+    say(f"[case] graded 1e6 sigma abs err / bound max {np.max(err / bound):.3f}, rel err sigma_r {err[-1] / s2[-1]:.2e}")
+    assert np.all(err <= bound)
+    gap = s2[r - 1] - ex["ritz"][r]
+    sin = metrics.sin_theta_max(Phi, P2)
+    assert sin <= 1e-10 + 1e3 * u * s2[0] / gap, sin
+    assert metrics.orth_err(Phi) <= 1e-13
+    assert metrics.lowrank_rel_diff(Phi, A, P2, A2) <= 1e-11
+
+
+def test_fp32_rank_cut_flag():
+    """FP32 path, sigma_l / sigma_1 ~ 1e-14: the pivoted Cholesky of the FP64 Gram matrix stops early, the
+    informational RANK_CUT flag is raised, and the leading modes still meet the FP32 tolerances."""
+    m, n, r, p, q, seed = 4096, 200, 3, 27, 1, 9
+    St = _graded(m, n, 1.0, 3, 33)   # sigma_k = 10^(-(k-1)/2)
+    Sd, S64 = upload(St, torch.float32)
+    plan = rp.Plan(m, n, r, p, q, dtype=torch.float32, device=DEV)
+    Phi_t, sig, A_t = plan.compute(Sd, seed)
+    flags = plan.status()
+    plan.close()
+    say(f"[case] rank cut flags={flags}")
+    assert flags & rp.FLAG_RANK_CUT and not flags & rp.FLAG_BREAKDOWN
+    om = sketch_for(seed, n, r + p, torch.float32)
+    P2, s2, A2, ex = orpod.rpod_stable(S64, r, om, q)
+    assert metrics.sigma_rel_err(sig.cpu().numpy(), s2) <= 1e-5
+    assert metrics.sin_theta_max(Phi_t.double().cpu().numpy().T, P2) <= 1e-4
+
+
 def test_rank_deficient_fp32():
     # exact rank 5 with l = 12 > rank: trailing sketch directions are noise
     m, n = 3000, 200
