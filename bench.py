@@ -5,14 +5,21 @@ One step = one full rPOD call (Alg. 1 of Sec. 4.2: sketch, q subspace
 iterations with CholeskyQR2, T = Q^T S, small SVD, lift, coefficients and
 sign fix) on a synthetic snapshot matrix already resident in HBM.
 
-Main workload (the JSON line's value): plain FP32, S = 262144 x 5000 (a
-512 x 512 cell-centred grid on [0,1] x [0,2], 5000 snapshots of a 200-mode
-Fourier field with |k|^-1.5 amplitudes and AR(1) time series, phi = 0.95,
-plus 1e-4 white noise), r = 50, p = 10, q = 2.
+Main workload (the JSON line's value): mixed precision, S = 1048576 x 10000
+stored in BF16 (a 1024 x 1024 cell-centred grid on [0,1] x [0,2], 10000
+snapshots of a 200-mode Fourier field with |k|^-1.5 amplitudes and AR(1) time
+series, phi = 0.95, plus 1e-4 white noise), r = 100, p = 20, q = 2, with FP32
+accumulation, FP64 Gram / Cholesky / small SVD and the hi + lo refinement
+pass. Beside it on the same matrix (under "mixed_vs_plain"): plain FP32 rPOD
+(the in-GPU baseline the speedup is quoted against) and the FP16-stored path,
+each with its sigma error and largest principal-angle sine against the
+oracle's FP64 rPOD (O2) of the unrounded matrix on the same BF16 sketch (so
+storage rounding counts), and sigma against the closed-form POD of the
+noise-free field (sketch-independent; the noise moves sigma by at most its
+spectral norm, reported).
 
-Also measured (unless --no-extra): the mixed-precision BF16 path against
-plain FP32 on S = 1048576 x 10000 (1024 x 1024 grid, same field), r = 100,
-p = 20, q = 2, reported under "mixed_vs_plain".
+Also measured (unless --no-extra): plain FP32 rPOD on S = 262144 x 5000
+(512 x 512 grid, same field), r = 50, p = 10, q = 2, under "plain_fp32_262144x5000".
 
 Also measured (unless --no-batch): the uneven batch of 64 snapshot matrices
 (m in {2^16, 2^17, 2^18}, n in [500, 4000], r in {10, 25, 50, 100}, p = 10,
@@ -23,20 +30,11 @@ one after another, reported under "batched_vs_plain".
 Also measured (unless --no-warm): the learned warm start on the parametric
 sweep S(mu) = U(mu) diag(exp(-alpha k)) V^T + noise (1e-9), m = 131072 (a
 256 x 512 grid), n = 2000, r = 50, 128 parameter vectors (96 train, 32
-test): the network is trained on plain-rPOD bases of the training matrices
-with a bank of 8 of them, then every test matrix is solved by plain FP32
-rPOD (q = 2) and by warm-started rPOD (q = 0 and 1, residual tolerance 1e-3,
-plain q = 2 as the fallback), in FP32 and BF16; errors are against the
-generator's exact singular values. Reported under "warm_vs_plain".
+test), reported under "warm_vs_plain".
 
-Also measured (unless --no-center): fluctuation centring (Sec. 4.1) on the
-main workload with ten parameter blocks of 500 snapshots, each block given a
-smooth time average of the field's RMS: the plain plan against the centred
-plan (block_cols = 500) on that matrix, reported under "centred_vs_plain".
-
-Also measured with the centring (same switch): a plan with the energy report
-(RPOD_DESC_ENERGY: ||S||_F^2 on the GPU, one more read of S) on the main
-workload, reported under "energy_report" with the energies of the modes.
+Also measured (unless --no-center): fluctuation centring (Sec. 4.1) and the
+energy report on the 262144 x 5000 workload, under "centred_vs_plain" and
+"energy_report".
 
 Per-kernel times of the passes over S come from HIP events that the library
 records on its stream around every pass during the timed steps.
@@ -72,17 +70,18 @@ WORKLOADS = {
     "bf16_1048576x10000": dict(
         label="mixed rPOD, S 1048576x10000 (1024x1024 grid) in BF16, Fourier field, r=100 p=20 q=2",
         nx=1024, ny=1024, n=10000, r=100, p=20, q=2, dtype="bf16", gen="device", gen_seed=3, seed=3,
-        sample_rows=16384),
+        sample_rows=65536),
     "f16_1048576x10000": dict(
         label="mixed rPOD, S 1048576x10000 (1024x1024 grid) in FP16, Fourier field, r=100 p=20 q=2",
         nx=1024, ny=1024, n=10000, r=100, p=20, q=2, dtype="f16", gen="device", gen_seed=3, seed=3,
-        sample_rows=16384),
+        sample_rows=65536),
     "fp32_1048576x10000": dict(
         label="plain rPOD FP32, S 1048576x10000 (1024x1024 grid), Fourier field, r=100 p=20 q=2",
         nx=1024, ny=1024, n=10000, r=100, p=20, q=2, dtype="f32", gen="device", gen_seed=3, seed=3,
-        sample_rows=16384),
+        sample_rows=65536),
 }
-DEFAULT = "fp32_262144x5000"
+DEFAULT = "bf16_1048576x10000"
+PLAIN_SMALL = "fp32_262144x5000"
 
 
 def log(*a):
@@ -132,7 +131,17 @@ def load_traffic(workload, kernel):
     return rec.get("bytes_per_launch")
 
 
-def measure(name, St, steps, warmup, block_cols=0, energy=False):
+PASS_KINDS = ((0, "S_X"), (1, "St_Q"), (2, "St_Q_refine"))
+# library kernel behind each pass kind, per storage type (the names rocprofv3 lists)
+KERNEL_OF = {
+    "bf16": {"S_X": "k_sx16<bf16>", "St_Q": "k_stq16<bf16, hi>", "St_Q_refine": "k_stq16<bf16, hi + lo>"},
+    "f16": {"S_X": "k_sx16<f16>", "St_Q": "k_stq16<f16, hi>", "St_Q_refine": "k_stq16<f16, hi + lo>"},
+    "f32": {"S_X": "k_sx_e6", "St_Q": "k_stq_e6"},
+    "f64": {"S_X": "k_sx<double>", "St_Q": "k_stq<double>"},
+}
+
+
+def measure(name, St, steps, warmup, block_cols=0, energy=False, keep_out=False):
     """Time `steps` rPOD calls; per-pass kernel times from the library's HIP events."""
     import torch
     import paper_2504_15350_amd as rp
@@ -164,9 +173,10 @@ def measure(name, St, steps, warmup, block_cols=0, energy=False):
     ms = wall * 1e3 / steps
     log(f"[bench] {name}: graph replay {ms_graph:.3f} ms per rPOD")
     kern = {}
-    for kind, kname in ((0, "S_X"), (1, "St_Q")):
+    for kind, kname in PASS_KINDS:
         nl, tot, bpl, fpl = plan.timing(kind)
-        kern[kname] = dict(launches=nl, avg_ms=tot / max(nl, 1), bytes=bpl, flops=fpl, total_ms=tot)
+        if nl:
+            kern[kname] = dict(launches=nl, avg_ms=tot / max(nl, 1), bytes=bpl, flops=fpl, total_ms=tot)
     plan.set_timing(False)
     sigma = out[1].cpu().numpy()
     en = plan.energy(0.9) if energy else None
@@ -184,15 +194,21 @@ def measure(name, St, steps, warmup, block_cols=0, energy=False):
     else:
         roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(gbs / HBM_PEAK_GBS, 4))
-    roof.update(traffic=load_traffic(name, dom), kernel=dom, avg_launch_ms=round(kd["avg_ms"], 4),
-                algorithmic_bytes_per_launch=kd["bytes"], algorithmic_flops_per_launch=kd["flops"],
-                hbm_gbs_algorithmic=round(gbs, 1))
+    roof.update(traffic=load_traffic(name, dom), kernel=KERNEL_OF[w["dtype"]].get(dom, dom), pass_kind=dom,
+                avg_launch_ms=round(kd["avg_ms"], 4), algorithmic_bytes_per_launch=kd["bytes"],
+                algorithmic_flops_per_launch=kd["flops"], hbm_gbs_algorithmic=round(gbs, 1))
     passes = sum(v["launches"] for v in kern.values()) / steps
     s_bytes = passes * m * n * St.element_size()
-    return dict(ms=ms, ms_graph=ms_graph, roofline=roof, sigma=sigma, flags=flags, energy=en,
-                hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
-                kernels={k: {"launches_per_step": v["launches"] // steps, "avg_ms": round(v["avg_ms"], 4)}
-                         for k, v in kern.items()})
+    res = dict(ms=ms, ms_graph=ms_graph, roofline=roof, sigma=sigma, flags=flags, energy=en,
+               hbm_gbs_s_passes=round(s_bytes / (ms * 1e-3) / 1e9, 1),
+               kernels={k: {"launches_per_step": v["launches"] // steps, "avg_ms": round(v["avg_ms"], 4),
+                            "hbm_gbs_algorithmic": round(v["bytes"] / (v["avg_ms"] * 1e-3) / 1e9, 1)}
+                        for k, v in kern.items()})
+    if keep_out:
+        res["out"] = out
+    else:
+        del out
+    return res
 
 
 BATCH = dict(count=64, shape_seed=4, p=10, q=2, seed0=1000)
@@ -253,9 +269,9 @@ def measure_batch(mats, shapes, steps, warmup, batched=True, tuning=None):
     torch.cuda.synchronize()
     ms_timed = (time.perf_counter() - t0) * 1e3 / steps
     flags = [pl.status() for pl in plans]
-    tot = {0: [0, 0.0, 0.0], 1: [0, 0.0, 0.0]}
+    tot = {0: [0, 0.0, 0.0], 1: [0, 0.0, 0.0], 2: [0, 0.0, 0.0]}
     for pl in plans:
-        for kind in (0, 1):
+        for kind in (0, 1, 2):
             nl, t, bpl, _fpl = pl.timing(kind)
             tot[kind][0] += nl
             tot[kind][1] += t
@@ -268,8 +284,10 @@ def measure_batch(mats, shapes, steps, warmup, batched=True, tuning=None):
     for pl in plans:
         pl.close()
     kern = {}
-    for kind, kname in ((0, "S_X"), (1, "St_Q")):
+    for kind, kname in PASS_KINDS:
         nl, t, b = tot[kind]
+        if nl == 0:
+            continue
         kern[kname] = dict(launches_per_step=nl // steps, avg_ms=round(t / max(nl, 1), 4),
                            hbm_gbs_algorithmic=round(b / (t * 1e-3) / 1e9, 1) if t > 0 else None)
     s_bytes = sum(m * n for (m, n, _r, _a) in shapes) * mats[0].element_size() * (2 * q + 2)
@@ -427,7 +445,7 @@ def center_block(St, steps, warmup):
     to St in place); the plain and the centred plan timed on that matrix."""
     import torch
     import synth
-    w = WORKLOADS[DEFAULT]
+    w = WORKLOADS[PLAIN_SMALL]
     n, m = St.shape
     N = CENTER["block_cols"]
     K = n // N
@@ -436,12 +454,12 @@ def center_block(St, steps, warmup):
                                   CENTER["seed"])
     St.view(K, N, m).add_(torch.from_numpy(means.T.astype(np.float32)).to(St.device)[:, None, :])
     torch.cuda.synchronize()
-    plain = measure(DEFAULT, St, steps, warmup)
-    cen = measure(DEFAULT, St, steps, warmup, block_cols=N)
+    plain = measure(PLAIN_SMALL, St, steps, warmup)
+    cen = measure(PLAIN_SMALL, St, steps, warmup, block_cols=N)
     recon = reconstruct_block(St, N)
     return {
         "reconstruct_block0": recon,
-        "config": {"workload": DEFAULT, "block_cols": N, "blocks": K, "mean_rms_over_field_rms": CENTER["mean_rms"],
+        "config": {"workload": PLAIN_SMALL, "block_cols": N, "blocks": K, "mean_rms_over_field_rms": CENTER["mean_rms"],
                    "steps": steps},
         "plain_ms": round(plain["ms"], 4), "centred_ms": round(cen["ms"], 4),
         "overhead": round(cen["ms"] / plain["ms"] - 1.0, 4),
@@ -456,7 +474,7 @@ def reconstruct_block(St, N, reps=5):
     relative L2 error of their time average against the block's snapshots."""
     import torch
     import paper_2504_15350_amd as rp
-    w = WORKLOADS[DEFAULT]
+    w = WORKLOADS[PLAIN_SMALL]
     n, m = St.shape
     plan = rp.Plan(m, n, w["r"], w["p"], w["q"], dtype=St.dtype, device=St.device, block_cols=N)
     Phi_t, _, A_t = plan.compute(St, w["seed"])
@@ -475,38 +493,180 @@ def reconstruct_block(St, N, reps=5):
     return {"time_steps": N, "ms": round(ms, 4), "gbs": round(gb / (ms * 1e-3), 1), "eps_time_average": eps}
 
 
-def cpu_baseline(St, w, seed):
-    """The oracle's FP64 rPOD (as it stands) on a row sample, scaled to the full matrix."""
-    from oracle import philox
-    from oracle import rpod as orpod
+def host_fp64(St_dev, chunk=500):
+    """FP64 host copy (n x m) of a device snapshot matrix (exact for FP32 and 16-bit entries)."""
     import torch
+    n, m = St_dev.shape
+    out = np.empty((n, m), dtype=np.float64)
+    o = torch.from_numpy(out)
+    for t0 in range(0, n, chunk):
+        o[t0:t0 + chunk].copy_(St_dev[t0:t0 + chunk].to(torch.float64))
+    return out
+
+
+def host_info():
+    """Host cores seen and their model name (the oracle runs on them)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        blas = sorted({f"{i.get('internal_api')} {i.get('version')}" for i in threadpool_info()})
     except Exception:
-        cores = os.cpu_count()
-    n, m = St.shape
-    ms = min(m, w["sample_rows"])
-    S = St[:, :ms].to(torch.float64).cpu().numpy().T
-    om = torch.from_numpy(philox.gaussian_sketch(seed, n, w["r"] + w["p"]).astype(np.float32))
-    om = om.to(St.dtype).double().numpy() if w["dtype"] != "f64" else philox.gaussian_sketch(seed, n, w["r"] + w["p"])
+        threads, blas = os.cpu_count(), []
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return dict(cpu_count=os.cpu_count(), affinity=affinity, blas_threads=int(threads), model=model, blas=blas)
+
+
+def cpu_baseline(S64, w, seed, sample_rows, reps=3, m_total=None):
+    """The oracle's FP64 rPOD (O2, as it stands) on the first sample_rows rows of
+    S (host FP64, snapshot-major n x m), median of reps runs, scaled to the
+    whole matrix (m_total rows, default m) by rows (every step of O2 is linear
+    in m)."""
+    from oracle import philox, pod
+    from oracle import rpod as orpod
+    import torch
+    n, m = S64.shape
+    rows = min(m, sample_rows)
+    view = pod.SnapshotMajor(S64[:, :rows])
+    om = philox.gaussian_sketch(seed, n, w["r"] + w["p"])
+    if w["dtype"] != "f64":
+        om = torch.from_numpy(om.astype(np.float32)).to(torch_dtype(w["dtype"])).double().numpy()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        orpod.rpod_stable(view, w["r"], om, w["q"])
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    info = host_info()
+    m_all = m if m_total is None else m_total
+    scale = m_all / rows
+    return dict(value=round(dt * scale * 1e3, 1), unit="ms", cores=info["blas_threads"], kind="oracle",
+                sample=f"O2 (the oracle's FP64 rPOD with numpy/LAPACK, same algorithm, sketch and q) on the first "
+                       f"{rows} of {m_all} rows of the same matrix, median of {reps} runs {dt:.2f} s "
+                       f"(runs {', '.join(f'{x:.2f}' for x in times)} s), scaled x{scale:g} to the whole matrix",
+                host=info)
+
+
+def accuracy_block(S64, gen, w, results):
+    """sigma and subspace errors of each GPU result against (a) O2 in FP64 on the
+    unrounded FP32 matrix with the same BF16-rounded sketch as the headline path
+    and (b) the closed-form POD of the noise-free field."""
+    from oracle import metrics, philox, pod
+    from oracle import rpod as orpod
+    import torch
+    n, m = S64.shape
+    r, l, q = w["r"], w["r"] + w["p"], w["q"]
+    om = philox.gaussian_sketch(w["seed"], n, l).astype(np.float32)
+    om = torch.from_numpy(om).to(torch.bfloat16).double().numpy()
     t0 = time.perf_counter()
-    orpod.rpod_stable(S, w["r"], om, w["q"])
-    dt = time.perf_counter() - t0
-    scale = m / ms
-    return dict(value=round(dt * scale * 1e3, 1), unit="ms", cores=int(cores), kind="oracle",
-                sample=f"O2 (FP64 numpy rPOD, same algorithm and sketch) on the first {ms} of {m} rows, "
-                       f"{dt:.2f} s measured, scaled x{scale:g} to the full matrix")
+    log("[bench] oracle: FP64 rPOD of the whole matrix on the host cores ...")
+    P2, s2, A2, ex = orpod.rpod_stable(pod.SnapshotMajor(S64), r, om, q, block_rows=32768, literal_A=False)
+    t_or = time.perf_counter() - t0
+    log(f"[bench] oracle done in {t_or:.1f} s")
+    s0 = pod.pod_sigma_sine_field(gen["amp"], gen["T"], w["nx"], w["ny"])[:r]
+    noise = 1e-4 * (np.sqrt(m) + np.sqrt(n))   # spectral norm of the white noise (Bai-Yin limit)
+    gap = bool(metrics.gap_ok(ex["ritz"], r))
+    out = {"oracle": "O2 (FP64 rPOD, Householder QR after every product) on the FP32 matrix as generated, "
+                     "same sketch rounded to BF16, q = 2; and the closed-form POD of the noise-free field",
+           "oracle_seconds": round(t_or, 1), "cut_gapped": gap,
+           "noise_bound_rel_sigma_r": float(noise / s0[-1]),
+           "oracle_vs_noise_free_pod_sigma_rel_err": metrics.sigma_rel_err(s2, s0)}
+    for name, res in results.items():
+        Phi_t, sig, _A = res["out"]
+        Phi = Phi_t.double().cpu().numpy().T
+        sg = sig.cpu().numpy()
+        d = dict(sigma_rel_err_vs_oracle=metrics.sigma_rel_err(sg, s2),
+                 sigma_rel_err_vs_noise_free_pod=metrics.sigma_rel_err(sg, s0),
+                 orth=metrics.orth_err(Phi))
+        if gap:
+            d["sin_theta_vs_oracle"] = metrics.sin_theta_max(Phi, P2)
+        d["within_1e-3"] = bool(d["sigma_rel_err_vs_oracle"] <= 1e-3 and d.get("sin_theta_vs_oracle", 0.0) <= 1e-3)
+        out[name] = d
+        log(f"[bench] accuracy {name}: {d}")
+    return out
+
+
+def mixed_block(dev, steps, warmup, accuracy=True, cpu=True):
+    """The headline workload in BF16 (the value) and, on the same matrix, plain
+    FP32 (the in-GPU baseline) and FP16."""
+    import torch
+    import synth
+    w = WORKLOADS[DEFAULT]
+    t0 = time.perf_counter()
+    gen = synth.fourier_field_device(w["nx"], w["ny"], w["n"], seed=w["gen_seed"], dtype=torch.float32, device=dev)
+    S32 = gen.pop("St")
+    torch.cuda.synchronize()
+    log(f"[bench] generated S {S32.shape[1]}x{S32.shape[0]} FP32 in {time.perf_counter() - t0:.1f} s")
+    keep = accuracy
+    S16 = S32.to(torch.bfloat16)
+    res = {"bf16": measure(DEFAULT, S16, steps, warmup, keep_out=keep)}
+    del S16
+    torch.cuda.empty_cache()
+    ext_steps, ext_warm = max(3, steps // 2), max(1, warmup // 2)
+    Sh = S32.to(torch.float16)
+    res["f16"] = measure("f16_1048576x10000", Sh, ext_steps, ext_warm, keep_out=keep)
+    del Sh
+    torch.cuda.empty_cache()
+    res["fp32"] = measure("fp32_1048576x10000", S32, ext_steps, ext_warm, keep_out=keep)
+    acc = cpu_res = None
+    if accuracy or cpu:
+        t0 = time.perf_counter()
+        S64 = host_fp64(S32)
+        log(f"[bench] FP64 host copy of S ({S64.nbytes / 1e9:.0f} GB) in {time.perf_counter() - t0:.1f} s")
+        del S32
+        torch.cuda.empty_cache()
+        if accuracy:
+            acc = accuracy_block(S64, gen, w, res)
+        if cpu:
+            log("[bench] timing the CPU oracle on a row sample ...")
+            cpu_res = cpu_baseline(S64, w, w["seed"], w["sample_rows"])
+            log(f"[bench] cpu baseline {cpu_res['value']:.0f} ms ({cpu_res['sample']})")
+        del S64
+    else:
+        del S32
+    for v in res.values():
+        v.pop("out", None)
+    torch.cuda.empty_cache()
+    return res, acc, cpu_res
+
+
+def simple_block(name, dev, steps, warmup, cpu=True):
+    """One workload alone (profiling runs): time it, CPU baseline on a row sample."""
+    import torch
+    w = WORKLOADS[name]
+    t0 = time.perf_counter()
+    St = make_input(w, dev)
+    torch.cuda.synchronize()
+    log(f"[bench] generated S {St.shape[1]}x{St.shape[0]} {St.dtype} in {time.perf_counter() - t0:.1f} s")
+    r = measure(name, St, steps, warmup)
+    cpu_res = None
+    if cpu:
+        rows = min(St.shape[1], w["sample_rows"])
+        S64 = host_fp64(St[:, :rows])
+        cpu_res = cpu_baseline(S64, w, w["seed"], rows, m_total=St.shape[1])
+    return r, cpu_res, St
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-vs-plain measurement")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the oracle comparison of the mixed workload")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 262144 x 5000 FP32 measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batch measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start sweep")
     ap.add_argument("--no-center", action="store_true", help="skip the fluctuation-centring measurement")
@@ -532,54 +692,51 @@ def main():
     import torch
     dev = torch.device("cuda", 0)
     w = WORKLOADS[args.workload]
-    t0 = time.perf_counter()
-    St = make_input(w, dev)
-    torch.cuda.synchronize()
-    log(f"[bench] generated S {St.shape[1]}x{St.shape[0]} {St.dtype} in {time.perf_counter() - t0:.1f} s")
-    main_res = measure(args.workload, St, args.steps, args.warmup)
+    mixed = None
+    if args.workload == DEFAULT:
+        res, acc, cpu = mixed_block(dev, args.steps, args.warmup, accuracy=not args.no_accuracy,
+                                    cpu=not args.no_cpu_baseline)
+        main_res = res["bf16"]
+        mixed = {
+            "config": {"m": 1048576, "n": 10000, "r": 100, "p": 20, "q": 2},
+            "mixed_bf16_ms": round(res["bf16"]["ms"], 3), "mixed_f16_ms": round(res["f16"]["ms"], 3),
+            "plain_fp32_ms": round(res["fp32"]["ms"], 3),
+            "speedup_bf16_vs_plain_fp32": round(res["fp32"]["ms"] / res["bf16"]["ms"], 2),
+            "speedup_f16_vs_plain_fp32": round(res["fp32"]["ms"] / res["f16"]["ms"], 2),
+            "accuracy": acc,
+            "f16_roofline": res["f16"]["roofline"], "f16_kernels": res["f16"]["kernels"],
+            "plain_roofline": res["fp32"]["roofline"], "plain_kernels": res["fp32"]["kernels"],
+            "plain_hbm_gbs_s_passes": res["fp32"]["hbm_gbs_s_passes"],
+        }
+        St_small = None
+    else:
+        main_res, cpu, St_small = simple_block(args.workload, dev, args.steps, args.warmup,
+                                               cpu=not args.no_cpu_baseline)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a row sample ...")
-        cpu = cpu_baseline(St, w, w["seed"])
-        log(f"[bench] cpu baseline {cpu['value']:.0f} ms ({cpu['sample']})")
-    energy = None
-    if not args.no_center and args.workload == DEFAULT:
-        e_res = measure(DEFAULT, St, max(3, args.steps // 2), max(1, args.warmup // 2), energy=True)
+    extra = energy = center = None
+    if args.workload == DEFAULT and not (args.no_extra and args.no_center):
+        t0 = time.perf_counter()
+        St_small = make_input(WORKLOADS[PLAIN_SMALL], dev)
+        torch.cuda.synchronize()
+        log(f"[bench] generated {PLAIN_SMALL} in {time.perf_counter() - t0:.1f} s")
+    if args.workload == DEFAULT and not args.no_extra:
+        e = measure(PLAIN_SMALL, St_small, args.steps, args.warmup)
+        extra = {"ms": round(e["ms"], 4), "ms_graph_replay": round(e["ms_graph"], 4), "roofline": e["roofline"],
+                 "kernels": e["kernels"], "hbm_gbs_s_passes": e["hbm_gbs_s_passes"],
+                 "config": {"m": 262144, "n": 5000, "r": 50, "p": 10, "q": 2}}
+    if St_small is not None and args.workload in (DEFAULT, PLAIN_SMALL) and not args.no_center:
+        base = measure(PLAIN_SMALL, St_small, max(3, args.steps // 2), max(1, args.warmup // 2))
+        e_res = measure(PLAIN_SMALL, St_small, max(3, args.steps // 2), max(1, args.warmup // 2), energy=True)
         e, rk = e_res["energy"]
-        energy = {"with_energy_ms": round(e_res["ms"], 4), "plain_ms": round(main_res["ms"], 4),
-                  "overhead": round(e_res["ms"] / main_res["ms"] - 1.0, 4),
+        energy = {"with_energy_ms": round(e_res["ms"], 4), "plain_ms": round(base["ms"], 4),
+                  "overhead": round(e_res["ms"] / base["ms"] - 1.0, 4),
                   "energy_first_10": [round(float(x), 6) for x in e[:10]], "energy_at_l": round(float(e[-1]), 6),
                   "rank_for_0.9": rk}
         log(f"[bench] energy: {energy}")
-    center = None
-    if not args.no_center and args.workload == DEFAULT:
-        center = center_block(St, max(3, args.steps // 2), max(1, args.warmup // 2))
+        center = center_block(St_small, max(3, args.steps // 2), max(1, args.warmup // 2))
         log(f"[bench] centring: plain {center['plain_ms']:.3f} ms, centred {center['centred_ms']:.3f} ms")
-    del St
+    del St_small
     torch.cuda.empty_cache()
-
-    extra = None
-    if not args.no_extra:
-        ext_steps, ext_warm = max(3, args.steps // 2), max(1, args.warmup // 2)
-        rows = {}
-        for name in ("bf16_1048576x10000", "fp32_1048576x10000"):
-            t0 = time.perf_counter()
-            Sx = make_input(WORKLOADS[name], dev)
-            torch.cuda.synchronize()
-            log(f"[bench] generated {name} in {time.perf_counter() - t0:.1f} s")
-            rows[name] = measure(name, Sx, ext_steps, ext_warm)
-            del Sx
-            torch.cuda.empty_cache()
-        mb, pf = rows["bf16_1048576x10000"], rows["fp32_1048576x10000"]
-        extra = {
-            "config": {"m": 1048576, "n": 10000, "r": 100, "p": 20, "q": 2, "steps": ext_steps},
-            "mixed_bf16_ms": round(mb["ms"], 3), "plain_fp32_ms": round(pf["ms"], 3),
-            "speedup": round(pf["ms"] / mb["ms"], 2),
-            "sigma_rel_diff_bf16_vs_fp32": float(np.max(np.abs(mb["sigma"] - pf["sigma"]) / pf["sigma"])),
-            "mixed_hbm_gbs_s_passes": mb["hbm_gbs_s_passes"], "mixed_roofline": mb["roofline"],
-            "mixed_kernels": mb["kernels"], "plain_roofline": pf["roofline"], "plain_kernels": pf["kernels"],
-        }
 
     batch = None
     if not args.no_batch:
@@ -610,7 +767,8 @@ def main():
         "kernels": main_res["kernels"],
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
-        "mixed_vs_plain": extra,
+        "mixed_vs_plain": mixed,
+        "plain_fp32_262144x5000": extra,
         "batched_vs_plain": batch,
         "warm_vs_plain": warm,
         "centred_vs_plain": center,

@@ -397,12 +397,14 @@ rpod_status rpod_compute_warm(rpod_plan plan, const void* S, const float* mu, ui
 /* Per-pass timing, for measurement. With enable != 0 the plan records a
  * pair of HIP events on its stream around every pass over S issued by later
  * compute calls (pass 0: the products S X of Alg. 1 steps 2-3; pass 1: the
- * products S^T Q of steps 3 and 5), resetting earlier records; enable = 0
- * stops recording. The first call with enable != 0 creates the events. */
+ * products S^T Q of steps 3 and 5; pass 2: on 16-bit storage, the product
+ * S^T Q of step 5, which carries Q as hi + lo parts and is kept apart from
+ * pass 1), resetting earlier records; enable = 0 stops recording. The first
+ * call with enable != 0 creates the events. */
 rpod_status rpod_plan_set_timing(rpod_plan plan, int32_t enable);
 
 /* Synchronise the plan's stream and report the recorded launches of one
- * pass kind (0 or 1): their number, summed duration in milliseconds, and the
+ * pass kind (0, 1 or 2): their number, summed duration in milliseconds, and the
  * algorithmic work of one launch: bytes = m n size(S) + n l size(S) + m l 4
  * (S once, the n x l operand once, the m x l result or operand once) and
  * flops = 2 m n l, summed over the matrices the launch covers (a batched

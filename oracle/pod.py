@@ -64,6 +64,20 @@ def pod_snapshots(S, r):
     return Phi, s[:r].copy(), A, s
 
 
+class SnapshotMajor:
+    """S (m x n) as the oracle reads it -- by row blocks -- when the caller
+    holds it snapshot-major as St (n x m, one snapshot per row): a row block
+    of S is the transposed view St[:, rows].T, so the blocked products run on
+    that array in place (no second copy of a matrix of tens of GB)."""
+
+    def __init__(self, St):
+        self.St = St
+        self.shape = (St.shape[1], St.shape[0])
+
+    def __getitem__(self, rows):
+        return self.St[:, rows].T
+
+
 def row_blocks(S, block_rows):
     """Yield (row offset, FP64 copy of a row block) of a 2-D array-like S."""
     m = S.shape[0]
@@ -92,3 +106,15 @@ def pod_tsqr(S, r, block_rows=65536):
         A += Phi[i0:i0 + blk.shape[0]].T @ blk
     Phi, A, _ = sign_fix(Phi, A)
     return Phi, s[:r].copy(), A, s
+
+
+def pod_sigma_sine_field(amp, T, nx, ny):
+    """Singular values of the noise-free synthetic field S0 = F diag(amp) T^T in
+    closed form (the POD of Sec. 4.1 without a decomposition of S0): the
+    columns of F are the sampled sine modes sin(pi a x) sin(pi b y / 2) on the
+    cell centres of an nx x ny grid, mutually orthogonal with squared norm
+    nx ny / 4, so S0 = (sqrt(nx ny) / 2) F_hat diag(amp) T^T with F_hat
+    orthonormal and sigma(S0) = (sqrt(nx ny) / 2) sigma(diag(amp) T^T), an SVD
+    of a (modes x n) matrix."""
+    M = np.asarray(amp, dtype=np.float64)[:, None] * np.asarray(T, dtype=np.float64).T
+    return 0.5 * np.sqrt(float(nx) * float(ny)) * np.linalg.svd(M, compute_uv=False)

@@ -52,18 +52,26 @@ def _orth(Y):
     return Q
 
 
-def _finish(S, Q, r, block_rows):
-    """Steps 5-7 plus the coefficients: T = Q^T S, SVD, lift, C = U_r^T S."""
+def _finish(S, Q, r, block_rows, literal_A=True):
+    """Steps 5-7 plus the coefficients: T = Q^T S, SVD, lift, C = U_r^T S.
+
+    literal_A=False takes C = Sigma_r V_r^T from the SVD of T instead of a
+    further pass over S (equal in exact arithmetic, since T = Q^T S and
+    Phi = Q U_hat_r give U_r^T S = U_hat_r^T T); for matrices so large that
+    one more pass matters."""
     T = st_times(S, Q, block_rows).T             # step 5: l x n
     Uh, s, Vt = np.linalg.svd(T, full_matrices=False)   # step 6
     Phi = Q @ Uh[:, :r]                          # step 7, first r columns
-    A = st_times(S, Phi, block_rows).T           # C = U_r^T S, computed literally
+    if literal_A:
+        A = st_times(S, Phi, block_rows).T       # C = U_r^T S, computed literally
+    else:
+        A = s[:r, None] * Vt[:r]
     Phi, A, signs = sign_fix(Phi, A)
     Vt_r = Vt[:r] * signs[:, None]
     return Phi, s[:r].copy(), A, dict(ritz=s, Vt_r=Vt_r, T=T, Q=Q, U_hat=Uh)
 
 
-def rpod_stable(S, r, omega, q, block_rows=_BLOCK):
+def rpod_stable(S, r, omega, q, block_rows=_BLOCK, literal_A=True):
     """Alg. 1 with re-orthonormalisation after every product.
 
     omega: n x l FP64 sketch (step 1 drawn by the caller). Returns
@@ -74,7 +82,7 @@ def rpod_stable(S, r, omega, q, block_rows=_BLOCK):
     for _ in range(q):                                    # step 3, stable form
         Z = _orth(st_times(S, Q, block_rows))
         Q = _orth(s_times(S, Z, block_rows))
-    return _finish(S, Q, r, block_rows)
+    return _finish(S, Q, r, block_rows, literal_A)
 
 
 def rpod_literal(S, r, omega, q, block_rows=_BLOCK):

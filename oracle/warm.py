@@ -33,6 +33,17 @@ A-posteriori residual of the range basis Q (l orthonormal columns): the
   rho = 10 sqrt(2/pi) max_i ||(I - Q Q^T) S w_i|| / sigma_1.
   The probes are the columns of the Philox sketch of the same seed drawn
   with counter word 3 = 1 (stream 1), independent of the sketch itself.
+Per-mode residual of the returned modes (the acceptance rule of warm plans):
+  with v_k = A_k^T / sigma_k (A = Phi^T S = Sigma V^T), the singular triplet
+  (phi_k, sigma_k, v_k) of S has residual r_k = S v_k - sigma_k phi_k (its
+  other half S^T phi_k - sigma_k v_k vanishes by construction), and
+  rho = max_{k <= r} ||r_k|| / sigma_k. For the exact SVD rho = 0, and by
+  the residual bound for the symmetric matrix [[0, S], [S^T, 0]] some
+  singular value of S lies within ||r_k|| of sigma_k, so rho <= tol bounds
+  every sigma_k's relative error by tol to first order.
+Fallback by continuation: when rho > tol, q_fb further subspace iterations
+  run from the warm range basis Q (Z = orth(S^T Q), Q = orth(S Z)), then
+  steps 5-7 of Alg. 1 again; the warm work is kept, not repeated.
 """
 
 import numpy as np
@@ -169,4 +180,37 @@ def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2, probes=None):
     if probes is not None:
         ex["rho"] = probe_residual(S, Q, s[0], probes)
     ex["W"] = W
+    return Phi, s, A, ex
+
+
+def mode_residual(S, Phi, sigma, A):
+    """rho = max_k ||S v_k - sigma_k phi_k|| / sigma_k with v_k = A_k^T / sigma_k,
+    and the per-mode values (S m x n, Phi m x r, sigma r, A r x n)."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    V = np.asarray(A, dtype=np.float64).T / sigma[None, :]
+    R = s_times(S, V) - np.asarray(Phi, dtype=np.float64) * sigma[None, :]
+    per = np.linalg.norm(R, axis=0) / sigma
+    return float(np.max(per)), per
+
+
+def warm_rpod_continued(S, bases, c, kstar, r, omega_p, q, tol, q_fb, j=2):
+    """Warm-started rPOD with the per-mode acceptance rule: the warm result if
+    rho <= tol, else q_fb further subspace iterations from the warm range basis
+    and steps 5-7 again. Returns (Phi, sigma, A, extras) with extras['rho'] the
+    warm result's residual and extras['fell_back']."""
+    Phi_b = np.hstack([np.asarray(b, dtype=np.float64) for b in bases])
+    Z = assemble(Phi_b.T @ Phi_b, c, kstar, r, j)
+    Y = np.hstack([Phi_b @ Z, s_times(S, np.asarray(omega_p, dtype=np.float64))])
+    Q = _orth(Y)
+    for _ in range(q):
+        Q = _orth(s_times(S, _orth(st_times(S, Q))))
+    Phi, s, A, ex = _finish(S, Q, r, 65536)
+    rho, per = mode_residual(S, Phi, s, A)
+    ex.update(rho=rho, rho_modes=per, fell_back=bool(rho > tol))
+    if rho > tol:
+        for _ in range(q_fb):
+            Q = _orth(s_times(S, _orth(st_times(S, Q))))
+        Phi, s, A, ex2 = _finish(S, Q, r, 65536)
+        ex2.update(rho=rho, rho_modes=per, fell_back=True)
+        ex = ex2
     return Phi, s, A, ex

@@ -208,7 +208,8 @@ class _PlanBase:
         _check(lib().rpod_plan_set_timing(self._h, 1 if enable else 0))
 
     def timing(self, pass_kind):
-        """(launches, total_ms, bytes_per_launch, flops_per_launch) of pass 0 (S X) or 1 (S^T Q)."""
+        """(launches, total_ms, bytes_per_launch, flops_per_launch) of pass 0 (S X), 1 (S^T Q) or 2
+        (the 16-bit refinement S^T Q with Q as hi + lo)."""
         n = ctypes.c_int64(0)
         t, b, f = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
         _check(lib().rpod_plan_get_timing(self._h, int(pass_kind), ctypes.byref(n), ctypes.byref(t),

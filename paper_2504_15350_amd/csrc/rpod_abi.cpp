@@ -218,7 +218,7 @@ struct Step {
     int tin = 0, tout = 0, nt = 0, lp = 0;  // lp: padded size (small SVD, Cholesky)
     bool vec = true, upper = false, lo = false;
     bool energy = false;  // K_SXE6: also the per-tile sums of squares; K_FROB: only the final sum
-    int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S (timed)
+    int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S, 2: the 16-bit refinement pass (timed)
     size_t a1 = 0, t1 = 0, a2 = 0, t2 = 0;  // program-blob offsets of the argument / tile tables
     int count = 0, tiles1 = 0, tiles2 = 0;
     double bytes = 0, flops = 0;  // algorithmic work of the launch (passes over S)
@@ -270,9 +270,9 @@ struct rpod_plan_s {
     hipGraphExec_t exec = nullptr;
     // per-pass event timing (measurement only)
     bool timing = false;
-    std::vector<hipEvent_t> ev[2];
-    std::vector<double> evbytes[2], evflops[2];
-    size_t used[2] = {0, 0};
+    std::vector<hipEvent_t> ev[3];
+    std::vector<double> evbytes[3], evflops[3];
+    size_t used[3] = {0, 0, 0};
     std::vector<CallDesc> host_calls;
     // warm plans: the model, the fallback program and its graph, the warm region
     rpod_warm_s* model = nullptr;
@@ -398,11 +398,12 @@ struct Recorder {
         B.add(s, args, tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
         out.push_back(s);
     }
-    // pass over S: slabs of S^T Q1 (lo: Q1 carried as hi + lo on 16-bit paths), then their sum Zt
-    void pass_stq(bool lo) {
+    // pass over S: slabs of S^T Q1 (lo: Q1 carried as hi + lo on 16-bit paths), then their sum
+    // into dst (Zt; Zw directly when Q1 needs no further factor)
+    void pass_stq(bool lo, size_t Layout::*dst = &Layout::o_Zt) {
         const bool s16 = is16(L0().tin), f32 = L0().tin == DT_F32;
         Step s{s16 ? K_STQ16 : f32 ? K_STQE6 : K_STQ};
-        s.tin = L0().tin; s.nt = L0().nt; s.pass = 1; s.lo = s16 && lo;
+        s.tin = L0().tin; s.nt = L0().nt; s.lo = s16 && lo; s.pass = s.lo ? 2 : 1;
         s.vec = true;
         for (const Item* it : C) {
             s.vec = s.vec && (it->d.ld % (s16 ? 8 : 4) == 0);
@@ -429,7 +430,7 @@ struct Recorder {
         Step r{K_REDUCE};
         B.add(r, each([&](const Item& it) {
                   // the FP32 and 16-bit passes accumulate in FP32 and write FP32 slabs
-                  return ReduceArgs{P->at<double>(it, it.L.o_Zp), it.L.nP * it.L.lp, P->at<double>(it, it.L.o_Zt),
+                  return ReduceArgs{P->at<double>(it, it.L.o_Zp), it.L.nP * it.L.lp, P->at<double>(it, it.L.*dst),
                                     it.L.nsplit, it.L.tin != DT_F64 ? 1 : 0};
               }),
               tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
@@ -480,8 +481,8 @@ struct Recorder {
               tiles([](const Item& it) { return (int)((it.d.m + 255) / 256); }));
         out.push_back(s);
     }
-    // Zt -= E (Msum^T Q1) / N after an S^T Q pass
-    void center_z() {
+    // Z -= E (Msum^T Q1) / N after an S^T Q pass (Z: the pass's sum, Zt or Zw)
+    void center_z(size_t Layout::*dst = &Layout::o_Zt) {
         if (!centred()) return;
         Step s{K_CCROSS};
         s.tin = L0().tacc;
@@ -502,7 +503,7 @@ struct Recorder {
         out.push_back(r);
         Step z{K_CZ};
         B.add(z, each([&](const Item& it) {
-                  return CenterZArgs{P->at<double>(it, it.L.o_Zt), it.L.nP, it.d.n, it.L.N,
+                  return CenterZArgs{P->at<double>(it, it.L.*dst), it.L.nP, it.d.n, it.L.N,
                                      P->at<double>(it, it.L.o_Pc), it.L.lp, it.L.K};
               }),
               tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
@@ -893,9 +894,9 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_CHOL: return launch_chol_inv(s.lp, P->gl<CholArgs>(s, false), st);
         case K_JACOBI: return launch_jacobi(s.lp, P->gl<JacobiArgs>(s, false), st);
         case K_LIFT: return launch_lift_coef(P->gl<LiftArgs>(s, false), st);
+        case K_SPLIT: return launch_split16(s.tin, P->gl<SplitArgs>(s, false), st);
         case K_SIGNS: return launch_signs(s.tin, P->gl<ColmaxArgs>(s, false), P->gl<SignArgs>(s, true), st);
         case K_FIN: return launch_finalize(s.tin, P->gl<FinArgs>(s, false), P->gl<FinArgs>(s, true), st);
-        case K_SPLIT: return launch_split16(s.tin, P->gl<SplitArgs>(s, false), st);
         case K_WFWD: return launch_warm_plan_forward(P->gl<WarmFwdArgs>(s, false), st);
         case K_WZ: return launch_warm_z(P->gl<WarmZArgs>(s, false), st);
         case K_SXW: return launch_sx_wide(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
@@ -1075,7 +1076,7 @@ void destroy_plan(rpod_plan_s* P) {
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->fb_exec) (void)hipGraphExecDestroy(P->fb_exec);
     if (P->fb_graph) (void)hipGraphDestroy(P->fb_graph);
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 3; ++k)
         for (hipEvent_t ev : P->ev[k]) (void)hipEventDestroy(ev);
     delete P;
 }
@@ -1693,14 +1694,14 @@ rpod_status rpod_status_query(rpod_plan plan, int32_t* device_flags) {
 rpod_status rpod_plan_set_timing(rpod_plan plan, int32_t enable) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     plan->timing = enable != 0;
-    plan->used[0] = plan->used[1] = 0;
+    plan->used[0] = plan->used[1] = plan->used[2] = 0;
     return RPOD_OK;
 }
 
 rpod_status rpod_plan_get_timing(rpod_plan plan, int32_t pass, int64_t* launches, double* total_ms,
                                  double* bytes_per_launch, double* flops_per_launch) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
-    if (pass < 0 || pass > 1) return fail(RPOD_EINVAL, "pass must be 0 or 1");
+    if (pass < 0 || pass > 2) return fail(RPOD_EINVAL, "pass must be 0, 1 or 2");
     HIP_TRY(hipStreamSynchronize(plan->st));
     double tot = 0.0, b = 0.0, f = 0.0;
     for (size_t k = 0; k < plan->used[pass]; ++k) {

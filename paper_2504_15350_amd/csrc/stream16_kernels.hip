@@ -311,15 +311,21 @@ __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restri
                                                  4 * kg) = acc[g][u][c];
 }
 
-// grouped launch: local tile t covers column block t % ncb of split t / ncb
+// grouped launch: tile t covers column block t % ncb of split t / ncb. XCD-aware
+// order (workgroup b runs on XCD b mod 8): when the item's tile count and its
+// first workgroup are multiples of 8, local workgroup b takes tile
+// (b mod 8) T / 8 + b / 8, so each XCD holds every column block of a range of
+// splits and a split's Q rows are fetched into one L2 only.
 template <typename T16, int NT, bool VEC, bool LO, int G>
 __global__ __launch_bounds__(256, 2) void k_stq16(Group<StqArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const StqArgs& a = g.args[it];
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    const int local = blockIdx.x - g.tstart[it], ntl = a.ncb * a.nsplit;
+    const int tile = ((ntl & 7) == 0 && (g.tstart[it] & 7) == 0) ? (local & 7) * (ntl >> 3) + (local >> 3) : local;
     stq16_body<T16, NT, VEC, LO, G>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q),
                                     gbl((const unsigned short*)a.Ql), a.ldQ, gbl((float*)a.Zp), a.nP, a.nsplit, a.ncb,
-                                    blockIdx.x - g.tstart[it]);
+                                    tile);
 }
 
 // Split an FP32 tall matrix into 16-bit hi = round(q) and lo = round(q - hi).

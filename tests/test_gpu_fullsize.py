@@ -5,10 +5,9 @@ benchmark times (default plans, the same generators and seeds).
   p = 10, q = 2: compared with the oracle's O2 on the whole matrix (FP64 on
   the host, a few seconds), FP32 tolerances.
 * Mixed BF16, S 1048576 x 10000 (1024 x 1024 grid), r = 100, p = 20, q = 2:
-  too large for the oracle as a whole, so checked on what holds at any size
-  and on sampled outputs the oracle computes one by one: Phi orthonormal,
-  sigma descending and equal to the row norms of A (A = U_r^T T = Sigma V^T),
-  and A[:, j] = Phi^T S[:, j] for sampled snapshots j in FP64.
+  compared with the oracle's O2 on the same BF16 matrix, upcast exactly to
+  FP64 on the host (about 84 GB, streamed by row blocks; a minute or so of
+  FP64 BLAS), mixed-path tolerances.
 """
 
 import sys
@@ -19,7 +18,7 @@ import torch
 
 import paper_2504_15350_amd as rp
 import synth
-from oracle import metrics, philox
+from oracle import metrics, philox, pod
 from oracle import rpod as orpod
 
 pytestmark = pytest.mark.gpu
@@ -63,7 +62,21 @@ def test_fp32_headline_full_size():
     assert res.get("sin", 0.0) <= 1e-4 and res.get("A", 0.0) <= 1e-4
 
 
-def test_bf16_mixed_full_size_sampled():
+def host_fp64(St_dev, chunk=500):
+    """FP64 host copy (n x m) of a device snapshot matrix, exact for 16-bit and FP32 entries."""
+    n, m = St_dev.shape
+    out = np.empty((n, m), dtype=np.float64)
+    o = torch.from_numpy(out)
+    for t0 in range(0, n, chunk):
+        o[t0:t0 + chunk].copy_(St_dev[t0:t0 + chunk].to(torch.float64))
+    return out
+
+
+def test_bf16_mixed_full_size_against_oracle():
+    """The mixed-precision workload at full size against O2 on the same BF16 S
+    (upcast exactly to FP64 on the host, about 84 GB) and the same BF16-rounded
+    sketch, with the mixed-path tolerances; the coefficients through
+    Sigma_r V_r^T of the oracle's small SVD (exact given its T = Q^T S)."""
     nx, ny, n, r, p, q, seed = 1024, 1024, 10000, 100, 20, 2, 3
     m = nx * ny
     say(f"[full bf16] m={m} n={n} r={r} p={p} q={q} seed={seed}")
@@ -76,18 +89,19 @@ def test_bf16_mixed_full_size_sampled():
     s = sig.cpu().numpy()
     Phi = Phi_t.double().cpu().numpy().T        # (m, r)
     A = A_t.double().cpu().numpy().T            # (r, n)
-    orth = metrics.orth_err(Phi)
-    rownorm = np.linalg.norm(A, axis=1)
-    cons = float(np.max(np.abs(rownorm - s) / s))
-    cols = np.random.default_rng(11).choice(n, size=8, replace=False)
-    worst = 0.0
-    for j in cols:
-        sj = St[int(j)].double().cpu().numpy()  # snapshot j, exact in FP64
-        ref = Phi.T @ sj
-        worst = max(worst, float(np.max(np.abs(A[:, j] - ref)) / np.linalg.norm(sj)))
-    say(f"[full bf16] flags={flags} orth={orth:.2e} |A_k|-sigma_k={cons:.2e} A[:, j] vs Phi^T S[:, j]={worst:.2e}")
+    del Phi_t, A_t
+    S64 = host_fp64(St)
+    del St
+    torch.cuda.empty_cache()
+    om = philox.gaussian_sketch(seed, n, r + p).astype(np.float32)
+    om = torch.from_numpy(om).to(torch.bfloat16).double().numpy()
+    P2, s2, A2, ex = orpod.rpod_stable(pod.SnapshotMajor(S64), r, om, q, block_rows=32768, literal_A=False)
+    res = dict(sigma=metrics.sigma_rel_err(s, s2), orth=metrics.orth_err(Phi))
+    if metrics.gap_ok(ex["ritz"], r):
+        res["sin"] = metrics.sin_theta_max(Phi, P2)
+        res["A"] = metrics.lowrank_rel_diff(Phi, A, P2, A2)
+    say(f"[full bf16] flags={flags} {res}")
     assert flags == 0
-    assert np.all(s > 0) and np.all(np.diff(s) <= 0)
-    assert orth <= 1e-5
-    assert cons <= 1e-5
-    assert worst <= 1e-4
+    assert np.all(np.diff(s) <= 0)
+    assert res["sigma"] <= 1e-3 and res["orth"] <= 1e-5
+    assert res.get("sin", 0.0) <= 1e-3 and res.get("A", 0.0) <= 1e-3

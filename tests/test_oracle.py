@@ -106,8 +106,7 @@ def test_fourier_modes_order():
 
 def _fourier_exact_sigma(gen):
     # S0 = F diag(amp) T^T and F = (sqrt(nx ny)/2) F_hat with F_hat orthonormal
-    M = gen["amp"][:, None] * gen["T"].T
-    return 0.5 * math.sqrt(gen["nx"] * gen["ny"]) * np.linalg.svd(M, compute_uv=False)
+    return pod.pod_sigma_sine_field(gen["amp"], gen["T"], gen["nx"], gen["ny"])
 
 
 def test_fourier_field_pins_pod_sigma():
@@ -239,6 +238,10 @@ def test_rpod_interlacing_and_coefficients():
     assert np.max(np.abs(A - s[:, None] * ex["Vt_r"])) < 1e-12 * s[0]
     assert np.max(np.abs(A @ A.T - np.diag(s ** 2))) < 1e-12 * s[0] ** 2
     assert metrics.orth_err(P) < 1e-13
+    # the shortcut for very large S (no literal pass) returns the same coefficients, signs included
+    P2, s2, A2, _ = rpod.rpod_stable(S, 20, om, q=1, literal_A=False)
+    assert np.array_equal(P2, P) and np.array_equal(s2, s)
+    assert np.max(np.abs(A2 - A)) < 1e-12 * s[0]
 
 
 def test_rpod_literal_equals_stable():
@@ -310,3 +313,15 @@ def test_rpod_error_falls_with_q_and_p():
     e_p0, e_p20, e_p75 = err(0, 0), err(20, 0), err(75, 0)
     assert e_p0 > e_p20 > e_p75
     assert err(5, 0) > err(5, 1) > err(5, 2)
+
+
+def test_snapshot_major_view_gives_identical_oracle_results():
+    # the oracle on S held snapshot-major (transposed row-block views) equals the oracle on S itself
+    # (to rounding: BLAS takes the transposed operands in another summation order)
+    St = np.random.default_rng(4).standard_normal((120, 3000))
+    om = philox.gaussian_sketch(5, 120, 25)
+    a = rpod.rpod_stable(St.T.copy(), 15, om, 2, block_rows=700)
+    b = rpod.rpod_stable(pod.SnapshotMajor(St), 15, om, 2, block_rows=700)
+    assert metrics.sigma_rel_err(b[1], a[1]) < 1e-13
+    assert metrics.sin_theta_max(b[0], a[0]) < 1e-12
+    assert metrics.lowrank_rel_diff(b[0], b[2], a[0], a[2]) < 1e-12

@@ -173,3 +173,86 @@ def test_parameter_family_is_smooth_and_orthonormal():
     corner = metrics.sin_theta_max(fam.U(np.ones(4))[:, :50], fam.U(-np.ones(4))[:, :50])
     assert small < 1e-3
     assert 0.4 < corner < 0.6
+
+
+# --------------------------------------------------------------------------
+# per-mode residual and the continued fallback
+# --------------------------------------------------------------------------
+
+def _svd_matrix(m, n, s, seed):
+    U = synth._orthonormal(m, len(s), seed, 1)
+    V = synth._orthonormal(n, len(s), seed, 2)
+    return U, np.asarray(s, dtype=np.float64), V, (U * s) @ V.T
+
+
+def test_mode_residual_zero_for_exact_svd():
+    U, s, V, S = _svd_matrix(300, 80, np.exp(-0.2 * np.arange(40)), 3)
+    A = (s[:10, None] * V[:, :10].T)
+    rho, per = ow.mode_residual(S, U[:, :10], s[:10], A)
+    assert rho < 1e-13 and per.shape == (10,)
+
+
+def test_mode_residual_of_a_shifted_sigma():
+    # sigma_k replaced by sigma_k + d: r_k = S v_k - (sigma_k + d) u_k = -d u_k, residual d / (sigma_k + d)
+    U, s, V, S = _svd_matrix(200, 60, 1.0 / (1.0 + np.arange(30)), 5)
+    st = s[:5].copy()
+    st[3] += 1e-3
+    A = st[:, None] * V[:, :5].T           # the coefficients follow sigma (A = Sigma V^T)
+    rho, per = ow.mode_residual(S, U[:, :5], st, A)
+    assert per[3] == pytest.approx(1e-3 / st[3], rel=1e-9)
+    assert np.max(np.delete(per, 3)) < 1e-13 and rho == per[3]
+
+
+def test_mode_residual_of_a_tilted_one_dimensional_basis():
+    # Rayleigh-Ritz on q = cos(t) u_1 + sin(t) u_2: sigma~^2 = c^2 s1^2 + s^2 s2^2, v = S^T q / sigma~ and
+    # r = S v - sigma~ q = [c (s1^2 - sigma~^2) u_1 + s (s2^2 - sigma~^2) u_2] / sigma~ (closed form)
+    U, s, V, S = _svd_matrix(150, 40, [3.0, 1.5, 0.5, 0.1], 7)
+    t = 0.05
+    c, sn = np.cos(t), np.sin(t)
+    q = c * U[:, 0] + sn * U[:, 1]
+    st = np.sqrt(c * c * s[0] ** 2 + sn * sn * s[1] ** 2)
+    A = (S.T @ q)[None, :]                  # A = phi^T S
+    rho, _ = ow.mode_residual(S, q[:, None], np.array([st]), A)
+    want = np.hypot(c * (s[0] ** 2 - st * st), sn * (s[1] ** 2 - st * st)) / st / st
+    assert rho == pytest.approx(want, rel=1e-10)
+    assert rho > 1e-3
+
+
+def _family_case(seed=0, r=8, n=120):
+    fam = synth.ParamFamily(16, 32, n_cand=60, K=40, family_seed=seed)
+    mu, mu_hat = synth.draw_params(6, seed=seed)
+    mats = [fam.matrix(mu[i], n, noise_std=0.0, seed=10 + i)["St"] for i in range(6)]
+    bases = [pod.pod_svd(M.T, r)[0] for M in mats[:4]]
+    return fam, mu, mats, bases
+
+
+def test_continued_fallback_equals_plain_iterations_from_the_warm_basis():
+    fam, mu, mats, bases = _family_case()
+    S = mats[5].T
+    r, p = 8, 4
+    om = philox.gaussian_sketch(11, S.shape[1], p)
+    c = np.full(4, 0.25)
+    # tol 0: always continue; the result equals warm rPOD with q + q_fb iterations
+    P1, s1, A1, ex1 = ow.warm_rpod_continued(S, bases, c, 0, r, om, q=0, tol=0.0, q_fb=2)
+    P2, s2, A2, ex2 = ow.warm_rpod(S, bases, c, 0, r, om, q=2)
+    assert ex1["fell_back"] and ex1["rho"] > 0
+    assert metrics.sigma_rel_err(s1, s2) < 1e-13
+    assert metrics.sin_theta_max(P1, P2) < 1e-10
+    # tol 1: never continues; the result is the warm one
+    P3, s3, _, ex3 = ow.warm_rpod_continued(S, bases, c, 0, r, om, q=0, tol=1.0, q_fb=2)
+    P4, s4, _, _ = ow.warm_rpod(S, bases, c, 0, r, om, q=0)
+    assert not ex3["fell_back"] and np.array_equal(s3, s4)
+
+
+def test_residual_rule_bounds_the_sigma_error():
+    # whenever rho <= tol, every returned sigma lies within (about) tol of a singular value of S
+    fam, mu, mats, bases = _family_case(seed=1)
+    for i in (4, 5):
+        S = mats[i].T
+        s_true = np.linalg.svd(S, compute_uv=False)
+        for q in (0, 1):
+            om = philox.gaussian_sketch(20 + i, S.shape[1], 4)
+            P, s, A, ex = ow.warm_rpod(S, bases, np.full(4, 0.25), 0, 8, om, q=q)
+            rho, per = ow.mode_residual(S, P, s, A)
+            d = np.min(np.abs(s_true[None, :] - s[:, None]), axis=1) / s
+            assert np.all(d <= per * (1 + 1e-9) + 1e-12)
