@@ -385,21 +385,25 @@ def warm_block(dev, reps):
     exact = [fam.spectrum(mu[i][3], fam.K)[:r] for i in test]
     del F_dev
 
-    def run(kind, mats, q=None):
-        if kind == "plain":
-            pl = rp.Plan(m, n, r, p, 2, dtype=mats[0].dtype, device=dev)
-            call = lambda j: pl.compute(mats[j], 4000 + j, check=False)[1]
-        else:
-            pl = rp.WarmPlan(model, n, p, q, q_fallback=2, tol=1e-3, dtype=mats[0].dtype, device=dev)
-            state = {}
+    ok = [e >= 1e-3 * e[0] for e in exact]   # modes within three decades of sigma_1
 
-            def call(j):
-                out = pl.compute(mats[j], mu_hat[test[j]], 4000 + j, check=False)
-                state[j] = out[3]
-                return out[1]
-        sig = [call(j) for j in range(len(mats))]   # warm-up pass, also the results
+    def run(kind, mats, q=2, tol=1e9, q_fb=0):
+        if kind == "plain":
+            pl = rp.Plan(m, n, r, p, q, dtype=mats[0].dtype, device=dev)
+            first = lambda j: (pl.compute(mats[j], 4000 + j, check=False)[1], None, None)
+            call = lambda j: pl.compute(mats[j], 4000 + j, check=False)
+        else:
+            pl = rp.WarmPlan(model, n, p, q, q_fallback=q_fb, tol=tol, dtype=mats[0].dtype, device=dev)
+
+            def first(j):
+                o = pl.compute(mats[j], mu_hat[test[j]], 4000 + j, check=False)
+                return o[1], o[3], o[4]
+            call = lambda j: pl.compute(mats[j], mu_hat[test[j]], 4000 + j, check=False, decision=False)
+        res = [first(j) for j in range(len(mats))]   # warm-up pass, also the results and decisions
         torch.cuda.synchronize()
-        errs = [float(np.max(np.abs(s_.cpu().numpy() - e) / e)) for s_, e in zip(sig, exact)]
+        rel = [np.abs(r_[0].cpu().numpy() - e) / e for r_, e in zip(res, exact)]
+        errs = [float(np.max(x)) for x in rel]
+        errs_ok = [float(np.max(x[k])) for x, k in zip(rel, ok)]
         t = time.perf_counter()
         for _ in range(reps):
             for j in range(len(mats)):
@@ -407,20 +411,29 @@ def warm_block(dev, reps):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / (reps * len(mats))
         pl.status()
-        fb = sum(state.values()) if kind != "plain" else None
         pl.close()
-        return dict(ms_per_matrix=round(ms, 4), sigma_err_median=float(np.median(errs)),
-                    sigma_err_max=float(np.max(errs)), frac_within_1e3=float(np.mean(np.array(errs) <= 1e-3)),
-                    fallbacks=fb)
+        d = dict(ms_per_matrix=round(ms, 4), sigma_err_median=float(np.median(errs)),
+                 sigma_err_max=float(np.max(errs)), frac_within_1e3=float(np.mean(np.array(errs) <= 1e-3)),
+                 sigma_err_max_leading=float(np.max(errs_ok)),
+                 frac_within_1e3_leading=float(np.mean(np.array(errs_ok) <= 1e-3)))
+        if kind != "plain":
+            rho = np.array([r_[2] for r_ in res])
+            d.update(continued=int(sum(bool(r_[1]) for r_ in res)), tol=tol, q_fallback=q_fb,
+                     rho_median=float(np.median(rho)), rho_max=float(np.max(rho)))
+        return d
 
-    out = {"plain_fp32_q2": run("plain", tests), "warm_fp32_q0": run("warm", tests, 0),
-           "warm_fp32_q1": run("warm", tests, 1)}
+    out = {"plain_fp32_q2": run("plain", tests), "plain_fp32_q1": run("plain", tests, 1),
+           "warm_fp32_q0_accept_all": run("warm", tests, 0),
+           "warm_fp32_q1_accept_all": run("warm", tests, 1),
+           "warm_fp32_q0_tol1e-2_cont1": run("warm", tests, 0, 1e-2, 1),
+           "warm_fp32_q0_tol1e-3_cont1": run("warm", tests, 0, 1e-3, 1),
+           "warm_fp32_q0_tol1e-3_cont2": run("warm", tests, 0, 1e-3, 2)}
     tests16 = [St.to(torch.bfloat16) for St in tests]
     del tests
     torch.cuda.empty_cache()
     out["plain_bf16_q2"] = run("plain", tests16)
-    out["warm_bf16_q0"] = run("warm", tests16, 0)
-    out["warm_bf16_q1"] = run("warm", tests16, 1)
+    out["warm_bf16_q0_accept_all"] = run("warm", tests16, 0)
+    out["warm_bf16_q0_tol1e-2_cont1"] = run("warm", tests16, 0, 1e-2, 1)
     del tests16
     model.close()
     plain.close()
@@ -430,10 +443,106 @@ def warm_block(dev, reps):
         v["speedup_vs_plain_fp32"] = round(base / v["ms_per_matrix"], 2)
         log(f"[bench] warm sweep {k}: {v}")
     return {"config": {"m": m, "n": n, "r": r, "p": p, "matrices": W["count"], "train": W["n_train"],
-                       "test": len(test), "bank": 8, "epochs": W["epochs"], "noise_std": W["noise"],
-                       "residual_tol": 1e-3, "fallback_q": 2, "reps": reps},
+                       "test": len(test), "bank": 8, "epochs": W["epochs"], "noise_std": W["noise"], "reps": reps,
+                       "rule": "accept the warm result if max_k ||S v_k - sigma_k phi_k|| / sigma_k <= tol, "
+                               "else continue q_fallback iterations from the warm range basis",
+                       "leading": "modes with exact sigma_k >= 1e-3 sigma_1"},
             "train_seconds": round(t_train, 3), "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
             "results": out}
+
+
+# The paper's own shape: N_C = 8192 cells (64 x 128) and 225 parameter blocks
+# x 401 steps = 90225 snapshots per field; 10 modes, p swept, q = 1. beta
+# calibrates the field so that 10 modes hold the share of the singular-value
+# sum the paper tabulates for its variables (q-like about 27 %, psi-like
+# about 41 %; computed from all 8192 singular values of the generated field).
+PAPER = dict(nx=64, ny=128, n=90225, r=10, q=1, ps=(0, 5, 10, 20, 50, 75), seed=17,
+             fields=(("q_like", 1.5), ("psi_like", 2.0)))
+PAPER_NAME = "paper_8192x90225"
+
+
+def paper_block(dev, steps, warmup, cpu=True):
+    """Row P: GPU FP32 and BF16 rPOD for every p on both calibrated fields,
+    their accuracy against O1 (deterministic POD), and O1 / O2 timed on the host."""
+    import torch
+    import synth
+    import paper_2504_15350_amd as rp
+    from oracle import metrics, philox, pod
+    from oracle import rpod as orpod
+    W = PAPER
+    out = {"config": {"workload": PAPER_NAME, "m": W["nx"] * W["ny"], "n": W["n"], "r": W["r"], "q": W["q"],
+                      "p": list(W["ps"]), "grid": "64 x 128 cells", "snapshots": "225 parameter blocks x 401 steps"},
+           "paper": {"pod_seconds": "> 4000", "rpod_seconds_p75": "about 6", "speedup": "about 700",
+                     "hardware": "CPU, not stated",
+                     "where": "Sec. 5, the figure of POD and rPOD CPU time as p varies; Sec. 5.4, Tab. cpu_time"},
+           "fields": {}}
+    for fname, beta in W["fields"]:
+        t0 = time.perf_counter()
+        gen = synth.fourier_field_device(W["nx"], W["ny"], W["n"], beta=beta, seed=W["seed"], device=dev)
+        St = gen.pop("St")
+        n, m = St.shape
+        torch.cuda.synchronize()
+        log(f"[bench] paper shape {fname} (beta {beta}): generated S {m}x{n} in {time.perf_counter() - t0:.1f} s")
+        St16 = St.to(torch.bfloat16)
+        gpu = {}
+        for tname, Sd in (("fp32", St), ("bf16", St16)):
+            for p in W["ps"]:
+                plan = rp.Plan(m, n, W["r"], p, W["q"], dtype=Sd.dtype, device=dev)
+                for _ in range(warmup):
+                    res = plan.compute(Sd, W["seed"], check=False)
+                plan.status()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(steps):
+                    res = plan.compute(Sd, W["seed"], check=False)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t1) * 1e3 / steps
+                plan.status()
+                plan.close()
+                l = W["r"] + p
+                passes = 2 * W["q"] + 2
+                gbs = passes * m * n * Sd.element_size() / (ms * 1e-3) / 1e9
+                gpu[f"{tname}_p{p}"] = dict(ms=round(ms, 4), s_pass_gbs=round(gbs, 1), l=l,
+                                            out=(res[0].double().cpu().numpy().T, res[1].cpu().numpy()))
+                log(f"[bench] paper {fname} {tname} p={p}: {ms:.3f} ms per rPOD ({gbs:.0f} GB/s over S)")
+        del St16
+        S64 = host_fp64(St)
+        del St
+        torch.cuda.empty_cache()
+        S = S64.T                                   # m x n view
+        t1 = time.perf_counter()
+        log(f"[bench] paper {fname}: O1 (method of snapshots, eigh of S S^T) on the host ...")
+        P1, s1, _A1, s_all = pod.pod_snapshots(S, W["r"])
+        t_o1 = time.perf_counter() - t1
+        e_sum = float(np.sum(s_all[:W["r"]]) / np.sum(s_all))
+        log(f"[bench] paper {fname}: O1 in {t_o1:.1f} s; 10 modes hold {100 * e_sum:.1f} % of the singular-value sum")
+        fld = {"beta": beta, "energy_share_10_modes_sigma_sum": round(e_sum, 4),
+               "energy_share_10_modes_sigma_squared": round(float(np.sum(s_all[:W['r']] ** 2) / np.sum(s_all ** 2)), 4),
+               "o1_seconds": round(t_o1, 1), "by_p": {}}
+        for p in W["ps"]:
+            row = {}
+            if cpu:
+                om = philox.gaussian_sketch(W["seed"], n, W["r"] + p)
+                t1 = time.perf_counter()
+                P2, s2, _A2, _ex = orpod.rpod_stable(S, W["r"], om, W["q"])
+                row["o2_seconds"] = round(time.perf_counter() - t1, 2)
+                row["o2_sigma_err_vs_o1"] = metrics.sigma_rel_err(s2, s1)
+                row["o2_sin_theta_vs_o1"] = metrics.sin_theta_max(P2, P1)
+            for tname in ("fp32", "bf16"):
+                g = gpu[f"{tname}_p{p}"]
+                Phi, sg = g.pop("out")
+                g["sigma_err_vs_o1"] = metrics.sigma_rel_err(sg, s1)
+                g["sin_theta_vs_o1"] = metrics.sin_theta_max(Phi, P1)
+                row[tname] = g
+            if cpu:
+                row["o1_over_gpu_bf16"] = round(t_o1 * 1e3 / row["bf16"]["ms"], 0)
+                row["o2_over_gpu_bf16"] = round(row["o2_seconds"] * 1e3 / row["bf16"]["ms"], 1)
+            fld["by_p"][str(p)] = row
+            log(f"[bench] paper {fname} p={p}: {row}")
+        out["fields"][fname] = fld
+        del S64, S
+    out["host"] = host_info()
+    return out
 
 
 CENTER = dict(block_cols=500, mean_rms=1.0, seed=2)
@@ -560,35 +669,36 @@ def cpu_baseline(S64, w, seed, sample_rows, reps=3, m_total=None):
 
 def accuracy_block(S64, gen, w, results):
     """sigma and subspace errors of each GPU result against (a) O2 in FP64 on the
-    unrounded FP32 matrix with the same BF16-rounded sketch as the headline path
-    and (b) the closed-form POD of the noise-free field."""
+    unrounded FP32 matrix with the same sketch as that path (the Gaussian draws
+    rounded to its storage type), so that the comparison isolates the effect of
+    the storage precision, and (b) the closed-form POD of the noise-free field."""
     from oracle import metrics, philox, pod
     from oracle import rpod as orpod
     import torch
     n, m = S64.shape
     r, l, q = w["r"], w["r"] + w["p"], w["q"]
-    om = philox.gaussian_sketch(w["seed"], n, l).astype(np.float32)
-    om = torch.from_numpy(om).to(torch.bfloat16).double().numpy()
-    t0 = time.perf_counter()
-    log("[bench] oracle: FP64 rPOD of the whole matrix on the host cores ...")
-    P2, s2, A2, ex = orpod.rpod_stable(pod.SnapshotMajor(S64), r, om, q, block_rows=32768, literal_A=False)
-    t_or = time.perf_counter() - t0
-    log(f"[bench] oracle done in {t_or:.1f} s")
+    om64 = philox.gaussian_sketch(w["seed"], n, l)
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16, "fp32": torch.float32}
     s0 = pod.pod_sigma_sine_field(gen["amp"], gen["T"], w["nx"], w["ny"])[:r]
     noise = 1e-4 * (np.sqrt(m) + np.sqrt(n))   # spectral norm of the white noise (Bai-Yin limit)
-    gap = bool(metrics.gap_ok(ex["ritz"], r))
     out = {"oracle": "O2 (FP64 rPOD, Householder QR after every product) on the FP32 matrix as generated, "
-                     "same sketch rounded to BF16, q = 2; and the closed-form POD of the noise-free field",
-           "oracle_seconds": round(t_or, 1), "cut_gapped": gap,
-           "noise_bound_rel_sigma_r": float(noise / s0[-1]),
-           "oracle_vs_noise_free_pod_sigma_rel_err": metrics.sigma_rel_err(s2, s0)}
+                     "with each path's own sketch (the Gaussian draws rounded to its storage type), q = 2; "
+                     "and the closed-form POD of the noise-free field",
+           "noise_bound_rel_sigma_r": float(noise / s0[-1]), "oracle_seconds": {}}
     for name, res in results.items():
+        om = torch.from_numpy(om64).to(tdt[name]).double().numpy()
+        t0 = time.perf_counter()
+        log(f"[bench] oracle for the {name} sketch: FP64 rPOD of the whole matrix on the host cores ...")
+        P2, s2, A2, ex = orpod.rpod_stable(pod.SnapshotMajor(S64), r, om, q, block_rows=32768, literal_A=False)
+        out["oracle_seconds"][name] = round(time.perf_counter() - t0, 1)
+        gap = bool(metrics.gap_ok(ex["ritz"], r))
         Phi_t, sig, _A = res["out"]
         Phi = Phi_t.double().cpu().numpy().T
         sg = sig.cpu().numpy()
         d = dict(sigma_rel_err_vs_oracle=metrics.sigma_rel_err(sg, s2),
                  sigma_rel_err_vs_noise_free_pod=metrics.sigma_rel_err(sg, s0),
-                 orth=metrics.orth_err(Phi))
+                 oracle_sigma_rel_err_vs_noise_free_pod=metrics.sigma_rel_err(s2, s0),
+                 orth=metrics.orth_err(Phi), cut_gapped=gap)
         if gap:
             d["sin_theta_vs_oracle"] = metrics.sin_theta_max(Phi, P2)
         d["within_1e-3"] = bool(d["sigma_rel_err_vs_oracle"] <= 1e-3 and d.get("sin_theta_vs_oracle", 0.0) <= 1e-3)
@@ -597,7 +707,7 @@ def accuracy_block(S64, gen, w, results):
     return out
 
 
-def mixed_block(dev, steps, warmup, accuracy=True, cpu=True):
+def mixed_block(dev, steps, warmup, accuracy=True, cpu=True, others=True):
     """The headline workload in BF16 (the value) and, on the same matrix, plain
     FP32 (the in-GPU baseline) and FP16."""
     import torch
@@ -613,12 +723,13 @@ def mixed_block(dev, steps, warmup, accuracy=True, cpu=True):
     res = {"bf16": measure(DEFAULT, S16, steps, warmup, keep_out=keep)}
     del S16
     torch.cuda.empty_cache()
-    ext_steps, ext_warm = max(3, steps // 2), max(1, warmup // 2)
-    Sh = S32.to(torch.float16)
-    res["f16"] = measure("f16_1048576x10000", Sh, ext_steps, ext_warm, keep_out=keep)
-    del Sh
-    torch.cuda.empty_cache()
-    res["fp32"] = measure("fp32_1048576x10000", S32, ext_steps, ext_warm, keep_out=keep)
+    if others:
+        ext_steps, ext_warm = max(3, steps // 2), max(1, warmup // 2)
+        Sh = S32.to(torch.float16)
+        res["f16"] = measure("f16_1048576x10000", Sh, ext_steps, ext_warm, keep_out=keep)
+        del Sh
+        torch.cuda.empty_cache()
+        res["fp32"] = measure("fp32_1048576x10000", S32, ext_steps, ext_warm, keep_out=keep)
     acc = cpu_res = None
     if accuracy or cpu:
         t0 = time.perf_counter()
@@ -663,13 +774,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [PAPER_NAME])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the oracle comparison of the mixed workload")
     ap.add_argument("--no-extra", action="store_true", help="skip the 262144 x 5000 FP32 measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batch measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start sweep")
     ap.add_argument("--no-center", action="store_true", help="skip the fluctuation-centring measurement")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="on the headline workload, time BF16 alone (no FP16 / FP32 runs on the same matrix)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES bytes (the reference kernel for scaling "
                          "HBM byte counters) and exit")
@@ -688,6 +801,18 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the row-sharded multi-GPU "
               f"design is not built in this version", file=sys.stderr)
         sys.exit(2)
+    if args.workload == PAPER_NAME:
+        import torch
+        res = paper_block(torch.device("cuda", 0), args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        b = res["fields"]["psi_like"]["by_p"]["75"]["bf16"]
+        line = {"metric": "rPOD time-to-r-modes", "value": b["ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": b["ms"], "higher_is_better": False, "scaling": "weak",
+                "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+                "config": {"workload": PAPER_NAME, "field": "psi_like", "r": 10, "p": 75, "q": 1,
+                           "parallelism": "single GPU"},
+                "paper_shape": res}
+        print(json.dumps(line), flush=True)
+        return
 
     import torch
     dev = torch.device("cuda", 0)
@@ -695,19 +820,18 @@ def main():
     mixed = None
     if args.workload == DEFAULT:
         res, acc, cpu = mixed_block(dev, args.steps, args.warmup, accuracy=not args.no_accuracy,
-                                    cpu=not args.no_cpu_baseline)
+                                    cpu=not args.no_cpu_baseline, others=not args.headline_only)
         main_res = res["bf16"]
-        mixed = {
-            "config": {"m": 1048576, "n": 10000, "r": 100, "p": 20, "q": 2},
-            "mixed_bf16_ms": round(res["bf16"]["ms"], 3), "mixed_f16_ms": round(res["f16"]["ms"], 3),
-            "plain_fp32_ms": round(res["fp32"]["ms"], 3),
-            "speedup_bf16_vs_plain_fp32": round(res["fp32"]["ms"] / res["bf16"]["ms"], 2),
-            "speedup_f16_vs_plain_fp32": round(res["fp32"]["ms"] / res["f16"]["ms"], 2),
-            "accuracy": acc,
-            "f16_roofline": res["f16"]["roofline"], "f16_kernels": res["f16"]["kernels"],
-            "plain_roofline": res["fp32"]["roofline"], "plain_kernels": res["fp32"]["kernels"],
-            "plain_hbm_gbs_s_passes": res["fp32"]["hbm_gbs_s_passes"],
-        }
+        mixed = {"config": {"m": 1048576, "n": 10000, "r": 100, "p": 20, "q": 2},
+                 "mixed_bf16_ms": round(res["bf16"]["ms"], 3), "accuracy": acc}
+        if "fp32" in res:
+            mixed.update({
+                "mixed_f16_ms": round(res["f16"]["ms"], 3), "plain_fp32_ms": round(res["fp32"]["ms"], 3),
+                "speedup_bf16_vs_plain_fp32": round(res["fp32"]["ms"] / res["bf16"]["ms"], 2),
+                "speedup_f16_vs_plain_fp32": round(res["fp32"]["ms"] / res["f16"]["ms"], 2),
+                "f16_roofline": res["f16"]["roofline"], "f16_kernels": res["f16"]["kernels"],
+                "plain_roofline": res["fp32"]["roofline"], "plain_kernels": res["fp32"]["kernels"],
+                "plain_hbm_gbs_s_passes": res["fp32"]["hbm_gbs_s_passes"]})
         St_small = None
     else:
         main_res, cpu, St_small = simple_block(args.workload, dev, args.steps, args.warmup,

@@ -313,7 +313,7 @@ rpod_status rpod_sketch_bits(uint64_t seed, int64_t n, int32_t l, uint32_t* out,
  * optimiser Adam with L2 weight decay added to the gradient. Every step
  * (forward, loss, backward, Adam, bank Grams) runs in the library's kernels.
  * ------------------------------------------------------------------------ */
-#define RPOD_FLAG_RESIDUAL 0x10  /* warm start: residual above tolerance (informational) */
+#define RPOD_FLAG_RESIDUAL 0x10  /* warm start: result rejected, continuation ran (informational) */
 #define RPOD_WARM_PARAMS 69128
 
 typedef struct {
@@ -373,26 +373,71 @@ rpod_status rpod_warm_predict(rpod_warm model, const float* mu, int32_t N, float
  * m, r = the model's r, p >= 1 Gaussian columns next to the predicted
  * subspace (l = r + p <= 128), q >= 0 subspace iterations after it. A
  * compute call runs Y = [W, S Omega_p] (Omega_p: the first p columns of the
- * sketch of `seed`), CholeskyQR2, q iterations, T = Q^T S and steps 6-7 of
- * Alg. 1, then the a-posteriori residual of the range basis Q (l columns),
- * the probabilistic bound of Halko, Martinsson and Tropp (SIAM Review 2011,
- * Sec. 4.3, eq. 4.3) relative to the largest computed singular value:
- *   rho = 10 sqrt(2/pi) max_{i <= 16} ||(I - Q Q^T) S w_i|| / sigma_1,
- * w_i the columns of the sketch of `seed` drawn with counter word 3 = 1 (see
- * rpod_generate_omega), S w_i with FP64 products; rho bounds
- * ||S - Q Q^T S|| / sigma_1 from above with probability >= 1 - 10^-16.
- * If rho > tol (or the warm run broke down) the plain rPOD with q_fallback
- * iterations and the full sketch of `seed` recomputes the outputs. The model
- * must outlive the plan; its weights and bank are read at every call. */
+ * sketch of `seed`), the CholeskyQR orthonormalisation, q iterations,
+ * T = Q^T S and steps 6-7 of Alg. 1, then checks every returned triplet
+ * (sigma_k, phi_k, v_k = a_k / sigma_k, a_k the k-th row of A):
+ *   rho_k = ||S v_k - sigma_k phi_k|| / sigma_k,  rho = max_k rho_k,
+ * S v_k from a product with FP64 arithmetic. The pair (phi_k, v_k) is then
+ * an approximate singular pair: some singular value of S lies within
+ * sigma_k rho_k of sigma_k. If rho <= tol the warm result stands; otherwise
+ * (or if rho is not finite) q_fallback further subspace iterations continue
+ * from the warm range basis Q and steps 5-7 run again, overwriting the
+ * outputs (RPOD_FLAG_RESIDUAL is set in the status word). The decision is
+ * taken on the device inside the same launch graph: no host round trip.
+ * A breakdown in either part is reported as by rpod_compute. The model must
+ * outlive the plan; its weights and bank are read at every call. */
 rpod_status rpod_workspace_size_warm(const rpod_desc* desc, rpod_warm model, int32_t q_fallback, size_t* bytes);
 rpod_status rpod_plan_create_warm(rpod_plan* plan, const rpod_desc* desc, rpod_warm model, int32_t q_fallback,
                                   double tol, void* workspace, size_t workspace_bytes, void* hip_stream);
 
-/* mu: host, 4 floats (normalised parameter vector). fell_back, rho: host,
- * may be NULL. Synchronises the plan's stream once (to read rho) before it
- * decides on the fallback, which is then only enqueued. */
+/* mu: host, 4 floats (normalised parameter vector). fell_back (1 if the
+ * warm result was rejected and the continuation ran) and rho (of the warm
+ * result): host, may be NULL; if either is non-NULL the call synchronises
+ * the plan's stream to read them, else it only enqueues. */
 rpod_status rpod_compute_warm(rpod_plan plan, const void* S, const float* mu, uint64_t seed, void* Phi,
                               double* sigma, void* A, int32_t* fell_back, double* rho);
+
+/* rho_modes: host, r doubles: the rho_k of the warm result of the last
+ * compute call. Synchronises the plan's stream. */
+rpod_status rpod_warm_residuals(rpod_plan plan, double* rho_modes);
+
+/* ------------------------------------------------------------------------
+ * Adaptive rank (the energy rule of Sec. 4.1 chooses the number of modes;
+ * Alg. 1 needs the sketch width before it starts). The sketch grows by
+ * blocks of b columns with the blocked fixed-accuracy range finder of Yu,
+ * Gu and Li (SIAM J. Matrix Anal. Appl. 39, 2018, randQB_EI):
+ *   E = ||S||_F^2; for block i = 0, 1, ...:
+ *     Q_i = orth(S Omega_i - Q (B Omega_i)); q times:
+ *       Z_i = orth(S^T Q_i - B^T (Q^T Q_i)), Q_i = orth(S Z_i - Q (B Z_i));
+ *     B_i = Q_i^T S; Q = [Q, Q_i]; B = [B; B_i]; E = E - ||B_i||_F^2
+ *   until E <= (1 - delta) ||S||_F^2 or l = l_max,
+ * E being the exact squared Frobenius error ||S - Q B||_F^2. The
+ * orthonormalisations are CholeskyQR2 of [Q, block] (the Cholesky factor of
+ * the joint Gram projects the block off Q; twice). Steps 6-7 of Alg. 1 then
+ * run on B for all l columns, and the energy rank is the smallest r with
+ * (sigma_1^2 + .. + sigma_r^2) / ||S||_F^2 >= delta (-1 if none). Omega_i
+ * are columns i b .. i b + b - 1 of the sketch of `seed` (the columns
+ * rpod_compute would use with l = l_max). With q = 0 the l columns of Q span
+ * S Omega[:, :l], as in rpod_compute with that l. The whole loop, the stopping
+ * test included, runs on the device in one launch graph: blocks after the
+ * stop and the finishes for other widths are skipped launches.
+ * desc: m, n, ld, dtype as for rpod_compute; r = l_max (a multiple of p, at
+ * most 128 and at most min(m, n)); p = b (a positive multiple of 16); q
+ * >= 0 power iterations per block; flags 0; block_cols 0. 0 < delta <= 1.
+ * Per-pass timing records nothing for these plans. */
+rpod_status rpod_workspace_size_adaptive(const rpod_desc* desc, double delta, size_t* bytes);
+rpod_status rpod_plan_create_adaptive(rpod_plan* plan, const rpod_desc* desc, double delta, void* workspace,
+                                      size_t workspace_bytes, void* hip_stream);
+
+/* S as for rpod_compute. Outputs (device, room for l_max modes): Phi m x l
+ * column-major (leading dimension m), sigma l values, A n x l row-major
+ * (A[j l + k]), l = the sketch width used; storage types as for
+ * rpod_compute. l_used, rank (the energy rank) and residual (E / ||S||_F^2
+ * when the loop stopped): host, may be NULL; if any is non-NULL the call
+ * synchronises the plan's stream to read them, else it only enqueues.
+ * Errors as for rpod_compute (rpod_status_query). */
+rpod_status rpod_compute_adaptive(rpod_plan plan, const void* S, uint64_t seed, void* Phi, double* sigma, void* A,
+                                  int32_t* l_used, int32_t* rank, double* residual);
 
 /* Per-pass timing, for measurement. With enable != 0 the plan records a
  * pair of HIP events on its stream around every pass over S issued by later

@@ -25,14 +25,6 @@ Predicted subspace: W = P(c)^j Phi_k*, k* = argmax c (lowest index on ties):
 Warm rPOD: Y = [W, S Omega_p] (Omega_p the first p columns of the Gaussian
   sketch), Q = orth(Y), q subspace iterations as in Alg. 1 (stable form),
   then steps 5-7 of Alg. 1 and the coefficients.
-A-posteriori residual of the range basis Q (l orthonormal columns): the
-  probabilistic bound of Halko, Martinsson and Tropp (SIAM Review 2011,
-  Sec. 4.3, eq. 4.3), ||(I - Q Q^T) S|| <= 10 sqrt(2/pi) max_i ||(I - Q Q^T)
-  S w_i|| with probability at least 1 - 10^-d for d independent standard
-  Gaussian probes w_i, taken relative to sigma_1:
-  rho = 10 sqrt(2/pi) max_i ||(I - Q Q^T) S w_i|| / sigma_1.
-  The probes are the columns of the Philox sketch of the same seed drawn
-  with counter word 3 = 1 (stream 1), independent of the sketch itself.
 Per-mode residual of the returned modes (the acceptance rule of warm plans):
   with v_k = A_k^T / sigma_k (A = Phi^T S = Sigma V^T), the singular triplet
   (phi_k, sigma_k, v_k) of S has residual r_k = S v_k - sigma_k phi_k (its
@@ -154,20 +146,9 @@ def assemble(GW, c, kstar, r, j=2):
     return Z
 
 
-PROBES = 16                        # d, the number of Gaussian probes
-HMT_FACTOR = 10.0 * np.sqrt(2.0 / np.pi)
-
-
-def probe_residual(S, Q, sigma1, probes):
-    """rho = 10 sqrt(2/pi) max_i ||(I - Q Q^T) S w_i|| / sigma_1 (HMT 2011, eq. 4.3)."""
-    Y = s_times(S, np.asarray(probes, dtype=np.float64))
-    R = Y - Q @ (Q.T @ Y)
-    return float(HMT_FACTOR * np.max(np.linalg.norm(R, axis=0)) / sigma1)
-
-
-def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2, probes=None):
-    """Warm-started rPOD; returns (Phi, sigma, A, extras); extras['rho'] is the
-    probe residual of the final range basis when `probes` is given."""
+def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2):
+    """Warm-started rPOD; returns (Phi, sigma, A, extras) with extras['rho'],
+    extras['rho_modes'] the per-mode residual of the result."""
     Phi_b = np.hstack([np.asarray(b, dtype=np.float64) for b in bases])
     Z = assemble(Phi_b.T @ Phi_b, c, kstar, r, j)
     W = Phi_b @ Z
@@ -177,8 +158,7 @@ def warm_rpod(S, bases, c, kstar, r, omega_p, q, j=2, probes=None):
         Zs = _orth(st_times(S, Q))
         Q = _orth(s_times(S, Zs))
     Phi, s, A, ex = _finish(S, Q, r, 65536)
-    if probes is not None:
-        ex["rho"] = probe_residual(S, Q, s[0], probes)
+    ex["rho"], ex["rho_modes"] = mode_residual(S, Phi, s, A)
     ex["W"] = W
     return Phi, s, A, ex
 

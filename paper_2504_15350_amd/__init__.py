@@ -14,9 +14,10 @@ the coefficients as A_t (n, r) with A_t[j, k] = coefficient k of snapshot j.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
-__all__ = ["RpodError", "Plan", "BatchPlan", "Tuning", "autotune", "WarmModel", "WarmPlan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
+__all__ = ["RpodError", "Plan", "BatchPlan", "Tuning", "autotune", "WarmModel", "WarmPlan", "AdaptivePlan", "rpod", "generate_omega", "sketch_bits", "lib", "LIB_PATH",
            "STATUS", "FLAG_SHIFTED", "FLAG_BREAKDOWN", "FLAG_NONFINITE", "FLAG_JACOBI_SLOW", "FLAG_RANK_CUT"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -116,6 +117,12 @@ def lib():
                                       ctypes.c_size_t, vp],
             "rpod_compute_warm": [vp, vp, ctypes.POINTER(ctypes.c_float), u64, vp, vp, vp, ctypes.POINTER(i32),
                                   ctypes.POINTER(ctypes.c_double)],
+            "rpod_warm_residuals": [vp, ctypes.POINTER(ctypes.c_double)],
+            "rpod_workspace_size_adaptive": [ctypes.POINTER(_Desc), ctypes.c_double, ctypes.POINTER(ctypes.c_size_t)],
+            "rpod_plan_create_adaptive": [ctypes.POINTER(vp), ctypes.POINTER(_Desc), ctypes.c_double, vp,
+                                          ctypes.c_size_t, vp],
+            "rpod_compute_adaptive": [vp, vp, u64, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -501,6 +508,60 @@ class WarmModel:
             pass
 
 
+class AdaptivePlan(_PlanBase):
+    """Adaptive-rank plan (rpod_plan_create_adaptive / rpod_compute_adaptive):
+    the sketch grows by `block` columns, up to l_max, until the captured
+    energy ||Q^T S||_F^2 / ||S||_F^2 reaches delta."""
+
+    def __init__(self, m, n, l_max, block, q, delta, dtype=torch.float32, ld=None, device="cuda", stream=None):
+        self.device = _norm_device(device)
+        self.m, self.n, self.l_max, self.block, self.q = int(m), int(n), int(l_max), int(block), int(q)
+        self.delta = float(delta)
+        self.ld = self.m if ld is None else int(ld)
+        self.dtype = dtype
+        self.out_dtype = torch.float64 if dtype == torch.float64 else torch.float32
+        self._desc = make_desc(m, n, l_max, block, q, dtype, ld)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().rpod_workspace_size_adaptive(ctypes.byref(self._desc), self.delta, ctypes.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        sptr, self.stream = _stream_ptr(stream, self.device)
+        h = ctypes.c_void_p()
+        _check(lib().rpod_plan_create_adaptive(ctypes.byref(h), ctypes.byref(self._desc), self.delta,
+                                               _dev_ptr(self.workspace), nbytes.value, sptr))
+        self._h = h
+
+    def compute(self, St, seed, out=None, check=True, info=True):
+        """-> (Phi_t (l, m), sigma (l,), A_t (n, l), l, rank, residual); l is the sketch
+        width used, rank the energy rank (-1 if l_max fell short), residual
+        ||S - Q B||_F^2 / ||S||_F^2. With info=False the call only enqueues and
+        returns the full buffers (l_max modes, of which the first l are valid)
+        with l, rank, residual None."""
+        _check_St(St, self.dtype, self.device, self.m, self.n, self.ld)
+        if out is None:
+            out = (torch.empty((self.l_max, self.m), dtype=self.out_dtype, device=self.device),
+                   torch.empty((self.l_max,), dtype=torch.float64, device=self.device),
+                   torch.empty((self.n * self.l_max,), dtype=self.out_dtype, device=self.device))
+        Phi, sigma, A = out
+        lu, rk, res = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        _check(lib().rpod_compute_adaptive(self._h, _dev_ptr(St), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                           _dev_ptr(Phi), _dev_ptr(sigma), _dev_ptr(A),
+                                           ctypes.byref(lu) if info else None, ctypes.byref(rk) if info else None,
+                                           ctypes.byref(res) if info else None))
+        if check:
+            self.status()
+        if not info:
+            return Phi, sigma, A, None, None, None
+        l = lu.value
+        return Phi[:l], sigma[:l], A.view(-1)[:self.n * l].view(self.n, l), l, rk.value, res.value
+
+    def status(self):
+        fl = ctypes.c_int32(0)
+        st = lib().rpod_status_query(self._h, ctypes.byref(fl))
+        self.last_flags = fl.value
+        _check(st)
+        return fl.value
+
+
 class WarmPlan(_PlanBase):
     """A warm-started plan for one matrix shape (rpod_plan_create_warm / rpod_compute_warm)."""
 
@@ -523,8 +584,9 @@ class WarmPlan(_PlanBase):
                                            float(tol), _dev_ptr(self.workspace), nbytes.value, sptr))
         self._h = h
 
-    def compute(self, St, mu, seed, out=None, check=True):
-        """-> (Phi_t (r, m), sigma (r,), A_t (n, r), fell_back, rho)."""
+    def compute(self, St, mu, seed, out=None, check=True, decision=True):
+        """-> (Phi_t (r, m), sigma (r,), A_t (n, r), fell_back, rho). With
+        decision=False the call only enqueues and fell_back, rho are None."""
         _check_St(St, self.dtype, self.device, self.m, self.n, self.ld)
         if out is None:
             out = (torch.empty((self.r, self.m), dtype=torch.float32, device=self.device),
@@ -535,11 +597,20 @@ class WarmPlan(_PlanBase):
         fb = ctypes.c_int32(0)
         rho = ctypes.c_double(0)
         _check(lib().rpod_compute_warm(self._h, _dev_ptr(St), mu_arr, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)),
-                                       _dev_ptr(Phi), _dev_ptr(sigma), _dev_ptr(A), ctypes.byref(fb),
-                                       ctypes.byref(rho)))
+                                       _dev_ptr(Phi), _dev_ptr(sigma), _dev_ptr(A),
+                                       ctypes.byref(fb) if decision else None,
+                                       ctypes.byref(rho) if decision else None))
         if check:
             self.status()
+        if not decision:
+            return Phi, sigma, A, None, None
         return Phi, sigma, A, bool(fb.value), rho.value
+
+    def residuals(self):
+        """rho_k of the last call's warm result (numpy, r values)."""
+        buf = (ctypes.c_double * self.r)()
+        _check(lib().rpod_warm_residuals(self._h, buf))
+        return np.array(buf[:], dtype=np.float64)
 
     def status(self):
         fl = ctypes.c_int32(0)

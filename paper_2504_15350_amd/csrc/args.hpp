@@ -188,6 +188,29 @@ struct ZeroArgs {
     int count;
 };
 
+// ---- adaptive rank (blocked range finder) ----
+struct EyeArgs {  // R (lp x lp, FP64) = I
+    double* R;
+    int lp;
+};
+
+struct AdaptDecideArgs {  // after block i: E_i = ||S||_F^2 - sum_{j <= i} cap[j], stop test
+    const double* fro2;
+    const double* cap;    // ||B_j||_F^2 of every finished block
+    double* E;            // E_i, one per block
+    int* flags;           // status words of the matrix
+    double delta;
+    int i, kmax, b;
+};
+
+struct AdaptRankArgs {  // the energy rank of the l computed singular values
+    const double* sig;
+    const double* fro2;
+    int* flags;
+    double delta;
+    int l;
+};
+
 // ---- learned warm start ----
 struct WarmFwdArgs {  // network forward of the call's parameter vector
     const float* params;
@@ -205,23 +228,26 @@ struct WarmZArgs {  // coordinates Z of the predicted subspace in the bank, FP32
     int r, Kr, lp, iters;
 };
 
-struct ProbeResArgs {  // per row chunk: sums over rows of (Y[:, i] - (Q1 M)[:, i])^2, i < d
-    const double* Y;      // m x d (ldY)
+struct ModeResArgs {  // per row chunk: sums over rows of (Y[:, k] - sig_k^2 Phi[:, k])^2, k < r
+    const double* Y;      // m x r (ldY): S A^T with FP64 products
     int64_t ldY, m;
-    const float* Q1;      // m x lp (ldQ)
-    int64_t ldQ;
-    const double* M;      // lp x d (ld lp)
-    double* part;         // nchunk x d
-    int lp, d;
+    const float* Phi;     // m x r (ldP): the returned modes before the sign convention
+    int64_t ldP;
+    const double* sig;    // r
+    double* part;         // nchunk x r
+    int64_t rows;         // rows per chunk (a multiple of 64)
+    int r;
 };
 
-struct ProbeFinalArgs {  // rho = factor max_i sqrt(sum of part[:, i]) / sig[0]
+struct ModeResFinalArgs {  // rho_k = sqrt(sum of part[:, k]) / sig_k^2, rho = max_k rho_k
     const double* part;
     const double* sig;
-    double* rho;
-    int* flags;
+    double* rho_modes;    // r
+    double* rho;          // 1
+    int* flags;           // status word: DEV_FLAG_RESIDUAL when the result is rejected
+    int* decision;        // 1 when rejected (the continuation runs), else 0
     double tol;
-    int d, nchunk;
+    int r, nchunk;
 };
 
 // Workgroup -> (item, local tile) for grouped launches.
@@ -236,13 +262,24 @@ __device__ __forceinline__ int group_item(const int* tstart, int count, int b) {
 }
 #endif
 
-// One grouped launch as seen by a kernel.
+// One grouped launch as seen by a kernel. skip (device, may be NULL): the
+// whole launch does nothing unless (*skip & skip_mask) != 0 -- a step of a
+// recorded program that runs only when an earlier kernel raised a flag.
 template <typename A>
 struct Group {
     const A* args;
     const int* tstart;
     const CallDesc* calls;
     int count;
+    const int* skip = nullptr;
+    int skip_mask = 0;
 };
+
+#ifdef __HIPCC__
+template <typename A>
+__device__ __forceinline__ bool group_skipped(const Group<A>& g) {
+    return g.skip != nullptr && !(*g.skip & g.skip_mask);
+}
+#endif
 
 }  // namespace rpod

@@ -26,6 +26,8 @@ static Group<A> mkgc(const GroupLaunch<A>& L) {
     g.tstart = L.tstart;
     g.calls = L.calls;
     g.count = L.count;
+    g.skip = L.skip;
+    g.skip_mask = L.skip_mask;
     return g;
 }
 
@@ -40,6 +42,7 @@ __device__ __forceinline__ double to_d(T x) {
 // column lp + k of X = the indicator of block k over all ld rows (ind)
 template <typename T>
 __global__ __launch_bounds__(256) void k_center_prep(Group<CprepArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const CprepArgs& a = g.args[it];
     const int t = blockIdx.x - g.tstart[it];
@@ -66,6 +69,7 @@ __global__ __launch_bounds__(256) void k_center_prep(Group<CprepArgs> g) {
 // columns are corrected 16 at a time (their loads issued together)
 template <typename T>
 __global__ __launch_bounds__(256) void k_center_y(Group<CenterYArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const CenterYArgs& a = g.args[it];
     __shared__ double cs[4096];  // K lp <= 4096
@@ -105,6 +109,7 @@ __global__ __launch_bounds__(256) void k_center_y(Group<CenterYArgs> g) {
 constexpr int CX_R = 32, CX_LD = CX_R + 1;
 template <typename T>
 __global__ __launch_bounds__(256) void k_center_cross(Group<CrossArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const CrossArgs& a = g.args[it];
     const int ch = blockIdx.x - g.tstart[it];
@@ -162,6 +167,7 @@ __global__ __launch_bounds__(256) void k_center_cross(Group<CrossArgs> g) {
 // one tile per entry o: P[o] = the sum of its nchunk partial sums (contiguous);
 // thread t adds chunks t, t + 256, .. in order, then a fixed tree in LDS
 __global__ __launch_bounds__(256) void k_center_sum(Group<CrossSumArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const CrossSumArgs& a = g.args[it];
     const int o = blockIdx.x - g.tstart[it];
@@ -180,6 +186,7 @@ __global__ __launch_bounds__(256) void k_center_sum(Group<CrossSumArgs> g) {
 
 // 256 entries per tile over the ld x lp array Z
 __global__ __launch_bounds__(256) void k_center_z(Group<CenterZArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const CenterZArgs& a = g.args[it];
     const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * 256 + threadIdx.x;

@@ -16,6 +16,8 @@ static Group<A> mkge(const GroupLaunch<A>& L) {
     g.tstart = L.tstart;
     g.calls = L.calls;
     g.count = L.count;
+    g.skip = L.skip;
+    g.skip_mask = L.skip_mask;
     return g;
 }
 
@@ -39,6 +41,7 @@ __device__ __forceinline__ double block_sum256(double s, double* red) {
 
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_frob_part(Group<FrobArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const FrobArgs& a = g.args[it];
     const int w = blockIdx.x - g.tstart[it];
@@ -64,6 +67,7 @@ __global__ __launch_bounds__(256) void k_frob_part(Group<FrobArgs> g) {
 }
 
 __global__ __launch_bounds__(256) void k_frob_sum(Group<FrobArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const FrobArgs& a = g.args[it];
     double s = 0.0;

@@ -21,6 +21,8 @@ struct GroupLaunch {
     const CallDesc* calls; // device call table
     int count;             // matrices in the group
     int tiles;             // workgroups of the launch
+    const int* skip = nullptr;  // device; the launch does nothing unless (*skip & skip_mask)
+    int skip_mask = 0;
 };
 
 // Streaming "skinny-right" product Y = S X on matrix cores (FP64/FP32 S).
@@ -173,6 +175,21 @@ hipError_t launch_sketch_bits(uint64_t seed, int64_t n, int l, uint32_t* out, hi
 
 hipError_t launch_zero_ints(const GroupLaunch<ZeroArgs>& L, hipStream_t st);
 
+// ---- adaptive rank (small_kernels.hip) ----
+// Status words of a matrix used by adaptive plans: bit k of ADAPT_ACTIVE lets
+// block k run, bit k of ADAPT_STOP selects the finish for k blocks; the
+// sketch width reached and the energy rank are published as plain words.
+constexpr int ADAPT_ACTIVE = 3, ADAPT_STOP = 4, ADAPT_LUSED = 5, ADAPT_RANK = 6;
+constexpr int ADAPT_MAX_BLOCKS = 8;
+hipError_t launch_eye(const GroupLaunch<EyeArgs>& L, hipStream_t st);
+// one thread: E_i, then either ADAPT_STOP |= 1 << (i + 1) and ADAPT_LUSED =
+// (i + 1) b (E_i <= (1 - delta) ||S||_F^2, not finite, or the last block), or
+// ADAPT_ACTIVE |= 1 << (i + 1)
+hipError_t launch_adapt_decide(const GroupLaunch<AdaptDecideArgs>& L, hipStream_t st);
+// one thread: ADAPT_RANK = the smallest r with (sigma_1^2 + .. + sigma_r^2) /
+// ||S||_F^2 >= delta (cumulative sum in order), or -1
+hipError_t launch_adapt_rank(const GroupLaunch<AdaptRankArgs>& L, hipStream_t st);
+
 // ---- learned warm start (warm_kernels.hip) ----
 // Network 4 -> 256 -> 256 -> K (tanh, tanh, softmax), FP32 parameters packed
 // as W1 (256 x 4, row-major), b1, W2 (256 x 256), b2, W3 (K x 256), b3.
@@ -211,18 +228,19 @@ hipError_t launch_block_sumsq(const double* src, int64_t sa, int64_t sb, int r, 
                               hipStream_t st);
 // Plan steps (grouped): network forward of the call's parameter vector, the
 // predicted subspace's coordinates (tiles: lp ceil(ldX / 64) per matrix,
-// iters <= 2), and the a-posteriori residual of the range basis: per 256-row
-// chunk the squared norms of Y - Q1 M for the d <= WARM_PROBES probe columns
-// (tiles: ceil(m / 256)), then rho = WARM_HMT_FACTOR max_i ||(Y - Q1 M)[:, i]||
-// / sig[0] (one workgroup per matrix; DEV_FLAG_RESIDUAL when rho > tol or
-// not finite). lp <= WARM_MAXLP.
-constexpr int WARM_PROBES = 16, WARM_MAXLP = 128;
+// iters <= 2), and the residual of each returned singular triplet: per chunk
+// of `rows` rows the squared norms of Y[:, k] - sig_k^2 Phi[:, k] (tiles:
+// ceil(m / rows)), then rho_k = ||Y[:, k] - sig_k^2 Phi[:, k]|| / sig_k^2 and
+// rho = max_k rho_k (one workgroup per matrix; rejection when rho > tol or
+// not finite). r <= WARM_MAXLP.
+constexpr int WARM_MAXLP = 128;
+constexpr int WARM_RES_ROWS = 1024;  // rows per chunk of the residual sums
+constexpr int WARM_DECISION = 2;     // status word of a matrix holding the warm start's decision
 constexpr int WARM_PROJ_COLS = 256;  // column block of the FP64 S^T Q kernel (holds lp <= 128)
-constexpr double WARM_HMT_FACTOR = 7.978845608028654;  // 10 sqrt(2 / pi)
 hipError_t launch_warm_plan_forward(const GroupLaunch<WarmFwdArgs>& L, hipStream_t st);
 hipError_t launch_warm_z(const GroupLaunch<WarmZArgs>& L, hipStream_t st);
-hipError_t launch_warm_probe_res(const GroupLaunch<ProbeResArgs>& P, const GroupLaunch<ProbeFinalArgs>& F,
-                                 hipStream_t st);
+hipError_t launch_warm_mode_res(const GroupLaunch<ModeResArgs>& P, const GroupLaunch<ModeResFinalArgs>& F,
+                                hipStream_t st);
 
 // Write count call-table entries from host values (through kernel arguments).
 hipError_t launch_set_calls(CallDesc* table, const CallDesc* host, int count, hipStream_t st);

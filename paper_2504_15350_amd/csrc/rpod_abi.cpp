@@ -211,7 +211,8 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
 // Recorded program
 // ---------------------------------------------------------------------------
 enum Kind { K_ZERO, K_OMEGA, K_SX, K_SXE6, K_SX16, K_STQ, K_STQE6, K_STQ16, K_REDUCE, K_GRAM, K_CHOL, K_JACOBI, K_LIFT,
-            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_PROBE, K_CPREP, K_CY, K_CCROSS, K_CSUM, K_CZ, K_FROB };
+            K_SIGNS, K_FIN, K_SPLIT, K_WFWD, K_WZ, K_SXW, K_MRES, K_CPREP, K_CY, K_CCROSS, K_CSUM, K_CZ, K_FROB,
+            K_EYE, K_ADEC, K_ARANK };
 
 struct Step {
     Kind kind;
@@ -219,6 +220,9 @@ struct Step {
     bool vec = true, upper = false, lo = false;
     bool energy = false;  // K_SXE6: also the per-tile sums of squares; K_FROB: only the final sum
     int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S, 2: the 16-bit refinement pass (timed)
+    // conditional steps (warm and adaptive plans, one matrix): the launch does
+    // nothing unless status word skip_word of the matrix has a bit of skip_mask
+    int skip_word = -1, skip_mask = 0;
     size_t a1 = 0, t1 = 0, a2 = 0, t2 = 0;  // program-blob offsets of the argument / tile tables
     int count = 0, tiles1 = 0, tiles2 = 0;
     double bytes = 0, flops = 0;  // algorithmic work of the launch (passes over S)
@@ -274,21 +278,23 @@ struct rpod_plan_s {
     std::vector<double> evbytes[3], evflops[3];
     size_t used[3] = {0, 0, 0};
     std::vector<CallDesc> host_calls;
-    // warm plans: the model, the fallback program and its graph, the warm region
+    // warm plans: the model and the warm region (predicted coordinates, network
+    // output, the residual product S A^T, its chunk sums, rho and rho_k)
     rpod_warm_s* model = nullptr;
-    std::vector<std::vector<Step>> fb_programs;
-    hipGraph_t fb_graph = nullptr;
-    hipGraphExec_t fb_exec = nullptr;
-    size_t o_warm = 0, w_Xw = 0, w_c = 0, w_kstar = 0, w_Xv = 0, w_Yres = 0, w_part = 0, w_rho = 0;
-    size_t w_pZp = 0, w_pC = 0, w_pM = 0;  // residual probes: split-K slabs, Zw^T W, R^-1 Zw^T W
-    int probe_nsplit = 1;
-    int64_t probe_split_rows = 0;
+    size_t o_warm = 0, w_Xw = 0, w_c = 0, w_kstar = 0, w_Yres = 0, w_part = 0, w_rho = 0, w_rhom = 0;
+    int res_nchunk = 0;
     int64_t ldXw = 0;
     double tol = 0.0;
     int q_fb = 0;
+    // adaptive plans: block width, block count, energy threshold, and the
+    // adaptive region (||B_i||_F^2 and E_i per block, Frobenius partial sums)
+    int adapt_b = 0, adapt_kmax = 0;
+    double delta = 0.0;
+    size_t o_adapt = 0;
 
     template <typename T>
     T* wat(size_t off) const { return reinterpret_cast<T*>(ws + o_warm + off); }
+    double* adat(size_t k) const { return reinterpret_cast<double*>(ws + o_adapt) + k; }
     int* flags(const Item& it) const { return reinterpret_cast<int*>(ws + o_flags) + FLAG_INTS * it.idx; }
     template <typename T>
     T* at(const Item& it, size_t off) const { return reinterpret_cast<T*>(ws + it.off + off); }
@@ -301,6 +307,10 @@ struct rpod_plan_s {
         g.calls = calls();
         g.count = s.count;
         g.tiles = second ? s.tiles2 : s.tiles1;
+        if (s.skip_word >= 0) {  // plans with conditional steps hold one matrix
+            g.skip = reinterpret_cast<const int*>(ws + o_flags) + s.skip_word;
+            g.skip_mask = s.skip_mask;
+        }
         return g;
     }
 };
@@ -336,6 +346,14 @@ struct Recorder {
         return v;
     }
 
+    // steps recorded since `first` run only if status word `word` has a bit of `mask`
+    void only_if(size_t first, int word, int mask) {
+        for (size_t k = first; k < out.size(); ++k) {
+            out[k].skip_word = word;
+            out[k].skip_mask = mask;
+            out[k].pass = -1;  // not timed: skipped launches would distort the averages
+        }
+    }
     void zero() {
         Step s{K_ZERO};
         B.add(s, each([&](const Item& it) { return ZeroArgs{P->flags(it), FLAG_INTS}; }),
@@ -563,16 +581,135 @@ struct Recorder {
         sx_tall(dt, L0().nt, true, apply(Out, Out, kfin, true));  // shifted retry, in place (no-op otherwise)
         gram(dt, gargs(Out, true));
         chol(cargs(kfin, 2));
-        if (is16(L0().tin)) {
-            Step s{K_SPLIT};
-            s.tin = L0().tin;
-            B.add(s, each([&](const Item& it) {
-                      return SplitArgs{P->at<float>(it, it.L.o_Q1), it.L.mP * it.L.lp,
-                                       P->at<unsigned short>(it, it.L.o_Qh), P->at<unsigned short>(it, it.L.o_Ql)};
-                  }),
-                  tiles([](const Item& it) { return (int)((it.L.mP * it.L.lp / 4 + 255) / 256); }));
-            out.push_back(s);
-        }
+        split_q();
+    }
+    // One CholeskyQR of the tall Y into Q1 = Y R^-1 for an iterate of which only
+    // the span matters (the product S^T Q1 of a subspace iteration that is not
+    // the last: the n-side basis and the next CholeskyQR2 follow), and a second
+    // factorisation only after a shifted first one (CholeskyQR3 of Fukaya et
+    // al.); no factor is left for the consumer: S^T Q1 itself is the iterate.
+    // Q1's rounding in its storage type perturbs its span the same way whether
+    // or not a second pass then orthonormalises it.
+    void orth_tall_once() {
+        const int dt = L0().tacc;
+        auto In = [&](const Item& it) { return (void*)P->at<char>(it, it.L.o_Y); };
+        auto Out = [&](const Item& it) { return (void*)P->at<char>(it, it.L.o_Q1); };
+        auto Rx = [&](const Item& it, int k) {
+            return dt == DT_F64 ? (const void*)P->at<char>(it, it.L.o_R64[k]) : (const void*)P->at<char>(it, it.L.o_R32[k]);
+        };
+        auto gargs = [&](auto buf, bool cond) {
+            return each([&](const Item& it) {
+                return GramArgs{buf(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
+            });
+        };
+        auto cargs = [&](int k, int mode) {
+            return each([&](const Item& it) {
+                return CholArgs{P->at<double>(it, it.L.o_G), it.d.m, P->at<double>(it, it.L.o_R64[k]),
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+            });
+        };
+        auto apply = [&](auto src, auto dst, int k, bool cond) {
+            return each([&](const Item& it) {
+                return SxArgs{src(it), it.L.mP, it.d.m, it.L.lp, Rx(it, k), it.L.lp, dst(it), it.L.mP, it.L.mP,
+                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+            });
+        };
+        gram(dt, gargs(In, false));
+        chol(cargs(0, 0));
+        sx_tall(dt, L0().nt, true, apply(In, Out, 0, false));
+        gram(dt, gargs(Out, true));                              // after a shift only
+        chol(cargs(2, 2));
+        sx_tall(dt, L0().nt, true, apply(Out, Out, 2, true));    // in place, after a shift only
+        split_q();
+    }
+    // 16-bit storage: Q1 (FP32) as hi + lo BF16/FP16 parts for the passes S^T Q
+    void split_q() {
+        if (!is16(L0().tin)) return;
+        Step s{K_SPLIT};
+        s.tin = L0().tin;
+        B.add(s, each([&](const Item& it) {
+                  return SplitArgs{P->at<float>(it, it.L.o_Q1), it.L.mP * it.L.lp,
+                                   P->at<unsigned short>(it, it.L.o_Qh), P->at<unsigned short>(it, it.L.o_Ql)};
+              }),
+              tiles([](const Item& it) { return (int)((it.L.mP * it.L.lp / 4 + 255) / 256); }));
+        out.push_back(s);
+    }
+    // Adaptive plans: explicit CholeskyQR2 of Q1[:, :lp] in place. The leading
+    // columns hold the orthonormal basis so far and the trailing block the
+    // newest product, so the Cholesky factor of the whole Gram also projects
+    // the block off the basis (block Gram-Schmidt), and the second pass
+    // repeats the projection. Shifted CholeskyQR3 after a breakdown as in
+    // orth_tall; the last factor is applied, not left pending.
+    void orth_joint() {
+        const int dt = L0().tacc;
+        auto Q = [&](const Item& it) { return (void*)P->at<char>(it, it.L.o_Q1); };
+        auto Rx = [&](const Item& it, int k) {
+            return dt == DT_F64 ? (const void*)P->at<char>(it, it.L.o_R64[k]) : (const void*)P->at<char>(it, it.L.o_R32[k]);
+        };
+        auto gargs = [&](bool cond) {
+            return each([&](const Item& it) {
+                return GramArgs{Q(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
+                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
+            });
+        };
+        auto cargs = [&](int k, int mode) {
+            return each([&](const Item& it) {
+                return CholArgs{P->at<double>(it, it.L.o_G), it.d.m, P->at<double>(it, it.L.o_R64[k]),
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+            });
+        };
+        auto apply = [&](int k, bool cond) {
+            return each([&](const Item& it) {
+                return SxArgs{Q(it), it.L.mP, it.d.m, it.L.lp, Rx(it, k), it.L.lp, Q(it), it.L.mP, it.L.mP,
+                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+            });
+        };
+        gram(dt, gargs(false));
+        chol(cargs(0, 0));
+        sx_tall(dt, L0().nt, true, apply(0, false));
+        gram(dt, gargs(false));
+        chol(cargs(1, 1));
+        sx_tall(dt, L0().nt, true, apply(1, true));   // shifted retry only
+        gram(dt, gargs(true));
+        chol(cargs(1, 2));
+        sx_tall(dt, L0().nt, true, apply(1, false));  // the last factor
+    }
+    // *dst = ||Zt[:, :l]||_F^2 (FP64, n rows): adaptive plans, ||B_i||_F^2 of a block
+    void frob_z(double* part, double* dst) {
+        Step s{K_FROB};
+        s.tin = DT_F64;
+        s.vec = true;
+        auto args = each([&](const Item& it) {
+            return FrobArgs{P->at<double>(it, it.L.o_Zt), it.L.nP, it.d.n, it.L.l, part, dst, 64, -1};
+        });
+        B.add(s, args, tiles([](const Item&) { return 64; }));
+        B.add(s, args, tiles([](const Item&) { return 1; }), true);
+        out.push_back(s);
+    }
+    void adapt_decide(int i) {
+        Step s{K_ADEC};
+        B.add(s, each([&](const Item& it) {
+                  return AdaptDecideArgs{P->at<double>(it, it.L.o_Fro), P->adat(0), P->adat(ADAPT_MAX_BLOCKS),
+                                         P->flags(it), P->delta, i, P->adapt_kmax, P->adapt_b};
+              }),
+              tiles([](const Item&) { return 1; }));
+        out.push_back(s);
+    }
+    void eye1() {  // R64[1] = I: the basis is explicit, step 7 lifts with Q1 itself
+        Step s{K_EYE};
+        B.add(s, each([&](const Item& it) { return EyeArgs{P->at<double>(it, it.L.o_R64[1]), it.L.lp}; }),
+              tiles([](const Item& it) { return (it.L.lp * it.L.lp + 255) / 256; }));
+        out.push_back(s);
+    }
+    void adapt_rank() {
+        Step s{K_ARANK};
+        B.add(s, each([&](const Item& it) {
+                  return AdaptRankArgs{P->at<double>(it, it.L.o_sig), P->at<double>(it, it.L.o_Fro), P->flags(it),
+                                       P->delta, it.L.l};
+              }),
+              tiles([](const Item&) { return 1; }));
+        out.push_back(s);
     }
     // Zw = Zt R^-1 (R from the last tall orthonormalisation): Zw = S^T Q
     void small_from_slabs() {
@@ -787,62 +924,55 @@ struct Recorder {
         sx(DT_F32, DT_F32, L.nt, false,
            std::vector<SxArgs>{{M->at<float>(M->L.bank), M->mP, it.d.m, M->Kr, P->wat<float>(P->w_Xw), P->ldXw,
                                 P->at<char>(it, L.o_Y), L.mP, L.mP, nullptr, 0, -1, r}});
-        orth_tall(1);
+        // the iterates before the last product S^T Q need only their span
+        if (it.d.q > 0) orth_tall_once(); else orth_tall(1);
         for (int i = 0; i < it.d.q; ++i) {
-            pass_stq(false);
-            small_from_slabs();
+            pass_stq(false, &Layout::o_Zw);
             basis_small();
             pass_sx();
-            orth_tall(1);
+            if (i + 1 < it.d.q) orth_tall_once(); else orth_tall(1);
         }
         pass_stq(true);
         small_from_slabs();
         finish();
-        // a-posteriori residual of the range basis Q = Q1 R^-1 (Halko, Martinsson
-        // and Tropp 2011, eq. 4.3): d Gaussian probes W (stream 1 of the call's
-        // seed), Y = S W with FP64 products, Q^T Y = Zw^T W (Zw = S^T Q from the
-        // last pass), M = R^-1 Q^T Y, and the norms of Y - Q1 M
-        constexpr int d = WARM_PROBES;
-        double* Xp = P->wat<double>(P->w_Xv);
-        double* Yp = P->wat<double>(P->w_Yres);
-        Step o2{K_OMEGA};
-        o2.tout = DT_F64;
-        OmegaArgs pa{};
-        pa.out = Xp; pa.n = it.d.n; pa.rows_pad = L.nP; pa.ldo = L.nP; pa.seed = 0;
-        pa.l = d; pa.lpad = d; pa.call = it.idx; pa.stream = 1;
-        B.add(o2, std::vector<OmegaArgs>{pa}, std::vector<int>{(int)((L.nP + 255) / 256) * (d / 2)});
-        out.push_back(o2);
+        // residual of each returned triplet: Y = S A^T with FP64 products (A^T of
+        // the internal FP64 coefficients, n x r), then rho_k and the decision
         Step w{K_SXW};
-        w.tin = L.tin; w.nt = d / 16;
+        w.tin = L.tin; w.nt = L.ntr;
         w.vec = it.d.ld % (s16 ? 8 : 4) == 0;
-        B.add(w, std::vector<SxArgs>{{nullptr, it.d.ld, it.d.m, it.d.n, Xp, L.nP, Yp, L.mP, L.mP, nullptr, 0, it.idx, 0}},
+        B.add(w, std::vector<SxArgs>{{nullptr, it.d.ld, it.d.m, it.d.n, P->at<double>(it, L.o_At), L.nP,
+                                      P->wat<double>(P->w_Yres), L.mP, L.mP, nullptr, 0, it.idx, r}},
               std::vector<int>{(int)(L.mP / 256)});
         out.push_back(w);
-        Step k{K_STQ};  // C = Zw^T W: FP64 split-K over the n rows, one 256-column block
-        k.tin = DT_F64; k.nt = d / 16; k.vec = true;
-        StqArgs ka{};
-        ka.S = P->at<double>(it, L.o_Zw); ka.ldS = L.nP; ka.m = it.d.n; ka.n = L.lp;
-        ka.Q = Xp; ka.Ql = nullptr; ka.ldQ = L.nP; ka.Zp = P->wat<double>(P->w_pZp); ka.nP = WARM_PROJ_COLS;
-        ka.split_rows = P->probe_split_rows; ka.nsplit = P->probe_nsplit; ka.ncb = 1; ka.call = -1;
-        B.add(k, std::vector<StqArgs>{ka}, std::vector<int>{ka.nsplit});
-        out.push_back(k);
-        Step rd{K_REDUCE};
-        B.add(rd, std::vector<ReduceArgs>{{P->wat<double>(P->w_pZp), (int64_t)WARM_PROJ_COLS * d,
-                                           P->wat<double>(P->w_pC), P->probe_nsplit, 0}},
-              std::vector<int>{(WARM_PROJ_COLS * d + 255) / 256});
-        out.push_back(rd);
-        sx(DT_F64, DT_F64, d / 16, false,
-           std::vector<SxArgs>{{P->at<char>(it, L.o_R64[1]), L.lp, L.lp, L.lp, P->wat<double>(P->w_pC), WARM_PROJ_COLS,
-                                P->wat<double>(P->w_pM), L.lp, L.lp, nullptr, 0, -1}});
-        Step rs{K_PROBE};
-        const int nchunk = (int)((it.d.m + 255) / 256);
-        B.add(rs, std::vector<ProbeResArgs>{{Yp, L.mP, it.d.m, P->at<float>(it, L.o_Q1), L.mP, P->wat<double>(P->w_pM),
-                                             P->wat<double>(P->w_part), L.lp, d}},
-              std::vector<int>{nchunk});
-        B.add(rs, std::vector<ProbeFinalArgs>{{P->wat<double>(P->w_part), P->at<double>(it, L.o_sig),
-                                               P->wat<double>(P->w_rho), P->flags(it), P->tol, d, nchunk}},
+        Step rs{K_MRES};
+        B.add(rs, std::vector<ModeResArgs>{{P->wat<double>(P->w_Yres), L.mP, it.d.m, P->at<float>(it, L.o_Phi), L.mP,
+                                            P->at<double>(it, L.o_sig), P->wat<double>(P->w_part),
+                                            (int64_t)WARM_RES_ROWS, r}},
+              std::vector<int>{P->res_nchunk});
+        B.add(rs, std::vector<ModeResFinalArgs>{{P->wat<double>(P->w_part), P->at<double>(it, L.o_sig),
+                                                 P->wat<double>(P->w_rhom), P->wat<double>(P->w_rho), P->flags(it),
+                                                 P->flags(it) + WARM_DECISION, P->tol, r, P->res_nchunk}},
               std::vector<int>{1}, true);
         out.push_back(rs);
+        // continuation after a rejection: q_fb more subspace iterations from the
+        // warm range basis (Zw = S^T Q of the last pass is the first iterate's
+        // n-side factor), then steps 5-7 again over the same buffers
+        if (P->q_fb > 0) {
+            const size_t first = out.size();
+            basis_small();
+            pass_sx();
+            for (int i = 1; i < P->q_fb; ++i) {
+                orth_tall_once();
+                pass_stq(false, &Layout::o_Zw);
+                basis_small();
+                pass_sx();
+            }
+            orth_tall(1);
+            pass_stq(true);
+            small_from_slabs();
+            finish();
+            only_if(first, WARM_DECISION, 1);
+        }
     }
     void record() {
         zero();
@@ -852,16 +982,17 @@ struct Recorder {
         pass_sx(true);      // step 2 (and the block sums of S; FP32 energy: the partial sums of squares)
         frob(true);
         center_y();
-        orth_tall(1);       // step 4 (Q of the sketch)
-        for (int it = 0; it < C[0]->d.q; ++it) {  // step 3, re-orthonormalised after every product
-            pass_stq(false);
-            center_z();
-            small_from_slabs();
+        // step 4 (Q of the sketch); the iterates before the last product S^T Q need only their span
+        const int q = C[0]->d.q;
+        if (q > 0) orth_tall_once(); else orth_tall(1);
+        for (int it = 0; it < q; ++it) {  // step 3, re-orthonormalised after every product
+            pass_stq(false, &Layout::o_Zw);
+            center_z(&Layout::o_Zw);
             basis_small();
             center_prep(false);
             pass_sx();
             center_y();
-            orth_tall(1);
+            if (it + 1 < q) orth_tall_once(); else orth_tall(1);
         }
         pass_stq(true);     // step 5 (refinement on 16-bit paths)
         center_z();
@@ -900,7 +1031,7 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_WFWD: return launch_warm_plan_forward(P->gl<WarmFwdArgs>(s, false), st);
         case K_WZ: return launch_warm_z(P->gl<WarmZArgs>(s, false), st);
         case K_SXW: return launch_sx_wide(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
-        case K_PROBE: return launch_warm_probe_res(P->gl<ProbeResArgs>(s, false), P->gl<ProbeFinalArgs>(s, true), st);
+        case K_MRES: return launch_warm_mode_res(P->gl<ModeResArgs>(s, false), P->gl<ModeResFinalArgs>(s, true), st);
         case K_CPREP: return launch_center_prep(s.tin, P->gl<CprepArgs>(s, false), st);
         case K_CY: return launch_center_y(s.tin, P->gl<CenterYArgs>(s, false), st);
         case K_CCROSS: return launch_center_cross(s.tin, P->gl<CrossArgs>(s, false), st);
@@ -908,6 +1039,9 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_CZ: return launch_center_z(P->gl<CenterZArgs>(s, false), st);
         case K_FROB:
             return launch_frob(s.tin, s.vec, s.energy, P->gl<FrobArgs>(s, false), P->gl<FrobArgs>(s, true), st);
+        case K_EYE: return launch_eye(P->gl<EyeArgs>(s, false), st);
+        case K_ADEC: return launch_adapt_decide(P->gl<AdaptDecideArgs>(s, false), st);
+        case K_ARANK: return launch_adapt_rank(P->gl<AdaptRankArgs>(s, false), st);
     }
     return hipErrorInvalidValue;
 }
@@ -1074,8 +1208,6 @@ rpod_status workspace_bytes(const rpod_desc* descs, int32_t count, const rpod_tu
 void destroy_plan(rpod_plan_s* P) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
-    if (P->fb_exec) (void)hipGraphExecDestroy(P->fb_exec);
-    if (P->fb_graph) (void)hipGraphDestroy(P->fb_graph);
     for (int k = 0; k < 3; ++k)
         for (hipEvent_t ev : P->ev[k]) (void)hipEventDestroy(ev);
     delete P;
@@ -1154,6 +1286,113 @@ rpod_status compute_impl(rpod_plan_s* P, const void* const* S, const uint64_t* s
 }
 
 // ---------------------------------------------------------------------------
+// Adaptive plans (blocked range finder of Yu, Gu and Li 2018, randQB_EI, with
+// the energy rule of Sec. 4.1 as its stopping test)
+// ---------------------------------------------------------------------------
+// An item of width l on the buffers of `base`: the layout scalars of an
+// l-column plan (l a multiple of 16), the base's buffer offsets.
+Item width_variant(const Item& base, int l) {
+    Item v = base;
+    v.d.r = l;
+    v.d.p = 0;
+    v.L.l = l;
+    v.L.lp = l;
+    v.L.nt = l / 16;
+    v.L.rp = l;
+    v.L.ntr = l / 16;
+    v.L.lpa = l;
+    v.L.nta = l / 16;
+    return v;
+}
+
+// One program: the sketch, then block i = 0 .. kmax - 1, each of which runs
+// only while the stopping test has not fired (block 0 always), then the
+// finish for k = 1 .. kmax blocks, of which exactly one runs.
+void record_adaptive(rpod_plan_s* P, Builder& B) {
+    P->programs.assign(1, {});
+    std::vector<Step>& out = P->programs[0];
+    const Item& base = P->items[0];
+    const int b = P->adapt_b, kmax = P->adapt_kmax, q = base.d.q;
+    const size_t si = dt_size(base.L.tin), sa = dt_size(base.L.tacc);
+    Recorder R0{P, B, {&base}, out};
+    R0.zero();
+    R0.frob(false);   // ||S||_F^2: a pass of its own off FP32
+    R0.omega();       // all l_max columns; block i uses columns i b .. i b + b - 1
+    for (int i = 0; i < kmax; ++i) {
+        // the block's own operands: its sketch columns, its columns of Q1 (and
+        // of the hi / lo parts), S^T Q_i of the power steps in Zt, B_i^T into Zw
+        Item blk = width_variant(base, b);
+        blk.L.o_X += (size_t)i * b * base.L.nP * si;
+        blk.L.o_Q1 += (size_t)i * b * base.L.mP * sa;
+        blk.L.o_Y = blk.L.o_Q1;
+        blk.L.o_Qh += (size_t)i * b * base.L.mP * 2;
+        blk.L.o_Ql += (size_t)i * b * base.L.mP * 2;
+        blk.L.o_Zw = base.L.o_Zt;
+        blk.L.o_Zt = base.L.o_Zw + (size_t)i * b * base.L.nP * 8;
+        Item joint = width_variant(base, (i + 1) * b);  // [Q_0 .. Q_{i-1}, Y_i] in Q1
+        Recorder Rb{P, B, {&blk}, out}, Rj{P, B, {&joint}, out};
+        const size_t first = out.size();
+        Rb.pass_sx(i == 0);   // Y_i = S Omega_i into Q1's block (block 0: FP32 energy partial sums)
+        if (i == 0) R0.frob(true);
+        Rj.orth_joint();      // Q_i = orth(Y_i - Q (Q^T Y_i)), twice
+        for (int j = 0; j < q; ++j) {
+            Rb.split_q();
+            Rb.pass_stq(false, &Layout::o_Zw);  // S^T Q_i (Q_i is orthogonal to Q: B^T Q^T Q_i vanishes)
+            Rb.basis_small();                   // Z_i = orth(S^T Q_i) into the block's sketch columns
+            Rb.pass_sx();                       // S Z_i into Q1's block
+            Rj.orth_joint();                    // Q_i = orth(S Z_i - Q (B Z_i)), twice
+        }
+        Rb.split_q();
+        Rb.pass_stq(true, &Layout::o_Zt);       // B_i^T = S^T Q_i into Zw's block
+        Rb.frob_z(P->adat(2 * ADAPT_MAX_BLOCKS), P->adat(i));
+        Rb.adapt_decide(i);
+        if (i > 0) Rb.only_if(first, ADAPT_ACTIVE, 1 << i);
+    }
+    for (int k = 1; k <= kmax; ++k) {
+        Item fin = width_variant(base, k * b);  // Q1[:, :k b] explicit, B^T = Zw[:, :k b]
+        Recorder Rf{P, B, {&fin}, out};
+        const size_t first = out.size();
+        Rf.eye1();
+        Rf.finish();          // steps 6-7 of Alg. 1 on B, outputs of k b modes
+        Rf.adapt_rank();
+        Rf.only_if(first, ADAPT_STOP, 1 << k);
+    }
+    for (Step& st : out) st.pass = -1;  // per-pass timing is not kept for adaptive plans
+}
+
+rpod_status adaptive_build(rpod_plan_s* P, const rpod_desc* desc, double delta, std::vector<char>* blob_out,
+                           size_t* bytes) {
+    if (desc == nullptr) return fail(RPOD_EINVAL, "desc is NULL");
+    if (desc->flags != 0) return fail(RPOD_EINVAL, "adaptive plans take flags = 0 (||S||_F^2 is always computed)");
+    if (desc->block_cols != 0) return fail(RPOD_EUNSUPPORTED, "adaptive plans take block_cols = 0");
+    const int b = desc->p, lmax = desc->r;
+    if (b < 16 || b % 16 != 0) return fail(RPOD_EINVAL, "p (the block width) must be a positive multiple of 16 (got %d)", b);
+    if (lmax < b || lmax % b != 0 || lmax > 128)
+        return fail(RPOD_EINVAL, "r (the largest sketch width) must be a multiple of p and at most 128 (got %d)", lmax);
+    if (!(delta > 0.0 && delta <= 1.0)) return fail(RPOD_EINVAL, "delta must lie in (0, 1]");
+    rpod_desc d = *desc;
+    d.r = lmax;
+    d.p = 0;
+    d.flags = RPOD_DESC_ENERGY;
+    BatchLayout bl;
+    rpod_status s = batch_layout(&d, 1, nullptr, bl);
+    if (s != RPOD_OK) return s;
+    P->items = bl.items;
+    P->o_flags = bl.o_flags;
+    P->o_calls = bl.o_calls;
+    P->o_adapt = bl.o_items_end;
+    P->o_prog = P->o_adapt + 1024;  // cap[8], E[8], 64 partial sums
+    P->delta = delta;
+    P->adapt_b = b;
+    P->adapt_kmax = lmax / b;
+    Builder B;
+    record_adaptive(P, B);
+    *bytes = P->o_prog + (B.blob.size() + 255) / 256 * 256;
+    if (blob_out) *blob_out = B.blob;
+    return RPOD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Warm plans
 // ---------------------------------------------------------------------------
 rpod_status warm_check(const rpod_desc* d, const rpod_warm_s* M) {
@@ -1182,18 +1421,11 @@ size_t warm_region(rpod_plan_s* P) {
     P->w_Xw = take((size_t)P->ldXw * L.lp * 4);
     P->w_c = take(WARM_K * 8);
     P->w_kstar = take(sizeof(int));
-    P->w_Xv = take((size_t)L.nP * WARM_PROBES * 8);
-    P->w_Yres = take((size_t)L.mP * WARM_PROBES * 8);
-    P->w_part = take((size_t)((it.d.m + 255) / 256) * WARM_PROBES * 8);
+    P->w_Yres = take((size_t)L.mP * L.rp * 8);
+    P->res_nchunk = (int)((it.d.m + WARM_RES_ROWS - 1) / WARM_RES_ROWS);
+    P->w_part = take((size_t)P->res_nchunk * it.d.r * 8);
     P->w_rho = take(8);
-    // split-K of Zw^T W over the n rows: splits of >= 256 rows, at most 64
-    int64_t ns = (it.d.n + 255) / 256;
-    if (ns > 64) ns = 64;
-    P->probe_split_rows = roundup((it.d.n + ns - 1) / ns, 64);
-    P->probe_nsplit = (int)((it.d.n + P->probe_split_rows - 1) / P->probe_split_rows);
-    P->w_pZp = take((size_t)P->probe_nsplit * WARM_PROJ_COLS * WARM_PROBES * 8);
-    P->w_pC = take((size_t)WARM_PROJ_COLS * WARM_PROBES * 8);
-    P->w_pM = take((size_t)L.lp * WARM_PROBES * 8);
+    P->w_rhom = take((size_t)it.d.r * 8);
     return off;
 }
 
@@ -1224,15 +1456,6 @@ rpod_status warm_build(rpod_plan_s* P, const rpod_desc* desc, rpod_warm_s* M, in
         std::vector<const Item*> cls{&P->items[0]};
         Recorder R{P, B, cls, P->programs[0]};
         R.record_warm();
-    }
-    // the fallback: plain rPOD with q_fb iterations on the same buffers
-    Item fb = P->items[0];
-    fb.d.q = q_fb;
-    P->fb_programs.assign(1, {});
-    {
-        std::vector<const Item*> cls{&fb};
-        Recorder R{P, B, cls, P->fb_programs[0]};
-        R.record();
     }
     *bytes = P->o_prog + (B.blob.size() + 255) / 256 * 256;
     if (blob_out) *blob_out = B.blob;
@@ -1504,13 +1727,81 @@ rpod_status rpod_plan_create_warm(rpod_plan* plan, const rpod_desc* desc, rpod_w
     const char* ng = std::getenv("RPOD_NO_GRAPH");
     if (!(ng && ng[0] == '1')) {
         e = capture(P, P->programs, &P->graph, &P->exec);
-        if (e == hipSuccess) e = capture(P, P->fb_programs, &P->fb_graph, &P->fb_exec);
         if (e != hipSuccess) {
             destroy_plan(P);
             return fail(RPOD_EHIP, "capturing the launch graphs failed: %s", hipGetErrorString(e));
         }
     }
     *plan = P;
+    return RPOD_OK;
+}
+
+rpod_status rpod_workspace_size_adaptive(const rpod_desc* desc, double delta, size_t* bytes) {
+    if (bytes == nullptr) return fail(RPOD_EINVAL, "bytes is NULL");
+    rpod_plan_s tmp;
+    return adaptive_build(&tmp, desc, delta, nullptr, bytes);
+}
+
+rpod_status rpod_plan_create_adaptive(rpod_plan* plan, const rpod_desc* desc, double delta, void* workspace,
+                                      size_t workspace_bytes, void* hip_stream) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (workspace == nullptr || (uintptr_t)workspace % 256 != 0)
+        return fail(RPOD_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    rpod_plan_s* P = new (std::nothrow) rpod_plan_s;
+    if (P == nullptr) return fail(RPOD_ENOMEM, "host allocation of the plan failed");
+    P->ws = static_cast<char*>(workspace);
+    P->ws_bytes = workspace_bytes;
+    P->st = static_cast<hipStream_t>(hip_stream);
+    std::vector<char> blob;
+    size_t need = 0;
+    rpod_status s = adaptive_build(P, desc, delta, &blob, &need);
+    if (s != RPOD_OK) {
+        delete P;
+        return s;
+    }
+    if (workspace_bytes < need) {
+        delete P;
+        return fail(RPOD_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+    }
+    P->host_calls.resize(1);
+    hipError_t e = hipMemsetAsync(workspace, 0, need, P->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->ws + P->o_prog, blob.data(), blob.size(), hipMemcpyHostToDevice, P->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->st);
+    if (e != hipSuccess) {
+        destroy_plan(P);
+        return fail(RPOD_EHIP, "initialising the workspace failed: %s", hipGetErrorString(e));
+    }
+    const char* ng = std::getenv("RPOD_NO_GRAPH");
+    if (!(ng && ng[0] == '1')) {
+        e = capture(P, P->programs, &P->graph, &P->exec);
+        if (e != hipSuccess) {
+            destroy_plan(P);
+            return fail(RPOD_EHIP, "capturing the launch graph failed: %s", hipGetErrorString(e));
+        }
+    }
+    *plan = P;
+    return RPOD_OK;
+}
+
+rpod_status rpod_compute_adaptive(rpod_plan plan, const void* S, uint64_t seed, void* Phi, double* sigma, void* A,
+                                  int32_t* l_used, int32_t* rank, double* residual) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    if (plan->adapt_kmax == 0) return fail(RPOD_EINVAL, "not an adaptive plan: use rpod_compute");
+    rpod_status s = compute_impl(plan, &S, &seed, &Phi, &sigma, &A);
+    if (s != RPOD_OK) return s;
+    if (l_used == nullptr && rank == nullptr && residual == nullptr) return RPOD_OK;
+    int w[8] = {0};
+    double E[ADAPT_MAX_BLOCKS] = {0}, fro = 0.0;
+    const Item& it = plan->items[0];
+    HIP_TRY(hipMemcpyAsync(w, plan->flags(it), sizeof(w), hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipMemcpyAsync(E, plan->adat(ADAPT_MAX_BLOCKS), sizeof(E), hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipMemcpyAsync(&fro, plan->at<double>(it, it.L.o_Fro), sizeof(double), hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipStreamSynchronize(plan->st));
+    const int lu = w[ADAPT_LUSED];
+    if (l_used) *l_used = lu;
+    if (rank) *rank = w[ADAPT_RANK];
+    if (residual) *residual = (lu > 0 && fro > 0.0) ? E[lu / plan->adapt_b - 1] / fro : std::nan("");
     return RPOD_OK;
 }
 
@@ -1521,20 +1812,25 @@ rpod_status rpod_compute_warm(rpod_plan plan, const void* S, const float* mu, ui
     if (mu == nullptr) return fail(RPOD_EINVAL, "mu is NULL");
     rpod_status s = compute_impl(plan, &S, &seed, &Phi, &sigma, &A, mu);
     if (s != RPOD_OK) return s;
+    if (fell_back == nullptr && rho == nullptr) return RPOD_OK;
     double rh = 0.0;
-    int fl = 0;
+    int dec = 0;
     HIP_TRY(hipMemcpyAsync(&rh, plan->wat<double>(plan->w_rho), sizeof(double), hipMemcpyDeviceToHost, plan->st));
-    HIP_TRY(hipMemcpyAsync(&fl, plan->flags(plan->items[0]), sizeof(int), hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipMemcpyAsync(&dec, plan->flags(plan->items[0]) + WARM_DECISION, sizeof(int), hipMemcpyDeviceToHost,
+                           plan->st));
     HIP_TRY(hipStreamSynchronize(plan->st));
-    const bool fb = !(rh <= plan->tol) || (fl & (RPOD_FLAG_BREAKDOWN | RPOD_FLAG_NONFINITE));
-    if (fb) {
-        if (plan->fb_exec != nullptr && !plan->timing)
-            HIP_TRY(hipGraphLaunch(plan->fb_exec, plan->st));
-        else
-            HIP_TRY(replay(plan, plan->fb_programs, plan->st));
-    }
-    if (fell_back) *fell_back = fb ? 1 : 0;
+    if (fell_back) *fell_back = dec;
     if (rho) *rho = rh;
+    return RPOD_OK;
+}
+
+rpod_status rpod_warm_residuals(rpod_plan plan, double* rho_modes) {
+    if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
+    if (plan->model == nullptr) return fail(RPOD_EINVAL, "not a warm plan");
+    if (rho_modes == nullptr) return fail(RPOD_EINVAL, "rho_modes is NULL");
+    HIP_TRY(hipMemcpyAsync(rho_modes, plan->wat<double>(plan->w_rhom), sizeof(double) * plan->items[0].d.r,
+                           hipMemcpyDeviceToHost, plan->st));
+    HIP_TRY(hipStreamSynchronize(plan->st));
     return RPOD_OK;
 }
 
@@ -1550,6 +1846,7 @@ rpod_status rpod_compute(rpod_plan plan, const void* S, uint64_t seed, void* Phi
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     if (plan->items.size() != 1) return fail(RPOD_EINVAL, "plan holds a batch: use rpod_compute_batched");
     if (plan->model != nullptr) return fail(RPOD_EINVAL, "warm plan: use rpod_compute_warm");
+    if (plan->adapt_kmax > 0) return fail(RPOD_EINVAL, "adaptive plan: use rpod_compute_adaptive");
     return compute_impl(plan, &S, &seed, &Phi, &sigma, &A);
 }
 
@@ -1559,6 +1856,7 @@ rpod_status rpod_compute_batched(rpod_plan plan, const void* const* S, const uin
     if (S == nullptr || seeds == nullptr || Phi == nullptr || sigma == nullptr || A == nullptr)
         return fail(RPOD_EINVAL, "pointer arrays must be non-NULL");
     if (plan->model != nullptr) return fail(RPOD_EINVAL, "warm plan: use rpod_compute_warm");
+    if (plan->adapt_kmax > 0) return fail(RPOD_EINVAL, "adaptive plan: use rpod_compute_adaptive");
     return compute_impl(plan, S, seeds, Phi, sigma, A);
 }
 
@@ -1585,6 +1883,8 @@ rpod_status rpod_energy(rpod_plan plan, int32_t item, double delta, double* ener
     if (item < 0 || item >= (int32_t)plan->items.size())
         return fail(RPOD_EINVAL, "item %d out of range (the plan has %zu matrices)", item, plan->items.size());
     if (!(delta > 0.0 && delta < 1.0)) return fail(RPOD_EINVAL, "delta must lie in (0, 1)");
+    if (plan->adapt_kmax > 0)
+        return fail(RPOD_EINVAL, "adaptive plan: its energy rank comes from rpod_compute_adaptive");
     const Item& it = plan->items[item];
     if (it.L.nfro == 0) return fail(RPOD_EINVAL, "the plan was made without RPOD_DESC_ENERGY");
     std::vector<double> sig(it.L.lp, 0.0);

@@ -24,10 +24,13 @@ static Group<A> mkg(const GroupLaunch<A>& L) {
     g.tstart = L.tstart;
     g.calls = L.calls;
     g.count = L.count;
+    g.skip = L.skip;
+    g.skip_mask = L.skip_mask;
     return g;
 }
 
 __global__ void k_zero_ints(Group<ZeroArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const ZeroArgs& a = g.args[it];
     const int i = (blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
@@ -94,6 +97,7 @@ __device__ __forceinline__ void omega_body(uint64_t seed, int64_t n, int l, int 
 // grouped: local tile t covers rows 256 (t % nb) .. and column pair t / nb
 template <typename T>
 __global__ void k_omega(Group<OmegaArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const OmegaArgs& a = g.args[it];
     const int t = blockIdx.x - g.tstart[it];
@@ -238,6 +242,7 @@ __device__ __forceinline__ void gram_body(const GLOBAL Tin* __restrict__ Y, int6
 // so the second and third reads of the rows come from that XCD's L2.
 template <typename Tin, int NT>
 __global__ __launch_bounds__(256) void k_gram(Group<GramArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const GramArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
@@ -261,6 +266,7 @@ __global__ __launch_bounds__(256) void k_gram(Group<GramArgs> g) {
 
 // grouped: npairs(nt) tiles of 256 elements per matrix
 __global__ __launch_bounds__(256) void k_gram_reduce(Group<GramArgs> g, int nt) {
+    if (group_skipped(g)) return;
     __shared__ double part[8][32];
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const GramArgs& ga = g.args[it];
@@ -388,6 +394,7 @@ __device__ __forceinline__ int blk(int ib, int jb) { return (jb * (jb + 1) / 2 +
 
 template <int NB>
 __global__ __launch_bounds__(64 * NB) void k_chol_blk(Group<CholArgs> gr) {
+    if (group_skipped(gr)) return;
     constexpr int LP = 16 * NB, NTHR = 64 * NB, CPL = (LP + 63) / 64, NTRI = NB * (NB + 1) / 2 * 256;
     __shared__ __attribute__((aligned(16))) double rowb[2][LP];
     __shared__ __attribute__((aligned(16))) double Rs[NTRI];  // R, upper blocks
@@ -899,6 +906,7 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
 // eight lanes per column pair: 4 lp threads per workgroup
 template <int LP>
 __global__ __launch_bounds__(4 * LP) void k_jacobi(Group<JacobiArgs> g) {
+    if (group_skipped(g)) return;
     const JacobiArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
     jacobi_chol_body<LP, 4 * LP>(a.G, a.l, a.UB, a.sig, a.flags, a.tol, nullptr, a.C, a.ldc);
 }
@@ -919,6 +927,7 @@ hipError_t launch_jacobi(int lp, const GroupLaunch<JacobiArgs>& L, hipStream_t s
 
 // M = Rinv * UB[:, :r] and Ur = UB[:, :r], both lp x rp column-major (zero pad).
 __global__ void k_lift_coef(Group<LiftArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const LiftArgs& la = g.args[it];
     const double* __restrict__ Rinv = la.Rinv;
@@ -953,6 +962,7 @@ hipError_t launch_lift_coef(const GroupLaunch<LiftArgs>& L, hipStream_t st) {
 // grouped: local tile t covers row chunk t % nchunk of column t / nchunk
 template <typename T>
 __global__ __launch_bounds__(256) void k_colmax(Group<ColmaxArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const ColmaxArgs& a = g.args[it];
     const int t = blockIdx.x - g.tstart[it];
@@ -1006,6 +1016,7 @@ __global__ __launch_bounds__(256) void k_colmax(Group<ColmaxArgs> g) {
 // keeps the largest magnitude, lowest row on ties (the same entry whatever
 // the order of the comparisons).
 __global__ __launch_bounds__(64) void k_signs(Group<SignArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SignArgs& a = g.args[it];
     const int c = blockIdx.x - g.tstart[it];
@@ -1045,6 +1056,7 @@ hipError_t launch_signs(int tphi, const GroupLaunch<ColmaxArgs>& C, const GroupL
 // thread); outputs from the call table
 template <typename T>
 __global__ void k_fin_phi(Group<FinArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const FinArgs& a = g.args[it];
     const int t = blockIdx.x - g.tstart[it];
@@ -1070,6 +1082,7 @@ __global__ void k_fin_phi(Group<FinArgs> g) {
 
 template <typename T>
 __global__ void k_fin_a(Group<FinArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const FinArgs& a = g.args[it];
     const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
@@ -1095,6 +1108,66 @@ hipError_t launch_finalize(int tphi, const GroupLaunch<FinArgs>& P, const GroupL
         hipLaunchKernelGGL(k_fin_phi<float>, dim3(P.tiles), dim3(256), 0, st, mkg(P));
         hipLaunchKernelGGL(k_fin_a<float>, dim3(A.tiles), dim3(256), 0, st, mkg(A));
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive rank: identity factor, stopping decision, energy rank
+// ---------------------------------------------------------------------------
+__global__ void k_eye(Group<EyeArgs> g) {
+    if (group_skipped(g)) return;
+    const int it = group_item(g.tstart, g.count, blockIdx.x);
+    const EyeArgs& a = g.args[it];
+    const int e = (blockIdx.x - g.tstart[it]) * 256 + threadIdx.x;
+    if (e < a.lp * a.lp) a.R[e] = (e / a.lp == e % a.lp) ? 1.0 : 0.0;
+}
+
+hipError_t launch_eye(const GroupLaunch<EyeArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_eye, dim3(L.tiles), dim3(256), 0, st, mkg(L));
+    return hipGetLastError();
+}
+
+__global__ void k_adapt_decide(Group<AdaptDecideArgs> g) {
+    if (group_skipped(g)) return;
+    const AdaptDecideArgs& a = g.args[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const double f = *a.fro2;
+    double E = f;
+    for (int j = 0; j <= a.i; ++j) E -= a.cap[j];
+    a.E[a.i] = E;
+    const bool stop = E <= (1.0 - a.delta) * f || !(E == E) || a.i + 1 >= a.kmax;
+    if (stop) {
+        a.flags[ADAPT_STOP] |= 1 << (a.i + 1);
+        a.flags[ADAPT_LUSED] = (a.i + 1) * a.b;
+    } else {
+        a.flags[ADAPT_ACTIVE] |= 1 << (a.i + 1);
+    }
+}
+
+hipError_t launch_adapt_decide(const GroupLaunch<AdaptDecideArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_adapt_decide, dim3(L.count), dim3(64), 0, st, mkg(L));
+    return hipGetLastError();
+}
+
+__global__ void k_adapt_rank(Group<AdaptRankArgs> g) {
+    if (group_skipped(g)) return;
+    const AdaptRankArgs& a = g.args[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const double f = *a.fro2;
+    double cum = 0.0;
+    int r = -1;
+    for (int k = 0; k < a.l; ++k) {
+        cum += __dmul_rn(a.sig[k], a.sig[k]);  // no fused multiply-add: the host's rounding
+        if (cum / f >= a.delta) {
+            r = k + 1;
+            break;
+        }
+    }
+    a.flags[ADAPT_RANK] = r;
+}
+
+hipError_t launch_adapt_rank(const GroupLaunch<AdaptRankArgs>& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_adapt_rank, dim3(L.count), dim3(64), 0, st, mkg(L));
     return hipGetLastError();
 }
 

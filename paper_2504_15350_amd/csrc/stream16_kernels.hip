@@ -171,6 +171,7 @@ __device__ __forceinline__ void sx16_body(const GLOBAL unsigned short* __restric
 
 template <typename T16, int NT, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_sx16(Group<SxArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
@@ -318,6 +319,7 @@ __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restri
 // splits and a split's Q rows are fetched into one L2 only.
 template <typename T16, int NT, bool VEC, bool LO, int G>
 __global__ __launch_bounds__(256, 2) void k_stq16(Group<StqArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const StqArgs& a = g.args[it];
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
@@ -331,6 +333,7 @@ __global__ __launch_bounds__(256, 2) void k_stq16(Group<StqArgs> g) {
 // Split an FP32 tall matrix into 16-bit hi = round(q) and lo = round(q - hi).
 template <typename T16>
 __global__ void k_split16(Group<SplitArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SplitArgs& sa = g.args[it];
     const GLOBAL float* __restrict__ Q = gbl(sa.Q);
@@ -359,6 +362,8 @@ static Group<A> mkgroup16(const GroupLaunch<A>& L) {
     g.tstart = L.tstart;
     g.calls = L.calls;
     g.count = L.count;
+    g.skip = L.skip;
+    g.skip_mask = L.skip_mask;
     return g;
 }
 

@@ -221,6 +221,7 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
 template <int NT, bool VEC, bool EN = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1, 2))) void k_sx_e6(
     Group<SxArgs> g) {
+    if (group_skipped(g)) return;
     __shared__ __attribute__((aligned(16))) unsigned short xs[2 * 3 * 16 * NT * E6_XLD];
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
@@ -386,6 +387,7 @@ __device__ __forceinline__ void stq_e6_body(const GLOBAL float* __restrict__ S, 
 template <int NT, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1, 2))) void k_stq_e6(
     Group<StqArgs> g) {
+    if (group_skipped(g)) return;
     __shared__ __attribute__((aligned(16))) float ss[E6_HB * E6_LDS];
     __shared__ __attribute__((aligned(16))) unsigned short qs[3 * 16 * NT * E6_LDQ];
     const int it = group_item(g.tstart, g.count, blockIdx.x);
@@ -409,6 +411,8 @@ static Group<A> mke6(const GroupLaunch<A>& L) {
     g.tstart = L.tstart;
     g.calls = L.calls;
     g.count = L.count;
+    g.skip = L.skip;
+    g.skip_mask = L.skip_mask;
     return g;
 }
 

@@ -113,6 +113,7 @@ __device__ __forceinline__ void sx_body(const GLOBAL Tin* S, int64_t ldS, int64_
 
 template <typename Tin, typename Tout, int NT, bool VEC, bool UPPER>
 __global__ __launch_bounds__(256) void k_sx(Group<SxArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(256) void k_sx(Group<SxArgs> g) {
 // Y (FP64) = S X with X in FP64 and S of any storage type, FP64 matrix cores.
 template <typename Tin, int NT, bool VEC>
 __global__ __launch_bounds__(256) void k_sx_wide(Group<SxArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
@@ -191,6 +193,7 @@ __device__ __forceinline__ void stq_body(const GLOBAL Tin* __restrict__ S, int64
 // grouped launch: local tile t covers column block t % ncb of split t / ncb
 template <typename Tin, int NT, bool VEC>
 __global__ __launch_bounds__(256) void k_stq(Group<StqArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const StqArgs& a = g.args[it];
     const int t = blockIdx.x - g.tstart[it];
@@ -298,6 +301,7 @@ __device__ __forceinline__ void stq32_body(const GLOBAL float* __restrict__ S, i
 
 template <int NT, bool VEC, int HBU>
 __global__ __launch_bounds__(256) void k_stq32(Group<StqArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const StqArgs& a = g.args[it];
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
@@ -307,6 +311,7 @@ __global__ __launch_bounds__(256) void k_stq32(Group<StqArgs> g) {
 
 // out[e] = sum of the nsplit slabs in FP64, fixed order; 256 elements per workgroup
 __global__ void k_reduce_slabs(Group<ReduceArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const ReduceArgs& a = g.args[it];
     const int64_t e = (int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x;
@@ -335,18 +340,20 @@ __global__ void k_reduce_slabs(Group<ReduceArgs> g) {
 // launchers
 // ---------------------------------------------------------------------------
 template <typename A>
-static Group<A> mkgroup(const A* args, const int* ts, int count, const CallDesc* calls) {
+static Group<A> mkgroup(const GroupLaunch<A>& L) {
     Group<A> g;
-    g.args = args;
-    g.tstart = ts;
-    g.calls = calls;
-    g.count = count;
+    g.args = L.args;
+    g.tstart = L.tstart;
+    g.calls = L.calls;
+    g.count = L.count;
+    g.skip = L.skip;
+    g.skip_mask = L.skip_mask;
     return g;
 }
 
 template <typename Tin, typename Tout, int NT>
 static hipError_t sx_nt(const GroupLaunch<SxArgs>& L, bool vec, bool upper, hipStream_t st) {
-    const Group<SxArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
+    const Group<SxArgs> g = mkgroup(L);
     if (upper)
         hipLaunchKernelGGL((k_sx<Tin, Tout, NT, true, true>), dim3(L.tiles), dim3(256), 0, st, g);
     else if (vec)
@@ -369,7 +376,7 @@ static hipError_t sx_dispatch(int nt, const GroupLaunch<SxArgs>& L, bool vec, bo
 
 template <typename Tin, int NT>
 static hipError_t sxw_nt(const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st) {
-    const Group<SxArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
+    const Group<SxArgs> g = mkgroup(L);
     if (vec)
         hipLaunchKernelGGL((k_sx_wide<Tin, NT, true>), dim3(L.tiles), dim3(256), 0, st, g);
     else
@@ -407,7 +414,7 @@ hipError_t launch_sx(int tin, int tout, int nt, bool vec, bool upper, const Grou
 
 template <typename Tin, int NT>
 static hipError_t stq_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
-    const Group<StqArgs> g = mkgroup(L.args, L.tstart, L.count, L.calls);
+    const Group<StqArgs> g = mkgroup(L);
     if constexpr (sizeof(Tin) == 4) {  // FP32: the LDS-staged kernel, two column tiles per wave
         if (vec)
             hipLaunchKernelGGL((k_stq32<NT, true, 2>), dim3(L.tiles), dim3(256), 0, st, g);
@@ -442,7 +449,7 @@ hipError_t launch_stq(int tin, int nt, bool vec, const GroupLaunch<StqArgs>& L, 
 }
 
 hipError_t launch_reduce_slabs(const GroupLaunch<ReduceArgs>& L, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_slabs, dim3(L.tiles), dim3(256), 0, st, mkgroup(L.args, L.tstart, L.count, L.calls));
+    hipLaunchKernelGGL(k_reduce_slabs, dim3(L.tiles), dim3(256), 0, st, mkgroup(L));
     return hipGetLastError();
 }
 

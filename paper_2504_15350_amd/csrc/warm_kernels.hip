@@ -19,6 +19,8 @@ static Group<A> mkw(const GroupLaunch<A>& L) {
     g.tstart = L.tstart;
     g.calls = L.calls;
     g.count = L.count;
+    g.skip = L.skip;
+    g.skip_mask = L.skip_mask;
     return g;
 }
 
@@ -277,6 +279,7 @@ hipError_t launch_block_sumsq(const double* src, int64_t sa, int64_t sb, int r, 
 // plan steps (grouped)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_warm_plan_fwd(Group<WarmFwdArgs> g) {
+    if (group_skipped(g)) return;
     const WarmFwdArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
     const GLOBAL float* P = gbl(a.params);
     const int j = threadIdx.x;
@@ -307,6 +310,7 @@ hipError_t launch_warm_plan_forward(const GroupLaunch<WarmFwdArgs>& L, hipStream
 //   iters 2: Z[e][i] = c_e sum_b G_W[e][b] c_b G_W[b][k* r + i]
 // (G_W symmetric: read as G_W[b][e], coalesced over e).
 __global__ __launch_bounds__(256) void k_warm_z(Group<WarmZArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const WarmZArgs& a = g.args[it];
     const int t = blockIdx.x - g.tstart[it];
@@ -345,71 +349,70 @@ hipError_t launch_warm_z(const GroupLaunch<WarmZArgs>& L, hipStream_t st) {
     return hipGetLastError();
 }
 
-// A-posteriori residual of the range basis Q = Q1 R^-1 (Halko, Martinsson and
-// Tropp 2011, eq. 4.3): with Y = S W for d Gaussian probes and M = R^-1 Q^T Y,
-// (I - Q Q^T) S W = Y - Q1 M. One thread per row: the d residual entries of
-// the row from its Q1 row and M (staged in LDS), squares summed over the
-// workgroup's 256 rows in a fixed order.
-__global__ __launch_bounds__(256) void k_warm_probe_res(Group<ProbeResArgs> g) {
+// Residual of each returned singular triplet (sigma_k, phi_k, v_k), v_k =
+// a_k / sigma_k with a_k the k-th coefficient row: S v_k - sigma_k phi_k =
+// (S a_k - sigma_k^2 phi_k) / sigma_k, and Y = S A^T comes from an FP64
+// product. Wave w of a workgroup takes the modes k = w mod 4; each lane sums
+// the squares over rows lane, lane + 64, ... of the chunk, then a fixed
+// butterfly over the wave. The error of sigma_k is at most sigma_k rho_k
+// (the pair is an approximate eigenpair of the symmetric embedding
+// [0 S; S^T 0] with residual norm sigma_k rho_k).
+__global__ __launch_bounds__(256) void k_warm_mode_res(Group<ModeResArgs> g) {
+    if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
-    const ProbeResArgs& a = g.args[it];
-    const int ch = blockIdx.x - g.tstart[it];
-    __shared__ double Ms[WARM_MAXLP * WARM_PROBES];
-    __shared__ double red[WARM_PROBES][256];
-    for (int e = threadIdx.x; e < a.lp * a.d; e += 256) Ms[e] = a.M[e];
-    __syncthreads();
-    const int64_t i = (int64_t)ch * 256 + threadIdx.x;
-    double acc[WARM_PROBES];
-#pragma unroll
-    for (int c = 0; c < WARM_PROBES; ++c) acc[c] = 0.0;
-    if (i < a.m) {
-        const GLOBAL double* Y = gbl(a.Y);
-#pragma unroll
-        for (int c = 0; c < WARM_PROBES; ++c) acc[c] = c < a.d ? Y[(int64_t)c * a.ldY + i] : 0.0;
-        const GLOBAL float* Q = gbl(a.Q1);
-        for (int k = 0; k < a.lp; ++k) {
-            const double q = (double)Q[(int64_t)k * a.ldQ + i];
-#pragma unroll
-            for (int c = 0; c < WARM_PROBES; ++c) acc[c] = fma(-q, Ms[c * a.lp + k], acc[c]);
+    const ModeResArgs& a = g.args[it];
+    const int64_t i0 = (int64_t)(blockIdx.x - g.tstart[it]) * a.rows;
+    const int64_t i1 = i0 + a.rows < a.m ? i0 + a.rows : a.m;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const GLOBAL double* Y = gbl(a.Y);
+    const GLOBAL float* Phi = gbl(a.Phi);
+    for (int k = wave; k < a.r; k += 4) {
+        const double s2 = a.sig[k] * a.sig[k];
+        double acc = 0.0;
+        for (int64_t i = i0 + lane; i < i1; i += 64) {
+            const double d = Y[(int64_t)k * a.ldY + i] - s2 * (double)Phi[(int64_t)k * a.ldP + i];
+            acc = fma(d, d, acc);
         }
-    }
 #pragma unroll
-    for (int c = 0; c < WARM_PROBES; ++c) red[c][threadIdx.x] = acc[c] * acc[c];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-#pragma unroll
-            for (int c = 0; c < WARM_PROBES; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
-        }
-        __syncthreads();
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) a.part[(int64_t)(blockIdx.x - g.tstart[it]) * a.r + k] = acc;
     }
-    if ((int)threadIdx.x < a.d) a.part[(int64_t)ch * a.d + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_warm_probe_final(Group<ProbeFinalArgs> g) {
-    const ProbeFinalArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
-    __shared__ double nr[WARM_PROBES];
-    if ((int)threadIdx.x < a.d) {
+__global__ __launch_bounds__(128) void k_warm_mode_final(Group<ModeResFinalArgs> g) {
+    if (group_skipped(g)) return;
+    const ModeResFinalArgs& a = g.args[blockIdx.x];  // one workgroup per matrix
+    __shared__ double rk[WARM_MAXLP];
+    const int k = threadIdx.x;
+    if (k < a.r) {
         double s = 0.0;
-        for (int ch = 0; ch < a.nchunk; ++ch) s += a.part[(int64_t)ch * a.d + threadIdx.x];
-        nr[threadIdx.x] = sqrt(s);
+        for (int c = 0; c < a.nchunk; ++c) s += a.part[(int64_t)c * a.r + k];
+        const double sg = a.sig[k];
+        rk[k] = sqrt(s) / (sg * sg);
+        a.rho_modes[k] = rk[k];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double mx = 0.0;
-        for (int c = 0; c < a.d; ++c) mx = (nr[c] > mx || nr[c] != nr[c]) ? nr[c] : mx;
-        const double rho = WARM_HMT_FACTOR * mx / a.sig[0];
+        bool bad = false;
+        for (int c = 0; c < a.r; ++c) {
+            bad = bad || !(rk[c] == rk[c]) || rk[c] > 1.0e308;
+            mx = rk[c] > mx ? rk[c] : mx;
+        }
+        const double rho = bad ? __builtin_nan("") : mx;
         *a.rho = rho;
-        if (!(rho <= a.tol)) atomicOr(a.flags, DEV_FLAG_RESIDUAL);
+        const bool reject = !(rho <= a.tol);
+        *a.decision = reject ? 1 : 0;
+        if (reject) atomicOr(a.flags, DEV_FLAG_RESIDUAL);
     }
 }
 
-hipError_t launch_warm_probe_res(const GroupLaunch<ProbeResArgs>& P, const GroupLaunch<ProbeFinalArgs>& F,
-                                 hipStream_t st) {
-    hipLaunchKernelGGL(k_warm_probe_res, dim3(P.tiles), dim3(256), 0, st, mkw(P));
+hipError_t launch_warm_mode_res(const GroupLaunch<ModeResArgs>& P, const GroupLaunch<ModeResFinalArgs>& F,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_warm_mode_res, dim3(P.tiles), dim3(256), 0, st, mkw(P));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_warm_probe_final, dim3(F.count), dim3(64), 0, st, mkw(F));
+    hipLaunchKernelGGL(k_warm_mode_final, dim3(F.count), dim3(128), 0, st, mkw(F));
     return hipGetLastError();
 }
 

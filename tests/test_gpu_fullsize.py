@@ -105,3 +105,39 @@ def test_bf16_mixed_full_size_against_oracle():
     assert np.all(np.diff(s) <= 0)
     assert res["sigma"] <= 1e-3 and res["orth"] <= 1e-5
     assert res.get("sin", 0.0) <= 1e-3 and res.get("A", 0.0) <= 1e-3
+
+
+@pytest.mark.parametrize("dtype,p", [(torch.float32, 20), (torch.bfloat16, 75)])
+def test_paper_shape_wide(dtype, p):
+    """The paper's own shape, wide: S 8192 x 90225 (64 x 128 cells, 225
+    parameter blocks x 401 steps), r = 10, q = 1, psi-like field (beta 2):
+    against O2 on the same stored values with the same rounded sketch."""
+    nx, ny, n, r, q, seed = 64, 128, 90225, 10, 1, 17
+    m = nx * ny
+    say(f"[paper wide] m={m} n={n} r={r} p={p} q={q} dtype={dtype} seed={seed}")
+    g = synth.fourier_field_device(nx, ny, n, beta=2.0, seed=seed, dtype=dtype, device=DEV)
+    Sd = g["St"]
+    plan = rp.Plan(m, n, r, p, q, dtype=dtype, device=DEV)
+    Phi_t, sig, A_t = plan.compute(Sd, seed)
+    torch.cuda.synchronize()
+    flags = plan.last_flags
+    plan.close()
+    Phi = Phi_t.double().cpu().numpy().T
+    A = A_t.double().cpu().numpy().T
+    s = sig.cpu().numpy()
+    S64 = Sd.double().cpu().numpy().T          # the stored values, exactly
+    del Sd, g
+    om = philox.gaussian_sketch(seed, n, r + p)
+    om = torch.from_numpy(om.astype(np.float32)).to(dtype).double().numpy()
+    P2, s2, A2, ex = orpod.rpod_stable(S64, r, om, q)
+    res = dict(sigma=metrics.sigma_rel_err(s, s2), orth=metrics.orth_err(Phi))
+    gap = metrics.gap_ok(ex["ritz"], r)
+    if gap:
+        res["sin"] = metrics.sin_theta_max(Phi, P2)
+        res["A"] = metrics.lowrank_rel_diff(Phi, A, P2, A2)
+    say(f"[paper wide] flags={flags} gap={gap} {res}")
+    tol = dict(sigma=1e-5, sin=1e-4, A=1e-4) if dtype == torch.float32 else dict(sigma=1e-3, sin=1e-3, A=1e-3)
+    assert flags == 0
+    assert np.all(np.diff(s) <= 0)
+    assert res["sigma"] <= tol["sigma"] and res["orth"] <= 1e-5, res
+    assert gap and res["sin"] <= tol["sin"] and res["A"] <= tol["A"], res

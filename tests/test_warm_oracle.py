@@ -108,39 +108,6 @@ def test_argmax_takes_lowest_index_on_ties():
     assert ow.argmax_first([0.1, 0.4, 0.4, 0.1]) == 1
 
 
-def test_probe_residual_is_zero_when_q_spans_the_range():
-    """Exact rank-10 S and Q = its left singular vectors: (I - Q Q^T) S = 0."""
-    g = synth.lowrank_exp(500, 80, decay=0.1, noise_std=0.0, seed=11)
-    U, s, Vt = np.linalg.svd(g["St"].T, full_matrices=False)
-    S = (U[:, :10] * s[:10]) @ Vt[:10]
-    probes = philox.gaussian_sketch(3, 80, ow.PROBES, stream=1)
-    assert ow.probe_residual(S, U[:, :10], s[0], probes) < 1e-13
-
-
-def test_probe_residual_brackets_the_true_residual():
-    """Q = the k leading left singular vectors: ||(I - QQ^T) S||_2 = sigma_{k+1}.
-    The estimate is at least sigma_{k+1} / sigma_1 (HMT eq. 4.3, failure
-    probability 10^-16 with 16 probes) and at most the factor times
-    sigma_{k+1} max_i ||w_i|| / sigma_1 (a deterministic bound)."""
-    g = synth.lowrank_exp(600, 120, decay=0.08, noise_std=1e-3, seed=21)
-    S = g["St"].T
-    U, s, Vt = np.linalg.svd(S, full_matrices=False)
-    probes = philox.gaussian_sketch(5, 120, ow.PROBES, stream=1)
-    wmax = np.max(np.linalg.norm(probes, axis=0))
-    for k in (5, 20, 40):
-        rho = ow.probe_residual(S, U[:, :k], s[0], probes)
-        true = s[k] / s[0]
-        assert true <= rho <= ow.HMT_FACTOR * true * wmax * (1 + 1e-12)
-
-
-def test_probes_are_independent_of_the_sketch():
-    """Stream 1 differs from the sketch stream 0 of the same seed."""
-    a = philox.gaussian_sketch(7, 50, 16)
-    b = philox.gaussian_sketch(7, 50, 16, stream=1)
-    assert np.abs(np.corrcoef(a.ravel(), b.ravel())[0, 1]) < 0.1
-    assert not np.allclose(a, b)
-
-
 def test_warm_start_with_the_exact_basis_equals_exact_pod():
     """W = the exact leading basis (one-hot c on it): q = 0 already gives O1."""
     fam = synth.ParamFamily(32, 64, K=100)
@@ -153,14 +120,13 @@ def test_warm_start_with_the_exact_basis_equals_exact_pod():
     c = np.full(8, 1e-30)
     c[2] = 1.0
     om = np.random.default_rng(15).standard_normal((300, 10))
-    probes = philox.gaussian_sketch(16, 300, ow.PROBES, stream=1)
-    Phi, s, A, ex = ow.warm_rpod(S, bases, c / c.sum(), 2, r, om, q=0, probes=probes)
+    Phi, s, A, ex = ow.warm_rpod(S, bases, c / c.sum(), 2, r, om, q=0)
     P1, s1, A1, _ = pod.pod_svd(S, r)
     assert metrics.sigma_rel_err(s, s1) < 1e-12
     assert metrics.sin_theta_max(Phi, P1) < 1e-10
-    # the l = 30 dimensional range basis cannot beat sigma_31 (S has rank ~100)
-    sfull = np.linalg.svd(S, compute_uv=False)
-    assert sfull[30] / sfull[0] <= ex["rho"] < np.inf
+    # the returned triplets are exact singular triplets: every residual vanishes
+    # although the range basis misses most of S (rank ~100 > l = 30)
+    assert ex["rho"] < 1e-10
 
 
 def test_parameter_family_is_smooth_and_orthonormal():
