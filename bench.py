@@ -418,22 +418,27 @@ def warm_block(dev, reps):
                  frac_within_1e3_leading=float(np.mean(np.array(errs_ok) <= 1e-3)))
         if kind != "plain":
             rho = np.array([r_[2] for r_ in res])
-            d.update(continued=int(sum(bool(r_[1]) for r_ in res)), tol=tol, q_fallback=q_fb,
-                     rho_median=float(np.median(rho)), rho_max=float(np.max(rho)))
+            d.update(continued=int(sum(bool(r_[1]) for r_ in res)), tol=tol if np.isfinite(tol) else "unchecked",
+                     q_fallback=q_fb)
+            if np.all(np.isfinite(rho)):
+                d.update(rho_median=float(np.median(rho)), rho_max=float(np.max(rho)))
         return d
 
+    inf = float("inf")
     out = {"plain_fp32_q2": run("plain", tests), "plain_fp32_q1": run("plain", tests, 1),
-           "warm_fp32_q0_accept_all": run("warm", tests, 0),
-           "warm_fp32_q1_accept_all": run("warm", tests, 1),
+           "warm_fp32_q0_unchecked": run("warm", tests, 0, inf),
+           "warm_fp32_q1_unchecked": run("warm", tests, 1, inf),
+           "warm_fp32_q1_checked_accept_all": run("warm", tests, 1),
+           "warm_fp32_q1_tol1e-2_cont1": run("warm", tests, 1, 1e-2, 1),
            "warm_fp32_q0_tol1e-2_cont1": run("warm", tests, 0, 1e-2, 1),
-           "warm_fp32_q0_tol1e-3_cont1": run("warm", tests, 0, 1e-3, 1),
            "warm_fp32_q0_tol1e-3_cont2": run("warm", tests, 0, 1e-3, 2)}
     tests16 = [St.to(torch.bfloat16) for St in tests]
     del tests
     torch.cuda.empty_cache()
     out["plain_bf16_q2"] = run("plain", tests16)
-    out["warm_bf16_q0_accept_all"] = run("warm", tests16, 0)
-    out["warm_bf16_q0_tol1e-2_cont1"] = run("warm", tests16, 0, 1e-2, 1)
+    out["plain_bf16_q1"] = run("plain", tests16, 1)
+    out["warm_bf16_q1_unchecked"] = run("warm", tests16, 1, inf)
+    out["warm_bf16_q1_tol1e-2_cont1"] = run("warm", tests16, 1, 1e-2, 1)
     del tests16
     model.close()
     plain.close()

@@ -384,6 +384,9 @@ rpod_status rpod_warm_predict(rpod_warm model, const float* mu, int32_t N, float
  * from the warm range basis Q and steps 5-7 run again, overwriting the
  * outputs (RPOD_FLAG_RESIDUAL is set in the status word). The decision is
  * taken on the device inside the same launch graph: no host round trip.
+ * tol = +infinity accepts every warm result without the check: the residual
+ * product (one more pass over S, with FP64 arithmetic) is not run, rho is
+ * reported as NaN and q_fallback is unused.
  * A breakdown in either part is reported as by rpod_compute. The model must
  * outlive the plan; its weights and bank are read at every call. */
 rpod_status rpod_workspace_size_warm(const rpod_desc* desc, rpod_warm model, int32_t q_fallback, size_t* bytes);
@@ -398,7 +401,8 @@ rpod_status rpod_compute_warm(rpod_plan plan, const void* S, const float* mu, ui
                               double* sigma, void* A, int32_t* fell_back, double* rho);
 
 /* rho_modes: host, r doubles: the rho_k of the warm result of the last
- * compute call. Synchronises the plan's stream. */
+ * compute call. Synchronises the plan's stream. RPOD_EINVAL for a plan made
+ * with tol = +infinity (nothing is computed). */
 rpod_status rpod_warm_residuals(rpod_plan plan, double* rho_modes);
 
 /* ------------------------------------------------------------------------

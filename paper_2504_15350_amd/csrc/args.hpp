@@ -34,6 +34,7 @@ struct SxArgs {  // Y = S X
     int call;  // >= 0: S comes from call table entry `call`
     int cmax;  // > 0: only output columns < cmax are stored
     double* fpart;  // FP32 first pass with the energy report: per-tile sums of S's squares
+    int64_t col0;   // the product starts at column col0 of S (split-K over the columns; X already offset)
 };
 
 struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)
@@ -51,9 +52,10 @@ struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)
 struct ReduceArgs {  // out = sum of nsplit slabs
     const void* Zp;  // FP64 slabs, or FP32 ones when f32 is set
     int64_t count;
-    double* out;
+    void* out;       // FP64, or FP32 when out32 is set
     int nsplit;
     int f32;
+    int out32;
 };
 
 // Fluctuation snapshots (Sec. 4.1): S' = S - M E^T / N with M the block sums

@@ -65,6 +65,9 @@ struct Layout {
     int tin, tacc;
     int nsplit, ncb_lo;
     int64_t split_rows;
+    // split-K over the columns for S X on short, wide matrices (1: none)
+    int nsplit_x;
+    int64_t split_cols_x;
     // FP64 small SVD: C = Zw^T Q2 by split-K over the n rows (contiguous splits)
     int nsplit_c;
     int64_t split_rows_c;
@@ -75,7 +78,7 @@ struct Layout {
     int K, lpa, nta, ncc;
     int64_t N, cchunk;
     // byte offsets into the matrix's workspace region
-    size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
+    size_t o_X, o_Y, o_Q1, o_Qh, o_Ql, o_Zp, o_Yp, o_Zt, o_Zw, o_Zw2, o_Gpart, o_G;
     size_t o_R64[3], o_R32[3], o_UB, o_sig, o_M64, o_M32, o_Ur, o_Phi, o_At, o_pval, o_pidx, o_signs;
     size_t o_Cb, o_Cp, o_Pc;  // centring: E^T X / N, slabs of Msum^T Q1 and their sum
     size_t o_Fp, o_Fro;       // energy: partial sums of ||S||_F^2 and the sum
@@ -154,6 +157,18 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
         L.split_rows_c = roundup((d->n + nsc - 1) / nsc, 64);
         L.nsplit_c = (int)((d->n + L.split_rows_c - 1) / L.split_rows_c);
     }
+    {   // S X runs one workgroup per 256 rows; with fewer than 512 such tiles (a
+        // single plan) the columns are split so that about 2048 workgroups run,
+        // each split at least 1024 columns, the slabs summed afterwards
+        const int64_t rt = L.mP / 256;
+        int64_t nsx = 1;
+        if (rt < 512 && wg_target >= 2048) {
+            nsx = std::min<int64_t>((2048 + rt - 1) / rt, std::max<int64_t>(1, d->n / 1024));
+            nsx = std::min<int64_t>(nsx, 128);
+        }
+        L.split_cols_x = roundup((d->n + nsx - 1) / nsx, 32);
+        L.nsplit_x = (int)((d->n + L.split_cols_x - 1) / L.split_cols_x);
+    }
     int64_t nc = d->m / 2048;
     L.nchunk = (int)(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
     L.N = d->block_cols;
@@ -177,6 +192,7 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.o_Qh = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Ql = take(s16 ? (size_t)L.mP * L.lp * 2 : 0);
     L.o_Zp = take((size_t)L.nsplit * L.nP * L.lp * (L.tin == DT_F64 ? 8 : 4));  // FP32 slabs off the FP64 path
+    L.o_Yp = take(L.nsplit_x > 1 ? (size_t)L.nsplit_x * L.mP * L.lpa * sa : 0);   // slabs of a split S X
     L.o_Zt = take((size_t)L.nP * L.lp * 8);
     L.o_Zw = take((size_t)L.nP * L.lp * 8);
     L.o_Zw2 = take((size_t)L.nP * L.lp * 8);
@@ -292,23 +308,28 @@ struct rpod_plan_s {
     double delta = 0.0;
     size_t o_adapt = 0;
 
+    // Workspace addresses. The recorder also runs without a workspace (to size
+    // one), so addresses are formed as integers: no arithmetic on a null pointer.
     template <typename T>
-    T* wat(size_t off) const { return reinterpret_cast<T*>(ws + o_warm + off); }
-    double* adat(size_t k) const { return reinterpret_cast<double*>(ws + o_adapt) + k; }
-    int* flags(const Item& it) const { return reinterpret_cast<int*>(ws + o_flags) + FLAG_INTS * it.idx; }
+    T* addr(size_t off) const { return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(ws) + off); }
     template <typename T>
-    T* at(const Item& it, size_t off) const { return reinterpret_cast<T*>(ws + it.off + off); }
-    CallDesc* calls() const { return reinterpret_cast<CallDesc*>(ws + o_calls); }
+    T* wat(size_t off) const { return addr<T>(o_warm + off); }
+    double* adat(size_t k) const { return addr<double>(o_adapt + k * sizeof(double)); }
+    int* flags(const Item& it) const { return flag(it, 0); }
+    int* flag(const Item& it, int k) const { return addr<int>(o_flags + sizeof(int) * (FLAG_INTS * it.idx + k)); }
+    template <typename T>
+    T* at(const Item& it, size_t off) const { return addr<T>(it.off + off); }
+    CallDesc* calls() const { return addr<CallDesc>(o_calls); }
     template <typename A>
     GroupLaunch<A> gl(const Step& s, bool second) const {
         GroupLaunch<A> g;
-        g.args = reinterpret_cast<const A*>(ws + o_prog + (second ? s.a2 : s.a1));
-        g.tstart = reinterpret_cast<const int*>(ws + o_prog + (second ? s.t2 : s.t1));
+        g.args = addr<const A>(o_prog + (second ? s.a2 : s.a1));
+        g.tstart = addr<const int>(o_prog + (second ? s.t2 : s.t1));
         g.calls = calls();
         g.count = s.count;
         g.tiles = second ? s.tiles2 : s.tiles1;
         if (s.skip_word >= 0) {  // plans with conditional steps hold one matrix
-            g.skip = reinterpret_cast<const int*>(ws + o_flags) + s.skip_word;
+            g.skip = addr<const int>(o_flags + sizeof(int) * s.skip_word);
             g.skip_mask = s.skip_mask;
         }
         return g;
@@ -407,14 +428,41 @@ struct Recorder {
             s.flops += 2.0 * it->d.m * it->d.n * it->L.l;
         }
         s.energy = first && f32 && L0().nfro > 0;  // FP32 energy report: sums of squares from this pass
-        std::vector<SxArgs> args = each([&](const Item& it) {
-            SxArgs a{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, it.L.o_X), it.L.nP,
-                     P->at<char>(it, it.L.o_Y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
-            if (s.energy) a.fpart = P->at<double>(it, it.L.o_Fp);
-            return a;
-        });
-        B.add(s, args, tiles([](const Item& it) { return (int)(it.L.mP / 256); }));
+        // one record per matrix, or per column split (short, wide matrices) into
+        // slabs that a reduction then sums into Y; the energy pass is not split
+        std::vector<SxArgs> args;
+        std::vector<int> t;
+        std::vector<ReduceArgs> red;
+        std::vector<int> rt;
+        const int w = 16 * s.nt;  // columns of Y written
+        for (const Item* itp : C) {
+            const Item& it = *itp;
+            const int ns = s.energy ? 1 : it.L.nsplit_x;
+            const size_t sa = dt_size(it.L.tacc);
+            for (int k = 0; k < ns; ++k) {
+                const int64_t c0 = (int64_t)k * it.L.split_cols_x;
+                const int64_t nc = ns == 1 ? it.d.n : std::min<int64_t>(it.L.split_cols_x, it.d.n - c0);
+                const size_t y = ns == 1 ? it.L.o_Y : it.L.o_Yp + (size_t)k * it.L.mP * w * sa;
+                SxArgs a{nullptr, it.d.ld, it.d.m, nc, P->at<char>(it, it.L.o_X + (size_t)c0 * dt_size(it.L.tin)),
+                         it.L.nP, P->at<char>(it, y), it.L.mP, it.L.mP, nullptr, 0, it.idx};
+                a.col0 = c0;
+                if (s.energy) a.fpart = P->at<double>(it, it.L.o_Fp);
+                args.push_back(a);
+                t.push_back((int)(it.L.mP / 256));
+            }
+            if (ns > 1) {
+                const int o32 = it.L.tacc != DT_F64 ? 1 : 0;
+                red.push_back(ReduceArgs{P->at<char>(it, it.L.o_Yp), it.L.mP * w, P->at<char>(it, it.L.o_Y), ns, o32, o32});
+                rt.push_back((int)((it.L.mP * w + 255) / 256));
+            }
+        }
+        B.add(s, args, t);
         out.push_back(s);
+        if (!red.empty()) {
+            Step r{K_REDUCE};
+            B.add(r, red, rt);
+            out.push_back(r);
+        }
     }
     // pass over S: slabs of S^T Q1 (lo: Q1 carried as hi + lo on 16-bit paths), then their sum
     // into dst (Zt; Zw directly when Q1 needs no further factor)
@@ -506,7 +554,7 @@ struct Recorder {
         s.tin = L0().tacc;
         B.add(s, each([&](const Item& it) {
                   const size_t so = dt_size(it.L.tacc);
-                  return CrossArgs{P->at<char>(it, it.L.o_Y) + (size_t)it.L.lp * it.L.mP * so,
+                  return CrossArgs{P->at<char>(it, it.L.o_Y + (size_t)it.L.lp * it.L.mP * so),
                                    P->at<char>(it, it.L.o_Q1), it.L.mP, it.d.m, it.L.cchunk,
                                    P->at<double>(it, it.L.o_Cp), it.L.lp, it.L.K, it.L.ncc};
               }),
@@ -558,19 +606,19 @@ struct Recorder {
         auto gargs = [&](auto buf, bool cond) {
             return each([&](const Item& it) {
                 return GramArgs{buf(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
+                                cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
             });
         };
         auto cargs = [&](int k, int mode) {
             return each([&](const Item& it) {
                 return CholArgs{P->at<double>(it, it.L.o_G), it.d.m, P->at<double>(it, it.L.o_R64[k]),
-                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flag(it, 1), it.L.l, it.L.lp, mode};
             });
         };
         auto apply = [&](auto src, auto dst, int k, bool cond) {
             return each([&](const Item& it) {
                 return SxArgs{src(it), it.L.mP, it.d.m, it.L.lp, Rx(it, k), it.L.lp, dst(it), it.L.mP, it.L.mP,
-                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+                              cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, -1};
             });
         };
         gram(dt, gargs(In, false));
@@ -600,19 +648,19 @@ struct Recorder {
         auto gargs = [&](auto buf, bool cond) {
             return each([&](const Item& it) {
                 return GramArgs{buf(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
+                                cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
             });
         };
         auto cargs = [&](int k, int mode) {
             return each([&](const Item& it) {
                 return CholArgs{P->at<double>(it, it.L.o_G), it.d.m, P->at<double>(it, it.L.o_R64[k]),
-                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flag(it, 1), it.L.l, it.L.lp, mode};
             });
         };
         auto apply = [&](auto src, auto dst, int k, bool cond) {
             return each([&](const Item& it) {
                 return SxArgs{src(it), it.L.mP, it.d.m, it.L.lp, Rx(it, k), it.L.lp, dst(it), it.L.mP, it.L.mP,
-                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+                              cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, -1};
             });
         };
         gram(dt, gargs(In, false));
@@ -650,19 +698,19 @@ struct Recorder {
         auto gargs = [&](bool cond) {
             return each([&](const Item& it) {
                 return GramArgs{Q(it), it.L.mP, it.d.m, P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
+                                cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, gram_nwg(it.d.m, it.L.gram_cap, it.L.nt)};
             });
         };
         auto cargs = [&](int k, int mode) {
             return each([&](const Item& it) {
                 return CholArgs{P->at<double>(it, it.L.o_G), it.d.m, P->at<double>(it, it.L.o_R64[k]),
-                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flag(it, 1), it.L.l, it.L.lp, mode};
             });
         };
         auto apply = [&](int k, bool cond) {
             return each([&](const Item& it) {
                 return SxArgs{Q(it), it.L.mP, it.d.m, it.L.lp, Rx(it, k), it.L.lp, Q(it), it.L.mP, it.L.mP,
-                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+                              cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, -1};
             });
         };
         gram(dt, gargs(false));
@@ -727,20 +775,20 @@ struct Recorder {
             return each([&](const Item& it) {
                 return GramArgs{P->at<char>(it, second ? it.L.o_Zw2 : it.L.o_Zw), it.L.nP, it.d.n,
                                 P->at<double>(it, it.L.o_Gpart), P->at<double>(it, it.L.o_G),
-                                cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
+                                cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
             });
         };
         auto app = [&](size_t Layout::*src, size_t Layout::*dst, int k, bool cond) {
             return each([&](const Item& it) {
                 return SxArgs{P->at<char>(it, it.L.*src), it.L.nP, it.d.n, it.L.lp, P->at<char>(it, it.L.o_R64[k]),
-                              it.L.lp, P->at<char>(it, it.L.*dst), it.L.nP, it.L.nP, cond ? P->flags(it) + 1 : nullptr,
+                              it.L.lp, P->at<char>(it, it.L.*dst), it.L.nP, it.L.nP, cond ? P->flag(it, 1) : nullptr,
                               cond ? 1 : 0, -1};
             });
         };
         auto cargs = [&](int k, int mode) {
             return each([&](const Item& it) {
                 return CholArgs{P->at<double>(it, it.L.o_G), it.d.n, P->at<double>(it, it.L.o_R64[k]),
-                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flag(it, 1), it.L.l, it.L.lp, mode};
             });
         };
         gram(DT_F64, gargs(false, false));
@@ -758,7 +806,7 @@ struct Recorder {
         auto gargs = [&](size_t Layout::*src, bool cond) {
             return each([&](const Item& it) {
                 return GramArgs{P->at<char>(it, it.L.*src), it.L.nP, it.d.n, P->at<double>(it, it.L.o_Gpart),
-                                P->at<double>(it, it.L.o_G), cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0,
+                                P->at<double>(it, it.L.o_G), cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0,
                                 gram_nwg(it.d.n, it.L.gram_cap, it.L.nt)};
             });
         };
@@ -766,13 +814,13 @@ struct Recorder {
             return each([&](const Item& it) {
                 return SxArgs{P->at<char>(it, it.L.*src), it.L.nP, it.d.n, it.L.lp, P->at<char>(it, it.L.o_R64[k]),
                               it.L.lp, P->at<char>(it, it.L.o_Zw2), it.L.nP, it.L.nP,
-                              cond ? P->flags(it) + 1 : nullptr, cond ? 1 : 0, -1};
+                              cond ? P->flag(it, 1) : nullptr, cond ? 1 : 0, -1};
             });
         };
         auto cargs = [&](int k, int mode) {
             return each([&](const Item& it) {
                 return CholArgs{P->at<double>(it, it.L.o_G), it.d.n, P->at<double>(it, it.L.o_R64[k]),
-                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flags(it) + 1, it.L.l, it.L.lp, mode};
+                                P->at<float>(it, it.L.o_R32[k]), P->flags(it), P->flag(it, 1), it.L.l, it.L.lp, mode};
             });
         };
         gram(DT_F64, gargs(&Layout::o_Zw, false));
@@ -917,7 +965,7 @@ struct Recorder {
         g.bytes = (double)it.d.m * it.d.n * sz + (double)it.d.n * p * sz + (double)it.d.m * p * 4.0;
         g.flops = 2.0 * it.d.m * it.d.n * p;
         SxArgs ga{nullptr, it.d.ld, it.d.m, it.d.n, P->at<char>(it, L.o_X), L.nP,
-                  P->at<char>(it, L.o_Y) + (size_t)r * L.mP * dt_size(L.tacc), L.mP, L.mP, nullptr, 0, it.idx, p};
+                  P->at<char>(it, L.o_Y + (size_t)r * L.mP * dt_size(L.tacc)), L.mP, L.mP, nullptr, 0, it.idx, p};
         B.add(g, std::vector<SxArgs>{ga}, std::vector<int>{(int)(L.mP / 256)});
         out.push_back(g);
         // the predicted subspace W = bank Z into the first r columns
@@ -935,6 +983,7 @@ struct Recorder {
         pass_stq(true);
         small_from_slabs();
         finish();
+        if (std::isinf(P->tol)) return;  // accept every warm result: no residual, no continuation
         // residual of each returned triplet: Y = S A^T with FP64 products (A^T of
         // the internal FP64 coefficients, n x r), then rho_k and the decision
         Step w{K_SXW};
@@ -951,7 +1000,7 @@ struct Recorder {
               std::vector<int>{P->res_nchunk});
         B.add(rs, std::vector<ModeResFinalArgs>{{P->wat<double>(P->w_part), P->at<double>(it, L.o_sig),
                                                  P->wat<double>(P->w_rhom), P->wat<double>(P->w_rho), P->flags(it),
-                                                 P->flags(it) + WARM_DECISION, P->tol, r, P->res_nchunk}},
+                                                 P->flag(it, WARM_DECISION), P->tol, r, P->res_nchunk}},
               std::vector<int>{1}, true);
         out.push_back(rs);
         // continuation after a rejection: q_fb more subspace iterations from the
@@ -1813,10 +1862,15 @@ rpod_status rpod_compute_warm(rpod_plan plan, const void* S, const float* mu, ui
     rpod_status s = compute_impl(plan, &S, &seed, &Phi, &sigma, &A, mu);
     if (s != RPOD_OK) return s;
     if (fell_back == nullptr && rho == nullptr) return RPOD_OK;
+    if (std::isinf(plan->tol)) {  // no check was recorded
+        if (fell_back) *fell_back = 0;
+        if (rho) *rho = std::nan("");
+        return RPOD_OK;
+    }
     double rh = 0.0;
     int dec = 0;
     HIP_TRY(hipMemcpyAsync(&rh, plan->wat<double>(plan->w_rho), sizeof(double), hipMemcpyDeviceToHost, plan->st));
-    HIP_TRY(hipMemcpyAsync(&dec, plan->flags(plan->items[0]) + WARM_DECISION, sizeof(int), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(&dec, plan->flag(plan->items[0], WARM_DECISION), sizeof(int), hipMemcpyDeviceToHost,
                            plan->st));
     HIP_TRY(hipStreamSynchronize(plan->st));
     if (fell_back) *fell_back = dec;
@@ -1828,6 +1882,7 @@ rpod_status rpod_warm_residuals(rpod_plan plan, double* rho_modes) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     if (plan->model == nullptr) return fail(RPOD_EINVAL, "not a warm plan");
     if (rho_modes == nullptr) return fail(RPOD_EINVAL, "rho_modes is NULL");
+    if (std::isinf(plan->tol)) return fail(RPOD_EINVAL, "the plan was made with tol = +infinity: no residuals");
     HIP_TRY(hipMemcpyAsync(rho_modes, plan->wat<double>(plan->w_rhom), sizeof(double) * plan->items[0].d.r,
                            hipMemcpyDeviceToHost, plan->st));
     HIP_TRY(hipStreamSynchronize(plan->st));

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256, 2) void k_sx16(Group<SxArgs> g) {
     if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
-    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    const void* S = static_cast<const char*>(a.call >= 0 ? g.calls[a.call].S : a.S) + a.col0 * a.ldS * 2;
     sx16_body<T16, NT, VEC>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.X), a.ldX,
                             gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
                             blockIdx.x - g.tstart[it]);

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
-    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    const void* S = static_cast<const char*>(a.call >= 0 ? g.calls[a.call].S : a.S) + a.col0 * a.ldS * 4;
     if constexpr (EN) {
         __shared__ double red[256];
         double sq = 0.0;

@@ -117,7 +117,8 @@ __global__ __launch_bounds__(256) void k_sx(Group<SxArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
-    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    const void* S = static_cast<const char*>(a.call >= 0 ? g.calls[a.call].S : a.S) +
+                    a.col0 * a.ldS * (int64_t)sizeof(Tin);
     sx_body<Tin, Tin, Tout, NT, VEC, UPPER>(gbl((const Tin*)S), a.ldS, a.m, a.n, gbl((const Tin*)a.X), a.ldX,
                                             gbl((Tout*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
                                             blockIdx.x - g.tstart[it]);
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(256) void k_sx_wide(Group<SxArgs> g) {
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const SxArgs& a = g.args[it];
     if (a.cond != nullptr && !(*a.cond & a.cond_mask)) return;
-    const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
+    const void* S = static_cast<const char*>(a.call >= 0 ? g.calls[a.call].S : a.S) +
+                    a.col0 * a.ldS * (int64_t)sizeof(Tin);
     sx_body<Tin, double, double, NT, VEC, false>(gbl((const Tin*)S), a.ldS, a.m, a.n, gbl((const double*)a.X),
                                                  a.ldX, gbl((double*)a.Y), a.ldY, a.mstore,
                                                  a.cmax > 0 ? a.cmax : 16 * NT, blockIdx.x - g.tstart[it]);
@@ -333,7 +335,11 @@ __global__ void k_reduce_slabs(Group<ReduceArgs> g) {
             for (int u = 0; u < 8; ++u) p8[u] += Zp[(int64_t)(k + u) * a.count];
         for (; k < ns; ++k) p8[k & 7] += Zp[(int64_t)k * a.count];
     }
-    *gbl(a.out + e) = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
+    const double v = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
+    if (a.out32)
+        *gbl((float*)a.out + e) = (float)v;
+    else
+        *gbl((double*)a.out + e) = v;
 }
 
 // ---------------------------------------------------------------------------

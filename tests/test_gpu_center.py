@@ -69,6 +69,8 @@ def centred_case(St, r, p, q, seed, dtype, N, ld=None, name=""):
     (40, 25, 640, 10, 50, 14, 1, torch.float32, 0),     # 64 blocks with l = 64: widest first pass
     (64, 64, 400, 40, 20, 10, 2, torch.bfloat16, 0),
     (64, 64, 400, 100, 20, 10, 1, torch.float16, 8),
+    (32, 64, 8000, 400, 20, 10, 1, torch.float32, 0),  # short, wide: the first pass splits its columns
+    (32, 64, 8000, 500, 20, 10, 1, torch.bfloat16, 0),
 ])
 def test_centred_matches_oracle(nx, ny, n, N, r, p, q, dtype, ldpad):
     St = field(nx, ny, n, N, seed=nx + n + N)

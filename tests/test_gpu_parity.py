@@ -286,6 +286,19 @@ def test_mixed_ragged(m, n, r, p, q, dtype, ldpad):
     case(g["St"], r, p, q, 7, dtype, ld=m + ldpad if ldpad else None, name="mixed-ragged")
 
 
+@pytest.mark.parametrize("m,n,r,p,q,dtype,ldpad", [
+    (3000, 20000, 20, 10, 1, torch.float64, 0),     # 12 row tiles: the columns split 19 ways
+    (3001, 20000, 20, 10, 2, torch.float32, 3),     # odd leading dimension, ragged rows
+    (8192, 33333, 10, 75, 1, torch.float32, 0),     # the paper's rows, ragged last split
+    (2048, 9000, 30, 20, 1, torch.bfloat16, 0),
+    (2049, 9000, 30, 20, 1, torch.float16, 7),
+])
+def test_short_wide_split_columns(m, n, r, p, q, dtype, ldpad):
+    """Short, wide S: S X splits its columns into slabs summed afterwards."""
+    g = synth.lowrank_exp(m, n, decay=0.08, noise_std=1e-5, seed=m + n)
+    case(g["St"], r, p, q, 7, dtype, ld=m + ldpad if ldpad else None, name="short-wide")
+
+
 # ---------------------------------------------------------------------------
 # degenerate inputs and errors
 # ---------------------------------------------------------------------------

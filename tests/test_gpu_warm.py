@@ -332,3 +332,21 @@ def test_trained_network_gains_over_untrained_and_plain(world):
     assert med["trained"] < med["plain_q0"]
     for p_ in (pw, pu, pp):
         p_.close()
+
+
+def test_unchecked_plan_equals_the_accepted_warm_result(world):
+    """tol = +inf records no residual and no continuation: the outputs equal
+    those of a checked plan that accepts, rho is NaN, residuals() refuses."""
+    model = make_model(world)
+    i = int(world["test"][3])
+    mu = world["mu_hat"][i]
+    chk = rp.WarmPlan(model, N, P, 1, q_fallback=2, tol=1e9, device=DEV)
+    unc = rp.WarmPlan(model, N, P, 1, q_fallback=2, tol=float("inf"), device=DEV)
+    a = chk.compute(world["Sd"][i], mu, 31)
+    b = unc.compute(world["Sd"][i], mu, 31)
+    assert not a[3] and not b[3] and np.isnan(b[4]) and np.isfinite(a[4])
+    assert all(torch.equal(x, y) for x, y in zip(a[:3], b[:3]))
+    with pytest.raises(rp.RpodError):
+        unc.residuals()
+    chk.close()
+    unc.close()
