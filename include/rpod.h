@@ -273,6 +273,22 @@ rpod_status rpod_reconstruct(int32_t dtype, int64_t m, int32_t r, int64_t T, con
                              const void* alpha, void* out, const void* ref, int64_t ld_ref, void* workspace,
                              size_t workspace_bytes, void* hip_stream, double* eps);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): rpod_reconstruct without
+ * a workspace argument. Same arguments, meaning and results, except that the
+ * fields are always formed by fused multiply-adds in dtype (never on the
+ * matrix cores, whose operand staging needs a workspace), so FP32 fields may
+ * differ from rpod_reconstruct's in the last bits; the error is the same
+ * computation. Its scratch (the time-averaged coefficients, the partial sums
+ * of the error) is a static device array of about 1 MB per GPU, kept until
+ * the process ends; the call allocates nothing. m <= 2^24 (RPOD_EINVAL
+ * beyond). Every call on one GPU shares that array: calls that overlap on
+ * one GPU (different streams or threads) race and must be serialised by the
+ * caller. */
+rpod_status rpod_reconstruct_noalloc(int32_t dtype, int64_t m, int32_t r, int64_t T, const void* Phi,
+                                     const void* mean, const void* alpha, void* out, const void* ref, int64_t ld_ref,
+                                     void* hip_stream, double* eps);
+
 /* The Gaussian sketch of Alg. 1 step 1 (entries N(0,1), Sec. 4.2), drawn on
  * the GPU: out (device) receives the n x l matrix column-major with leading
  * dimension ldo >= n, as double (dtype RPOD_F64) or float (RPOD_F32, the

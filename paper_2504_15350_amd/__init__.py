@@ -86,6 +86,8 @@ def lib():
             "rpod_reconstruct_workspace_size": [i64, i32, ctypes.POINTER(ctypes.c_size_t)],
             "rpod_reconstruct": [i32, i64, i32, i64, vp, vp, vp, vp, vp, i64, vp, ctypes.c_size_t, vp,
                                  ctypes.POINTER(ctypes.c_double)],
+            "rpod_reconstruct_noalloc": [i32, i64, i32, i64, vp, vp, vp, vp, vp, i64, vp,
+                                         ctypes.POINTER(ctypes.c_double)],
             "rpod_generate_omega": [u64, i64, i32, i32, vp, i64, vp],
             "rpod_sketch_bits": [u64, i64, i32, vp, vp],
             "rpod_plan_set_timing": [vp, i32],

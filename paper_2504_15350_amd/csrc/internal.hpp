@@ -96,6 +96,11 @@ hipError_t launch_center_sum(const GroupLaunch<CrossSumArgs>& L, hipStream_t st)
 // Reconstruction mean + Phi alpha (out may be NULL) and, with ref, the sums
 // ||avg ref - avg recon||^2 and ||avg ref||^2 into out2[0], out2[1] (abar: r
 // doubles, part: 2 ceil(m / 256) doubles of scratch). dt: DT_F64 or DT_F32.
+// Static scratch of rpod_reconstruct_noalloc: layout and the device address of
+// the current GPU's copy (looked up once per GPU).
+constexpr int64_t RECON_NOALLOC_MAX_M = (int64_t)1 << 24;
+constexpr int64_t RECON_NOALLOC_DOUBLES = 256 + 2 * (RECON_NOALLOC_MAX_M / 256);
+hipError_t recon_scratch(double** ptr);
 hipError_t launch_reconstruct(int dt, int64_t m, int r, int64_t T, const void* Phi, const void* mean,
                               const void* alpha, void* out, const void* ref, int64_t ld_ref, double* abar,
                               double* part, double* out2, hipStream_t st);

@@ -11,10 +11,42 @@
 //                 f = avg_t ref[i, t] (eight interleaved sums, fixed order),
 //                 g = mean[i] + sum_k Phi[i, k] abar_k
 //   k_recon_sum   the tiles' sums, in order
+#include <mutex>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
 namespace rpod {
+
+// Scratch of the entry point that allocates nothing (rpod_reconstruct_noalloc):
+// abar (doubles 0..127), the two sums (128, 129) and the error's partial sums
+// (from 256: two per 256-row tile, for m up to RECON_NOALLOC_MAX_M). Each GPU
+// holds its own copy until the process ends; every call on a GPU shares it.
+static __device__ __align__(256) double scratch[RECON_NOALLOC_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t recon_scratch(double** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        // the device address of this GPU's copy (the array's name in host code
+        // is only a stand-in for the symbol)
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_recon_abar(const T* __restrict__ alpha, int r, int64_t T_, double* abar) {

@@ -2034,6 +2034,32 @@ rpod_status rpod_reconstruct(int32_t dtype, int64_t m, int32_t r, int64_t T, con
     return RPOD_OK;
 }
 
+rpod_status rpod_reconstruct_noalloc(int32_t dtype, int64_t m, int32_t r, int64_t T, const void* Phi,
+                                     const void* mean, const void* alpha, void* out, const void* ref, int64_t ld_ref,
+                                     void* hip_stream, double* eps) {
+    if (dtype != RPOD_F64 && dtype != RPOD_F32) return fail(RPOD_EINVAL, "dtype must be RPOD_F64 or RPOD_F32");
+    if (T < 1) return fail(RPOD_EINVAL, "T must be >= 1");
+    if (m < 1 || r < 1 || r > 128) return fail(RPOD_EINVAL, "need m >= 1 and 1 <= r <= 128");
+    if (m > RECON_NOALLOC_MAX_M)
+        return fail(RPOD_EINVAL, "m = %lld exceeds the static scratch of this entry point (m <= %lld); "
+                    "use rpod_reconstruct with a workspace", (long long)m, (long long)RECON_NOALLOC_MAX_M);
+    if (Phi == nullptr || alpha == nullptr) return fail(RPOD_EINVAL, "Phi and alpha must be non-NULL");
+    if (ref != nullptr && ld_ref < m) return fail(RPOD_EINVAL, "ld_ref (%lld) must be >= m", (long long)ld_ref);
+    double* sc = nullptr;
+    HIP_TRY(recon_scratch(&sc));
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // every scratch word the kernels read is written earlier in the same call: nothing to clear
+    HIP_TRY(launch_reconstruct(dtype == RPOD_F64 ? DT_F64 : DT_F32, m, r, T, Phi, mean, alpha, out, ref, ld_ref, sc,
+                               sc + 256, sc + 128, st));
+    if (ref != nullptr && eps != nullptr) {
+        double h[2] = {0.0, 0.0};
+        HIP_TRY(hipMemcpyAsync(h, sc + 128, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        *eps = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+    }
+    return RPOD_OK;
+}
+
 rpod_status rpod_status_query(rpod_plan plan, int32_t* device_flags) {
     if (plan == nullptr) return fail(RPOD_EINVAL, "plan is NULL");
     std::vector<int32_t> f(plan->items.size(), 0);
