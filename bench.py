@@ -466,7 +466,7 @@ PAPER = dict(nx=64, ny=128, n=90225, r=10, q=1, ps=(0, 5, 10, 20, 50, 75), seed=
 PAPER_NAME = "paper_8192x90225"
 
 
-def paper_block(dev, steps, warmup, cpu=True):
+def paper_block(dev, steps, warmup, cpu=True, accuracy=True):
     """Row P: GPU FP32 and BF16 rPOD for every p on both calibrated fields,
     their accuracy against O1 (deterministic POD), and O1 / O2 timed on the host."""
     import torch
@@ -511,6 +511,13 @@ def paper_block(dev, steps, warmup, cpu=True):
                                             out=(res[0].double().cpu().numpy().T, res[1].cpu().numpy()))
                 log(f"[bench] paper {fname} {tname} p={p}: {ms:.3f} ms per rPOD ({gbs:.0f} GB/s over S)")
         del St16
+        if not accuracy:   # timing only (profiling runs): no host copy, O1 or O2
+            for v in gpu.values():
+                v.pop("out")
+            out["fields"][fname] = {"beta": beta, "gpu": gpu}
+            del St
+            torch.cuda.empty_cache()
+            continue
         S64 = host_fp64(St)
         del St
         torch.cuda.empty_cache()
@@ -808,8 +815,10 @@ def main():
         sys.exit(2)
     if args.workload == PAPER_NAME:
         import torch
-        res = paper_block(torch.device("cuda", 0), args.steps, args.warmup, cpu=not args.no_cpu_baseline)
-        b = res["fields"]["psi_like"]["by_p"]["75"]["bf16"]
+        res = paper_block(torch.device("cuda", 0), args.steps, args.warmup, cpu=not args.no_cpu_baseline,
+                          accuracy=not args.no_accuracy)
+        f = res["fields"]["psi_like"]
+        b = f["by_p"]["75"]["bf16"] if "by_p" in f else f["gpu"]["bf16_p75"]
         line = {"metric": "rPOD time-to-r-modes", "value": b["ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
                 "warmup": args.warmup, "ms_per_step": b["ms"], "higher_is_better": False, "scaling": "weak",
                 "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
