@@ -63,7 +63,7 @@ struct Layout {
     int l, lp, nt, rp, ntr;
     int64_t mP, nP;
     int tin, tacc;
-    int nsplit, ncb_lo;
+    int nsplit;
     int64_t split_rows;
     // split-K over the columns for S X on short, wide matrices (1: none)
     int nsplit_x;
@@ -134,8 +134,8 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     L.tacc = d->dtype == RPOD_F64 ? DT_F64 : DT_F32;
     // split-K over rows for S^T Q. FP64: blocks of 256 columns and
     // contiguous splits of >= 256 rows. FP32: blocks of 256 columns, splits
-    // interleaved in units of 64 rows. 16-bit: blocks of 128 columns (256
-    // with the lo part), splits interleaved in steps of 128 rows.
+    // interleaved in units of 64 rows. 16-bit: blocks of 256 columns,
+    // splits interleaved in steps of 128 rows.
     const bool s16 = is16(L.tin), f32 = L.tin == DT_F32;
     const int64_t ncb = s16 ? L.nP / stq16_block_cols(false) : f32 ? L.nP / stq_e6_block_cols() : L.nP / 256;
     const int64_t target = (s16 || f32) ? wg_target : std::max<int64_t>(64, wg_target / 4);
@@ -144,13 +144,14 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     // per pass, the 2560 tiles filling five rounds of two workgroups per CU; more are slower)
     const int64_t smax = f32 ? 128 : 64;
     if (ns > smax) ns = smax;
-    const int64_t maxs = s16 ? (d->m + 127) / 128 : f32 ? (d->m + 63) / 64 : (d->m + 255) / 256;
+    // 16-bit: at least 1024 rows per split (measured at 8192 x 90225: 6 or 8 splits 3.16 ms per
+    // call, 15 splits 3.40 ms; short splits cost more in slab traffic than they gain)
+    const int64_t maxs = s16 ? std::max<int64_t>(1, d->m / 1024) : f32 ? (d->m + 63) / 64 : (d->m + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (f32 && ns >= 8) ns -= ns % 8;  // whole XCD groups of splits
     if (ns < 1) ns = 1;
     L.split_rows = roundup((d->m + ns - 1) / ns, 64);
     L.nsplit = (s16 || f32) ? (int)ns : (int)((d->m + L.split_rows - 1) / L.split_rows);
-    L.ncb_lo = (int)(L.nP / stq16_block_cols(true));
     {   // at most as many splits as the main product (its slab buffer holds these), >= 256 rows each
         int64_t nsc = std::min<int64_t>(L.nsplit, (d->n + 255) / 256);
         if (nsc < 1) nsc = 1;

@@ -182,105 +182,94 @@ __global__ __launch_bounds__(256, 2) void k_sx16(Group<SxArgs> g) {
 
 // ---------------------------------------------------------------------------
 // Z_s = S_s^T Q_s, 16-bit S, Q given as 16-bit hi (and lo) parts.
-// Workgroup: G blocks of 128 columns of S over the rows of split s, R rows
-// per step (R = 128; 64 when the lo part doubles the Q block). Per step the
-// Q block (R x 16 NT) is staged in LDS once and serves the G column blocks,
-// whose S blocks (R x 128) pass through one LDS buffer in turn; global reads
-// cover 4 columns x 256 bytes (R = 128) per wave instruction, the shape that
-// streams near the HBM peak, and are non-temporal. Operands are plain
-// 16-byte LDS reads (K along rows):
-//   A[mm][8 kg + i] = S[i0 + 32 k + 8 kg + i][j0 + 128 g + 32 w + 16 u + mm]
+// Workgroup: one per CU (its LDS), 4 x WN waves (stq16_grid), a block of
+// 256 columns of S over the rows of split s, 128 rows per step. Per step the S block (128 x 256) and the Q block (128 x 16 NT, hi
+// then lo) are staged in LDS; wave (wm, wn) multiplies S columns
+// 64 wm .. 64 wm + 63 with the Q n-tiles wn NTW .. wn NTW + NTW - 1
+// (NTW = ceil(NT / WN); tiles >= NT are skipped). Global reads cover
+// 4 columns x 256 bytes per wave instruction (the shape that streams near the
+// HBM peak) and are non-temporal; the next step's S and Q blocks are in
+// flight during the matrix-core work. Operands are plain 16-byte LDS reads
+// (K along rows):
+//   A[mm][8 kg + i] = S[i0 + 32 k + 8 kg + i][j0 + 64 wm + 16 t + mm]
 //   B[8 kg + i][nn] = Q[i0 + 32 k + 8 kg + i][16 c + nn]   (hi, then lo)
-// Loads of the next S block (and of the next step's Q block) are in flight
-// during each matrix-core phase. Splits are interleaved (step t of split s
-// covers rows R (t nsplit + s) .. +R-1), so the workgroups of one column
-// block read neighbouring pieces of every column.
+// so every accumulator sees its k steps in row order, hi before lo. Splits
+// are interleaved (step t of split s covers rows 128 (t nsplit + s) .. +127),
+// so the workgroups of one column block read neighbouring pieces of every
+// column. Measured at 1048576 x 10000, lp = 128 (BF16, back to back): hi
+// 4.71 ms against 5.15 ms for two 4-wave workgroups per CU on 128 x 128
+// blocks (bit-identical slabs), hi + lo 6.27 ms against 7.41 ms (64-row steps
+// there).
 // ---------------------------------------------------------------------------
-constexpr int STQ16_HB = 128;  // columns per block
+constexpr int STQ16_HB = 256;  // columns per block
+constexpr int STQ16_R = 128;   // rows per step
 
-template <typename T16, int NT, bool VEC, bool LO, int G>
+// 4 x WN waves: hi 4 x 2; hi + lo 4 x 4, or 4 x 3 when that divides the Q tiles (96 columns), and
+// 4 x 2 below 64 Q columns (16 waves would spill); 4 x 1 up to 32 Q columns (two workgroups per
+// CU). A wave grid that divides the Q tiles keeps the matrix-core loop free of tile guards
+// (measured: guards cost 0.5 ms of 5.3 at lp = 128).
+template <bool LO, int NT> struct stq16_grid {
+    static constexpr int WM = 4,
+                         WN = NT <= 2 ? 1 : !(LO && NT >= 4) ? 2 : (NT % 4 != 0 && NT % 3 == 0) ? 3 : 4;
+};
+
+template <typename T16, int NT, bool VEC, bool LO>
 __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restrict__ S, int64_t ldS, int64_t m,
                                            int64_t n, const GLOBAL unsigned short* __restrict__ Qh,
                                            const GLOBAL unsigned short* __restrict__ Ql, int64_t ldQ,
                                            GLOBAL float* __restrict__ Zp, int64_t nP, int nsplit, int ncb, int tile) {
-    constexpr int R = LO ? 64 : 128;
+    constexpr int WM = stq16_grid<LO, NT>::WM, WN = stq16_grid<LO, NT>::WN, NTHR = 64 * WM * WN;
+    constexpr int R = STQ16_R, HB = STQ16_HB;
     constexpr int LDS_ = R + 8;   // column stride (elements) of the LDS blocks
     constexpr int LPC = R / 8;    // 16-byte chunks per column of a block
     constexpr int NQ = LO ? 2 : 1;
-    constexpr int HB = STQ16_HB;
+    constexpr int MT = HB / WM / 16, NTW = (NT + WN - 1) / WN;
     __shared__ __attribute__((aligned(16))) unsigned short ss[HB * LDS_];
     __shared__ __attribute__((aligned(16))) unsigned short qs[NQ * 16 * NT * LDS_];
     const int cb = tile % ncb, sp = tile / ncb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r16 = lane & 15, kg = lane >> 4;
-    const int64_t j0 = (int64_t)cb * (G * HB);
+    const int r16 = lane & 15, kg = lane >> 4, wm = wave % WM, wn = wave / WM;
+    const int64_t j0 = (int64_t)cb * HB;
     const int64_t ib = (int64_t)sp * R, stride = (int64_t)nsplit * R;
-    constexpr int SCH = HB * LPC / 256;                // S chunks per thread and half
+    constexpr int SCHT = HB * LPC;                     // S chunks per block
+    constexpr int SCH = (SCHT + NTHR - 1) / NTHR;      // ... per thread
     constexpr int QCH = 16 * NT * LPC;                 // Q chunks per block
-    constexpr int QPT = (QCH + 255) / 256;
+    constexpr int QPT = (QCH + NTHR - 1) / NTHR;
 
-    f32x4 acc[G][2][NT];  // [block][u][c]
+    f32x4 acc[MT][NTW];
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int c = 0; c < NT; ++c) acc[g][u][c] = f32x4{0, 0, 0, 0};
+        for (int c = 0; c < NTW; ++c) acc[t][c] = f32x4{0, 0, 0, 0};
 
     u16x8 sr[SCH], qr[NQ][QPT];
-    auto fetch_s = [&](int64_t i0, int g) {
-#pragma unroll
-        for (int q = 0; q < SCH; ++q) {
-            const int ch = tid + 256 * q;
-            sr[q] = load_rows8<VEC>(S, ldS, m, n, i0 + 8 * (ch % LPC), j0 + HB * g + ch / LPC);
-        }
-    };
-    auto fetch_q = [&](int64_t i0) {
+    auto fetch = [&](int64_t i0) {
 #pragma unroll
         for (int q = 0; q < QPT; ++q) {
-            const int ch = tid + 256 * q;
+            const int ch = tid + NTHR * q;
             if (ch < QCH) {
                 const int64_t off = (int64_t)(ch / LPC) * ldQ + i0 + 8 * (ch % LPC);
                 qr[0][q] = *reinterpret_cast<const GLOBAL u16x8*>(Qh + off);
                 if (LO) qr[NQ - 1][q] = *reinterpret_cast<const GLOBAL u16x8*>(Ql + off);
             }
         }
-    };
-    auto put_s = [&]() {
 #pragma unroll
         for (int q = 0; q < SCH; ++q) {
-            const int ch = tid + 256 * q;
-            *reinterpret_cast<u16x8*>(ss + (ch / LPC) * LDS_ + 8 * (ch % LPC)) = sr[q];
+            const int ch = tid + NTHR * q;
+            if (SCHT % NTHR == 0 || ch < SCHT) sr[q] = load_rows8<VEC>(S, ldS, m, n, i0 + 8 * (ch % LPC), j0 + ch / LPC);
         }
     };
-    auto compute = [&](int g) {
-#pragma unroll
-        for (int k = 0; k < R / 32; ++k) {
-            u16x8 a[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                a[u] = *reinterpret_cast<const u16x8*>(ss + (32 * wave + 16 * u + r16) * LDS_ + 32 * k + 8 * kg);
-#pragma unroll
-            for (int h = 0; h < NQ; ++h)  // hi and lo far apart: no back-to-back dependence
-#pragma unroll
-                for (int c = 0; c < NT; ++c) {
-                    const u16x8 b =
-                        *reinterpret_cast<const u16x8*>(qs + (h * 16 * NT + 16 * c + r16) * LDS_ + 32 * k + 8 * kg);
-#pragma unroll
-                    for (int u = 0; u < 2; ++u) acc[g][u][c] = mma16<T16>::run(a[u], b, acc[g][u][c]);
-                }
-        }
-    };
-    if (ib < m) {
-        fetch_q(ib);
-        fetch_s(ib, 0);
-    }
+    if (ib < m) fetch(ib);
     for (int64_t i0 = ib; i0 < m; i0 += stride) {
         __syncthreads();  // previous step fully consumed
-        put_s();
+#pragma unroll
+        for (int q = 0; q < SCH; ++q) {
+            const int ch = tid + NTHR * q;
+            if (SCHT % NTHR == 0 || ch < SCHT) *reinterpret_cast<u16x8*>(ss + (ch / LPC) * LDS_ + 8 * (ch % LPC)) = sr[q];
+        }
 #pragma unroll
         for (int q = 0; q < QPT; ++q) {
-            const int ch = tid + 256 * q;
+            const int ch = tid + NTHR * q;
             if (ch < QCH) {
 #pragma unroll
                 for (int h = 0; h < NQ; ++h)
@@ -288,28 +277,41 @@ __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restri
             }
         }
         __syncthreads();
-        if constexpr (G == 2) {
-            fetch_s(i0, 1);  // second block of this step, in flight during the first block's work
-            compute(0);
-            __syncthreads();
-            put_s();
-            __syncthreads();
+        if (i0 + stride < m) fetch(i0 + stride);  // next step, in flight during this one's work
+#pragma unroll
+        for (int k = 0; k < R / 32; ++k) {
+            u16x8 b[NQ][NTW];
+#pragma unroll
+            for (int h = 0; h < NQ; ++h)
+#pragma unroll
+                for (int c = 0; c < NTW; ++c) {
+                    const int nt = NTW * wn + c;
+                    if (NT % WN == 0 || nt < NT)
+                        b[h][c] = *reinterpret_cast<const u16x8*>(qs + (h * 16 * NT + 16 * nt + r16) * LDS_ + 32 * k +
+                                                                  8 * kg);
+                }
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const u16x8 a = *reinterpret_cast<const u16x8*>(ss + (16 * MT * wm + 16 * t + r16) * LDS_ + 32 * k +
+                                                                8 * kg);
+#pragma unroll
+                for (int h = 0; h < NQ; ++h)  // every accumulator: hi, then lo
+#pragma unroll
+                    for (int c = 0; c < NTW; ++c)
+                        if (NT % WN == 0 || NTW * wn + c < NT) acc[t][c] = mma16<T16>::run(a, b[h][c], acc[t][c]);
+            }
         }
-        if (i0 + stride < m) {  // next step, in flight during the last block's work
-            fetch_q(i0 + stride);
-            fetch_s(i0 + stride, 0);
-        }
-        compute(G - 1);
     }
     GLOBAL float* zp = Zp + (int64_t)sp * nP * (16 * NT);  // FP32 slabs (summed in FP64 afterwards)
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int c = 0; c < NT; ++c)
-                *reinterpret_cast<GLOBAL f32x4*>(zp + (int64_t)(16 * c + r16) * nP + j0 + HB * g + 32 * wave + 16 * u +
-                                                 4 * kg) = acc[g][u][c];
+        for (int c = 0; c < NTW; ++c) {
+            const int nt = NTW * wn + c;
+            if (NT % WN == 0 || nt < NT)
+                *reinterpret_cast<GLOBAL f32x4*>(zp + (int64_t)(16 * nt + r16) * nP + j0 + 16 * MT * wm + 16 * t +
+                                                 4 * kg) = acc[t][c];
+        }
 }
 
 // grouped launch: tile t covers column block t % ncb of split t / ncb. XCD-aware
@@ -317,17 +319,17 @@ __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restri
 // first workgroup are multiples of 8, local workgroup b takes tile
 // (b mod 8) T / 8 + b / 8, so each XCD holds every column block of a range of
 // splits and a split's Q rows are fetched into one L2 only.
-template <typename T16, int NT, bool VEC, bool LO, int G>
-__global__ __launch_bounds__(256, 2) void k_stq16(Group<StqArgs> g) {
+template <typename T16, int NT, bool VEC, bool LO>
+__global__ __launch_bounds__((64 * stq16_grid<LO, NT>::WM * stq16_grid<LO, NT>::WN)) void k_stq16(Group<StqArgs> g) {
     if (group_skipped(g)) return;
     const int it = group_item(g.tstart, g.count, blockIdx.x);
     const StqArgs& a = g.args[it];
     const void* S = a.call >= 0 ? g.calls[a.call].S : a.S;
     const int local = blockIdx.x - g.tstart[it], ntl = a.ncb * a.nsplit;
     const int tile = ((ntl & 7) == 0 && (g.tstart[it] & 7) == 0) ? (local & 7) * (ntl >> 3) + (local >> 3) : local;
-    stq16_body<T16, NT, VEC, LO, G>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q),
-                                    gbl((const unsigned short*)a.Ql), a.ldQ, gbl((float*)a.Zp), a.nP, a.nsplit, a.ncb,
-                                    tile);
+    stq16_body<T16, NT, VEC, LO>(gbl((const unsigned short*)S), a.ldS, a.m, a.n, gbl((const unsigned short*)a.Q),
+                                 gbl((const unsigned short*)a.Ql), a.ldQ, gbl((float*)a.Zp), a.nP, a.nsplit, a.ncb,
+                                 tile);
 }
 
 // Split an FP32 tall matrix into 16-bit hi = round(q) and lo = round(q - hi).
@@ -378,11 +380,11 @@ static hipError_t sx16_nt(const GroupLaunch<SxArgs>& L, bool vec, hipStream_t st
 
 template <typename T16, int NT, bool LO>
 static hipError_t stq16_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t st) {
-    constexpr int G = LO ? 2 : 1;  // measured: one Q block per 128 columns (hi), per 256 (hi + lo)
+    const dim3 block(64 * stq16_grid<LO, NT>::WM * stq16_grid<LO, NT>::WN);
     if (vec)
-        hipLaunchKernelGGL((k_stq16<T16, NT, true, LO, G>), dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
+        hipLaunchKernelGGL((k_stq16<T16, NT, true, LO>), dim3(L.tiles), block, 0, st, mkgroup16(L));
     else
-        hipLaunchKernelGGL((k_stq16<T16, NT, false, LO, G>), dim3(L.tiles), dim3(256), 0, st, mkgroup16(L));
+        hipLaunchKernelGGL((k_stq16<T16, NT, false, LO>), dim3(L.tiles), block, 0, st, mkgroup16(L));
     return hipGetLastError();
 }
 
@@ -406,8 +408,8 @@ static hipError_t stq16_dispatch(int nt, const GroupLaunch<StqArgs>& L, bool vec
     }
 }
 
-int stq16_block_cols(bool lo) { return (lo ? 2 : 1) * STQ16_HB; }
-int stq16_rows_per_step(bool lo) { return lo ? 64 : 128; }
+int stq16_block_cols(bool) { return STQ16_HB; }
+int stq16_rows_per_step(bool) { return STQ16_R; }
 
 hipError_t launch_sx16(int tin, int nt, bool vec, const GroupLaunch<SxArgs>& L, hipStream_t st) {
     if (tin == DT_BF16) return sx16_dispatch<__bf16>(nt, L, vec, st);
