@@ -49,13 +49,14 @@ struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)
     int call;
 };
 
-struct ReduceArgs {  // out = sum of nsplit slabs
+struct ReduceArgs {  // out = scale * (sum of nsplit slabs)
     const void* Zp;  // FP64 slabs, or FP32 ones when f32 is set
     int64_t count;
     void* out;       // FP64, or FP32 when out32 is set
     int nsplit;
     int f32;
     int out32;
+    double scale = 1.0;  // a power of two (undoes the scale of an FP16 Q)
 };
 
 // Fluctuation snapshots (Sec. 4.1): S' = S - M E^T / N with M the block sums
@@ -178,11 +179,12 @@ struct OmegaArgs {  // Gaussian sketch; seed from call table entry `call` (or `s
     uint32_t stream;  // counter word 3 (0: the sketch, 1: the residual probes)
 };
 
-struct SplitArgs {  // 16-bit hi/lo split
+struct SplitArgs {  // 16-bit hi/lo split of scale * Q
     const float* Q;
     int64_t count;
     unsigned short* hi;
     unsigned short* lo;
+    float scale = 1.0f;  // a power of two
 };
 
 struct ZeroArgs {

@@ -57,6 +57,12 @@ size_t dt_size(int dt) {
 }
 
 bool is16(int dt) { return dt == DT_BF16 || dt == DT_F16; }
+// FP16 storage of Q (hi and lo parts for the passes S^T Q): Q's entries are at most about 1 in
+// magnitude (orthonormal columns), so its FP16 parts are taken of 2^14 Q and the slab sums scaled
+// back by 2^-14 (both exact): hi stays below 2^15 and the lo part, about 2^-11 of hi, stays a
+// normal FP16 number for entries down to about 2^-17 instead of 2^-3. BF16 has FP32's exponent
+// range and needs no scale.
+double q16_scale(int dt) { return dt == DT_F16 ? 0x1p14 : 1.0; }
 
 // Buffers and sizes of one matrix, derived from its description.
 struct Layout {
@@ -497,8 +503,10 @@ struct Recorder {
         Step r{K_REDUCE};
         B.add(r, each([&](const Item& it) {
                   // the FP32 and 16-bit passes accumulate in FP32 and write FP32 slabs
-                  return ReduceArgs{P->at<double>(it, it.L.o_Zp), it.L.nP * it.L.lp, P->at<double>(it, it.L.*dst),
-                                    it.L.nsplit, it.L.tin != DT_F64 ? 1 : 0};
+                  ReduceArgs a{P->at<double>(it, it.L.o_Zp), it.L.nP * it.L.lp, P->at<double>(it, it.L.*dst),
+                               it.L.nsplit, it.L.tin != DT_F64 ? 1 : 0};
+                  a.scale = 1.0 / q16_scale(it.L.tin);
+                  return a;
               }),
               tiles([](const Item& it) { return (int)((it.L.nP * it.L.lp + 255) / 256); }));
         out.push_back(r);
@@ -678,8 +686,10 @@ struct Recorder {
         Step s{K_SPLIT};
         s.tin = L0().tin;
         B.add(s, each([&](const Item& it) {
-                  return SplitArgs{P->at<float>(it, it.L.o_Q1), it.L.mP * it.L.lp,
-                                   P->at<unsigned short>(it, it.L.o_Qh), P->at<unsigned short>(it, it.L.o_Ql)};
+                  SplitArgs a{P->at<float>(it, it.L.o_Q1), it.L.mP * it.L.lp,
+                              P->at<unsigned short>(it, it.L.o_Qh), P->at<unsigned short>(it, it.L.o_Ql)};
+                  a.scale = (float)q16_scale(it.L.tin);
+                  return a;
               }),
               tiles([](const Item& it) { return (int)((it.L.mP * it.L.lp / 4 + 255) / 256); }));
         out.push_back(s);

@@ -349,7 +349,7 @@ __global__ __launch_bounds__((64 * stq16_grid<LO, NT>::WM * stq16_grid<LO, NT>::
                                  tile);
 }
 
-// Split an FP32 tall matrix into 16-bit hi = round(q) and lo = round(q - hi).
+// Split an FP32 tall matrix into 16-bit hi = round(c q) and lo = round(c q - hi), c a power of two.
 template <typename T16>
 __global__ void k_split16(Group<SplitArgs> g) {
     if (group_skipped(g)) return;
@@ -360,7 +360,7 @@ __global__ void k_split16(Group<SplitArgs> g) {
     GLOBAL unsigned short* __restrict__ lo = gbl(sa.lo);
     const int64_t e = ((int64_t)(blockIdx.x - g.tstart[it]) * blockDim.x + threadIdx.x) * 4;
     if (e >= sa.count) return;
-    const f32x4 q = *reinterpret_cast<const GLOBAL f32x4*>(Q + e);
+    const f32x4 q = *reinterpret_cast<const GLOBAL f32x4*>(Q + e) * sa.scale;  // exact: a power of two
     u16x4 h, l;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

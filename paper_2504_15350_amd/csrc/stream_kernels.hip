@@ -335,7 +335,7 @@ __global__ void k_reduce_slabs(Group<ReduceArgs> g) {
             for (int u = 0; u < 8; ++u) p8[u] += Zp[(int64_t)(k + u) * a.count];
         for (; k < ns; ++k) p8[k & 7] += Zp[(int64_t)k * a.count];
     }
-    const double v = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
+    const double v = (((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]))) * a.scale;
     if (a.out32)
         *gbl((float*)a.out + e) = (float)v;
     else
