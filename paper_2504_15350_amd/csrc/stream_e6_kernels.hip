@@ -102,11 +102,15 @@ __device__ __forceinline__ f32x4 e6_rows4(const GLOBAL float* S, int64_t ld, int
 // ---------------------------------------------------------------------------
 constexpr int E6_XLD = 40;  // halfwords per staged X column (32 rows + pad)
 
-template <int NT, bool VEC, bool EN = false>
+// SPL (tall products of 16-bit plans): 1 or 2, also the BF16 or FP16 parts hi = round(c y) and
+// lo = round(c y - hi) of every stored value (c = scale16), as the split of a 16-bit plan takes them.
+template <int NT, bool VEC, bool EN = false, int SPL = 0>
 __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, int64_t m, int64_t n,
                                            const GLOBAL float* __restrict__ X, int64_t ldX,
                                            GLOBAL float* Y, int64_t ldY, int64_t mstore, int cmax, int64_t bx,
-                                           unsigned short* xs, double* ssq = nullptr) {
+                                           unsigned short* xs, double* ssq = nullptr,
+                                           GLOBAL unsigned short* hi16 = nullptr, GLOBAL unsigned short* lo16 = nullptr,
+                                           float scale16 = 1.0f) {
     constexpr int XPART = 16 * NT * E6_XLD;     // one staged part
     constexpr int XB = 3 * XPART;               // one staged X block (three parts)
     constexpr int XCH = 16 * NT * 8;            // 16-byte FP32 chunks of a block (4 rows each)
@@ -204,13 +208,42 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = iw + 4 * (4 * g + v);
+            const f32x4 o = {acc[0][c][v], acc[1][c][v], acc[2][c][v], acc[3][c][v]};
             if (row + 3 < mstore) {
-                *reinterpret_cast<GLOBAL f32x4*>(py + row) =
-                    f32x4{acc[0][c][v], acc[1][c][v], acc[2][c][v], acc[3][c][v]};
+                *reinterpret_cast<GLOBAL f32x4*>(py + row) = o;
             } else {
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    if (row + t < mstore) py[row + t] = acc[t][c][v];
+                    if (row + t < mstore) py[row + t] = o[t];
+            }
+            if constexpr (SPL != 0) {
+                typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
+                u16x4_t h, l;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float x = o[t] * scale16;  // exact: a power of two
+                    if constexpr (SPL == 1) {
+                        const __bf16 hb = (__bf16)x;
+                        h[t] = __builtin_bit_cast(unsigned short, hb);
+                        l[t] = __builtin_bit_cast(unsigned short, (__bf16)(x - (float)hb));
+                    } else {
+                        const _Float16 hf = (_Float16)x;
+                        h[t] = __builtin_bit_cast(unsigned short, hf);
+                        l[t] = __builtin_bit_cast(unsigned short, (_Float16)(x - (float)hf));
+                    }
+                }
+                const int64_t off = (int64_t)(16 * c + r16) * ldY + row;
+                if (row + 3 < mstore) {
+                    *reinterpret_cast<GLOBAL u16x4_t*>(hi16 + off) = h;
+                    *reinterpret_cast<GLOBAL u16x4_t*>(lo16 + off) = l;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (row + t < mstore) {
+                            hi16[off + t] = h[t];
+                            lo16[off + t] = l[t];
+                        }
+                }
             }
         }
     }
@@ -218,7 +251,7 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
 
 // EN: the energy report's variant (also each tile's sum of squares of S, in
 // a fixed order: per lane, then a tree over the workgroup)
-template <int NT, bool VEC, bool EN = false>
+template <int NT, bool VEC, bool EN = false, int SPL = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1, 2))) void k_sx_e6(
     Group<SxArgs> g) {
     if (group_skipped(g)) return;
@@ -241,9 +274,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
         }
         if (threadIdx.x == 0 && a.fpart != nullptr) a.fpart[blockIdx.x - g.tstart[it]] = red[0];
     } else {
-        sx_e6_body<NT, VEC>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
-                            gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
-                            blockIdx.x - g.tstart[it], xs);
+        sx_e6_body<NT, VEC, false, SPL>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
+                                        gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
+                                        blockIdx.x - g.tstart[it], xs, nullptr, gbl(a.hi16), gbl(a.lo16), a.scale16);
     }
 }
 
@@ -417,7 +450,15 @@ static Group<A> mke6(const GroupLaunch<A>& L) {
 }
 
 template <int NT>
-static hipError_t sxe6_nt(const GroupLaunch<SxArgs>& L, bool vec, bool en, hipStream_t st) {
+static hipError_t sxe6_nt(const GroupLaunch<SxArgs>& L, bool vec, bool en, int spl, hipStream_t st) {
+    if (spl != 0) {  // tall products (16-byte aligned operands) with the 16-bit split of the result
+        if (!vec || en) return hipErrorInvalidValue;
+        if (spl == 1)
+            hipLaunchKernelGGL((k_sx_e6<NT, true, false, 1>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+        else
+            hipLaunchKernelGGL((k_sx_e6<NT, true, false, 2>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+        return hipGetLastError();
+    }
     if (en) {
         if (vec)
             hipLaunchKernelGGL((k_sx_e6<NT, true, true>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
@@ -440,9 +481,9 @@ static hipError_t stqe6_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sx_e6(int nt, bool vec, bool en, const GroupLaunch<SxArgs>& L, hipStream_t st) {
+hipError_t launch_sx_e6(int nt, bool vec, bool en, int spl, const GroupLaunch<SxArgs>& L, hipStream_t st) {
     switch (nt) {
-#define RPOD_E6_CASE(K) case K: return sxe6_nt<K>(L, vec, en, st);
+#define RPOD_E6_CASE(K) case K: return sxe6_nt<K>(L, vec, en, spl, st);
         RPOD_E6_CASE(1) RPOD_E6_CASE(2) RPOD_E6_CASE(3) RPOD_E6_CASE(4)
         RPOD_E6_CASE(5) RPOD_E6_CASE(6) RPOD_E6_CASE(7) RPOD_E6_CASE(8)
 #undef RPOD_E6_CASE
