@@ -719,6 +719,38 @@ def accuracy_block(S64, gen, w, results):
     return out
 
 
+def vendor_gemm_reference(S16, lp, reps=5):
+    """For context: torch.matmul (hipBLASLt) BF16 GEMMs of the pass shapes on the same matrix,
+    S X (X: n x lp), S^T Q (Q: m x lp) and S^T [Q_hi Q_lo] (2 lp columns, the refinement pass's
+    work). Random operands; BF16 outputs (FP32 accumulation inside)."""
+    import torch
+    n, m = S16.shape
+    dev = S16.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    X = torch.randn((n, lp), generator=g, device=dev).to(torch.bfloat16)
+    Q = torch.randn((m, lp), generator=g, device=dev).to(torch.bfloat16)
+    Q2 = torch.randn((m, 2 * lp), generator=g, device=dev).to(torch.bfloat16)
+    S = S16.t()  # the m x n matrix, column-major
+    out = {}
+    for name, f in (("S_X", lambda: torch.matmul(S, X)), ("St_Q", lambda: torch.matmul(S16, Q)),
+                    ("St_Q_2lp", lambda: torch.matmul(S16, Q2))):
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(e0.elapsed_time(e1) / reps, 4)
+    del X, Q, Q2
+    torch.cuda.empty_cache()
+    log(f"[bench] torch.matmul (hipBLASLt) BF16 at the pass shapes: {out} ms")
+    return out
+
+
 def mixed_block(dev, steps, warmup, accuracy=True, cpu=True, others=True):
     """The headline workload in BF16 (the value) and, on the same matrix, plain
     FP32 (the in-GPU baseline) and FP16."""
@@ -733,6 +765,7 @@ def mixed_block(dev, steps, warmup, accuracy=True, cpu=True, others=True):
     keep = accuracy
     S16 = S32.to(torch.bfloat16)
     res = {"bf16": measure(DEFAULT, S16, steps, warmup, keep_out=keep)}
+    vendor = vendor_gemm_reference(S16, 128) if others else None
     del S16
     torch.cuda.empty_cache()
     if others:
@@ -761,6 +794,8 @@ def mixed_block(dev, steps, warmup, accuracy=True, cpu=True, others=True):
     for v in res.values():
         v.pop("out", None)
     torch.cuda.empty_cache()
+    if vendor is not None:
+        res["vendor_gemm_ms"] = vendor
     return res, acc, cpu_res
 
 
@@ -846,6 +881,14 @@ def main():
                 "f16_roofline": res["f16"]["roofline"], "f16_kernels": res["f16"]["kernels"],
                 "plain_roofline": res["fp32"]["roofline"], "plain_kernels": res["fp32"]["kernels"],
                 "plain_hbm_gbs_s_passes": res["fp32"]["hbm_gbs_s_passes"]})
+        if "vendor_gemm_ms" in res:
+            k = res["bf16"]["kernels"]
+            mixed["vendor_gemm_reference"] = {
+                "what": "torch.matmul (hipBLASLt) BF16 GEMMs with the shapes of the passes over this matrix, random "
+                        "operands, l = 128 (S_X: S X; St_Q: S^T Q; St_Q_2lp: S^T Q with 2 l columns, the refinement "
+                        "pass's matrix-core work), beside this library's average pass times",
+                "hipblaslt_ms": res["vendor_gemm_ms"],
+                "library_ms": {kk: k[kk]["avg_ms"] for kk in ("S_X", "St_Q", "St_Q_refine") if kk in k}}
         St_small = None
     else:
         main_res, cpu, St_small = simple_block(args.workload, dev, args.steps, args.warmup,
