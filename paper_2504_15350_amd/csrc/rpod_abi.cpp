@@ -150,9 +150,10 @@ Layout make_layout(const rpod_desc* d, int64_t wg_target, int gram_cap) {
     // per pass, the 2560 tiles filling five rounds of two workgroups per CU; more are slower)
     const int64_t smax = f32 ? 128 : 64;
     if (ns > smax) ns = smax;
-    // 16-bit: at least 1024 rows per split (measured at 8192 x 90225: 6 or 8 splits 3.16 ms per
-    // call, 15 splits 3.40 ms; short splits cost more in slab traffic than they gain)
-    const int64_t maxs = s16 ? std::max<int64_t>(1, d->m / 1024) : f32 ? (d->m + 63) / 64 : (d->m + 255) / 256;
+    // 16-bit: at least about 1365 rows per split (measured at 8192 x 90225, BF16: at p = 75
+    // 6, 7 or 8 splits 2.97-2.99 ms per call, 12 splits 3.07 ms, 15 splits 3.40 ms; at p = 20
+    // 6 splits 1.46 ms, 8 splits 1.50 ms; short splits cost more in slab traffic than they gain)
+    const int64_t maxs = s16 ? std::max<int64_t>(1, d->m * 3 / 4096) : f32 ? (d->m + 63) / 64 : (d->m + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (f32 && ns >= 8) ns -= ns % 8;  // whole XCD groups of splits
     if (ns < 1) ns = 1;

@@ -280,6 +280,12 @@ def test_mixed_lowrank(dtype):
     (4099, 301, 17, 9, 1, torch.float16, 8),
     (70000, 150, 33, 15, 2, torch.bfloat16, 0),
     (257, 513, 30, 20, 1, torch.float16, 0),
+    # widths whose 16-column tiles do not divide the S^T Q wave grid (guarded tiles), or do with
+    # three wave columns, and widths not a multiple of 32 (separate hi/lo split pass)
+    (20000, 400, 60, 15, 1, torch.bfloat16, 0),  # lp 80
+    (9000, 700, 70, 20, 1, torch.float16, 8),    # lp 96
+    (20001, 500, 90, 15, 2, torch.float16, 0),   # lp 112
+    (12000, 600, 50, 55, 1, torch.bfloat16, 5),  # lp 112, odd leading dimension
 ])
 def test_mixed_ragged(m, n, r, p, q, dtype, ldpad):
     g = synth.lowrank_exp(m, n, decay=0.08, noise_std=1e-5, seed=m + n)
