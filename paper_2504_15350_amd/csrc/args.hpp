@@ -35,10 +35,6 @@ struct SxArgs {  // Y = S X
     int cmax;  // > 0: only output columns < cmax are stored
     double* fpart;  // FP32 first pass with the energy report: per-tile sums of S's squares
     int64_t col0;   // the product starts at column col0 of S (split-K over the columns; X already offset)
-    // tall products of 16-bit plans: also the 16-bit hi and lo parts of scale16 * Y (ld ldY)
-    unsigned short* hi16 = nullptr;
-    unsigned short* lo16 = nullptr;
-    float scale16 = 1.0f;
 };
 
 struct StqArgs {  // Z_s = S_s^T Q_s (split-K slabs)

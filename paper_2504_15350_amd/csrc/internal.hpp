@@ -77,9 +77,8 @@ hipError_t launch_split16(int tin, const GroupLaunch<SplitArgs>& L, hipStream_t 
 //   of stq_e6_block_cols(); nsplit a multiple of 8 keeps each split's column
 //   blocks on one XCD.
 // en: also write each tile's sum of the squares of the S entries it read to fpart[tile]
-// spl (vec only, not with en): 1 or 2, also write the BF16 or FP16 parts of scale16 Y to hi16 and
-// lo16 (the split of a 16-bit plan's Q, fused into its tall product)
-hipError_t launch_sx_e6(int nt, bool vec, bool en, int spl, const GroupLaunch<SxArgs>& L, hipStream_t st);
+// tall (with vec, not with en): products with few columns of S, the next step's loads issued early
+hipError_t launch_sx_e6(int nt, bool vec, bool en, bool tall, const GroupLaunch<SxArgs>& L, hipStream_t st);
 hipError_t launch_stq_e6(int nt, bool vec, const GroupLaunch<StqArgs>& L, hipStream_t st);
 int stq_e6_block_cols();
 

@@ -206,7 +206,7 @@ hipError_t launch_reconstruct_mfma(int64_t m, int r, int64_t T_, const float* Ph
         L.calls = nullptr;
         L.count = 1;
         L.tiles = (int)((m + 255) / 256);
-        e = launch_sx_e6(8, true, false, 0, L, st);
+        e = launch_sx_e6(8, true, false, true, L, st);  // K = r + 1: a tall product
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -246,7 +246,7 @@ struct Step {
     int tin = 0, tout = 0, nt = 0, lp = 0;  // lp: padded size (small SVD, Cholesky)
     bool vec = true, upper = false, lo = false;
     bool energy = false;  // K_SXE6: also the per-tile sums of squares; K_FROB: only the final sum
-    int spl = 0;          // K_SXE6: also the BF16 (1) or FP16 (2) hi/lo parts of the result
+    bool tall = false;    // K_SXE6: a product with few columns of S (early loads)
     int pass = -1;  // 0: a pass S X over S, 1: a pass S^T Q over S, 2: the 16-bit refinement pass (timed)
     // conditional steps (warm and adaptive plans, one matrix): the launch does
     // nothing unless status word skip_word of the matrix has a bit of skip_mask
@@ -418,29 +418,14 @@ struct Recorder {
     // tall FP32 x small product on the BF16 matrix cores with split operands
     // (FP32-accurate), used when the small side's rows lp are a multiple of 32
     // (the kernel reads X rows up to a multiple of 32); FP64 or other lp: sx()
-    // split16 (16-bit plans, the product that writes Q1): the FP32 kernel also writes Q1's 16-bit
-    // hi/lo parts, as split_q would; returns whether it did (else split_q must follow)
-    bool sx_tall(int tacc, int nt, bool upper, std::vector<SxArgs> args, bool split16 = false) {
-        if (tacc != DT_F32 || L0().lp % 32 != 0) {
-            sx(tacc, tacc, nt, upper, std::move(args));
-            return false;
-        }
+    void sx_tall(int tacc, int nt, bool upper, std::vector<SxArgs> args) {
+        if (tacc != DT_F32 || L0().lp % 32 != 0) return sx(tacc, tacc, nt, upper, std::move(args));
         Step s{K_SXE6};
-        s.tin = DT_F32; s.tout = DT_F32; s.nt = nt; s.vec = true;
-        if (split16 && is16(L0().tin)) {
-            s.spl = L0().tin == DT_BF16 ? 1 : 2;
-            for (size_t i = 0; i < args.size(); ++i) {
-                const Item& it = *C[i];
-                args[i].hi16 = P->at<unsigned short>(it, it.L.o_Qh);
-                args[i].lo16 = P->at<unsigned short>(it, it.L.o_Ql);
-                args[i].scale16 = (float)q16_scale(it.L.tin);
-            }
-        }
+        s.tin = DT_F32; s.tout = DT_F32; s.nt = nt; s.vec = true; s.tall = true;
         std::vector<int> t;
         for (const SxArgs& a : args) t.push_back((int)((std::max(a.mstore, a.m) + 255) / 256));
         B.add(s, args, t);
         out.push_back(s);
-        return s.spl != 0;
     }
     // pass over S: Y = S X (first: with the centring indicator columns, if any)
     void pass_sx(bool first = false) {
@@ -652,13 +637,13 @@ struct Recorder {
         };
         gram(dt, gargs(In, false));
         chol(cargs(0, 0));
-        const bool fused = sx_tall(dt, L0().nt, true, apply(In, Out, 0, false), true);
+        sx_tall(dt, L0().nt, true, apply(In, Out, 0, false));
         gram(dt, gargs(Out, false));
         chol(cargs(kfin, 1));
-        sx_tall(dt, L0().nt, true, apply(Out, Out, kfin, true), true);  // shifted retry, in place (no-op otherwise)
+        sx_tall(dt, L0().nt, true, apply(Out, Out, kfin, true));  // shifted retry, in place (no-op otherwise)
         gram(dt, gargs(Out, true));
         chol(cargs(kfin, 2));
-        if (!fused) split_q();
+        split_q();
     }
     // One CholeskyQR of the tall Y into Q1 = Y R^-1 for an iterate of which only
     // the span matters (the product S^T Q1 of a subspace iteration that is not
@@ -694,11 +679,11 @@ struct Recorder {
         };
         gram(dt, gargs(In, false));
         chol(cargs(0, 0));
-        const bool fused = sx_tall(dt, L0().nt, true, apply(In, Out, 0, false), true);
+        sx_tall(dt, L0().nt, true, apply(In, Out, 0, false));
         gram(dt, gargs(Out, true));                              // after a shift only
         chol(cargs(2, 2));
-        sx_tall(dt, L0().nt, true, apply(Out, Out, 2, true), true);  // in place, after a shift only
-        if (!fused) split_q();
+        sx_tall(dt, L0().nt, true, apply(Out, Out, 2, true));    // in place, after a shift only
+        split_q();
     }
     // 16-bit storage: Q1 (FP32) as hi + lo BF16/FP16 parts for the passes S^T Q
     void split_q() {
@@ -1095,7 +1080,7 @@ hipError_t run_step(const rpod_plan_s* P, const Step& s, hipStream_t st) {
         case K_ZERO: return launch_zero_ints(P->gl<ZeroArgs>(s, false), st);
         case K_OMEGA: return launch_omega(s.tout, P->gl<OmegaArgs>(s, false), st);
         case K_SX: return launch_sx(s.tin, s.tout, s.nt, s.vec, s.upper, P->gl<SxArgs>(s, false), st);
-        case K_SXE6: return launch_sx_e6(s.nt, s.vec, s.energy, s.spl, P->gl<SxArgs>(s, false), st);
+        case K_SXE6: return launch_sx_e6(s.nt, s.vec, s.energy, s.tall, P->gl<SxArgs>(s, false), st);
         case K_SX16: return launch_sx16(s.tin, s.nt, s.vec, P->gl<SxArgs>(s, false), st);
         case K_STQ: return launch_stq(s.tin, s.nt, s.vec, P->gl<StqArgs>(s, false), st);
         case K_STQE6: return launch_stq_e6(s.nt, s.vec, P->gl<StqArgs>(s, false), st);

@@ -102,15 +102,16 @@ __device__ __forceinline__ f32x4 e6_rows4(const GLOBAL float* S, int64_t ld, int
 // ---------------------------------------------------------------------------
 constexpr int E6_XLD = 40;  // halfwords per staged X column (32 rows + pad)
 
-// SPL (tall products of 16-bit plans): 1 or 2, also the BF16 or FP16 parts hi = round(c y) and
-// lo = round(c y - hi) of every stored value (c = scale16), as the split of a 16-bit plan takes them.
-template <int NT, bool VEC, bool EN = false, int SPL = 0>
+// TALL (products with few columns of S, K = 16 nt or r + 1: the tall R^-1 applications, the lift,
+// the reconstruction): the next step's S columns are loaded as soon as the current ones are split,
+// before the matrix-core work (with four steps per workgroup every exposed load latency counts:
+// 1048576 x 128 times 128 x 128, 367 against 393 us); long passes over S keep the loads after the
+// matrix-core work (262144 x 5000 with 64 columns: 1.07 against 1.12 ms).
+template <int NT, bool VEC, bool EN = false, bool TALL = false>
 __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, int64_t m, int64_t n,
                                            const GLOBAL float* __restrict__ X, int64_t ldX,
                                            GLOBAL float* Y, int64_t ldY, int64_t mstore, int cmax, int64_t bx,
-                                           unsigned short* xs, double* ssq = nullptr,
-                                           GLOBAL unsigned short* hi16 = nullptr, GLOBAL unsigned short* lo16 = nullptr,
-                                           float scale16 = 1.0f) {
+                                           unsigned short* xs, double* ssq = nullptr) {
     constexpr int XPART = 16 * NT * E6_XLD;     // one staged part
     constexpr int XB = 3 * XPART;               // one staged X block (three parts)
     constexpr int XCH = 16 * NT * 8;            // 16-byte FP32 chunks of a block (4 rows each)
@@ -182,7 +183,10 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
         for (int t = 0; t < 4; ++t)
             split8(f32x4{sv[0][t], sv[1][t], sv[2][t], sv[3][t]}, f32x4{sv[4][t], sv[5][t], sv[6][t], sv[7][t]}, ah[t],
                    am[t], al[t]);
-        if (more) load_x(j0 + 32);
+        if (more) {
+            load_x(j0 + 32);
+            if (TALL) load_s(j0 + 32);  // sv is free once split
+        }
         __syncthreads();  // block buf staged
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
@@ -194,7 +198,7 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
             for (int t = 0; t < 4; ++t) mma6(ah[t], am[t], al[t], bh, bm, bl, acc[t][c]);
         }
         if (more) {
-            load_s(j0 + 32);
+            if (!TALL) load_s(j0 + 32);
             put_x(buf ^ 1);  // block buf ^ 1 was last read before this step's barrier
             buf ^= 1;
         }
@@ -208,42 +212,13 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = iw + 4 * (4 * g + v);
-            const f32x4 o = {acc[0][c][v], acc[1][c][v], acc[2][c][v], acc[3][c][v]};
             if (row + 3 < mstore) {
-                *reinterpret_cast<GLOBAL f32x4*>(py + row) = o;
+                *reinterpret_cast<GLOBAL f32x4*>(py + row) =
+                    f32x4{acc[0][c][v], acc[1][c][v], acc[2][c][v], acc[3][c][v]};
             } else {
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    if (row + t < mstore) py[row + t] = o[t];
-            }
-            if constexpr (SPL != 0) {
-                typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
-                u16x4_t h, l;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float x = o[t] * scale16;  // exact: a power of two
-                    if constexpr (SPL == 1) {
-                        const __bf16 hb = (__bf16)x;
-                        h[t] = __builtin_bit_cast(unsigned short, hb);
-                        l[t] = __builtin_bit_cast(unsigned short, (__bf16)(x - (float)hb));
-                    } else {
-                        const _Float16 hf = (_Float16)x;
-                        h[t] = __builtin_bit_cast(unsigned short, hf);
-                        l[t] = __builtin_bit_cast(unsigned short, (_Float16)(x - (float)hf));
-                    }
-                }
-                const int64_t off = (int64_t)(16 * c + r16) * ldY + row;
-                if (row + 3 < mstore) {
-                    *reinterpret_cast<GLOBAL u16x4_t*>(hi16 + off) = h;
-                    *reinterpret_cast<GLOBAL u16x4_t*>(lo16 + off) = l;
-                } else {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (row + t < mstore) {
-                            hi16[off + t] = h[t];
-                            lo16[off + t] = l[t];
-                        }
-                }
+                    if (row + t < mstore) py[row + t] = acc[t][c][v];
             }
         }
     }
@@ -251,7 +226,7 @@ __device__ __forceinline__ void sx_e6_body(const GLOBAL float* S, int64_t ldS, i
 
 // EN: the energy report's variant (also each tile's sum of squares of S, in
 // a fixed order: per lane, then a tree over the workgroup)
-template <int NT, bool VEC, bool EN = false, int SPL = 0>
+template <int NT, bool VEC, bool EN = false, bool TALL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1, 2))) void k_sx_e6(
     Group<SxArgs> g) {
     if (group_skipped(g)) return;
@@ -274,9 +249,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
         }
         if (threadIdx.x == 0 && a.fpart != nullptr) a.fpart[blockIdx.x - g.tstart[it]] = red[0];
     } else {
-        sx_e6_body<NT, VEC, false, SPL>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
-                                        gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
-                                        blockIdx.x - g.tstart[it], xs, nullptr, gbl(a.hi16), gbl(a.lo16), a.scale16);
+        sx_e6_body<NT, VEC, false, TALL>(gbl((const float*)S), a.ldS, a.m, a.n, gbl((const float*)a.X), a.ldX,
+                                         gbl((float*)a.Y), a.ldY, a.mstore, a.cmax > 0 ? a.cmax : 16 * NT,
+                                         blockIdx.x - g.tstart[it], xs);
     }
 }
 
@@ -450,13 +425,9 @@ static Group<A> mke6(const GroupLaunch<A>& L) {
 }
 
 template <int NT>
-static hipError_t sxe6_nt(const GroupLaunch<SxArgs>& L, bool vec, bool en, int spl, hipStream_t st) {
-    if (spl != 0) {  // tall products (16-byte aligned operands) with the 16-bit split of the result
-        if (!vec || en) return hipErrorInvalidValue;
-        if (spl == 1)
-            hipLaunchKernelGGL((k_sx_e6<NT, true, false, 1>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
-        else
-            hipLaunchKernelGGL((k_sx_e6<NT, true, false, 2>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
+static hipError_t sxe6_nt(const GroupLaunch<SxArgs>& L, bool vec, bool en, bool tall, hipStream_t st) {
+    if (tall && vec && !en) {
+        hipLaunchKernelGGL((k_sx_e6<NT, true, false, true>), dim3(L.tiles), dim3(256), 0, st, mke6(L));
         return hipGetLastError();
     }
     if (en) {
@@ -481,9 +452,9 @@ static hipError_t stqe6_nt(const GroupLaunch<StqArgs>& L, bool vec, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sx_e6(int nt, bool vec, bool en, int spl, const GroupLaunch<SxArgs>& L, hipStream_t st) {
+hipError_t launch_sx_e6(int nt, bool vec, bool en, bool tall, const GroupLaunch<SxArgs>& L, hipStream_t st) {
     switch (nt) {
-#define RPOD_E6_CASE(K) case K: return sxe6_nt<K>(L, vec, en, spl, st);
+#define RPOD_E6_CASE(K) case K: return sxe6_nt<K>(L, vec, en, tall, st);
         RPOD_E6_CASE(1) RPOD_E6_CASE(2) RPOD_E6_CASE(3) RPOD_E6_CASE(4)
         RPOD_E6_CASE(5) RPOD_E6_CASE(6) RPOD_E6_CASE(7) RPOD_E6_CASE(8)
 #undef RPOD_E6_CASE

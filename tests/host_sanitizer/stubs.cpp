@@ -95,7 +95,7 @@ hipError_t launch_stq(int, int, bool, const GroupLaunch<StqArgs>& L, hipStream_t
 hipError_t launch_sx16(int, int, bool, const GroupLaunch<SxArgs>& L, hipStream_t) { return chk(L); }
 hipError_t launch_stq16(int, int, bool, bool, const GroupLaunch<StqArgs>& L, hipStream_t) { return chk(L); }
 hipError_t launch_split16(int, const GroupLaunch<SplitArgs>& L, hipStream_t) { return chk(L); }
-hipError_t launch_sx_e6(int, bool, bool, int, const GroupLaunch<SxArgs>& L, hipStream_t) { return chk(L); }
+hipError_t launch_sx_e6(int, bool, bool, bool, const GroupLaunch<SxArgs>& L, hipStream_t) { return chk(L); }
 hipError_t launch_stq_e6(int, bool, const GroupLaunch<StqArgs>& L, hipStream_t) { return chk(L); }
 hipError_t launch_reduce_slabs(const GroupLaunch<ReduceArgs>& L, hipStream_t) { return chk(L); }
 hipError_t launch_center_prep(int, const GroupLaunch<CprepArgs>& L, hipStream_t) { return chk(L); }
