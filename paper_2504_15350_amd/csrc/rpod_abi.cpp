@@ -1218,8 +1218,9 @@ rpod_status batch_layout(const rpod_desc* descs, int32_t count, const rpod_tunin
     }
     rpod_status ts = check_tuning(tune);
     if (ts != RPOD_OK) return ts;
-    // single matrix: 5120 = ten rounds of two workgroups on 256 CUs (16-bit: 80 column blocks x
-    // 64 splits; the hi + lo pass, 40 x 64, five rounds)
+    // single matrix: 5120 workgroups wanted (FP32 at 262144 x 5000: 20 column blocks x 128
+    // splits, five rounds of two workgroups per CU; 16-bit at 1048576 x 10000: 40 column blocks
+    // x 64 splits, ten rounds of one workgroup per CU)
     int64_t wg = count == 1 ? 5120 : std::max<int64_t>(256, 8192 / count);
     if (tune && tune->stq_workgroups > 0) wg = tune->stq_workgroups;
     const int gcap = (tune && tune->gram_workgroups > 0) ? tune->gram_workgroups : 0;  // 0: automatic
