@@ -34,7 +34,10 @@ test), reported under "warm_vs_plain".
 
 Also measured (unless --no-center): fluctuation centring (Sec. 4.1) and the
 energy report on the 262144 x 5000 workload, under "centred_vs_plain" and
-"energy_report".
+"energy_report"; and (unless --no-adaptive) the adaptive-rank plan on the same
+matrix (blocks of 16 columns up to 128, q = 2, the threshold set to the energy
+of the fixed plan's 40 leading modes) beside fixed plans with the width it
+stopped at and with 128 columns, under "adaptive_vs_fixed".
 
 Per-kernel times of the passes over S come from HIP events that the library
 records on its stream around every pass during the timed steps.
@@ -589,6 +592,52 @@ def center_block(St, steps, warmup):
     }
 
 
+def adaptive_block(St, energies, steps, warmup, block=16, l_max=128, q=2, modes=40):
+    """The adaptive-rank plan on the FP32 262144 x 5000 field: the sketch grows by
+    `block` columns up to l_max until it captures the energy that the leading
+    `modes` modes of the fixed plan hold; timed beside fixed plans with the
+    width it stopped at and with l_max."""
+    import torch
+    import paper_2504_15350_amd as rp
+    w = WORKLOADS[PLAIN_SMALL]
+    n, m = St.shape
+    delta = float(energies[modes - 1])
+    ap = rp.AdaptivePlan(m, n, l_max, block, q, delta, dtype=St.dtype, device=St.device)
+    _, sig_a, _, l, rank, resid = ap.compute(St, w["seed"])
+    sig_a = sig_a.cpu().numpy()
+
+    def timed(run):
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_a = timed(lambda: ap.compute(St, w["seed"], check=False, info=False))
+    flags = ap.status()
+    ap.close()
+    out = {"config": {"workload": PLAIN_SMALL, "block": block, "l_max": l_max, "q": q,
+                      "delta": round(delta, 6), "delta_rule": f"energy of the fixed plan's {modes} leading modes"},
+           "l": l, "rank": rank, "residual": resid, "adaptive_ms": round(ms_a, 4), "flags": flags}
+    for tag, lw in (("fixed_same_l", l), ("fixed_l_max", l_max)):
+        plan = rp.Plan(m, n, lw - 10, 10, q, dtype=St.dtype, device=St.device)
+        o = (torch.empty((lw - 10, m), dtype=plan.out_dtype, device=St.device),
+             torch.empty((lw - 10,), dtype=torch.float64, device=St.device),
+             torch.empty((n, lw - 10), dtype=plan.out_dtype, device=St.device))
+        out[tag + "_ms"] = round(timed(lambda: plan.compute(St, w["seed"], out=o, check=False)), 4)
+        plan.status()
+        if tag == "fixed_same_l":
+            s_f = o[1].cpu().numpy()
+            k = min(20, len(s_f))
+            out["sigma_leading20_rel_diff_vs_fixed_same_l"] = float(np.max(np.abs(sig_a[:k] - s_f[:k]) / s_f[:k]))
+        plan.close()
+    log(f"[bench] adaptive: {out}")
+    return out
+
+
 def reconstruct_block(St, N, reps=5):
     """The reduced-order fields of the first parameter block (its time average
     plus the 50 modes of the fluctuations weighted by their coefficients) and the
@@ -828,6 +877,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batch measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start sweep")
     ap.add_argument("--no-center", action="store_true", help="skip the fluctuation-centring measurement")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-rank measurement")
     ap.add_argument("--headline-only", action="store_true",
                     help="on the headline workload, time BF16 alone (no FP16 / FP32 runs on the same matrix)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -894,7 +944,7 @@ def main():
         main_res, cpu, St_small = simple_block(args.workload, dev, args.steps, args.warmup,
                                                cpu=not args.no_cpu_baseline)
 
-    extra = energy = center = None
+    extra = energy = center = adaptive = None
     if args.workload == DEFAULT and not (args.no_extra and args.no_center):
         t0 = time.perf_counter()
         St_small = make_input(WORKLOADS[PLAIN_SMALL], dev)
@@ -914,6 +964,8 @@ def main():
                   "energy_first_10": [round(float(x), 6) for x in e[:10]], "energy_at_l": round(float(e[-1]), 6),
                   "rank_for_0.9": rk}
         log(f"[bench] energy: {energy}")
+        if not args.no_adaptive:
+            adaptive = adaptive_block(St_small, e, max(3, args.steps // 2), max(1, args.warmup // 2))
         center = center_block(St_small, max(3, args.steps // 2), max(1, args.warmup // 2))
         log(f"[bench] centring: plain {center['plain_ms']:.3f} ms, centred {center['centred_ms']:.3f} ms")
     del St_small
@@ -954,6 +1006,7 @@ def main():
         "warm_vs_plain": warm,
         "centred_vs_plain": center,
         "energy_report": energy,
+        "adaptive_vs_fixed": adaptive,
     }
     print(json.dumps(res), flush=True)
 
