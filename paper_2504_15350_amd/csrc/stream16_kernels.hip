@@ -240,7 +240,13 @@ __device__ __forceinline__ void stq16_body(const GLOBAL unsigned short* __restri
                                            GLOBAL float* __restrict__ Zp, int64_t nP, int nsplit, int ncb, int tile) {
     constexpr int WM = stq16_grid<LO, NT>::WM, WN = stq16_grid<LO, NT>::WN, NTHR = 64 * WM * WN;
     constexpr int R = STQ16_R, HB = STQ16_HB;
-    constexpr int LDS_ = R + 8;   // column stride (elements) of the LDS blocks
+    // column stride of the LDS blocks: 288 bytes. The LDS serves 32 lanes of a 16-byte read per
+    // cycle over a 512-byte window (measured on gfx950): lanes (column c, chunk kg < 2) then hit
+    // 16-byte slot 18 c + kg mod 32, all distinct; a 272-byte stride (17 c + kg) put two lanes on
+    // one slot and spent 36-40 % of the LDS cycles on bank conflicts (back to back: hi pass
+    // 4.68 -> 4.57 ms, hi + lo 6.21 -> 6.09 ms; in the pipeline the call gains 0.1 ms;
+    // bit-identical)
+    constexpr int LDS_ = R + 16;
     constexpr int LPC = R / 8;    // 16-byte chunks per column of a block
     constexpr int NQ = LO ? 2 : 1;
     constexpr int MT = HB / WM / 16, NTW = (NT + WN - 1) / WN;
