@@ -687,7 +687,11 @@ __device__ __forceinline__ void jacobi_chol_body(const double* __restrict__ G, i
     constexpr int TPP = NTHR / NPAIR;
     constexpr int RPT = LP / TPP;
     static_assert(TPP == 8 && RPT * TPP == LP, "pair layout: eight lanes per pair");
-    constexpr int LDW = LP + 2;      // 16-byte aligned columns
+    // column stride: the smallest >= LP that is 16 mod 64 doubles, so consecutive columns start
+    // 128 bytes apart within the LDS's 512-byte window. The 32 lanes of one cycle are four column
+    // pairs' 128-byte runs (eight lanes per pair), mostly of consecutive columns: with LP + 2 they
+    // overlapped and 41 % of the LDS cycles were bank conflicts
+    constexpr int LDW = LP + (((16 - LP) % 64) + 64) % 64;
     __shared__ __attribute__((aligned(16))) double W[LP * LDW];   // A[row][col] at W[col * LDW + row]
     __shared__ double nrm[LP];
     __shared__ int perm[LP];
